@@ -1,0 +1,91 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module draws random numbers and lays out arrays; it holds none of the method's
+arithmetic.  Every array is produced with ``numpy.random.default_rng(seed)`` (PCG64),
+so the CPU oracle and the HIP library read identical bytes.
+
+Workloads (planar pushing, square slider of side 0.1 m, one point pusher):
+  * ``push_tiny``      -- 8 start/goal pairs x all 144 two-segment orders, 5+5 intervals;
+  * ``push_plain``     -- 64 pairs x all 1,728 three-segment orders, 8+8+8 intervals
+                          (110,592 TOs);
+  * ``push_hetero``    -- 131,072 i.i.d. orders, K ~ U{1..5} segments, ids ~ U{0..11},
+                          intervals per segment ~ U{5..15}, on 64 pairs.
+Start at rest at the origin with the pusher at the face centre; goal x, y ~ U[-0.3, 0.3] m,
+theta ~ U[-pi, pi]; pusher friction mu ~ U[0.3, 0.5].
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+MAXSEG = 6
+PUSH_MODES = 12          # id = 3 * face + slip, face 0..3, slip 0 stick / 1 slide+ / 2 slide-
+
+
+def push_pairs(seed: int, n: int):
+    """n start/goal pairs: x0 [n,4], goal [n,3], inst [n,1] (pusher friction)."""
+    rng = np.random.default_rng(seed)
+    goal = np.empty((n, 3))
+    goal[:, 0] = rng.uniform(-0.3, 0.3, n)
+    goal[:, 1] = rng.uniform(-0.3, 0.3, n)
+    goal[:, 2] = rng.uniform(-np.pi, np.pi, n)
+    mu = rng.uniform(0.3, 0.5, n)
+    x0 = np.zeros((n, 4))
+    return x0, goal, mu.reshape(n, 1)
+
+
+def all_orders(K: int, n_modes: int = PUSH_MODES) -> np.ndarray:
+    """Every order of exactly K segments, lexicographic: [n_modes**K, K] int32."""
+    return np.array(list(itertools.product(range(n_modes), repeat=K)), dtype=np.int32).reshape(-1, K)
+
+
+def _batch(x0, goal, inst, orders, knots_per_seg):
+    n_pairs = x0.shape[0]
+    n_ord, K = orders.shape
+    B = n_pairs * n_ord
+    modes = np.zeros((B, MAXSEG), np.int32)
+    knots = np.zeros((B, MAXSEG), np.int32)
+    modes[:, :K] = np.tile(orders, (n_pairs, 1))
+    knots[:, :K] = np.asarray(knots_per_seg, np.int32)[None, :]
+    nseg = np.full(B, K, np.int32)
+    rep = np.repeat(np.arange(n_pairs), n_ord)
+    return dict(x0=x0[rep].copy(), goal=goal[rep].copy(), inst=inst[rep].copy(), nseg=nseg, modes=modes,
+                knots=knots, pair=rep)
+
+
+def push_tiny(seed: int = 0, n_pairs: int = 8):
+    """8 pairs x 144 two-segment orders, 5+5 intervals (1,152 TOs)."""
+    x0, goal, inst = push_pairs(seed, n_pairs)
+    return _batch(x0, goal, inst, all_orders(2), (5, 5))
+
+
+def push_plain(seed: int = 1000, n_pairs: int = 64):
+    """64 pairs x 1,728 three-segment orders, 8+8+8 intervals (110,592 TOs)."""
+    x0, goal, inst = push_pairs(seed, n_pairs)
+    return _batch(x0, goal, inst, all_orders(3), (8, 8, 8))
+
+
+def push_hetero(seed: int = 2100, B: int = 131072, n_pairs: int = 64, kmin: int = 1, kmax: int = 5,
+                nmin: int = 5, nmax: int = 15):
+    """B i.i.d. orders of uneven segment and interval counts on n_pairs pairs."""
+    rng = np.random.default_rng(seed)
+    x0, goal, inst = push_pairs(seed + 1, n_pairs)
+    nseg = rng.integers(kmin, kmax + 1, B).astype(np.int32)
+    modes = rng.integers(0, PUSH_MODES, (B, MAXSEG)).astype(np.int32)
+    knots = rng.integers(nmin, nmax + 1, (B, MAXSEG)).astype(np.int32)
+    live = np.arange(MAXSEG)[None, :] < nseg[:, None]
+    modes[~live] = 0
+    knots[~live] = 0
+    pair = rng.integers(0, n_pairs, B)
+    return dict(x0=x0[pair].copy(), goal=goal[pair].copy(), inst=inst[pair].copy(), nseg=nseg, modes=modes,
+                knots=knots, pair=pair)
+
+
+def subset(batch: dict, idx) -> dict:
+    return {k: v[idx] for k, v in batch.items()}
+
+
+def n_intervals(batch: dict) -> np.ndarray:
+    live = np.arange(MAXSEG)[None, :] < batch["nseg"][:, None]
+    return (batch["knots"] * live).sum(1)
