@@ -1,0 +1,145 @@
+"""Benchmark of the batched mode-conditioned TO evaluator on one MI355X.
+
+A step is one comet_evaluate over the whole batch of the planar-pushing workload
+(64 start/goal pairs x all 1,728 three-segment orders, 8+8+8 intervals = 110,592 TOs,
+augmented-Lagrangian outer loop <= 20, Gauss-Newton inner loop <= 10), inputs resident in
+HBM.  Prints one JSON line with solves/s, the roofline of the solver kernel and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per control interval per Gauss-Newton iteration of the pushing task
+# (structure-aware count, masked rows excluded): linearisation ~150, block assembly ~450,
+# 7x7 Cholesky ~140, gains ~490, value update ~200, forward pass ~60 and ~110 per trial step
+# length (8 trials): ~2.4 kflop.  An outer (multiplier) update adds ~40 flop per interval.
+FLOP_PER_INTERVAL_GN = 2400.0
+FLOP_PER_INTERVAL_AL = 40.0
+PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(batch, seconds_target=15.0):
+    """Oracle (FP64, plain C, one sequence per thread over all host threads) on a
+    strided sample of the workload; returns solves/s."""
+    import oracle
+    n_threads = os.cpu_count() or 1
+    B = len(batch["nseg"])
+    f32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    n = 64 * n_threads
+    # calibrate on a small strided sample, then size the timed sample to ~seconds_target
+    idx = np.linspace(0, B - 1, n).astype(np.int64)
+    sub = {k: v[idx] for k, v in batch.items()}
+    t0 = time.perf_counter()
+    oracle.evaluate(f32(sub["x0"]), f32(sub["goal"]), f32(sub["inst"]), sub["nseg"], sub["modes"], sub["knots"],
+                    nthreads=n_threads)
+    dt = time.perf_counter() - t0
+    n2 = int(min(B, max(n, n * seconds_target / max(dt, 1e-3))))
+    idx = np.linspace(0, B - 1, n2).astype(np.int64)
+    sub = {k: v[idx] for k, v in batch.items()}
+    t0 = time.perf_counter()
+    oracle.evaluate(f32(sub["x0"]), f32(sub["goal"]), f32(sub["inst"]), sub["nseg"], sub["modes"], sub["knots"],
+                    nthreads=n_threads)
+    dt = time.perf_counter() - t0
+    return dict(value=n2 / dt, unit="solves/s", cores=n_threads, kind="oracle",
+                sample=f"{n2} of {B} TOs, evenly strided over the batch, FP64, {n_threads} threads, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the evaluator runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2609_21803_amd import instances as I
+    from paper_2609_21803_amd import native
+
+    torch.cuda.set_device(0)
+    batch = I.push_plain()
+    B = len(batch["nseg"])
+    N = 24
+    ctx = native.Context(max_batch=B, max_segments=6, max_intervals=N)
+    d = native.to_device(batch)
+    out = dict(cost=torch.empty(B, device="cuda"), viol=torch.empty(B, device="cuda"),
+               feasible=torch.empty(B, dtype=torch.uint8, device="cuda"),
+               traj=torch.empty((B, N + 1, 7), device="cuda"), stats=torch.empty((B, 4), dtype=torch.int32, device="cuda"))
+    for _ in range(args.warmup):
+        ctx.evaluate(**d, **out)
+    torch.cuda.synchronize()
+    ctx.check()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    kern_ms = []
+    torch.cuda.synchronize()
+    e0.record()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.evaluate(**d, **out)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / max(args.steps, 1)
+    kern_ms.append(ctx.kernel_ms())          # kernel of the last step, HIP events in the library
+    # one more step with per-launch kernel timing for the roofline average
+    for _ in range(2):
+        ctx.evaluate(**d, **out)
+        torch.cuda.synchronize()
+        kern_ms.append(ctx.kernel_ms())
+    stats = out["stats"].cpu().numpy()
+    feas = out["feasible"].cpu().numpy()
+    gn_units = float((stats[:, 1].astype(np.float64) * N).sum())
+    al_units = float((stats[:, 0].astype(np.float64) * N).sum())
+    flops = gn_units * FLOP_PER_INTERVAL_GN + al_units * FLOP_PER_INTERVAL_AL
+    kms = float(np.mean(kern_ms))
+    achieved = flops / (kms * 1e-3) / 1e12
+    solves_per_s = B / (ms * 1e-3)
+    res = {
+        "metric": "mode-TO solves/s at viol<=1e-5",
+        "value": solves_per_s,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "planar pushing: 64 seeded start/goal pairs x all 1,728 three-segment contact-mode "
+                               "orders, 8+8+8 intervals (110,592 TOs), AL<=20 x GN<=10",
+                   "batch": B, "intervals": N, "parallelism": "single GPU"},
+        "feasible_fraction": float(feas.mean()),
+        "feasible_solves_per_s": float(feas.sum()) / (ms * 1e-3),
+        "mean_gn_iterations": float(stats[:, 1].mean()),
+        "mean_al_iterations": float(stats[:, 0].mean()),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_push_solve", "kernel_ms": kms, "flop_per_launch": flops},
+        "wall_s_timed": wall,
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(batch)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,128 @@
+/*
+ * comet.h -- C ABI of the MI355X (gfx950) batched mode-conditioned trajectory-optimisation
+ * evaluator and of the greedy contact-mode expansion around it.
+ *
+ * The method (CoMET): for a fixed contact-mode order the planning problem of Eq. (1)
+ * reduces to the smooth constrained TO of Eq. (2); every candidate order is solved by a
+ * finite-budget local solver whose result is scored in physical units by Eq. (4) and
+ * ranked by the merit of Eq. (5); Alg. 1 expands the best-ranked orders by r-edit
+ * neighbourhoods and refines the best feasible ones (Sec. III-B, III-C).
+ *
+ * Conventions for every call:
+ *   - Array pointers are DEVICE pointers owned by the caller (for example the data of
+ *     torch tensors on cuda:0).  Struct pointers are HOST pointers.  The library never
+ *     frees caller memory and never keeps a caller pointer after a call returns.
+ *   - Calls that take a stream are asynchronous on that stream unless stated; a NULL
+ *     stream means the default stream of the current device.
+ *   - No exception crosses the ABI.  Host-detectable errors (null pointers, sizes beyond
+ *     what the context was created for) return COMET_EINVAL before any launch, and
+ *     comet_last_error() describes them.  Errors in device data (an out-of-range mode id,
+ *     a segment count outside [1, max_segments], too many intervals, a non-finite input)
+ *     do not stop the batch: that sequence gets cost = NaN, viol = +inf, feasible = 0 and
+ *     a device error counter is incremented; comet_check() reads and clears it.
+ *   - Units are SI throughout: m, rad, N, m/s.
+ *   - Outputs depend only on the inputs of the same sequence, never on the batch.
+ */
+#ifndef COMET_H
+#define COMET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  COMET_OK = 0,
+  COMET_EINVAL = -1, /* bad argument or bad device data (see comet_last_error) */
+  COMET_EHIP = -2,   /* a HIP runtime call failed */
+  COMET_ENOMEM = -3, /* device allocation failed */
+  COMET_ESTATE = -4  /* call not valid in the context's current state */
+} comet_status;
+
+typedef enum { COMET_TASK_PUSH = 0 } comet_task;
+
+typedef struct comet_ctx comet_ctx; /* opaque */
+
+/* Solver parameters of the per-order TO (Sec. III-C).  Defaults: comet_default_params.
+ *   al_max, gn_max          augmented-Lagrangian outer / Gauss-Newton inner budget
+ *                           (exploration budget t_exp of Alg. 1)
+ *   ref_al_max, ref_gn_max  refinement budget t_ref
+ *   chol_retries            Cholesky attempts with raised damping before a step is rejected
+ *   ls_trials               trial step lengths 1, 1/2, ..., 2^-(ls_trials-1), 1..16
+ *   max_rejects             consecutive rejected steps that end an inner loop
+ *   mu0, mu_min             initial / smallest penalty parameter mu (phi uses c^2/(2 mu))
+ *   rho0, rho_min, rho_max  damping of the local systems S_k = H_k + rho I + A^T A / mu
+ *   armijo_c1               sufficient-decrease constant of the trial steps
+ *   eta_star, omega_star,   scaled feasibility, stationarity and complementarity
+ *   rc_star                 tolerances of the stopping test
+ *   eps_feas                feasibility tolerance of the physical-unit score, Eq. (4)   */
+typedef struct {
+  int32_t al_max, gn_max, ref_al_max, ref_gn_max;
+  int32_t chol_retries, ls_trials, max_rejects, reserved;
+  double mu0, mu_min, rho0, rho_min, rho_max, armijo_c1;
+  double eta_star, omega_star, rc_star, eps_feas;
+} comet_solver_params;
+
+void comet_default_params(comet_solver_params* p);
+
+/* Create a context for one task on the current HIP device.  Allocates the device work
+ * space for up to max_batch sequences of up to max_segments segments and max_intervals
+ * control intervals each (synchronous).  Returns COMET_EINVAL for max_segments outside
+ * [1, 6], max_intervals outside [1, 512] or max_batch < 1, COMET_ENOMEM if the work space
+ * does not fit. */
+comet_status comet_create(comet_task task, const comet_solver_params* params, int64_t max_batch,
+                          int32_t max_segments, int32_t max_intervals, comet_ctx** out);
+void comet_destroy(comet_ctx* ctx);
+
+/* Message of the last error on this context (thread-unsafe; the context owns the string). */
+const char* comet_last_error(const comet_ctx* ctx);
+
+/* Task dimensions: state size nx, control size nu, instance parameters per sequence,
+ * number of mode ids, and the context limits. */
+comet_status comet_dims(const comet_ctx* ctx, int32_t* nx, int32_t* nu, int32_t* n_inst_params, int32_t* n_modes,
+                        int32_t* max_segments, int32_t* max_intervals, int64_t* max_batch);
+
+/* Row scales of the solver's internal constraint scaling (Sec. IV-A: each row type is
+ * divided by its median Jacobian-row 2-norm over sample orders).  out: host, n >= 12. */
+comet_status comet_row_scales(const comet_ctx* ctx, double* out, int32_t n);
+
+/* Synchronise `stream`, read and clear the device error counter.  Returns COMET_EINVAL
+ * (with the count in comet_last_error) if any sequence since the last check had invalid
+ * device data. */
+comet_status comet_check(comet_ctx* ctx, void* stream);
+
+/* Evaluate B candidate orders: one mode-conditioned TO per sequence (Eq. 2), scored by
+ * Eq. (4).  Pushing task: nx = 4 (x, y, theta, s), nu = 3 (F_n, F_t, v_s), one instance
+ * parameter (pusher friction), 12 mode ids = 3*face + slip (face 0..3 with outward normal
+ * at angle face*pi/2; slip 0 stick, 1 slide+, 2 slide-).
+ *   x0    [B, nx]      start state (float32)
+ *   goal  [B, 3]       goal pose (x, y, theta), theta not wrapped
+ *   inst  [B, 1]       instance parameters
+ *   nseg  [B]          number of segments K, 1..max_segments (int32)
+ *   modes [B, Smax]    mode id of each segment, Smax = max_segments; entries >= K ignored
+ *   knots [B, Smax]    control intervals of each segment (>= 1); their sum N <= max_intervals
+ *   warm  [B, Nmax+1, nx+nu] or NULL: initial primal (rows (x_k, u_k), Nmax = max_intervals);
+ *                      NULL = schedule-derived initial guess (Sec. IV-A)
+ *   refine 0 = exploration budget (al_max, gn_max), 1 = refinement budget
+ *   cost  [B]          J at the returned trajectory (float32)
+ *   viol  [B]          max(|g|_inf, |[h]_+|_inf) in physical units, Eq. (4)
+ *   feasible [B]       1 iff viol <= eps_feas (uint8)
+ *   traj  [B, Nmax+1, nx+nu] or NULL: row k = (x_k, u_k), row N has u = 0, rows > N zero
+ *   stats [B, 4] or NULL: (outer iterations, inner iterations, Cholesky failures, status)
+ *                      status 1 converged, 0 budget exhausted, 2 non-finite, 3 invalid input
+ * B = 0 is a no-op.  B > max_batch returns COMET_EINVAL. */
+comet_status comet_evaluate(comet_ctx* ctx, void* stream, int64_t B, const float* x0, const float* goal,
+                            const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
+                            const float* warm, int32_t refine, float* cost, float* viol, uint8_t* feasible,
+                            float* traj, int32_t* stats);
+
+/* Device time (milliseconds) of the last comet_evaluate on this context, measured with
+ * HIP events around its solver kernel on the caller's stream; valid after that stream
+ * has been synchronised.  Used for roofline accounting. */
+comet_status comet_last_kernel_ms(comet_ctx* ctx, float* ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

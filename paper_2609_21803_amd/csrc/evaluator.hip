@@ -1,0 +1,1005 @@
+// evaluator.hip -- batched mode-conditioned TO evaluator for MI355X (gfx950).
+//
+// One contact-mode order per lane.  Every lane runs its own augmented-Lagrangian /
+// Gauss-Newton solve (Sec. III-C) as a flat state machine: each trip of the wave loop is
+// one Gauss-Newton iteration (backward Riccati sweep, forward pass with all trial step
+// lengths, step application) for every lane still inside an inner loop, followed by the
+// outer update of the lanes whose inner loop ended.  Lanes of a wave therefore never
+// wait for each other's inner loops; only the trip count of the slowest lane in a wave
+// bounds the wave.
+//
+// Numerics: the model Jacobian, the gains and the forward pass run in FP32; the
+// primal trajectory is stored in FP64 and the row residuals (whose rounding, divided by
+// the penalty, sets the floor of the stationarity test) and merit sums are FP64; the
+// Riccati recursion (block assembly A^T A / mu,
+// Cholesky of S_k, gains, value update) runs in FP64 because the assembled blocks carry
+// 1/mu-scaled rank-deficient terms whose small eigenvalues FP32 rounding of the
+// assembly would erase.
+//
+// Work space (device, structure of arrays over sequence slots, so that a wave's 64 lanes
+// touch 64 consecutive words for every field): primal, multipliers, gains, step and
+// interval codes, one row per interval.  Inside a wave the rows are end-aligned so that
+// the backward sweep of sequences of different length stays in lock-step on the same row.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/comet.h"
+#include "push_model.h"
+
+namespace comet {
+
+using namespace push;
+
+constexpr int MAXSEG = 6;
+constexpr int MAXN = 512;
+constexpr int MAX_TRIALS = 16;
+constexpr int WAVE = 64;
+
+struct DevParams {
+  int al_max, gn_max, chol_retries, ls_trials, max_rejects;
+  double mu0, mu_min, rho0, rho_min, rho_max, armijo_c1, eta_star, omega_star, rc_star, eps_feas;
+};
+
+struct EvalArgs {
+  int64_t B;
+  int smax, nmax;                 // segment slots per sequence, max intervals (work-space rows)
+  int64_t S;                      // slot stride of the work space
+  const float* x0;
+  const float* goal;
+  const float* inst;
+  const int* nseg;
+  const int* modes;
+  const int* knots;
+  const float* warm;
+  float* cost;
+  float* viol;
+  uint8_t* feas;
+  float* traj;
+  int* stats;
+  double* zd;                     // [row][7][S]  (u_k, x_{k+1})
+  float* lam;                     // [row][5][S]
+  float* nu;                      // [row][5][S]
+  float* gains;                   // [row][35][S] (k, K row-major 7x4)
+  float* dz;                      // [row][7][S]
+  uint8_t* code;                  // [row][S]
+  unsigned* err;
+  DevParams prm;
+  double inv_scale[NTYPES];
+};
+
+__device__ inline int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+__device__ inline bool wave_any(bool p) { return __ballot(p) != 0; }
+
+// --------------------------------------------------------------------------------
+// Per-lane view of one sequence's work space.
+// --------------------------------------------------------------------------------
+struct Lane {
+  const EvalArgs* A;
+  int64_t slot;
+  int N, off;          // intervals, row offset (end alignment within the wave)
+  double x0[NX], goal[3], mu;
+
+  __device__ double& z(int k, int f) const { return A->zd[((int64_t)(off + k) * NW + f) * A->S + slot]; }
+  __device__ float& lam(int k, int r) const { return A->lam[((int64_t)(off + k) * NE + r) * A->S + slot]; }
+  __device__ float& nu(int k, int r) const { return A->nu[((int64_t)(off + k) * NE + r) * A->S + slot]; }
+  __device__ float& gain(int k, int f) const { return A->gains[((int64_t)(off + k) * NGAIN + f) * A->S + slot]; }
+  __device__ float& dz(int k, int f) const { return A->dz[((int64_t)(off + k) * NW + f) * A->S + slot]; }
+  __device__ int code(int k) const { return A->code[(int64_t)(off + k) * A->S + slot]; }
+
+  __device__ void load_x(int k, double* x) const {  // x_k
+    if (k == 0) {
+      for (int i = 0; i < NX; ++i) x[i] = x0[i];
+    } else {
+      for (int i = 0; i < NX; ++i) x[i] = z(k - 1, NU + i);
+    }
+  }
+  __device__ void load_w(int k, double* u, double* x1) const {
+    for (int i = 0; i < NU; ++i) u[i] = z(k, i);
+    for (int i = 0; i < NX; ++i) x1[i] = z(k, NU + i);
+  }
+};
+
+// scaled residuals of one interval; multiplier estimates; merit contribution
+struct RowEval {
+  double c[NR];       // scaled residuals
+  int en[NR];
+  float J[NR][NV];    // scaled Jacobian (nz entries only)
+};
+
+template <bool JAC>
+__device__ inline void eval_interval(const EvalArgs& A, const double* xk, const double* uk, const double* x1,
+                                     int code, double mu, RowEval& R) {
+  rows<float>(xk, uk, x1, code, mu, R.c, JAC ? R.J : nullptr, R.en);
+  const bool stick = ((code >> 2) & 3) == 0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const double is = A.inv_scale[row_type(r, stick)];
+    R.c[r] *= is;
+    if (JAC) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+        if (nz(r, i)) R.J[r][i] *= float(is);
+    }
+  }
+}
+
+// terminal rows, scaled
+__device__ inline void eval_terminal(const EvalArgs& A, const double* xN, const double* goal, double* c) {
+  c[0] = (xN[0] - goal[0]) * A.inv_scale[T_TXY];
+  c[1] = (xN[1] - goal[1]) * A.inv_scale[T_TXY];
+  c[2] = (xN[2] - goal[2]) * A.inv_scale[T_TTH];
+}
+
+// merit contribution of one interval's rows given multipliers
+__device__ inline double merit_rows(const RowEval& R, const float* lam, const float* nu, double mu) {
+  double phi = 0.0;
+#pragma unroll
+  for (int r = 0; r < NE; ++r)
+    if (R.en[r]) phi += double(lam[r]) * R.c[r] + R.c[r] * R.c[r] / (2.0 * mu);
+#pragma unroll
+  for (int r = 0; r < NE; ++r) {
+    if (!R.en[NE + r]) continue;
+    const double n = nu[r];
+    const double t = fmax(n + R.c[NE + r] / mu, 0.0);
+    phi += 0.5 * mu * (t * t - n * n);
+  }
+  return phi;
+}
+
+// --------------------------------------------------------------------------------
+// Sweeps over the intervals of the lanes selected by `on`.  All lanes iterate the same
+// end-aligned row index; lane-local interval k = row - off.
+// --------------------------------------------------------------------------------
+struct FactorOut {
+  double phi0, D, gnorm;
+  bool ok;
+};
+
+// Backward sweep: gradient, merit, Riccati factorisation and gains at the current z.
+// With FACTOR = false it only returns the gradient norm (outer stationarity test),
+// together with the scaled violation and complementarity residual.
+template <bool FACTOR>
+__device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double rho, const double* lamT,
+                               FactorOut& out, double& vs, double& rc) {
+  const EvalArgs& A = *L.A;
+  double P[NX][NX], p[NX], gx[NX];
+  double xk1[NX];
+  out.phi0 = 0.0;
+  out.D = 0.0;
+  out.gnorm = 0.0;
+  out.ok = true;
+  vs = 0.0;
+  rc = 0.0;
+  if (on) {
+    // terminal value function V_N and terminal gradient
+    double xN[NX], cT[NT];
+    L.load_x(L.N, xN);
+    eval_terminal(A, xN, L.goal, cT);
+    const double sT[NT] = {A.inv_scale[T_TXY], A.inv_scale[T_TXY], A.inv_scale[T_TTH]};
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      p[i] = 0.0;
+      gx[i] = 0.0;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) P[i][j] = 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < NT; ++r) {
+      const double y = lamT[r] + cT[r] / mu;
+      out.phi0 += lamT[r] * cT[r] + cT[r] * cT[r] / (2.0 * mu);
+      p[r] = y * sT[r];
+      gx[r] = y * sT[r];
+      P[r][r] = sT[r] * sT[r] / mu;
+      vs = fmax(vs, fabs(cT[r]));
+    }
+#pragma unroll
+    for (int i = 0; i < NX; ++i) xk1[i] = xN[i];
+  }
+  for (int t = 0; t < Nw; ++t) {
+    const int k = L.N - 1 - t;
+    if (!on || k < 0) continue;
+    double xk[NX], uk[NU], x1[NX];
+    L.load_x(k, xk);
+    L.load_w(k, uk, x1);
+    RowEval R;
+    const int code = L.code(k);
+    eval_interval<true>(A, xk, uk, x1, code, L.mu, R);
+    float lm[NE], nv[NE];
+#pragma unroll
+    for (int r = 0; r < NE; ++r) {
+      lm[r] = L.lam(k, r);
+      nv[r] = L.nu(k, r);
+    }
+    // multiplier estimates y and curvature weights w
+    double y[NR], w[NR];
+#pragma unroll
+    for (int r = 0; r < NE; ++r) {
+      y[r] = R.en[r] ? double(lm[r]) + R.c[r] / mu : 0.0;
+      w[r] = R.en[r] ? 1.0 / mu : 0.0;
+      if (R.en[r]) vs = fmax(vs, fabs(R.c[r]));
+    }
+#pragma unroll
+    for (int r = 0; r < NE; ++r) {
+      const double tt = double(nv[r]) + R.c[NE + r] / mu;
+      const bool act = R.en[NE + r] && tt > 0.0;
+      y[NE + r] = act ? tt : 0.0;
+      w[NE + r] = act ? 1.0 / mu : 0.0;
+      if (R.en[NE + r]) {
+        vs = fmax(vs, fmax(R.c[NE + r], 0.0));
+        rc = fmax(rc, fabs(fmin(-R.c[NE + r], double(nv[r]))));
+      }
+    }
+    out.phi0 += stage_cost(uk) + merit_rows(R, lm, nv, mu);
+    // gradient over v = (x_k, w_k): h = sum_r y_r a_r + cost gradient
+    double h[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) h[i] = 0.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+        if (nz(r, i)) h[i] += y[r] * double(R.J[r][i]);
+    h[VFN] += HF * uk[0];
+    h[VFT] += HF * uk[1];
+    h[VVS] += HV * uk[2];
+    // gradient of w_k = own rows + next interval's rows through x_{k+1}
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const double g = h[NX + i] + (i >= NU ? gx[i - NU] : 0.0);
+      out.gnorm = fmax(out.gnorm, fabs(g));
+    }
+#pragma unroll
+    for (int i = 0; i < NX; ++i) gx[i] = h[i];
+    if (!FACTOR || !out.ok) continue;
+
+    // ---- block assembly (FP64): G = sum_r w_r a_r a_r^T + cost Hessian, lower triangle
+    double G[NV][NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+      for (int j = 0; j < NV; ++j) G[i][j] = 0.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      double a[NV];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) a[i] = nz(r, i) ? double(R.J[r][i]) : 0.0;
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+          if (nz(r, i) && nz(r, j)) G[i][j] += w[r] * a[i] * a[j];
+    }
+    G[VFN][VFN] += HF;
+    G[VFT][VFT] += HF;
+    G[VVS][VVS] += HV;
+    // S = Q_ww + embed(P_{k+1}) + rho I ; qh = q_w + embed(p_{k+1})
+    double Sm[NW][NW], qh[NW], Qwx[NW][NX];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+#pragma unroll
+      for (int j = 0; j <= i; ++j) Sm[i][j] = G[NX + i][NX + j];
+      Sm[i][i] += rho;
+      qh[i] = h[NX + i];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) Qwx[i][j] = G[NX + i][j];
+    }
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      qh[NU + i] += p[i];
+#pragma unroll
+      for (int j = 0; j <= i; ++j) Sm[NU + i][NU + j] += P[i][j];
+    }
+    // Cholesky S = L L^T without pivoting, in place (lower triangle)
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      double d = Sm[j][j];
+#pragma unroll
+      for (int q = 0; q < j; ++q) d -= Sm[j][q] * Sm[j][q];
+      ok = ok && (d > 0.0) && isfinite(d);
+      const double lj = sqrt(fmax(d, 1e-300));
+      const double inv = 1.0 / lj;
+      Sm[j][j] = lj;
+#pragma unroll
+      for (int i = j + 1; i < NW; ++i) {
+        double s2 = Sm[i][j];
+#pragma unroll
+        for (int q = 0; q < j; ++q) s2 -= Sm[i][q] * Sm[j][q];
+        Sm[i][j] = s2 * inv;
+      }
+    }
+    if (!ok) {
+      out.ok = false;
+      continue;
+    }
+    // Y = L^-1 Qwx, yv = L^-1 qh
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const double inv = 1.0 / Sm[i][i];
+#pragma unroll
+      for (int q = 0; q < i; ++q) {
+        qh[i] -= Sm[i][q] * qh[q];
+#pragma unroll
+        for (int j = 0; j < NX; ++j) Qwx[i][j] -= Sm[i][q] * Qwx[q][j];
+      }
+      qh[i] *= inv;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) Qwx[i][j] *= inv;
+    }
+    // value function: P = Q_xx - Y^T Y, p = q_x - Y^T y ; model decrease D += -y^T y
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      double pi = h[i];
+#pragma unroll
+      for (int q = 0; q < NW; ++q) pi -= Qwx[q][i] * qh[q];
+      p[i] = pi;
+#pragma unroll
+      for (int j = 0; j <= i; ++j) {
+        double pij = G[i][j];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) pij -= Qwx[q][i] * Qwx[q][j];
+        P[i][j] = pij;
+        P[j][i] = pij;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NW; ++q) out.D -= qh[q] * qh[q];
+    // gains: k = -L^-T y, K = -L^-T Y (back substitution)
+#pragma unroll
+    for (int i = NW - 1; i >= 0; --i) {
+      const double inv = 1.0 / Sm[i][i];
+#pragma unroll
+      for (int q = i + 1; q < NW; ++q) {
+        qh[i] -= Sm[q][i] * qh[q];
+#pragma unroll
+        for (int j = 0; j < NX; ++j) Qwx[i][j] -= Sm[q][i] * Qwx[q][j];
+      }
+      qh[i] *= inv;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) Qwx[i][j] *= inv;
+    }
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      L.gain(k, i) = float(-qh[i]);
+#pragma unroll
+      for (int j = 0; j < NX; ++j) L.gain(k, NW + i * NX + j) = float(-Qwx[i][j]);
+    }
+  }
+}
+
+// Forward pass: dz from the gains (stored), merit at every trial step length.
+__device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, const double* lamT, int T,
+                              double* phi) {
+  const EvalArgs& A = *L.A;
+  float dx[NX] = {0.f, 0.f, 0.f, 0.f};
+  double xk[NX];
+#pragma unroll
+  for (int i = 0; i < MAX_TRIALS; ++i) phi[i] = 0.0;
+  if (on) L.load_x(0, xk);
+  for (int t = 0; t < Nw; ++t) {
+    const int k = t - (Nw - L.N);
+    if (!on || k < 0) continue;
+    double uk[NU], x1[NX];
+    L.load_w(k, uk, x1);
+    float dw[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      float s = L.gain(k, i);
+#pragma unroll
+      for (int j = 0; j < NX; ++j) s += L.gain(k, NW + i * NX + j) * dx[j];
+      dw[i] = s;
+      L.dz(k, i) = s;
+    }
+    float lm[NE], nv[NE];
+#pragma unroll
+    for (int r = 0; r < NE; ++r) {
+      lm[r] = L.lam(k, r);
+      nv[r] = L.nu(k, r);
+    }
+    const int code = L.code(k);
+    double alpha = 1.0;
+    for (int i = 0; i < T; ++i) {
+      double xt[NX], ut[NU], x1t[NX];
+#pragma unroll
+      for (int q = 0; q < NX; ++q) {
+        xt[q] = xk[q] + alpha * double(dx[q]);
+        x1t[q] = x1[q] + alpha * double(dw[NU + q]);
+      }
+#pragma unroll
+      for (int q = 0; q < NU; ++q) ut[q] = uk[q] + alpha * double(dw[q]);
+      RowEval R;
+      eval_interval<false>(A, xt, ut, x1t, code, L.mu, R);
+      const double contrib = stage_cost(ut) + merit_rows(R, lm, nv, mu);
+#pragma unroll
+      for (int q = 0; q < MAX_TRIALS; ++q)
+        if (q == i) phi[q] += contrib;
+      alpha *= 0.5;
+    }
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      xk[q] = x1[q];
+      dx[q] = dw[NU + q];
+    }
+  }
+  if (on) {
+    double alpha = 1.0;
+    for (int i = 0; i < T; ++i) {
+      double xt[NX], cT[NT];
+#pragma unroll
+      for (int q = 0; q < NX; ++q) xt[q] = xk[q] + alpha * double(dx[q]);
+      eval_terminal(A, xt, L.goal, cT);
+      double contrib = 0.0;
+#pragma unroll
+      for (int r = 0; r < NT; ++r) contrib += lamT[r] * cT[r] + cT[r] * cT[r] / (2.0 * mu);
+#pragma unroll
+      for (int q = 0; q < MAX_TRIALS; ++q)
+        if (q == i) phi[q] += contrib;
+      alpha *= 0.5;
+    }
+  }
+}
+
+__device__ void sweep_apply(const Lane& L, int Nw, bool on, double alpha) {
+  for (int t = 0; t < Nw; ++t) {
+    const int k = t - (Nw - L.N);
+    if (!on || k < 0) continue;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) L.z(k, i) += alpha * double(L.dz(k, i));
+  }
+}
+
+// first-order multiplier update lam += c/mu, nu = [nu + c/mu]_+
+__device__ void sweep_duals(const Lane& L, int Nw, bool on, double mu, double* lamT) {
+  const EvalArgs& A = *L.A;
+  for (int t = 0; t < Nw; ++t) {
+    const int k = t - (Nw - L.N);
+    if (!on || k < 0) continue;
+    double xk[NX], uk[NU], x1[NX];
+    L.load_x(k, xk);
+    L.load_w(k, uk, x1);
+    RowEval R;
+    eval_interval<false>(A, xk, uk, x1, L.code(k), L.mu, R);
+#pragma unroll
+    for (int r = 0; r < NE; ++r)
+      if (R.en[r]) L.lam(k, r) = float(double(L.lam(k, r)) + R.c[r] / mu);
+#pragma unroll
+    for (int r = 0; r < NE; ++r)
+      if (R.en[NE + r]) L.nu(k, r) = float(fmax(double(L.nu(k, r)) + R.c[NE + r] / mu, 0.0));
+  }
+  if (on) {
+    double xN[NX], cT[NT];
+    L.load_x(L.N, xN);
+    eval_terminal(A, xN, L.goal, cT);
+#pragma unroll
+    for (int r = 0; r < NT; ++r) lamT[r] += cT[r] / mu;
+  }
+}
+
+// physical-unit score (Eq. 4) and trajectory output
+__device__ void sweep_score(const Lane& L, int Nw, bool on, double& J, double& v) {
+  const EvalArgs& A = *L.A;
+  J = 0.0;
+  v = 0.0;
+  for (int t = 0; t < Nw; ++t) {
+    const int k = t - (Nw - L.N);
+    if (!on || k < 0) continue;
+    double xk[NX], uk[NU], x1[NX], c[NR];
+    int en[NR];
+    L.load_x(k, xk);
+    L.load_w(k, uk, x1);
+    rows<float>(xk, uk, x1, L.code(k), L.mu, c, (float(*)[NV]) nullptr, en);
+    J += stage_cost(uk);
+#pragma unroll
+    for (int r = 0; r < NE; ++r)
+      if (en[r]) v = fmax(v, fabs(c[r]));
+#pragma unroll
+    for (int r = NE; r < NR; ++r)
+      if (en[r]) v = fmax(v, fmax(c[r], 0.0));
+    if (!isfinite(J) || !isfinite(c[0]) || !isfinite(c[1]) || !isfinite(c[2]) || !isfinite(c[3])) v = INFINITY;
+    if (A.traj) {
+      float* T = A.traj + (L.slot * (int64_t)(A.nmax + 1) + k) * (NX + NU);
+#pragma unroll
+      for (int i = 0; i < NX; ++i) T[i] = float(xk[i]);
+#pragma unroll
+      for (int i = 0; i < NU; ++i) T[NX + i] = float(uk[i]);
+    }
+  }
+  if (on) {
+    double xN[NX];
+    L.load_x(L.N, xN);
+    v = fmax(v, fabs(xN[0] - L.goal[0]));
+    v = fmax(v, fabs(xN[1] - L.goal[1]));
+    v = fmax(v, fabs(xN[2] - L.goal[2]));
+    if (A.traj) {
+      float* T = A.traj + (L.slot * (int64_t)(A.nmax + 1) + L.N) * (NX + NU);
+#pragma unroll
+      for (int i = 0; i < NX; ++i) T[i] = float(xN[i]);
+#pragma unroll
+      for (int i = 0; i < NU; ++i) T[NX + i] = 0.f;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------------
+// The solver kernel: one sequence per lane, 64 lanes per block.
+// --------------------------------------------------------------------------------
+__global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
+  const int64_t b = (int64_t)blockIdx.x * WAVE + threadIdx.x;
+  const DevParams& prm = A.prm;
+  Lane L;
+  L.A = &A;
+  L.slot = b;
+  L.N = 0;
+  L.off = 0;
+  bool valid = b < A.B;
+  int K = 0;
+  if (valid) {
+    K = A.nseg[b];
+    valid = (K >= 1 && K <= A.smax);
+    int N = 0;
+    for (int j = 0; j < MAXSEG; ++j) {
+      if (!valid || j >= K) break;
+      const int m = A.modes[b * A.smax + j], n = A.knots[b * A.smax + j];
+      if (m < 0 || m >= NMODES || n < 1) valid = false;
+      N += n;
+    }
+    if (N > A.nmax) valid = false;
+    for (int i = 0; i < NX; ++i) {
+      L.x0[i] = A.x0[b * NX + i];
+      valid = valid && isfinite(L.x0[i]);
+    }
+    for (int i = 0; i < 3; ++i) {
+      L.goal[i] = A.goal[b * 3 + i];
+      valid = valid && isfinite(L.goal[i]);
+    }
+    L.mu = A.inst[b];
+    valid = valid && isfinite(L.mu);
+    L.N = valid ? N : 0;
+  }
+  const int Nw = wave_max(L.N);
+  L.off = Nw - L.N;
+  if (b < A.B && !valid) {
+    atomicAdd(A.err, 1u);
+    A.cost[b] = NAN;
+    A.viol[b] = INFINITY;
+    A.feas[b] = 0;
+    if (A.stats) {
+      A.stats[b * 4 + 0] = 0;
+      A.stats[b * 4 + 1] = 0;
+      A.stats[b * 4 + 2] = 0;
+      A.stats[b * 4 + 3] = 3;
+    }
+    if (A.traj)
+      for (int i = 0; i < (A.nmax + 1) * (NX + NU); ++i) A.traj[b * (int64_t)(A.nmax + 1) * (NX + NU) + i] = 0.f;
+  }
+  // interval codes, initial guess, zero multipliers
+  if (valid) {
+    int k = 0;
+    for (int j = 0; j < K; ++j) {
+      const int m = A.modes[b * A.smax + j], n = A.knots[b * A.smax + j];
+      const int mnext = (j + 1 < K) ? A.modes[b * A.smax + j + 1] : m;
+      for (int i = 0; i < n; ++i, ++k) {
+        const int smask = (i == n - 1 && (mnext / 3) != (m / 3)) ? 0 : 1;
+        A.code[(int64_t)(L.off + k) * A.S + b] = (uint8_t)make_code(m, smask);
+      }
+    }
+    const double fn = 0.05 * FMAX;
+    for (int k2 = 0; k2 < L.N; ++k2) {
+      const int c = L.code(k2);
+      const int slip = (c >> 2) & 3;
+      const double sg = (slip == 1) ? 1.0 : ((slip == 2) ? -1.0 : 0.0);
+      if (A.warm) {
+        const float* W = A.warm + b * (int64_t)(A.nmax + 1) * (NX + NU);
+        for (int i = 0; i < NU; ++i) L.z(k2, i) = W[k2 * (NX + NU) + NX + i];
+        for (int i = 0; i < NX; ++i) L.z(k2, NU + i) = W[(k2 + 1) * (NX + NU) + i];
+      } else {
+        const double tfrac = double(k2 + 1) / double(L.N);
+        L.z(k2, 0) = fn;
+        L.z(k2, 1) = sg * L.mu * fn;
+        L.z(k2, 2) = 0.0;
+        for (int i = 0; i < 3; ++i) L.z(k2, NU + i) = L.x0[i] + (L.goal[i] - L.x0[i]) * tfrac;
+        L.z(k2, NU + 3) = L.x0[3];
+      }
+      for (int r = 0; r < NE; ++r) {
+        L.lam(k2, r) = 0.f;
+        L.nu(k2, r) = 0.f;
+      }
+    }
+  }
+  // solver state
+  double mu = prm.mu0, eta = pow(prm.mu0, 0.1), omega = prm.mu0, rho = prm.rho0;
+  double lamT[NT] = {0.0, 0.0, 0.0};
+  int al = 0, gn_in = 0, gn_tot = 0, rejects = 0, tries = 0, cfails = 0, status = 0;
+  bool done = !valid;
+  const int T = min(max(prm.ls_trials, 1), MAX_TRIALS);
+
+  while (wave_any(!done)) {
+    const bool active = !done;
+    FactorOut fo;
+    double vs_unused, rc_unused;
+    sweep_backward<true>(L, Nw, active, mu, rho, lamT, fo, vs_unused, rc_unused);
+    bool step = false, inner_end = false, accepted = false;
+    double alpha_acc = 0.0;
+    if (active) {
+      if (fo.gnorm <= omega) {
+        inner_end = true;
+      } else if (!fo.ok) {
+        ++cfails;
+        if (tries < prm.chol_retries) {
+          rho = fmax(10.0 * rho, 1e-8);
+          ++tries;
+        } else {
+          tries = 0;
+          ++gn_in;
+          ++gn_tot;
+          rho = fmin(10.0 * rho, prm.rho_max);
+          if (++rejects >= prm.max_rejects || gn_in >= prm.gn_max) inner_end = true;
+        }
+      } else {
+        tries = 0;
+        ++gn_in;
+        ++gn_tot;
+        if (fo.D < 0.0 && isfinite(fo.phi0)) {
+          step = true;
+        } else {
+          rho = fmin(10.0 * rho, prm.rho_max);
+          if (++rejects >= prm.max_rejects || gn_in >= prm.gn_max) inner_end = true;
+        }
+      }
+    }
+    if (wave_any(step)) {
+      double phi[MAX_TRIALS];
+      sweep_forward(L, Nw, step, mu, lamT, T, phi);
+      if (step) {
+        int best = -1;
+        double alpha = 1.0, a_best = 0.0;
+        for (int i = 0; i < T; ++i) {
+          double ph = 0.0;
+#pragma unroll
+          for (int q = 0; q < MAX_TRIALS; ++q)
+            if (q == i) ph = phi[q];
+          if (best < 0 && isfinite(ph) && ph <= fo.phi0 + prm.armijo_c1 * alpha * fo.D) {
+            best = i;
+            a_best = alpha;
+          }
+          alpha *= 0.5;
+        }
+        if (best >= 0) {
+          accepted = true;
+          alpha_acc = a_best;
+          rho = fmax(rho / 3.0, prm.rho_min);
+          rejects = 0;
+        } else {
+          rho = fmin(10.0 * rho, prm.rho_max);
+          ++rejects;
+        }
+        if (rejects >= prm.max_rejects || gn_in >= prm.gn_max) inner_end = true;
+      }
+    }
+    if (wave_any(accepted)) sweep_apply(L, Nw, accepted, alpha_acc);
+    bool upd = false, fin = false;
+    if (wave_any(inner_end)) {
+      FactorOut go;
+      double vsv, rcv;
+      sweep_backward<false>(L, Nw, inner_end, mu, rho, lamT, go, vsv, rcv);
+      if (inner_end) {
+        ++al;
+        gn_in = 0;
+        rejects = 0;
+        if (!isfinite(vsv) || !isfinite(go.gnorm)) {
+          status = 2;
+          fin = true;
+        } else if (vsv <= eta) {
+          if (vsv <= prm.eta_star && go.gnorm <= prm.omega_star && rcv <= prm.rc_star) {
+            status = 1;
+            fin = true;
+          } else {
+            upd = true;
+            eta = fmax(eta * pow(mu, 0.9), prm.eta_star);
+            omega = fmax(omega * mu, prm.omega_star);
+          }
+        } else {
+          mu = fmax(0.1 * mu, prm.mu_min);
+          eta = fmax(pow(mu, 0.1), prm.eta_star);
+          omega = fmax(mu, prm.omega_star);
+        }
+        if (!fin && al >= prm.al_max) {
+          status = 0;
+          fin = true;
+          upd = false;
+        }
+      }
+    }
+    if (wave_any(upd)) sweep_duals(L, Nw, upd, mu, lamT);
+    if (wave_any(fin)) {
+      double J, v;
+      sweep_score(L, Nw, fin, J, v);
+      if (fin) {
+        if (status == 2 || !isfinite(J) || !isfinite(v)) {
+          J = NAN;
+          v = INFINITY;
+          status = 2;
+        }
+        A.cost[b] = float(J);
+        A.viol[b] = float(v);
+        A.feas[b] = (v <= prm.eps_feas) ? 1 : 0;
+        if (A.stats) {
+          A.stats[b * 4 + 0] = al;
+          A.stats[b * 4 + 1] = gn_tot;
+          A.stats[b * 4 + 2] = cfails;
+          A.stats[b * 4 + 3] = status;
+        }
+        if (A.traj) {  // zero rows beyond N
+          for (int k = L.N + 1; k <= A.nmax; ++k)
+            for (int i = 0; i < NX + NU; ++i) A.traj[(b * (int64_t)(A.nmax + 1) + k) * (NX + NU) + i] = 0.f;
+        }
+        done = true;
+      }
+    }
+  }
+}
+
+}  // namespace comet
+
+// ==================================================================================
+// Host side: context, row scales, C ABI.
+// ==================================================================================
+struct comet_ctx {
+  int task;
+  comet_solver_params prm;
+  int64_t max_batch, S;
+  int max_segments, max_intervals;
+  int device;
+  double scale[comet::push::NTYPES];
+  double* zd = nullptr;
+  float* lam = nullptr;
+  float* nu = nullptr;
+  float* gains = nullptr;
+  float* dz = nullptr;
+  uint8_t* code = nullptr;
+  unsigned* err = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+  std::string msg;
+};
+
+namespace {
+
+comet_status fail(comet_ctx* c, comet_status s, const std::string& m) {
+  if (c) c->msg = m;
+  return s;
+}
+
+// Row scales: for every row type, the median 2-norm of its physical Jacobian row over the
+// schedule-derived initial guesses of a fixed sample of orders (all 144 two-segment orders,
+// 5 + 5 intervals, start at rest at the origin, goal (0.1, 0.1, pi/4), pusher friction
+// 0.4); median of an even count = mean of the two middle values.  Evaluated in double on
+// the host with the same model code the device uses.
+void compute_scales(double* out) {
+  using namespace comet::push;
+  std::vector<double> vals[NTYPES];
+  const double x0[NX] = {0, 0, 0, 0}, goal[3] = {0.1, 0.1, M_PI / 4.0}, mu = 0.4;
+  for (int m1 = 0; m1 < NMODES; ++m1)
+    for (int m2 = 0; m2 < NMODES; ++m2) {
+      const int N = 10;
+      int code[N];
+      for (int k = 0; k < N; ++k) {
+        const int m = k < 5 ? m1 : m2;
+        const int smask = (k == 4 && (m2 / 3) != (m1 / 3)) ? 0 : 1;
+        code[k] = make_code(m, smask);
+      }
+      double xs[N + 1][NX], us[N][NU];
+      for (int i = 0; i < NX; ++i) xs[0][i] = x0[i];
+      for (int k = 0; k < N; ++k) {
+        const int slip = (code[k] >> 2) & 3;
+        const double sg = slip == 1 ? 1.0 : (slip == 2 ? -1.0 : 0.0);
+        us[k][0] = 0.05 * FMAX;
+        us[k][1] = sg * mu * us[k][0];
+        us[k][2] = 0.0;
+        const double t = double(k + 1) / N;
+        for (int i = 0; i < 3; ++i) xs[k + 1][i] = x0[i] + (goal[i] - x0[i]) * t;
+        xs[k + 1][3] = x0[3];
+      }
+      for (int k = 0; k < N; ++k) {
+        double c[NR], J[NR][NV];
+        int en[NR];
+        for (int r = 0; r < NR; ++r)
+          for (int i = 0; i < NV; ++i) J[r][i] = 0.0;
+        rows<double>(xs[k], us[k], xs[k + 1], code[k], mu, c, J, en);
+        const bool stick = ((code[k] >> 2) & 3) == 0;
+        for (int r = 0; r < NR; ++r) {
+          if (!en[r]) continue;
+          double n2 = 0.0;
+          for (int i = 0; i < NV; ++i) n2 += J[r][i] * J[r][i];
+          vals[row_type(r, stick)].push_back(std::sqrt(n2));
+        }
+      }
+      for (int r = 0; r < 2; ++r) vals[T_TXY].push_back(1.0);
+      vals[T_TTH].push_back(1.0);
+    }
+  for (int t = 0; t < NTYPES; ++t) {
+    std::vector<double>& v = vals[t];
+    std::sort(v.begin(), v.end());
+    const size_t n = v.size();
+    out[t] = (n == 0) ? 1.0 : ((n % 2) ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void comet_default_params(comet_solver_params* p) {
+  if (!p) return;
+  p->al_max = 20;
+  p->gn_max = 10;
+  p->ref_al_max = 40;
+  p->ref_gn_max = 25;
+  p->chol_retries = 6;
+  p->ls_trials = 8;
+  p->max_rejects = 4;
+  p->reserved = 0;
+  p->mu0 = 1e-2;
+  p->mu_min = 1e-4;
+  p->rho0 = 1e-4;
+  p->rho_min = 1e-8;
+  p->rho_max = 1e8;
+  p->armijo_c1 = 1e-4;
+  p->eta_star = 1e-6;
+  p->omega_star = 1e-4;
+  p->rc_star = 1e-6;
+  p->eps_feas = 1e-5;
+}
+
+comet_status comet_create(comet_task task, const comet_solver_params* params, int64_t max_batch,
+                          int32_t max_segments, int32_t max_intervals, comet_ctx** out) {
+  if (!out) return COMET_EINVAL;
+  *out = nullptr;
+  if (task != COMET_TASK_PUSH || max_batch < 1 || max_segments < 1 || max_segments > comet::MAXSEG ||
+      max_intervals < 1 || max_intervals > comet::MAXN)
+    return COMET_EINVAL;
+  comet_ctx* c = new comet_ctx();
+  c->task = task;
+  if (params) c->prm = *params;
+  else comet_default_params(&c->prm);
+  if (c->prm.ls_trials < 1 || c->prm.ls_trials > comet::MAX_TRIALS || c->prm.al_max < 1 || c->prm.gn_max < 1 ||
+      !(c->prm.mu0 > 0) || !(c->prm.mu_min > 0)) {
+    delete c;
+    return COMET_EINVAL;
+  }
+  c->max_batch = max_batch;
+  c->S = (max_batch + 63) / 64 * 64;
+  c->max_segments = max_segments;
+  c->max_intervals = max_intervals;
+  hipGetDevice(&c->device);
+  compute_scales(c->scale);
+  const int64_t R = max_intervals, S = c->S;
+  using namespace comet::push;
+  bool okm = hipMalloc(&c->zd, sizeof(double) * R * NW * S) == hipSuccess &&
+             hipMalloc(&c->lam, sizeof(float) * R * NE * S) == hipSuccess &&
+             hipMalloc(&c->nu, sizeof(float) * R * NE * S) == hipSuccess &&
+             hipMalloc(&c->gains, sizeof(float) * R * NGAIN * S) == hipSuccess &&
+             hipMalloc(&c->dz, sizeof(float) * R * NW * S) == hipSuccess &&
+             hipMalloc(&c->code, sizeof(uint8_t) * R * S) == hipSuccess &&
+             hipMalloc(&c->err, sizeof(unsigned)) == hipSuccess;
+  if (!okm) {
+    (void)hipGetLastError();
+    comet_destroy(c);
+    return COMET_ENOMEM;
+  }
+  if (hipMemset(c->err, 0, sizeof(unsigned)) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
+      hipEventCreate(&c->ev1) != hipSuccess) {
+    comet_destroy(c);
+    return COMET_EHIP;
+  }
+  *out = c;
+  return COMET_OK;
+}
+
+void comet_destroy(comet_ctx* c) {
+  if (!c) return;
+  if (c->zd) (void)hipFree(c->zd);
+  if (c->lam) (void)hipFree(c->lam);
+  if (c->nu) (void)hipFree(c->nu);
+  if (c->gains) (void)hipFree(c->gains);
+  if (c->dz) (void)hipFree(c->dz);
+  if (c->code) (void)hipFree(c->code);
+  if (c->err) (void)hipFree(c->err);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+}
+
+const char* comet_last_error(const comet_ctx* c) { return c ? c->msg.c_str() : "null context"; }
+
+comet_status comet_dims(const comet_ctx* c, int32_t* nx, int32_t* nu, int32_t* np, int32_t* nm, int32_t* ms,
+                        int32_t* mi, int64_t* mb) {
+  if (!c) return COMET_EINVAL;
+  if (nx) *nx = comet::push::NX;
+  if (nu) *nu = comet::push::NU;
+  if (np) *np = 1;
+  if (nm) *nm = comet::push::NMODES;
+  if (ms) *ms = c->max_segments;
+  if (mi) *mi = c->max_intervals;
+  if (mb) *mb = c->max_batch;
+  return COMET_OK;
+}
+
+comet_status comet_row_scales(const comet_ctx* c, double* out, int32_t n) {
+  if (!c || !out || n < comet::push::NTYPES) return COMET_EINVAL;
+  for (int t = 0; t < comet::push::NTYPES; ++t) out[t] = c->scale[t];
+  return COMET_OK;
+}
+
+comet_status comet_check(comet_ctx* c, void* stream) {
+  if (!c) return COMET_EINVAL;
+  unsigned h = 0;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return fail(c, COMET_EHIP, "stream synchronize failed");
+  if (hipMemcpy(&h, c->err, sizeof(unsigned), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemset(c->err, 0, sizeof(unsigned)) != hipSuccess)
+    return fail(c, COMET_EHIP, "reading the device error counter failed");
+  if (h) return fail(c, COMET_EINVAL, std::to_string(h) + " sequence(s) had invalid device data");
+  return COMET_OK;
+}
+
+comet_status comet_evaluate(comet_ctx* c, void* stream, int64_t B, const float* x0, const float* goal,
+                            const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
+                            const float* warm, int32_t refine, float* cost, float* viol, uint8_t* feasible,
+                            float* traj, int32_t* stats) {
+  if (!c) return COMET_EINVAL;
+  if (B == 0) return COMET_OK;
+  if (B < 0 || B > c->max_batch) return fail(c, COMET_EINVAL, "batch size outside [0, max_batch]");
+  if (!x0 || !goal || !inst || !nseg || !modes || !knots || !cost || !viol || !feasible)
+    return fail(c, COMET_EINVAL, "null input or output pointer");
+  if (refine != 0 && refine != 1) return fail(c, COMET_EINVAL, "refine must be 0 or 1");
+  hipStream_t s = (hipStream_t)stream;
+  comet::EvalArgs A;
+  std::memset(&A, 0, sizeof A);
+  A.B = B;
+  A.smax = c->max_segments;
+  A.nmax = c->max_intervals;
+  A.S = c->S;
+  A.x0 = x0; A.goal = goal; A.inst = inst; A.nseg = nseg; A.modes = modes; A.knots = knots; A.warm = warm;
+  A.cost = cost; A.viol = viol; A.feas = feasible; A.traj = traj; A.stats = stats;
+  A.zd = c->zd; A.lam = c->lam; A.nu = c->nu; A.gains = c->gains; A.dz = c->dz; A.code = c->code; A.err = c->err;
+  const comet_solver_params& p = c->prm;
+  A.prm.al_max = refine ? p.ref_al_max : p.al_max;
+  A.prm.gn_max = refine ? p.ref_gn_max : p.gn_max;
+  A.prm.chol_retries = p.chol_retries;
+  A.prm.ls_trials = p.ls_trials;
+  A.prm.max_rejects = p.max_rejects;
+  A.prm.mu0 = p.mu0; A.prm.mu_min = p.mu_min; A.prm.rho0 = p.rho0; A.prm.rho_min = p.rho_min;
+  A.prm.rho_max = p.rho_max; A.prm.armijo_c1 = p.armijo_c1; A.prm.eta_star = p.eta_star;
+  A.prm.omega_star = p.omega_star; A.prm.rc_star = p.rc_star; A.prm.eps_feas = p.eps_feas;
+  for (int t = 0; t < comet::push::NTYPES; ++t) A.inv_scale[t] = 1.0 / c->scale[t];
+  const unsigned grid = (unsigned)((B + comet::WAVE - 1) / comet::WAVE);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(s, &cap);
+  const bool timed = (cap == hipStreamCaptureStatusNone);
+  if (timed) (void)hipEventRecord(c->ev0, s);
+  hipLaunchKernelGGL(comet::k_push_solve, dim3(grid), dim3(comet::WAVE), 0, s, A);
+  if (timed) (void)hipEventRecord(c->ev1, s);
+  c->timed = timed;
+  if (hipGetLastError() != hipSuccess) return fail(c, COMET_EHIP, "kernel launch failed");
+  return COMET_OK;
+}
+
+comet_status comet_last_kernel_ms(comet_ctx* c, float* ms) {
+  if (!c || !ms) return COMET_EINVAL;
+  if (!c->timed) return fail(c, COMET_ESTATE, "last evaluate was captured, not timed");
+  if (hipEventElapsedTime(ms, c->ev0, c->ev1) != hipSuccess) return fail(c, COMET_EHIP, "event query failed");
+  return COMET_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+"""ctypes binding of the C ABI in ``include/comet.h`` (argument marshalling only).
+
+Every step of the evaluator runs in the HIP library ``libcomet.so``; this module only
+turns torch tensors into device pointers and the caller's stream into a HIP stream
+handle.  It raises if the library is missing or the GPU is absent: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, fields
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcomet.so")
+
+COMET_OK, COMET_EINVAL, COMET_EHIP, COMET_ENOMEM, COMET_ESTATE = 0, -1, -2, -3, -4
+TASK_PUSH = 0
+
+
+class SolverParamsC(C.Structure):
+    _fields_ = [("al_max", C.c_int32), ("gn_max", C.c_int32), ("ref_al_max", C.c_int32), ("ref_gn_max", C.c_int32),
+                ("chol_retries", C.c_int32), ("ls_trials", C.c_int32), ("max_rejects", C.c_int32),
+                ("reserved", C.c_int32), ("mu0", C.c_double), ("mu_min", C.c_double), ("rho0", C.c_double),
+                ("rho_min", C.c_double), ("rho_max", C.c_double), ("armijo_c1", C.c_double),
+                ("eta_star", C.c_double), ("omega_star", C.c_double), ("rc_star", C.c_double),
+                ("eps_feas", C.c_double)]
+
+
+class CometError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libcomet.so (built by ``__graft_entry__.build()``); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CometError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.comet_default_params.argtypes = [C.POINTER(SolverParamsC)]
+        L.comet_default_params.restype = None
+        L.comet_create.argtypes = [C.c_int, C.POINTER(SolverParamsC), C.c_int64, C.c_int32, C.c_int32,
+                                   C.POINTER(P)]
+        L.comet_create.restype = C.c_int
+        L.comet_destroy.argtypes = [P]
+        L.comet_destroy.restype = None
+        L.comet_last_error.argtypes = [P]
+        L.comet_last_error.restype = C.c_char_p
+        L.comet_dims.argtypes = [P] + [C.POINTER(C.c_int32)] * 6 + [C.POINTER(C.c_int64)]
+        L.comet_dims.restype = C.c_int
+        L.comet_row_scales.argtypes = [P, P, C.c_int32]
+        L.comet_row_scales.restype = C.c_int
+        L.comet_check.argtypes = [P, P]
+        L.comet_check.restype = C.c_int
+        L.comet_evaluate.argtypes = [P, P, C.c_int64] + [P] * 7 + [C.c_int32] + [P] * 5
+        L.comet_evaluate.restype = C.c_int
+        L.comet_last_kernel_ms.argtypes = [P, C.POINTER(C.c_float)]
+        L.comet_last_kernel_ms.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+@dataclass
+class SolverParams:
+    al_max: int = 20
+    gn_max: int = 10
+    ref_al_max: int = 40
+    ref_gn_max: int = 25
+    chol_retries: int = 6
+    ls_trials: int = 8
+    max_rejects: int = 4
+    reserved: int = 0
+    mu0: float = 1e-2
+    mu_min: float = 1e-4
+    rho0: float = 1e-4
+    rho_min: float = 1e-8
+    rho_max: float = 1e8
+    armijo_c1: float = 1e-4
+    eta_star: float = 1e-6
+    omega_star: float = 1e-4
+    rc_star: float = 1e-6
+    eps_feas: float = 1e-5
+
+    def c(self) -> SolverParamsC:
+        return SolverParamsC(*[getattr(self, f.name) for f in fields(self)])
+
+    @staticmethod
+    def library_defaults() -> "SolverParams":
+        p = SolverParamsC()
+        lib().comet_default_params(C.byref(p))
+        return SolverParams(*[getattr(p, f) for f, _ in SolverParamsC._fields_])
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise CometError("expected a contiguous tensor on the GPU")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def check(rc: int, ctx=None):
+    if rc != COMET_OK:
+        msg = lib().comet_last_error(ctx).decode() if ctx else ""
+        raise CometError(f"comet call failed with status {rc}: {msg}")
+
+
+class Context:
+    """One evaluator context (work space for max_batch sequences) on the current device."""
+
+    def __init__(self, max_batch: int, max_segments: int = 6, max_intervals: int = 24,
+                 params: SolverParams | None = None, task: int = TASK_PUSH):
+        self._h = C.c_void_p()
+        self.params = params or SolverParams()
+        p = self.params.c()
+        rc = lib().comet_create(task, C.byref(p), int(max_batch), int(max_segments), int(max_intervals),
+                                C.byref(self._h))
+        if rc != COMET_OK:
+            raise CometError(f"comet_create failed with status {rc}")
+        self.max_batch, self.max_segments, self.max_intervals = int(max_batch), int(max_segments), int(max_intervals)
+
+    def close(self):
+        if self._h:
+            lib().comet_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dims(self):
+        v = [C.c_int32() for _ in range(6)]
+        mb = C.c_int64()
+        check(lib().comet_dims(self._h, *[C.byref(x) for x in v], C.byref(mb)), self._h)
+        return dict(nx=v[0].value, nu=v[1].value, n_inst=v[2].value, n_modes=v[3].value,
+                    max_segments=v[4].value, max_intervals=v[5].value, max_batch=mb.value)
+
+    def row_scales(self):
+        import numpy as np
+        out = np.zeros(16)
+        check(lib().comet_row_scales(self._h, out.ctypes.data_as(C.c_void_p), 16), self._h)
+        return out[:12]
+
+    def check(self, stream=None):
+        check(lib().comet_check(self._h, _stream(stream)), self._h)
+
+    def kernel_ms(self) -> float:
+        ms = C.c_float()
+        check(lib().comet_last_kernel_ms(self._h, C.byref(ms)), self._h)
+        return ms.value
+
+    def evaluate(self, x0, goal, inst, nseg, modes, knots, warm=None, refine=0, cost=None, viol=None,
+                 feasible=None, traj=None, stats=None, want_traj=True, want_stats=True, stream=None):
+        """Device tensors in, device tensors out (allocated here when not given)."""
+        import torch
+        B = int(nseg.shape[0])
+        dev = nseg.device
+        if cost is None:
+            cost = torch.empty(B, dtype=torch.float32, device=dev)
+        if viol is None:
+            viol = torch.empty(B, dtype=torch.float32, device=dev)
+        if feasible is None:
+            feasible = torch.empty(B, dtype=torch.uint8, device=dev)
+        if traj is None and want_traj:
+            traj = torch.empty((B, self.max_intervals + 1, 7), dtype=torch.float32, device=dev)
+        if stats is None and want_stats:
+            stats = torch.empty((B, 4), dtype=torch.int32, device=dev)
+        rc = lib().comet_evaluate(self._h, _stream(stream), B, _ptr(x0), _ptr(goal), _ptr(inst), _ptr(nseg),
+                                  _ptr(modes), _ptr(knots), _ptr(warm), int(refine), _ptr(cost), _ptr(viol),
+                                  _ptr(feasible), _ptr(traj), _ptr(stats))
+        check(rc, self._h)
+        return dict(cost=cost, viol=viol, feasible=feasible, traj=traj, stats=stats)
+
+
+def to_device(batch: dict, device="cuda"):
+    """Seeded host arrays (see instances.py) -> device tensors in the ABI dtypes."""
+    import torch
+    f32 = lambda a: torch.as_tensor(a, dtype=torch.float32).contiguous().to(device)
+    i32 = lambda a: torch.as_tensor(a, dtype=torch.int32).contiguous().to(device)
+    return dict(x0=f32(batch["x0"]), goal=f32(batch["goal"]), inst=f32(batch["inst"]), nseg=i32(batch["nseg"]),
+                modes=i32(batch["modes"]), knots=i32(batch["knots"]))

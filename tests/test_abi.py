@@ -1,0 +1,47 @@
+"""CPU checks of the C ABI: the library loads and exports every declared symbol, and the
+host-only defaults agree with the binding and the oracle's parameters."""
+import ctypes as C
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"\b(comet_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2609_21803_amd import native
+    L = C.CDLL(native.LIB_PATH)
+    names = declared_functions()
+    assert "comet_evaluate" in names and "comet_create" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_default_params_agree_with_binding_and_oracle():
+    import oracle
+    from paper_2609_21803_amd import native
+    lib_defaults = native.SolverParams.library_defaults()
+    assert lib_defaults == native.SolverParams()
+    o = oracle.Params()
+    for f in ("al_max", "gn_max", "chol_retries", "ls_trials", "max_rejects", "mu0", "mu_min", "rho0", "rho_min",
+              "rho_max", "armijo_c1", "eta_star", "omega_star", "rc_star", "eps_feas"):
+        assert getattr(o, f) == getattr(lib_defaults, f), f
+    assert (lib_defaults.ref_al_max, lib_defaults.ref_gn_max) == (oracle.REFINE["al_max"], oracle.REFINE["gn_max"])
+
+
+def test_product_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2609_21803_amd")
+    for dp, _, fs in os.walk(pkg):
+        for f in fs:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dp, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src and "comet_oracle" not in src, f
