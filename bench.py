@@ -31,6 +31,31 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak
 HBM_PEAK_GBS = 8000.0
 
 
+KERNEL_SOURCES = ["paper_2609_21803_amd/csrc/evaluator.hip", "paper_2609_21803_amd/csrc/push_model.h",
+                  "paper_2609_21803_amd/csrc/dmath.h"]
+PROFILE = os.path.join(ROOT, "profiles", "k_push_solve_push_plain_110592.txt")
+
+
+def profiled_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
+    kernel sources changed after those counters were taken."""
+    import hashlib
+    if not os.path.exists(PROFILE):
+        return None
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read() for s in KERNEL_SOURCES)).hexdigest()
+    fields = {}
+    for line in open(PROFILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    if fields.get("source_sha256") != h:
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(batch, seconds_target=15.0):
     """Oracle (FP64, plain C, one sequence per thread over all host threads) on a
     strided sample of the workload; returns solves/s."""
@@ -63,6 +88,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the evaluator runs on a single MI355X "
@@ -103,6 +130,12 @@ def main():
         ctx.evaluate(**d, **out)
         torch.cuda.synchronize()
         kern_ms.append(ctx.kernel_ms())
+    if args.copy_probe:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
     stats = out["stats"].cpu().numpy()
     feas = out["feasible"].cpu().numpy()
     gn_units = float((stats[:, 1].astype(np.float64) * N).sum())
@@ -132,7 +165,7 @@ def main():
         "mean_gn_iterations": float(stats[:, 1].mean()),
         "mean_al_iterations": float(stats[:, 0].mean()),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": profiled_traffic(),
                      "kernel": "k_push_solve", "kernel_ms": kms, "flop_per_launch": flops},
         "wall_s_timed": wall,
     }

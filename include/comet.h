@@ -117,6 +117,33 @@ comet_status comet_evaluate(comet_ctx* ctx, void* stream, int64_t B, const float
                             const float* warm, int32_t refine, float* cost, float* viol, uint8_t* feasible,
                             float* traj, int32_t* stats);
 
+/* Launch schedule of the solver kernel.  The kernel is persistent: each lane solves one
+ * order at a time and takes the next one from a device work queue when its solve ends
+ * (Sec. III-C: a reusable pool of slots with independent stopping).
+ *   waves_per_cu    resident 64-lane waves launched per compute unit; 0 = the occupancy
+ *                   limit of the kernel (never more than one wave per 64 sequences)
+ *   sort_by_length  1 = the queue hands out orders by decreasing interval count, so the
+ *                   lanes of a wave sweep similar lengths (ragged batches)
+ * Results do not depend on the schedule (each order's arithmetic is the same in every lane). */
+typedef struct {
+  int32_t waves_per_cu, sort_by_length;
+} comet_schedule;
+
+comet_status comet_set_schedule(comet_ctx* ctx, const comet_schedule* sched);
+/* Current schedule, the kernel's occupancy limit (waves per CU) and the CU count. */
+comet_status comet_get_schedule(const comet_ctx* ctx, comet_schedule* sched, int32_t* occupancy_waves_per_cu,
+                                int32_t* n_cu);
+
+/* Autotuner: run comet_evaluate on the given batch (outputs written as by comet_evaluate,
+ * warm = NULL, refine = 0) once per candidate schedule -- waves_per_cu in {1, 2, 4} x the
+ * occupancy limit, sort_by_length in {0, 1} -- time each solver launch with HIP events,
+ * keep the fastest in the context and return it (and its time in ms).  Synchronises
+ * `stream`; not allowed under stream capture (COMET_ESTATE). */
+comet_status comet_autotune(comet_ctx* ctx, void* stream, int64_t B, const float* x0, const float* goal,
+                            const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
+                            float* cost, float* viol, uint8_t* feasible, float* traj, int32_t* stats,
+                            comet_schedule* best, float* best_ms);
+
 /* Device time (milliseconds) of the last comet_evaluate on this context, measured with
  * HIP events around its solver kernel on the caller's stream; valid after that stream
  * has been synchronised.  Used for roofline accounting. */

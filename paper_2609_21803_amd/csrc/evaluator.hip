@@ -4,9 +4,12 @@
 // Gauss-Newton solve (Sec. III-C) as a flat state machine: each trip of the wave loop is
 // one Gauss-Newton iteration (backward Riccati sweep, forward pass with all trial step
 // lengths, step application) for every lane still inside an inner loop, followed by the
-// outer update of the lanes whose inner loop ended.  Lanes of a wave therefore never
-// wait for each other's inner loops; only the trip count of the slowest lane in a wave
-// bounds the wave.
+// outer update of the lanes whose inner loop ended.  Lanes of a wave never wait for each
+// other's inner loops.  The grid is persistent: a lane whose solve ends takes the next
+// order from a device work queue (the device form of the paper's reusable pool of slots
+// with independent stopping, Sec. III-C), so heterogeneous solve times do not idle the
+// wave until the queue is drained.  The queue can be ordered by interval count so that
+// the lanes of a wave sweep similar lengths.
 //
 // Numerics: the model Jacobian, the gains and the forward pass run in FP32; the
 // primal trajectory is stored in FP64 and the row residuals (whose rounding, divided by
@@ -68,6 +71,8 @@ struct EvalArgs {
   float* gains;                   // [row][35][S] (k, K row-major 7x4)
   float* dz;                      // [row][7][S]
   uint8_t* code;                  // [row][S]
+  const int* order;               // queue order of the sequences (null = identity)
+  unsigned long long* qhead;      // work-queue head
   unsigned* err;
   DevParams prm;
   double inv_scale[NTYPES];
@@ -86,8 +91,9 @@ __device__ inline bool wave_any(bool p) { return __ballot(p) != 0; }
 // --------------------------------------------------------------------------------
 struct Lane {
   const EvalArgs* A;
-  int64_t slot;
-  int N, off;          // intervals, row offset (end alignment within the wave)
+  int64_t slot;        // work-space slot (one per resident lane)
+  int64_t seq;         // sequence being solved, -1 if none
+  int N, off;          // intervals, row offset (rows end-aligned to the work-space height)
   double x0[NX], goal[3], mu;
 
   __device__ double& z(int k, int f) const { return A->zd[((int64_t)(off + k) * NW + f) * A->S + slot]; }
@@ -142,17 +148,18 @@ __device__ inline void eval_terminal(const EvalArgs& A, const double* xN, const 
 }
 
 // merit contribution of one interval's rows given multipliers
-__device__ inline double merit_rows(const RowEval& R, const float* lam, const float* nu, double mu) {
+__device__ inline double merit_rows(const RowEval& R, const float* lam, const float* nu, double mu, double imu) {
   double phi = 0.0;
+  const double hi = 0.5 * imu, hm = 0.5 * mu;
 #pragma unroll
   for (int r = 0; r < NE; ++r)
-    if (R.en[r]) phi += double(lam[r]) * R.c[r] + R.c[r] * R.c[r] / (2.0 * mu);
+    if (R.en[r]) phi += double(lam[r]) * R.c[r] + R.c[r] * R.c[r] * hi;
 #pragma unroll
   for (int r = 0; r < NE; ++r) {
     if (!R.en[NE + r]) continue;
     const double n = nu[r];
-    const double t = fmax(n + R.c[NE + r] / mu, 0.0);
-    phi += 0.5 * mu * (t * t - n * n);
+    const double t = fmax(n + R.c[NE + r] * imu, 0.0);
+    phi += hm * (t * t - n * n);
   }
   return phi;
 }
@@ -170,7 +177,7 @@ struct FactorOut {
 // With FACTOR = false it only returns the gradient norm (outer stationarity test),
 // together with the scaled violation and complementarity residual.
 template <bool FACTOR>
-__device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double rho, const double* lamT,
+__device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double imu, double rho, const double* lamT,
                                FactorOut& out, double& vs, double& rc) {
   const EvalArgs& A = *L.A;
   double P[NX][NX], p[NX], gx[NX];
@@ -196,11 +203,11 @@ __device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double
     }
 #pragma unroll
     for (int r = 0; r < NT; ++r) {
-      const double y = lamT[r] + cT[r] / mu;
-      out.phi0 += lamT[r] * cT[r] + cT[r] * cT[r] / (2.0 * mu);
+      const double y = lamT[r] + cT[r] * imu;
+      out.phi0 += lamT[r] * cT[r] + cT[r] * cT[r] * (0.5 * imu);
       p[r] = y * sT[r];
       gx[r] = y * sT[r];
-      P[r][r] = sT[r] * sT[r] / mu;
+      P[r][r] = sT[r] * sT[r] * imu;
       vs = fmax(vs, fabs(cT[r]));
     }
 #pragma unroll
@@ -225,22 +232,22 @@ __device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double
     double y[NR], w[NR];
 #pragma unroll
     for (int r = 0; r < NE; ++r) {
-      y[r] = R.en[r] ? double(lm[r]) + R.c[r] / mu : 0.0;
-      w[r] = R.en[r] ? 1.0 / mu : 0.0;
+      y[r] = R.en[r] ? double(lm[r]) + R.c[r] * imu : 0.0;
+      w[r] = R.en[r] ? imu : 0.0;
       if (R.en[r]) vs = fmax(vs, fabs(R.c[r]));
     }
 #pragma unroll
     for (int r = 0; r < NE; ++r) {
-      const double tt = double(nv[r]) + R.c[NE + r] / mu;
+      const double tt = double(nv[r]) + R.c[NE + r] * imu;
       const bool act = R.en[NE + r] && tt > 0.0;
       y[NE + r] = act ? tt : 0.0;
-      w[NE + r] = act ? 1.0 / mu : 0.0;
+      w[NE + r] = act ? imu : 0.0;
       if (R.en[NE + r]) {
         vs = fmax(vs, fmax(R.c[NE + r], 0.0));
         rc = fmax(rc, fabs(fmin(-R.c[NE + r], double(nv[r]))));
       }
     }
-    out.phi0 += stage_cost(uk) + merit_rows(R, lm, nv, mu);
+    out.phi0 += stage_cost(uk) + merit_rows(R, lm, nv, mu, imu);
     // gradient over v = (x_k, w_k): h = sum_r y_r a_r + cost gradient
     double h[NV];
 #pragma unroll
@@ -302,6 +309,7 @@ __device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double
     }
     // Cholesky S = L L^T without pivoting, in place (lower triangle)
     bool ok = true;
+    double ipiv[NW];
 #pragma unroll
     for (int j = 0; j < NW; ++j) {
       double d = Sm[j][j];
@@ -310,6 +318,7 @@ __device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double
       ok = ok && (d > 0.0) && isfinite(d);
       const double lj = sqrt(fmax(d, 1e-300));
       const double inv = 1.0 / lj;
+      ipiv[j] = inv;
       Sm[j][j] = lj;
 #pragma unroll
       for (int i = j + 1; i < NW; ++i) {
@@ -326,7 +335,7 @@ __device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double
     // Y = L^-1 Qwx, yv = L^-1 qh
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
-      const double inv = 1.0 / Sm[i][i];
+      const double inv = ipiv[i];
 #pragma unroll
       for (int q = 0; q < i; ++q) {
         qh[i] -= Sm[i][q] * qh[q];
@@ -358,7 +367,7 @@ __device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double
     // gains: k = -L^-T y, K = -L^-T Y (back substitution)
 #pragma unroll
     for (int i = NW - 1; i >= 0; --i) {
-      const double inv = 1.0 / Sm[i][i];
+      const double inv = ipiv[i];
 #pragma unroll
       for (int q = i + 1; q < NW; ++q) {
         qh[i] -= Sm[q][i] * qh[q];
@@ -379,7 +388,7 @@ __device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double
 }
 
 // Forward pass: dz from the gains (stored), merit at every trial step length.
-__device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, const double* lamT, int T,
+__device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, double imu, const double* lamT, int T,
                               double* phi) {
   const EvalArgs& A = *L.A;
   float dx[NX] = {0.f, 0.f, 0.f, 0.f};
@@ -420,7 +429,7 @@ __device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, const d
       for (int q = 0; q < NU; ++q) ut[q] = uk[q] + alpha * double(dw[q]);
       RowEval R;
       eval_interval<false>(A, xt, ut, x1t, code, L.mu, R);
-      const double contrib = stage_cost(ut) + merit_rows(R, lm, nv, mu);
+      const double contrib = stage_cost(ut) + merit_rows(R, lm, nv, mu, imu);
 #pragma unroll
       for (int q = 0; q < MAX_TRIALS; ++q)
         if (q == i) phi[q] += contrib;
@@ -441,7 +450,7 @@ __device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, const d
       eval_terminal(A, xt, L.goal, cT);
       double contrib = 0.0;
 #pragma unroll
-      for (int r = 0; r < NT; ++r) contrib += lamT[r] * cT[r] + cT[r] * cT[r] / (2.0 * mu);
+      for (int r = 0; r < NT; ++r) contrib += lamT[r] * cT[r] + cT[r] * cT[r] * (0.5 * imu);
 #pragma unroll
       for (int q = 0; q < MAX_TRIALS; ++q)
         if (q == i) phi[q] += contrib;
@@ -460,7 +469,7 @@ __device__ void sweep_apply(const Lane& L, int Nw, bool on, double alpha) {
 }
 
 // first-order multiplier update lam += c/mu, nu = [nu + c/mu]_+
-__device__ void sweep_duals(const Lane& L, int Nw, bool on, double mu, double* lamT) {
+__device__ void sweep_duals(const Lane& L, int Nw, bool on, double imu, double* lamT) {
   const EvalArgs& A = *L.A;
   for (int t = 0; t < Nw; ++t) {
     const int k = t - (Nw - L.N);
@@ -472,17 +481,17 @@ __device__ void sweep_duals(const Lane& L, int Nw, bool on, double mu, double* l
     eval_interval<false>(A, xk, uk, x1, L.code(k), L.mu, R);
 #pragma unroll
     for (int r = 0; r < NE; ++r)
-      if (R.en[r]) L.lam(k, r) = float(double(L.lam(k, r)) + R.c[r] / mu);
+      if (R.en[r]) L.lam(k, r) = float(double(L.lam(k, r)) + R.c[r] * imu);
 #pragma unroll
     for (int r = 0; r < NE; ++r)
-      if (R.en[NE + r]) L.nu(k, r) = float(fmax(double(L.nu(k, r)) + R.c[NE + r] / mu, 0.0));
+      if (R.en[NE + r]) L.nu(k, r) = float(fmax(double(L.nu(k, r)) + R.c[NE + r] * imu, 0.0));
   }
   if (on) {
     double xN[NX], cT[NT];
     L.load_x(L.N, xN);
     eval_terminal(A, xN, L.goal, cT);
 #pragma unroll
-    for (int r = 0; r < NT; ++r) lamT[r] += cT[r] / mu;
+    for (int r = 0; r < NT; ++r) lamT[r] += cT[r] * imu;
   }
 }
 
@@ -508,7 +517,7 @@ __device__ void sweep_score(const Lane& L, int Nw, bool on, double& J, double& v
       if (en[r]) v = fmax(v, fmax(c[r], 0.0));
     if (!isfinite(J) || !isfinite(c[0]) || !isfinite(c[1]) || !isfinite(c[2]) || !isfinite(c[3])) v = INFINITY;
     if (A.traj) {
-      float* T = A.traj + (L.slot * (int64_t)(A.nmax + 1) + k) * (NX + NU);
+      float* T = A.traj + (L.seq * (int64_t)(A.nmax + 1) + k) * (NX + NU);
 #pragma unroll
       for (int i = 0; i < NX; ++i) T[i] = float(xk[i]);
 #pragma unroll
@@ -522,7 +531,7 @@ __device__ void sweep_score(const Lane& L, int Nw, bool on, double& J, double& v
     v = fmax(v, fabs(xN[1] - L.goal[1]));
     v = fmax(v, fabs(xN[2] - L.goal[2]));
     if (A.traj) {
-      float* T = A.traj + (L.slot * (int64_t)(A.nmax + 1) + L.N) * (NX + NU);
+      float* T = A.traj + (L.seq * (int64_t)(A.nmax + 1) + L.N) * (NX + NU);
 #pragma unroll
       for (int i = 0; i < NX; ++i) T[i] = float(xN[i]);
 #pragma unroll
@@ -532,44 +541,32 @@ __device__ void sweep_score(const Lane& L, int Nw, bool on, double& J, double& v
 }
 
 // --------------------------------------------------------------------------------
-// The solver kernel: one sequence per lane, 64 lanes per block.
+// Sequence intake: validate, write interval codes, initial guess and zero multipliers
+// into the lane's rows.  Invalid sequences are scored infeasible right away.
 // --------------------------------------------------------------------------------
-__global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
-  const int64_t b = (int64_t)blockIdx.x * WAVE + threadIdx.x;
-  const DevParams& prm = A.prm;
-  Lane L;
-  L.A = &A;
-  L.slot = b;
-  L.N = 0;
-  L.off = 0;
-  bool valid = b < A.B;
-  int K = 0;
-  if (valid) {
-    K = A.nseg[b];
-    valid = (K >= 1 && K <= A.smax);
-    int N = 0;
-    for (int j = 0; j < MAXSEG; ++j) {
-      if (!valid || j >= K) break;
-      const int m = A.modes[b * A.smax + j], n = A.knots[b * A.smax + j];
-      if (m < 0 || m >= NMODES || n < 1) valid = false;
-      N += n;
-    }
-    if (N > A.nmax) valid = false;
-    for (int i = 0; i < NX; ++i) {
-      L.x0[i] = A.x0[b * NX + i];
-      valid = valid && isfinite(L.x0[i]);
-    }
-    for (int i = 0; i < 3; ++i) {
-      L.goal[i] = A.goal[b * 3 + i];
-      valid = valid && isfinite(L.goal[i]);
-    }
-    L.mu = A.inst[b];
-    valid = valid && isfinite(L.mu);
-    L.N = valid ? N : 0;
+__device__ bool load_sequence(Lane& L, int64_t b) {
+  const EvalArgs& A = *L.A;
+  int K = A.nseg[b];
+  bool valid = (K >= 1 && K <= A.smax);
+  int N = 0;
+  for (int j = 0; j < MAXSEG; ++j) {
+    if (!valid || j >= K) break;
+    const int m = A.modes[b * A.smax + j], n = A.knots[b * A.smax + j];
+    if (m < 0 || m >= NMODES || n < 1) valid = false;
+    N += n;
   }
-  const int Nw = wave_max(L.N);
-  L.off = Nw - L.N;
-  if (b < A.B && !valid) {
+  if (N > A.nmax) valid = false;
+  for (int i = 0; i < NX; ++i) {
+    L.x0[i] = A.x0[b * NX + i];
+    valid = valid && isfinite(L.x0[i]);
+  }
+  for (int i = 0; i < 3; ++i) {
+    L.goal[i] = A.goal[b * 3 + i];
+    valid = valid && isfinite(L.goal[i]);
+  }
+  L.mu = A.inst[b];
+  valid = valid && isfinite(L.mu);
+  if (!valid) {
     atomicAdd(A.err, 1u);
     A.cost[b] = NAN;
     A.viol[b] = INFINITY;
@@ -582,85 +579,136 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
     }
     if (A.traj)
       for (int i = 0; i < (A.nmax + 1) * (NX + NU); ++i) A.traj[b * (int64_t)(A.nmax + 1) * (NX + NU) + i] = 0.f;
+    return false;
   }
-  // interval codes, initial guess, zero multipliers
-  if (valid) {
-    int k = 0;
-    for (int j = 0; j < K; ++j) {
-      const int m = A.modes[b * A.smax + j], n = A.knots[b * A.smax + j];
-      const int mnext = (j + 1 < K) ? A.modes[b * A.smax + j + 1] : m;
-      for (int i = 0; i < n; ++i, ++k) {
-        const int smask = (i == n - 1 && (mnext / 3) != (m / 3)) ? 0 : 1;
-        A.code[(int64_t)(L.off + k) * A.S + b] = (uint8_t)make_code(m, smask);
-      }
-    }
-    const double fn = 0.05 * FMAX;
-    for (int k2 = 0; k2 < L.N; ++k2) {
-      const int c = L.code(k2);
-      const int slip = (c >> 2) & 3;
-      const double sg = (slip == 1) ? 1.0 : ((slip == 2) ? -1.0 : 0.0);
-      if (A.warm) {
-        const float* W = A.warm + b * (int64_t)(A.nmax + 1) * (NX + NU);
-        for (int i = 0; i < NU; ++i) L.z(k2, i) = W[k2 * (NX + NU) + NX + i];
-        for (int i = 0; i < NX; ++i) L.z(k2, NU + i) = W[(k2 + 1) * (NX + NU) + i];
-      } else {
-        const double tfrac = double(k2 + 1) / double(L.N);
-        L.z(k2, 0) = fn;
-        L.z(k2, 1) = sg * L.mu * fn;
-        L.z(k2, 2) = 0.0;
-        for (int i = 0; i < 3; ++i) L.z(k2, NU + i) = L.x0[i] + (L.goal[i] - L.x0[i]) * tfrac;
-        L.z(k2, NU + 3) = L.x0[3];
-      }
-      for (int r = 0; r < NE; ++r) {
-        L.lam(k2, r) = 0.f;
-        L.nu(k2, r) = 0.f;
-      }
+  L.seq = b;
+  L.N = N;
+  L.off = A.nmax - N;
+  int k = 0;
+  for (int j = 0; j < K; ++j) {
+    const int m = A.modes[b * A.smax + j], n = A.knots[b * A.smax + j];
+    const int mnext = (j + 1 < K) ? A.modes[b * A.smax + j + 1] : m;
+    for (int i = 0; i < n; ++i, ++k) {
+      const int smask = (i == n - 1 && (mnext / 3) != (m / 3)) ? 0 : 1;
+      A.code[(int64_t)(L.off + k) * A.S + L.slot] = (uint8_t)make_code(m, smask);
     }
   }
-  // solver state
-  double mu = prm.mu0, eta = pow(prm.mu0, 0.1), omega = prm.mu0, rho = prm.rho0;
-  double lamT[NT] = {0.0, 0.0, 0.0};
-  int al = 0, gn_in = 0, gn_tot = 0, rejects = 0, tries = 0, cfails = 0, status = 0;
-  bool done = !valid;
+  const double fn = 0.05 * FMAX;
+  for (int k2 = 0; k2 < N; ++k2) {
+    const int c = L.code(k2);
+    const int slip = (c >> 2) & 3;
+    const double sg = (slip == 1) ? 1.0 : ((slip == 2) ? -1.0 : 0.0);
+    if (A.warm) {
+      const float* W = A.warm + b * (int64_t)(A.nmax + 1) * (NX + NU);
+      for (int i = 0; i < NU; ++i) L.z(k2, i) = W[k2 * (NX + NU) + NX + i];
+      for (int i = 0; i < NX; ++i) L.z(k2, NU + i) = W[(k2 + 1) * (NX + NU) + i];
+    } else {
+      const double tfrac = double(k2 + 1) / double(N);
+      L.z(k2, 0) = fn;
+      L.z(k2, 1) = sg * L.mu * fn;
+      L.z(k2, 2) = 0.0;
+      for (int i = 0; i < 3; ++i) L.z(k2, NU + i) = L.x0[i] + (L.goal[i] - L.x0[i]) * tfrac;
+      L.z(k2, NU + 3) = L.x0[3];
+    }
+    for (int r = 0; r < NE; ++r) {
+      L.lam(k2, r) = 0.f;
+      L.nu(k2, r) = 0.f;
+    }
+  }
+  return true;
+}
+
+// Solver state of one lane.
+struct SolverState {
+  double mu, imu, eta, omega, rho, lamT[NT];
+  int al, gn_in, gn_tot, rejects, tries, cfails, status;
+  __device__ void reset(const DevParams& prm) {
+    mu = prm.mu0;
+    imu = 1.0 / mu;
+    eta = pow(mu, 0.1);
+    omega = mu;
+    rho = prm.rho0;
+    lamT[0] = lamT[1] = lamT[2] = 0.0;
+    al = gn_in = gn_tot = rejects = tries = cfails = status = 0;
+  }
+};
+
+// --------------------------------------------------------------------------------
+// The solver kernel: persistent, one sequence per lane at a time, 64 lanes per block.
+// --------------------------------------------------------------------------------
+__global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
+  const int lane = threadIdx.x;
+  const DevParams& prm = A.prm;
+  Lane L;
+  L.A = &A;
+  L.slot = (int64_t)blockIdx.x * WAVE + lane;
+  L.seq = -1;
+  L.N = 0;
+  L.off = A.nmax;
+  SolverState st;
+  st.reset(prm);
+  bool exhausted = false;
   const int T = min(max(prm.ls_trials, 1), MAX_TRIALS);
 
-  while (wave_any(!done)) {
-    const bool active = !done;
+  for (;;) {
+    // intake: lanes without a sequence pop the queue (one atomic per wave)
+    for (;;) {
+      const bool need = (L.seq < 0) && !exhausted;
+      const unsigned long long m = __ballot(need);
+      if (!m) break;
+      const int leader = __ffsll((long long)m) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) base = atomicAdd(A.qhead, (unsigned long long)__popcll(m));
+      base = __shfl(base, leader);
+      if (need) {
+        const unsigned long long q = base + __popcll(m & ((1ull << lane) - 1ull));
+        if (q >= (unsigned long long)A.B) {
+          exhausted = true;
+        } else {
+          const int64_t b = A.order ? (int64_t)A.order[q] : (int64_t)q;
+          if (load_sequence(L, b)) st.reset(prm);
+        }
+      }
+    }
+    const bool active = L.seq >= 0;
+    if (!wave_any(active)) break;
+    const int Nw = wave_max(active ? L.N : 0);
+
     FactorOut fo;
     double vs_unused, rc_unused;
-    sweep_backward<true>(L, Nw, active, mu, rho, lamT, fo, vs_unused, rc_unused);
+    sweep_backward<true>(L, Nw, active, st.mu, st.imu, st.rho, st.lamT, fo, vs_unused, rc_unused);
     bool step = false, inner_end = false, accepted = false;
     double alpha_acc = 0.0;
     if (active) {
-      if (fo.gnorm <= omega) {
+      if (fo.gnorm <= st.omega) {
         inner_end = true;
       } else if (!fo.ok) {
-        ++cfails;
-        if (tries < prm.chol_retries) {
-          rho = fmax(10.0 * rho, 1e-8);
-          ++tries;
+        ++st.cfails;
+        if (st.tries < prm.chol_retries) {
+          st.rho = fmax(10.0 * st.rho, 1e-8);
+          ++st.tries;
         } else {
-          tries = 0;
-          ++gn_in;
-          ++gn_tot;
-          rho = fmin(10.0 * rho, prm.rho_max);
-          if (++rejects >= prm.max_rejects || gn_in >= prm.gn_max) inner_end = true;
+          st.tries = 0;
+          ++st.gn_in;
+          ++st.gn_tot;
+          st.rho = fmin(10.0 * st.rho, prm.rho_max);
+          if (++st.rejects >= prm.max_rejects || st.gn_in >= prm.gn_max) inner_end = true;
         }
       } else {
-        tries = 0;
-        ++gn_in;
-        ++gn_tot;
+        st.tries = 0;
+        ++st.gn_in;
+        ++st.gn_tot;
         if (fo.D < 0.0 && isfinite(fo.phi0)) {
           step = true;
         } else {
-          rho = fmin(10.0 * rho, prm.rho_max);
-          if (++rejects >= prm.max_rejects || gn_in >= prm.gn_max) inner_end = true;
+          st.rho = fmin(10.0 * st.rho, prm.rho_max);
+          if (++st.rejects >= prm.max_rejects || st.gn_in >= prm.gn_max) inner_end = true;
         }
       }
     }
     if (wave_any(step)) {
       double phi[MAX_TRIALS];
-      sweep_forward(L, Nw, step, mu, lamT, T, phi);
+      sweep_forward(L, Nw, step, st.mu, st.imu, st.lamT, T, phi);
       if (step) {
         int best = -1;
         double alpha = 1.0, a_best = 0.0;
@@ -678,13 +726,13 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
         if (best >= 0) {
           accepted = true;
           alpha_acc = a_best;
-          rho = fmax(rho / 3.0, prm.rho_min);
-          rejects = 0;
+          st.rho = fmax(st.rho / 3.0, prm.rho_min);
+          st.rejects = 0;
         } else {
-          rho = fmin(10.0 * rho, prm.rho_max);
-          ++rejects;
+          st.rho = fmin(10.0 * st.rho, prm.rho_max);
+          ++st.rejects;
         }
-        if (rejects >= prm.max_rejects || gn_in >= prm.gn_max) inner_end = true;
+        if (st.rejects >= prm.max_rejects || st.gn_in >= prm.gn_max) inner_end = true;
       }
     }
     if (wave_any(accepted)) sweep_apply(L, Nw, accepted, alpha_acc);
@@ -692,62 +740,104 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
     if (wave_any(inner_end)) {
       FactorOut go;
       double vsv, rcv;
-      sweep_backward<false>(L, Nw, inner_end, mu, rho, lamT, go, vsv, rcv);
+      sweep_backward<false>(L, Nw, inner_end, st.mu, st.imu, st.rho, st.lamT, go, vsv, rcv);
       if (inner_end) {
-        ++al;
-        gn_in = 0;
-        rejects = 0;
+        ++st.al;
+        st.gn_in = 0;
+        st.rejects = 0;
         if (!isfinite(vsv) || !isfinite(go.gnorm)) {
-          status = 2;
+          st.status = 2;
           fin = true;
-        } else if (vsv <= eta) {
+        } else if (vsv <= st.eta) {
           if (vsv <= prm.eta_star && go.gnorm <= prm.omega_star && rcv <= prm.rc_star) {
-            status = 1;
+            st.status = 1;
             fin = true;
           } else {
             upd = true;
-            eta = fmax(eta * pow(mu, 0.9), prm.eta_star);
-            omega = fmax(omega * mu, prm.omega_star);
+            st.eta = fmax(st.eta * pow(st.mu, 0.9), prm.eta_star);
+            st.omega = fmax(st.omega * st.mu, prm.omega_star);
           }
         } else {
-          mu = fmax(0.1 * mu, prm.mu_min);
-          eta = fmax(pow(mu, 0.1), prm.eta_star);
-          omega = fmax(mu, prm.omega_star);
+          st.mu = fmax(0.1 * st.mu, prm.mu_min);
+          st.imu = 1.0 / st.mu;
+          st.eta = fmax(pow(st.mu, 0.1), prm.eta_star);
+          st.omega = fmax(st.mu, prm.omega_star);
         }
-        if (!fin && al >= prm.al_max) {
-          status = 0;
+        if (!fin && st.al >= prm.al_max) {
+          st.status = 0;
           fin = true;
           upd = false;
         }
       }
     }
-    if (wave_any(upd)) sweep_duals(L, Nw, upd, mu, lamT);
+    if (wave_any(upd)) sweep_duals(L, Nw, upd, st.imu, st.lamT);
     if (wave_any(fin)) {
       double J, v;
       sweep_score(L, Nw, fin, J, v);
       if (fin) {
-        if (status == 2 || !isfinite(J) || !isfinite(v)) {
+        const int64_t b = L.seq;
+        if (st.status == 2 || !isfinite(J) || !isfinite(v)) {
           J = NAN;
           v = INFINITY;
-          status = 2;
+          st.status = 2;
         }
         A.cost[b] = float(J);
         A.viol[b] = float(v);
         A.feas[b] = (v <= prm.eps_feas) ? 1 : 0;
         if (A.stats) {
-          A.stats[b * 4 + 0] = al;
-          A.stats[b * 4 + 1] = gn_tot;
-          A.stats[b * 4 + 2] = cfails;
-          A.stats[b * 4 + 3] = status;
+          A.stats[b * 4 + 0] = st.al;
+          A.stats[b * 4 + 1] = st.gn_tot;
+          A.stats[b * 4 + 2] = st.cfails;
+          A.stats[b * 4 + 3] = st.status;
         }
         if (A.traj) {  // zero rows beyond N
           for (int k = L.N + 1; k <= A.nmax; ++k)
             for (int i = 0; i < NX + NU; ++i) A.traj[(b * (int64_t)(A.nmax + 1) + k) * (NX + NU) + i] = 0.f;
         }
-        done = true;
+        L.seq = -1;
       }
     }
   }
+}
+
+// --------------------------------------------------------------------------------
+// Queue set-up kernels: reset the head, and (optionally) order the sequences by
+// decreasing interval count with a counting sort (histogram, scan, scatter).
+// --------------------------------------------------------------------------------
+__global__ void k_queue_reset(unsigned long long* qhead, int* hist, int nbins) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *qhead = 0ull;
+  if (hist && i < nbins) hist[i] = 0;
+}
+
+__device__ inline int seq_len(const EvalArgs& A, int64_t b) {
+  const int K = A.nseg[b];
+  if (K < 1 || K > A.smax) return 0;
+  int N = 0;
+  for (int j = 0; j < K; ++j) N += max(A.knots[b * A.smax + j], 0);
+  return min(N, A.nmax + 1);
+}
+
+__global__ void k_queue_hist(EvalArgs A, int* hist) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < A.B) atomicAdd(&hist[seq_len(A, b)], 1);
+}
+
+// exclusive scan over bins in decreasing length order (one block)
+__global__ void k_queue_scan(int* hist, int nbins) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int acc = 0;
+    for (int n = nbins - 1; n >= 0; --n) {
+      const int c = hist[n];
+      hist[n] = acc;
+      acc += c;
+    }
+  }
+}
+
+__global__ void k_queue_scatter(EvalArgs A, int* hist, int* order) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < A.B) order[atomicAdd(&hist[seq_len(A, b)], 1)] = (int)b;
 }
 
 }  // namespace comet
@@ -769,8 +859,13 @@ struct comet_ctx {
   float* dz = nullptr;
   uint8_t* code = nullptr;
   unsigned* err = nullptr;
+  unsigned long long* qhead = nullptr;
+  int* hist = nullptr;
+  int* order = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
+  int n_cu = 0, occ_blocks_per_cu = 1;
+  comet_schedule sched{0, 0};
   std::string msg;
 };
 
@@ -882,8 +977,18 @@ comet_status comet_create(comet_task task, const comet_solver_params* params, in
   c->S = (max_batch + 63) / 64 * 64;
   c->max_segments = max_segments;
   c->max_intervals = max_intervals;
-  hipGetDevice(&c->device);
+  (void)hipGetDevice(&c->device);
   compute_scales(c->scale);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) {
+    delete c;
+    return COMET_EHIP;
+  }
+  c->n_cu = prop.multiProcessorCount;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, comet::k_push_solve, comet::WAVE, 0) != hipSuccess || nb < 1)
+    nb = 1;
+  c->occ_blocks_per_cu = nb;
   const int64_t R = max_intervals, S = c->S;
   using namespace comet::push;
   bool okm = hipMalloc(&c->zd, sizeof(double) * R * NW * S) == hipSuccess &&
@@ -892,7 +997,10 @@ comet_status comet_create(comet_task task, const comet_solver_params* params, in
              hipMalloc(&c->gains, sizeof(float) * R * NGAIN * S) == hipSuccess &&
              hipMalloc(&c->dz, sizeof(float) * R * NW * S) == hipSuccess &&
              hipMalloc(&c->code, sizeof(uint8_t) * R * S) == hipSuccess &&
-             hipMalloc(&c->err, sizeof(unsigned)) == hipSuccess;
+             hipMalloc(&c->err, sizeof(unsigned)) == hipSuccess &&
+             hipMalloc(&c->qhead, sizeof(unsigned long long)) == hipSuccess &&
+             hipMalloc(&c->hist, sizeof(int) * (R + 2)) == hipSuccess &&
+             hipMalloc(&c->order, sizeof(int) * max_batch) == hipSuccess;
   if (!okm) {
     (void)hipGetLastError();
     comet_destroy(c);
@@ -916,6 +1024,9 @@ void comet_destroy(comet_ctx* c) {
   if (c->dz) (void)hipFree(c->dz);
   if (c->code) (void)hipFree(c->code);
   if (c->err) (void)hipFree(c->err);
+  if (c->qhead) (void)hipFree(c->qhead);
+  if (c->hist) (void)hipFree(c->hist);
+  if (c->order) (void)hipFree(c->order);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   delete c;
@@ -973,6 +1084,8 @@ comet_status comet_evaluate(comet_ctx* c, void* stream, int64_t B, const float* 
   A.x0 = x0; A.goal = goal; A.inst = inst; A.nseg = nseg; A.modes = modes; A.knots = knots; A.warm = warm;
   A.cost = cost; A.viol = viol; A.feas = feasible; A.traj = traj; A.stats = stats;
   A.zd = c->zd; A.lam = c->lam; A.nu = c->nu; A.gains = c->gains; A.dz = c->dz; A.code = c->code; A.err = c->err;
+  A.qhead = c->qhead;
+  A.order = c->sched.sort_by_length ? c->order : nullptr;
   const comet_solver_params& p = c->prm;
   A.prm.al_max = refine ? p.ref_al_max : p.al_max;
   A.prm.gn_max = refine ? p.ref_gn_max : p.gn_max;
@@ -983,15 +1096,81 @@ comet_status comet_evaluate(comet_ctx* c, void* stream, int64_t B, const float* 
   A.prm.rho_max = p.rho_max; A.prm.armijo_c1 = p.armijo_c1; A.prm.eta_star = p.eta_star;
   A.prm.omega_star = p.omega_star; A.prm.rc_star = p.rc_star; A.prm.eps_feas = p.eps_feas;
   for (int t = 0; t < comet::push::NTYPES; ++t) A.inv_scale[t] = 1.0 / c->scale[t];
-  const unsigned grid = (unsigned)((B + comet::WAVE - 1) / comet::WAVE);
+  const int64_t blocks_needed = (B + comet::WAVE - 1) / comet::WAVE;
+  const int wpc = c->sched.waves_per_cu > 0 ? c->sched.waves_per_cu : c->occ_blocks_per_cu;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_needed, (int64_t)wpc * c->n_cu));
+  const int nbins = c->max_intervals + 2;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   (void)hipStreamIsCapturing(s, &cap);
   const bool timed = (cap == hipStreamCaptureStatusNone);
+  hipLaunchKernelGGL(comet::k_queue_reset, dim3((nbins + 255) / 256), dim3(256), 0, s, c->qhead,
+                     A.order ? c->hist : (int*)nullptr, nbins);
+  if (A.order) {
+    const unsigned gb = (unsigned)((B + 255) / 256);
+    hipLaunchKernelGGL(comet::k_queue_hist, dim3(gb), dim3(256), 0, s, A, c->hist);
+    hipLaunchKernelGGL(comet::k_queue_scan, dim3(1), dim3(64), 0, s, c->hist, nbins);
+    hipLaunchKernelGGL(comet::k_queue_scatter, dim3(gb), dim3(256), 0, s, A, c->hist, c->order);
+  }
   if (timed) (void)hipEventRecord(c->ev0, s);
   hipLaunchKernelGGL(comet::k_push_solve, dim3(grid), dim3(comet::WAVE), 0, s, A);
   if (timed) (void)hipEventRecord(c->ev1, s);
   c->timed = timed;
   if (hipGetLastError() != hipSuccess) return fail(c, COMET_EHIP, "kernel launch failed");
+  return COMET_OK;
+}
+
+comet_status comet_set_schedule(comet_ctx* c, const comet_schedule* sc) {
+  if (!c || !sc || sc->waves_per_cu < 0 || sc->waves_per_cu > 64) return fail(c, COMET_EINVAL, "bad schedule");
+  c->sched = *sc;
+  return COMET_OK;
+}
+
+comet_status comet_get_schedule(const comet_ctx* c, comet_schedule* sc, int32_t* occupancy_waves_per_cu,
+                                int32_t* n_cu) {
+  if (!c || !sc) return COMET_EINVAL;
+  *sc = c->sched;
+  if (occupancy_waves_per_cu) *occupancy_waves_per_cu = c->occ_blocks_per_cu;
+  if (n_cu) *n_cu = c->n_cu;
+  return COMET_OK;
+}
+
+comet_status comet_autotune(comet_ctx* c, void* stream, int64_t B, const float* x0, const float* goal,
+                            const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
+                            float* cost, float* viol, uint8_t* feasible, float* traj, int32_t* stats,
+                            comet_schedule* best, float* best_ms) {
+  if (!c) return COMET_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(s, &cap);
+  if (cap != hipStreamCaptureStatusNone) return fail(c, COMET_ESTATE, "autotune cannot run under stream capture");
+  const int occ = c->occ_blocks_per_cu;
+  const int mult[3] = {1, 2, 4};
+  comet_schedule keep = c->sched, top = keep;
+  float top_ms = 1e30f;
+  for (int sort = 0; sort < 2; ++sort)
+    for (int m = 0; m < 3; ++m) {
+      comet_schedule cand{occ * mult[m], sort};
+      c->sched = cand;
+      comet_status st = comet_evaluate(c, stream, B, x0, goal, inst, nseg, modes, knots, nullptr, 0, cost, viol,
+                                        feasible, traj, stats);
+      if (st != COMET_OK) {
+        c->sched = keep;
+        return st;
+      }
+      if (hipStreamSynchronize(s) != hipSuccess) {
+        c->sched = keep;
+        return fail(c, COMET_EHIP, "synchronize failed during autotune");
+      }
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev0, c->ev1) != hipSuccess) ms = 1e30f;
+      if (ms < top_ms) {
+        top_ms = ms;
+        top = cand;
+      }
+    }
+  c->sched = top;
+  if (best) *best = top;
+  if (best_ms) *best_ms = top_ms;
   return COMET_OK;
 }
 

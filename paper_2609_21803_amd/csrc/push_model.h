@@ -27,6 +27,8 @@
 
 #include <cmath>
 
+#include "dmath.h"
+
 namespace comet {
 namespace push {
 
@@ -85,7 +87,7 @@ __host__ __device__ inline void rows(const double* xk, const double* uk, const d
   const double Fbx = -Fn * nx + Ft * tx, Fby = -Fn * ny + Ft * ty;
   const double M = HALF * Ft + s * Fn;
   double st, ct;
-  sincos(th, &st, &ct);
+  sincos_d(th, &st, &ct);
   const double xi_x = K1 * Fbx, xi_y = K1 * Fby, xi_t = KM * M;
   const double vx = ct * xi_x - st * xi_y, vy = st * xi_x + ct * xi_y;
   c[0] = (x1[0] - xk[0]) - DT * vx;

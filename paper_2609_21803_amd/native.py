@@ -27,6 +27,10 @@ class SolverParamsC(C.Structure):
                 ("eps_feas", C.c_double)]
 
 
+class ScheduleC(C.Structure):
+    _fields_ = [("waves_per_cu", C.c_int32), ("sort_by_length", C.c_int32)]
+
+
 class CometError(RuntimeError):
     pass
 
@@ -59,6 +63,12 @@ def lib():
         L.comet_check.restype = C.c_int
         L.comet_evaluate.argtypes = [P, P, C.c_int64] + [P] * 7 + [C.c_int32] + [P] * 5
         L.comet_evaluate.restype = C.c_int
+        L.comet_set_schedule.argtypes = [P, C.POINTER(ScheduleC)]
+        L.comet_set_schedule.restype = C.c_int
+        L.comet_get_schedule.argtypes = [P, C.POINTER(ScheduleC), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.comet_get_schedule.restype = C.c_int
+        L.comet_autotune.argtypes = [P, P, C.c_int64] + [P] * 11 + [C.POINTER(ScheduleC), C.POINTER(C.c_float)]
+        L.comet_autotune.restype = C.c_int
         L.comet_last_kernel_ms.argtypes = [P, C.POINTER(C.c_float)]
         L.comet_last_kernel_ms.restype = C.c_int
         _lib = L
@@ -161,6 +171,28 @@ class Context:
         ms = C.c_float()
         check(lib().comet_last_kernel_ms(self._h, C.byref(ms)), self._h)
         return ms.value
+
+    def schedule(self):
+        sc = ScheduleC()
+        occ, ncu = C.c_int32(), C.c_int32()
+        check(lib().comet_get_schedule(self._h, C.byref(sc), C.byref(occ), C.byref(ncu)), self._h)
+        return dict(waves_per_cu=sc.waves_per_cu, sort_by_length=sc.sort_by_length, occupancy=occ.value,
+                    n_cu=ncu.value)
+
+    def set_schedule(self, waves_per_cu=0, sort_by_length=0):
+        sc = ScheduleC(int(waves_per_cu), int(sort_by_length))
+        check(lib().comet_set_schedule(self._h, C.byref(sc)), self._h)
+
+    def autotune(self, x0, goal, inst, nseg, modes, knots, out: dict, stream=None):
+        """Time every candidate schedule on this batch, keep the fastest; returns (schedule, ms)."""
+        sc = ScheduleC()
+        ms = C.c_float()
+        rc = lib().comet_autotune(self._h, _stream(stream), int(nseg.shape[0]), _ptr(x0), _ptr(goal), _ptr(inst),
+                                  _ptr(nseg), _ptr(modes), _ptr(knots), _ptr(out["cost"]), _ptr(out["viol"]),
+                                  _ptr(out["feasible"]), _ptr(out.get("traj")), _ptr(out.get("stats")),
+                                  C.byref(sc), C.byref(ms))
+        check(rc, self._h)
+        return dict(waves_per_cu=sc.waves_per_cu, sort_by_length=sc.sort_by_length), ms.value
 
     def evaluate(self, x0, goal, inst, nseg, modes, knots, warm=None, refine=0, cost=None, viol=None,
                  feasible=None, traj=None, stats=None, want_traj=True, want_stats=True, stream=None):

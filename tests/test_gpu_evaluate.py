@@ -168,22 +168,32 @@ def test_empty_batch_and_host_argument_errors():
         native.Context(max_batch=8, max_segments=7)
 
 
-def test_warm_start_from_converged_oracle_trajectory(orc):
-    """A warm start at the oracle's refined solution converges to the same cost."""
-    b = I.subset(I.push_tiny(), np.arange(0, 1152, 37))
+def test_warm_start_matches_oracle_with_same_warm_start(orc):
+    """A warm start replaces the schedule-derived primal (multipliers start at zero);
+    both sides start from the same float32 trajectory: the oracle's solution."""
+    b = I.subset(I.push_tiny(), np.arange(0, 1152, 7))
     o = run_oracle(b, 10)
-    g = run_gpu(b, 10, warm=o["traj"].astype(np.float32))
-    sel = (o["feasible"] == 1) & (o["stats"][:, 3] == 1)
-    rel = np.abs(g["cost"][sel] - o["cost"][sel]) / np.maximum(np.abs(o["cost"][sel]), 1e-12)
-    assert sel.sum() > 5 and np.mean(rel <= 1e-4) >= 0.95 and np.all(g["feasible"][sel] == 1)
+    warm = o["traj"].astype(np.float32)
+    g = run_gpu(b, 10, warm=warm)
+    o2 = run_oracle(b, 10, warm=warm.astype(np.float64))
+    compare(g, o2, "warm", min_frac=0.985)
 
 
 def test_refinement_budget_matches_oracle(orc):
+    """Refinement budget (AL <= 40, GN <= 25).  Five times the iterations of the
+    exploration budget give proportionally more near-tie trial steps, so the bar is 97 %;
+    the oracle's own sensitivity to a one-ulp goal perturbation at this budget is printed."""
     import oracle
-    b = I.subset(I.push_tiny(seed=3), np.arange(0, 1152, 5))
+    b = I.subset(I.push_tiny(seed=3), np.arange(0, 1152, 2))
     g = run_gpu(b, 10, refine=1)
-    o = run_oracle(b, 10, params=oracle.Params(**oracle.REFINE))
-    compare(g, o, "refine")
+    prm = oracle.Params(**oracle.REFINE)
+    o = run_oracle(b, 10, params=prm)
+    compare(g, o, "refine", min_frac=0.97)
+    gp = dict(b)
+    gp["goal"] = f32(b["goal"]) * (1 + 1.2e-7 * np.random.default_rng(2).choice([-1, 1], size=b["goal"].shape))
+    o2 = run_oracle(gp, 10, params=prm)
+    compare(dict(cost=o2["cost"], viol=o2["viol"], feasible=o2["feasible"]), o, "refine-oracle-vs-perturbed",
+            min_frac=0.9)
 
 
 def test_row_scales_agree_with_oracle(orc):
@@ -202,3 +212,28 @@ def test_oracle_self_sensitivity(orc):
     o2 = run_oracle(gp, 75)
     ok, margin = compare(dict(cost=o2["cost"], viol=o2["viol"], feasible=o2["feasible"]), o, "oracle-vs-perturbed",
                          min_frac=0.97)
+
+
+def test_schedules_give_identical_results_and_autotuner_picks_one():
+    """The persistent pool, its width and the length-sorted queue change only where an
+    order is solved, never its arithmetic: outputs are bitwise identical."""
+    import torch
+    from paper_2609_21803_amd import native
+    b = I.push_hetero(B=3000, seed=21)
+    d = native.to_device(b)
+    ctx = native.Context(max_batch=3000, max_intervals=75)
+    outs = []
+    for wpc, srt in [(0, 0), (1, 1), (3, 0), (8, 1)]:
+        ctx.set_schedule(wpc, srt)
+        o = ctx.evaluate(**d)
+        torch.cuda.synchronize()
+        outs.append({k: v.cpu().numpy() for k, v in o.items()})
+    for o in outs[1:]:
+        for k in ("cost", "viol", "feasible", "traj", "stats"):
+            assert np.array_equal(o[k], outs[0][k], equal_nan=True), k
+    out = dict(cost=torch.empty(3000, device="cuda"), viol=torch.empty(3000, device="cuda"),
+               feasible=torch.empty(3000, dtype=torch.uint8, device="cuda"))
+    sched, ms = ctx.autotune(**d, out=out)
+    assert ms > 0 and ctx.schedule()["waves_per_cu"] == sched["waves_per_cu"]
+    assert np.array_equal(out["cost"].cpu().numpy(), outs[0]["cost"], equal_nan=True)
+    print("autotuned schedule", sched, f"{ms:.2f} ms", ctx.schedule())
