@@ -43,6 +43,7 @@ typedef enum {
 typedef enum { COMET_TASK_PUSH = 0 } comet_task;
 
 typedef struct comet_ctx comet_ctx; /* opaque */
+typedef struct comet_mlp comet_mlp; /* opaque: learned proposal / warm-start network */
 
 /* Solver parameters of the per-order TO (Sec. III-C).  Defaults: comet_default_params.
  *   al_max, gn_max          augmented-Lagrangian outer / Gauss-Newton inner budget
@@ -148,6 +149,72 @@ comet_status comet_autotune(comet_ctx* ctx, void* stream, int64_t B, const float
  * HIP events around its solver kernel on the caller's stream; valid after that stream
  * has been synchronised.  Used for roofline accounting. */
 comet_status comet_last_kernel_ms(comet_ctx* ctx, float* ms);
+
+/* ---------------------------------------------------------------------------------
+ * Greedy contact-mode expansion (Alg. 1, Sec. III-B) on the device.
+ *
+ * Orders are keys: K << 60 | m_0 << 50 | m_1 << 40 | ... | m_5 << 0 (10 bits per mode id),
+ * so comparing keys compares the segment count, then the ids lexicographically.  The
+ * language is every order of 1..kcap segments over the task's mode ids.
+ *   kcap               segment cap (<= max_segments)
+ *   seed_max_segments  seed batch F_0 = every order with at most this many segments, in key order
+ *   radius             r of the r-edit neighbourhood (1 or 2): an edit inserts, deletes or
+ *                      substitutes one segment; neighbours are enumerated substitutions
+ *                      (position, then id), deletions (position), insertions (position, then
+ *                      id), and for r = 2 each one-edit neighbour's list in that order
+ *   rounds             expansion rounds after the seed (s_max)
+ *   frontier_W         at most this many best-ranked evaluated orders are expanded per round
+ *   knots_per_segment  intervals per segment; 0 = split n_total intervals as evenly as
+ *                      possible, the remainder going to the earliest segments
+ *   k_ref              feasible orders re-solved with the refinement budget at the end
+ *   batch_B            batch width B (<= max_batch); eval_budget caps the evaluated orders
+ *   mu_merit           mu of the merit M = J + mu max(v - eps_feas, 0), Eq. (5)
+ * Ranking is by (M, key) with NaN as +inf; refinement ranks feasible orders by (J, key) and
+ * returns the smallest refined J among refined-feasible orders (ties by key). */
+typedef struct {
+  int32_t kcap, seed_max_segments, radius, rounds, frontier_W, knots_per_segment, k_ref, n_total;
+  int64_t batch_B, eval_budget;
+  double mu_merit;
+} comet_expand_params;
+
+typedef struct {
+  int64_t evaluated;             /* orders evaluated (|V|) */
+  int32_t rounds_done;           /* evaluation rounds with a non-empty batch */
+  int32_t n_feasible;            /* evaluated orders with v <= eps_feas */
+  int64_t first_feasible_index;  /* 1-based position in evaluation order of the first feasible order, 0 = none */
+  double t_first_feasible_ms;    /* device wall clock from the start of the expansion to the first feasible
+                                    completed solve (-1 = none): time to first feasible plan */
+  double t_total_ms;             /* device time of the whole expansion including refinement */
+  int32_t n_refined, reserved;
+} comet_expand_stats;
+
+/* Run seed, s_max expansion rounds and refinement for one instance (x0 [nx], goal [3],
+ * inst [n_inst]: device pointers).  The loop runs as one captured HIP graph on an internal
+ * stream ordered after `stream`; the call synchronises and fills `stats` (host).  Outputs
+ * (device): best_nseg [1] (0 = no feasible plan), best_modes / best_knots [max_segments],
+ * best_cost / best_viol [1] (refined), best_traj [max_intervals+1, nx+nu] or NULL.
+ * learned: NULL for the plain method, else a proposal network that ranks generated
+ * neighbours and seeds their initial trajectories (the plain refinement judges every plan).
+ * EINVAL on inconsistent parameters (see comet_expand_params), ENOMEM if the work space
+ * (|V| <= eval_budget + batch_B, frontier_W x neighbourhood candidates <= 2^27) does not fit. */
+comet_status comet_expand(comet_ctx* ctx, void* stream, const float* x0, const float* goal, const float* inst,
+                          const comet_expand_params* params, comet_mlp* learned, int32_t* best_nseg,
+                          int32_t* best_modes, int32_t* best_knots, float* best_cost, float* best_viol,
+                          float* best_traj, comet_expand_stats* stats);
+
+/* One batch-construction step of Alg. 1 on given scores: rank the n evaluated orders
+ * (keys [n] uint64, merit [n] double, device) by (merit, key), traverse at most frontier_W of
+ * them and admit their unseen r-edit neighbours in enumeration order until `room` orders are
+ * admitted.  Writes out_keys [room] and out_n [1] (device, int64).  Synchronises `stream`. */
+comet_status comet_expand_next(comet_ctx* ctx, void* stream, int64_t n, const uint64_t* keys, const double* merit,
+                               const comet_expand_params* params, int64_t room, uint64_t* out_keys,
+                               int64_t* out_n);
+
+/* Evaluated set of the last comet_expand on this context, in evaluation order: up to cap
+ * keys, J and v (device buffers, any may be NULL) and the full count in n_out (device int64).
+ * Synchronises `stream`. */
+comet_status comet_expand_trace(comet_ctx* ctx, void* stream, int64_t cap, uint64_t* keys, double* J, double* v,
+                                int64_t* n_out);
 
 #ifdef __cplusplus
 }

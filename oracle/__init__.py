@@ -102,6 +102,8 @@ def lib():
         L.oracle_neighbours.restype = C.c_int64
         L.oracle_expand.argtypes = [P, P, C.c_double, C.POINTER(ExpandParams), C.POINTER(SolverParams),
                                     C.POINTER(SolverParams), C.c_int32, P, P, P, P, P, P, P, C.c_int64]
+        L.oracle_expand_next.argtypes = [C.c_int64, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int64, P]
+        L.oracle_expand_next.restype = C.c_int64
         L.oracle_enumerate.argtypes = [P, P, C.c_double, C.c_int32, C.POINTER(ExpandParams),
                                        C.POINTER(SolverParams), C.POINTER(SolverParams), C.c_int32, P, P, P, P]
         _lib = L
@@ -295,3 +297,12 @@ def enumerate_all(x0, goal, mu, ep: Expand, kmin=1, params: Params | None = None
     lib().oracle_enumerate(_p(x0), _p(goal), float(mu), kmin, C.byref(epc), C.byref(p1), C.byref(p2),
                            nthreads or default_threads(), C.byref(key), C.byref(J), C.byref(v), C.byref(n))
     return dict(best_key=int(key.value), best_cost=J.value, best_viol=v.value, evaluated=int(n.value))
+
+
+def expand_next(keys, merit, n_modes=12, kcap=3, radius=1, frontier_W=4096, room=131072):
+    """One batch-construction step of Alg. 1 on given (key, merit) pairs."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    merit = _f64(merit)
+    out = np.zeros(max(int(room), 1), np.uint64)
+    n = lib().oracle_expand_next(len(keys), _p(keys), _p(merit), n_modes, kcap, radius, frontier_W, int(room), _p(out))
+    return out[:n].copy()

@@ -1152,7 +1152,7 @@ int oracle_expand(const double *x0, const double *goal, double mu, const OracleE
   double *v = (double *)malloc(sizeof(double) * (size_t)(ep->batch_B + 16));
   KeySet seen;
   int s, K, q[MAXSEG];
-  int64_t first_feasible = 0, n_feas = 0;
+  int64_t first_feasible = 0, n_feas = 0, rounds_run = 0;
   set_init(&seen, cap);
   /* seed: all orders with at most seed_max_segments segments, in key order */
   {
@@ -1174,6 +1174,7 @@ int oracle_expand(const double *x0, const double *goal, double mu, const OracleE
   for (s = 0; nF > 0 && s <= ep->rounds; ++s) {
     int64_t room;
     eval_keys(F, nF, x0, goal, mu, ep, prm_exp, nthreads, J, v, NULL);
+    ++rounds_run;
     for (i = 0; i < nF; ++i) {
       V[nV].key = F[i];
       V[nV].J = J[i];
@@ -1208,7 +1209,7 @@ int oracle_expand(const double *x0, const double *goal, double mu, const OracleE
     }
   }
   counters[0] = nV;
-  counters[1] = s;
+  counters[1] = rounds_run;
   counters[2] = n_feas;
   counters[3] = first_feasible;
   /* refinement: the k_ref feasible orders of smallest J (ties by key), re-solved   */
@@ -1246,6 +1247,37 @@ int oracle_expand(const double *x0, const double *goal, double mu, const OracleE
   free(V); free(R); free(F); free(nb); free(tmp); free(J); free(v);
   free(seen.slot);
   return 0;
+}
+
+/* One batch-construction step of Alg. 1 on given merits: rank the evaluated orders by  */
+/* (merit, key), traverse at most W of them, append their unseen r-edit neighbours in  */
+/* enumeration order until `room` orders are admitted.  keys/merit: the evaluated set  */
+/* V (n entries, merit NaN ranks as +inf).  Returns the number admitted (out_keys).      */
+int64_t oracle_expand_next(int64_t n, const uint64_t *keys, const double *merit, int32_t n_modes, int32_t kcap,
+                           int32_t radius, int32_t frontier_W, int64_t room, uint64_t *out_keys) {
+  Entry *R = (Entry *)malloc(sizeof(Entry) * (size_t)(n + 1));
+  Key *nb = (Key *)malloc(sizeof(Key) * 4000000);
+  Key *tmp = (Key *)malloc(sizeof(Key) * 65536);
+  KeySet seen;
+  int64_t i, j, nF = 0;
+  set_init(&seen, n + room + 16);
+  for (i = 0; i < n; ++i) {
+    R[i].key = keys[i];
+    R[i].M = isnan(merit[i]) ? INFINITY : merit[i];
+    R[i].J = R[i].v = 0.0;
+    set_add(&seen, keys[i]);
+  }
+  qsort(R, (size_t)n, sizeof(Entry), cmp_entry_merit);
+  for (i = 0; i < n && i < frontier_W && nF < room; ++i) {
+    int64_t m = neighbours(R[i].key, n_modes, kcap, radius, nb, tmp);
+    for (j = 0; j < m && nF < room; ++j)
+      if (!set_has(&seen, nb[j])) {
+        set_add(&seen, nb[j]);
+        out_keys[nF++] = nb[j];
+      }
+  }
+  free(R); free(nb); free(tmp); free(seen.slot);
+  return nF;
 }
 
 /* Full enumeration of every order with 1..kcap segments (kmin..kcap if kmin > 1),  */

@@ -32,51 +32,11 @@
 #include <string>
 #include <vector>
 
-#include "../../include/comet.h"
-#include "push_model.h"
+#include "internal.h"
 
 namespace comet {
 
 using namespace push;
-
-constexpr int MAXSEG = 6;
-constexpr int MAXN = 512;
-constexpr int MAX_TRIALS = 16;
-constexpr int WAVE = 64;
-
-struct DevParams {
-  int al_max, gn_max, chol_retries, ls_trials, max_rejects;
-  double mu0, mu_min, rho0, rho_min, rho_max, armijo_c1, eta_star, omega_star, rc_star, eps_feas;
-};
-
-struct EvalArgs {
-  int64_t B;
-  int smax, nmax;                 // segment slots per sequence, max intervals (work-space rows)
-  int64_t S;                      // slot stride of the work space
-  const float* x0;
-  const float* goal;
-  const float* inst;
-  const int* nseg;
-  const int* modes;
-  const int* knots;
-  const float* warm;
-  float* cost;
-  float* viol;
-  uint8_t* feas;
-  float* traj;
-  int* stats;
-  double* zd;                     // [row][7][S]  (u_k, x_{k+1})
-  float* lam;                     // [row][5][S]
-  float* nu;                      // [row][5][S]
-  float* gains;                   // [row][35][S] (k, K row-major 7x4)
-  float* dz;                      // [row][7][S]
-  uint8_t* code;                  // [row][S]
-  const int* order;               // queue order of the sequences (null = identity)
-  unsigned long long* qhead;      // work-queue head
-  unsigned* err;
-  DevParams prm;
-  double inv_scale[NTYPES];
-};
 
 __device__ inline int wave_max(int v) {
 #pragma unroll
@@ -556,21 +516,26 @@ __device__ bool load_sequence(Lane& L, int64_t b) {
     N += n;
   }
   if (N > A.nmax) valid = false;
+  const int64_t bi = b * A.inst_stride;
   for (int i = 0; i < NX; ++i) {
-    L.x0[i] = A.x0[b * NX + i];
+    L.x0[i] = A.x0[bi * NX + i];
     valid = valid && isfinite(L.x0[i]);
   }
   for (int i = 0; i < 3; ++i) {
-    L.goal[i] = A.goal[b * 3 + i];
+    L.goal[i] = A.goal[bi * 3 + i];
     valid = valid && isfinite(L.goal[i]);
   }
-  L.mu = A.inst[b];
+  L.mu = A.inst[bi];
   valid = valid && isfinite(L.mu);
   if (!valid) {
     atomicAdd(A.err, 1u);
     A.cost[b] = NAN;
     A.viol[b] = INFINITY;
     A.feas[b] = 0;
+    if (A.cost64) {
+      A.cost64[b] = NAN;
+      A.viol64[b] = INFINITY;
+    }
     if (A.stats) {
       A.stats[b * 4 + 0] = 0;
       A.stats[b * 4 + 1] = 0;
@@ -648,6 +613,7 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
   SolverState st;
   st.reset(prm);
   bool exhausted = false;
+  const int64_t Bn = A.Bdev ? *A.Bdev : A.B;
   const int T = min(max(prm.ls_trials, 1), MAX_TRIALS);
 
   for (;;) {
@@ -662,7 +628,7 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
       base = __shfl(base, leader);
       if (need) {
         const unsigned long long q = base + __popcll(m & ((1ull << lane) - 1ull));
-        if (q >= (unsigned long long)A.B) {
+        if (q >= (unsigned long long)Bn) {
           exhausted = true;
         } else {
           const int64_t b = A.order ? (int64_t)A.order[q] : (int64_t)q;
@@ -784,6 +750,11 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
         A.cost[b] = float(J);
         A.viol[b] = float(v);
         A.feas[b] = (v <= prm.eps_feas) ? 1 : 0;
+        if (A.cost64) {
+          A.cost64[b] = J;
+          A.viol64[b] = v;
+        }
+        if (A.t_first && v <= prm.eps_feas) atomicMin(A.t_first, (unsigned long long)wall_clock64());
         if (A.stats) {
           A.stats[b * 4 + 0] = st.al;
           A.stats[b * 4 + 1] = st.gn_tot;
@@ -820,7 +791,8 @@ __device__ inline int seq_len(const EvalArgs& A, int64_t b) {
 
 __global__ void k_queue_hist(EvalArgs A, int* hist) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < A.B) atomicAdd(&hist[seq_len(A, b)], 1);
+  const int64_t Bn = A.Bdev ? *A.Bdev : A.B;
+  if (b < Bn) atomicAdd(&hist[seq_len(A, b)], 1);
 }
 
 // exclusive scan over bins in decreasing length order (one block)
@@ -837,7 +809,8 @@ __global__ void k_queue_scan(int* hist, int nbins) {
 
 __global__ void k_queue_scatter(EvalArgs A, int* hist, int* order) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < A.B) order[atomicAdd(&hist[seq_len(A, b)], 1)] = (int)b;
+  const int64_t Bn = A.Bdev ? *A.Bdev : A.B;
+  if (b < Bn) order[atomicAdd(&hist[seq_len(A, b)], 1)] = (int)b;
 }
 
 }  // namespace comet
@@ -845,36 +818,9 @@ __global__ void k_queue_scatter(EvalArgs A, int* hist, int* order) {
 // ==================================================================================
 // Host side: context, row scales, C ABI.
 // ==================================================================================
-struct comet_ctx {
-  int task;
-  comet_solver_params prm;
-  int64_t max_batch, S;
-  int max_segments, max_intervals;
-  int device;
-  double scale[comet::push::NTYPES];
-  double* zd = nullptr;
-  float* lam = nullptr;
-  float* nu = nullptr;
-  float* gains = nullptr;
-  float* dz = nullptr;
-  uint8_t* code = nullptr;
-  unsigned* err = nullptr;
-  unsigned long long* qhead = nullptr;
-  int* hist = nullptr;
-  int* order = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  bool timed = false;
-  int n_cu = 0, occ_blocks_per_cu = 1;
-  comet_schedule sched{0, 0};
-  std::string msg;
-};
-
 namespace {
 
-comet_status fail(comet_ctx* c, comet_status s, const std::string& m) {
-  if (c) c->msg = m;
-  return s;
-}
+comet_status fail(comet_ctx* c, comet_status s, const std::string& m) { return comet::fail_msg(c, s, m); }
 
 // Row scales: for every row type, the median 2-norm of its physical Jacobian row over the
 // schedule-derived initial guesses of a fixed sample of orders (all 144 two-segment orders,
@@ -932,6 +878,64 @@ void compute_scales(double* out) {
 }
 
 }  // namespace
+
+namespace comet {
+
+comet_status fail_msg(comet_ctx* c, comet_status st, const std::string& m) {
+  if (c) c->msg = m;
+  return st;
+}
+
+comet_status launch_evaluate(comet_ctx* c, hipStream_t s, const EvalLaunch& L) {
+  EvalArgs A;
+  std::memset(&A, 0, sizeof A);
+  A.B = L.B;
+  A.Bdev = L.B_dev;
+  A.smax = c->max_segments;
+  A.nmax = c->max_intervals;
+  A.S = c->S;
+  A.x0 = L.x0; A.goal = L.goal; A.inst = L.inst; A.inst_stride = L.inst_stride;
+  A.nseg = L.nseg; A.modes = L.modes; A.knots = L.knots; A.warm = L.warm;
+  A.cost = L.cost; A.viol = L.viol; A.feas = L.feas; A.traj = L.traj; A.stats = L.stats;
+  A.cost64 = L.cost64; A.viol64 = L.viol64; A.t_first = L.t_first;
+  A.zd = c->zd; A.lam = c->lam; A.nu = c->nu; A.gains = c->gains; A.dz = c->dz; A.code = c->code; A.err = c->err;
+  A.qhead = c->qhead;
+  A.order = c->sched.sort_by_length ? c->order : nullptr;
+  const comet_solver_params& p = c->prm;
+  A.prm.al_max = L.refine ? p.ref_al_max : p.al_max;
+  A.prm.gn_max = L.refine ? p.ref_gn_max : p.gn_max;
+  A.prm.chol_retries = p.chol_retries;
+  A.prm.ls_trials = p.ls_trials;
+  A.prm.max_rejects = p.max_rejects;
+  A.prm.mu0 = p.mu0; A.prm.mu_min = p.mu_min; A.prm.rho0 = p.rho0; A.prm.rho_min = p.rho_min;
+  A.prm.rho_max = p.rho_max; A.prm.armijo_c1 = p.armijo_c1; A.prm.eta_star = p.eta_star;
+  A.prm.omega_star = p.omega_star; A.prm.rc_star = p.rc_star; A.prm.eps_feas = p.eps_feas;
+  for (int t = 0; t < NTYPES; ++t) A.inv_scale[t] = 1.0 / c->scale[t];
+  const int64_t Bmax = L.B_dev ? L.B_max : L.B;
+  const int64_t blocks_needed = (Bmax + WAVE - 1) / WAVE;
+  const int wpc = c->sched.waves_per_cu > 0 ? c->sched.waves_per_cu : c->occ_blocks_per_cu;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_needed, (int64_t)wpc * c->n_cu));
+  const int nbins = c->max_intervals + 2;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(s, &cap);
+  const bool timed = (cap == hipStreamCaptureStatusNone);
+  hipLaunchKernelGGL(k_queue_reset, dim3((nbins + 255) / 256), dim3(256), 0, s, c->qhead,
+                     A.order ? c->hist : (int*)nullptr, nbins);
+  if (A.order) {
+    const unsigned gb = (unsigned)std::max<int64_t>(1, (Bmax + 255) / 256);
+    hipLaunchKernelGGL(k_queue_hist, dim3(gb), dim3(256), 0, s, A, c->hist);
+    hipLaunchKernelGGL(k_queue_scan, dim3(1), dim3(64), 0, s, c->hist, nbins);
+    hipLaunchKernelGGL(k_queue_scatter, dim3(gb), dim3(256), 0, s, A, c->hist, c->order);
+  }
+  if (timed) (void)hipEventRecord(c->ev0, s);
+  hipLaunchKernelGGL(k_push_solve, dim3(grid), dim3(WAVE), 0, s, A);
+  if (timed) (void)hipEventRecord(c->ev1, s);
+  c->timed = timed;
+  if (hipGetLastError() != hipSuccess) return fail_msg(c, COMET_EHIP, "kernel launch failed");
+  return COMET_OK;
+}
+
+}  // namespace comet
 
 extern "C" {
 
@@ -1017,6 +1021,8 @@ comet_status comet_create(comet_task task, const comet_solver_params* params, in
 
 void comet_destroy(comet_ctx* c) {
   if (!c) return;
+  comet::destroy_expand_ws(c);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
   if (c->zd) (void)hipFree(c->zd);
   if (c->lam) (void)hipFree(c->lam);
   if (c->nu) (void)hipFree(c->nu);
@@ -1074,49 +1080,13 @@ comet_status comet_evaluate(comet_ctx* c, void* stream, int64_t B, const float* 
   if (!x0 || !goal || !inst || !nseg || !modes || !knots || !cost || !viol || !feasible)
     return fail(c, COMET_EINVAL, "null input or output pointer");
   if (refine != 0 && refine != 1) return fail(c, COMET_EINVAL, "refine must be 0 or 1");
-  hipStream_t s = (hipStream_t)stream;
-  comet::EvalArgs A;
-  std::memset(&A, 0, sizeof A);
-  A.B = B;
-  A.smax = c->max_segments;
-  A.nmax = c->max_intervals;
-  A.S = c->S;
-  A.x0 = x0; A.goal = goal; A.inst = inst; A.nseg = nseg; A.modes = modes; A.knots = knots; A.warm = warm;
-  A.cost = cost; A.viol = viol; A.feas = feasible; A.traj = traj; A.stats = stats;
-  A.zd = c->zd; A.lam = c->lam; A.nu = c->nu; A.gains = c->gains; A.dz = c->dz; A.code = c->code; A.err = c->err;
-  A.qhead = c->qhead;
-  A.order = c->sched.sort_by_length ? c->order : nullptr;
-  const comet_solver_params& p = c->prm;
-  A.prm.al_max = refine ? p.ref_al_max : p.al_max;
-  A.prm.gn_max = refine ? p.ref_gn_max : p.gn_max;
-  A.prm.chol_retries = p.chol_retries;
-  A.prm.ls_trials = p.ls_trials;
-  A.prm.max_rejects = p.max_rejects;
-  A.prm.mu0 = p.mu0; A.prm.mu_min = p.mu_min; A.prm.rho0 = p.rho0; A.prm.rho_min = p.rho_min;
-  A.prm.rho_max = p.rho_max; A.prm.armijo_c1 = p.armijo_c1; A.prm.eta_star = p.eta_star;
-  A.prm.omega_star = p.omega_star; A.prm.rc_star = p.rc_star; A.prm.eps_feas = p.eps_feas;
-  for (int t = 0; t < comet::push::NTYPES; ++t) A.inv_scale[t] = 1.0 / c->scale[t];
-  const int64_t blocks_needed = (B + comet::WAVE - 1) / comet::WAVE;
-  const int wpc = c->sched.waves_per_cu > 0 ? c->sched.waves_per_cu : c->occ_blocks_per_cu;
-  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_needed, (int64_t)wpc * c->n_cu));
-  const int nbins = c->max_intervals + 2;
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  (void)hipStreamIsCapturing(s, &cap);
-  const bool timed = (cap == hipStreamCaptureStatusNone);
-  hipLaunchKernelGGL(comet::k_queue_reset, dim3((nbins + 255) / 256), dim3(256), 0, s, c->qhead,
-                     A.order ? c->hist : (int*)nullptr, nbins);
-  if (A.order) {
-    const unsigned gb = (unsigned)((B + 255) / 256);
-    hipLaunchKernelGGL(comet::k_queue_hist, dim3(gb), dim3(256), 0, s, A, c->hist);
-    hipLaunchKernelGGL(comet::k_queue_scan, dim3(1), dim3(64), 0, s, c->hist, nbins);
-    hipLaunchKernelGGL(comet::k_queue_scatter, dim3(gb), dim3(256), 0, s, A, c->hist, c->order);
-  }
-  if (timed) (void)hipEventRecord(c->ev0, s);
-  hipLaunchKernelGGL(comet::k_push_solve, dim3(grid), dim3(comet::WAVE), 0, s, A);
-  if (timed) (void)hipEventRecord(c->ev1, s);
-  c->timed = timed;
-  if (hipGetLastError() != hipSuccess) return fail(c, COMET_EHIP, "kernel launch failed");
-  return COMET_OK;
+  comet::EvalLaunch L;
+  L.B = B;
+  L.B_max = B;
+  L.x0 = x0; L.goal = goal; L.inst = inst; L.inst_stride = 1;
+  L.nseg = nseg; L.modes = modes; L.knots = knots; L.warm = warm; L.refine = refine;
+  L.cost = cost; L.viol = viol; L.feas = feasible; L.traj = traj; L.stats = stats;
+  return comet::launch_evaluate(c, (hipStream_t)stream, L);
 }
 
 comet_status comet_set_schedule(comet_ctx* c, const comet_schedule* sc) {

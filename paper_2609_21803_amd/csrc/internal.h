@@ -1,0 +1,111 @@
+// internal.h -- definitions shared by the evaluator and the expansion (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/comet.h"
+#include "push_model.h"
+
+namespace comet {
+
+using namespace push;
+
+constexpr int MAXSEG = 6;
+constexpr int MAXN = 512;
+constexpr int MAX_TRIALS = 16;
+constexpr int WAVE = 64;
+
+struct DevParams {
+  int al_max, gn_max, chol_retries, ls_trials, max_rejects;
+  double mu0, mu_min, rho0, rho_min, rho_max, armijo_c1, eta_star, omega_star, rc_star, eps_feas;
+};
+
+struct EvalArgs {
+  int64_t B;
+  int smax, nmax;                 // segment slots per sequence, max intervals (work-space rows)
+  int64_t S;                      // slot stride of the work space
+  const float* x0;
+  const float* goal;
+  const float* inst;
+  const int* nseg;
+  const int* modes;
+  const int* knots;
+  const float* warm;
+  float* cost;
+  float* viol;
+  uint8_t* feas;
+  float* traj;
+  int* stats;
+  double* zd;                     // [row][7][S]  (u_k, x_{k+1})
+  float* lam;                     // [row][5][S]
+  float* nu;                      // [row][5][S]
+  float* gains;                   // [row][35][S] (k, K row-major 7x4)
+  float* dz;                      // [row][7][S]
+  uint8_t* code;                  // [row][S]
+  const int64_t* Bdev;            // batch size read from device memory (graph capture), or null
+  int inst_stride;                // 1: x0/goal/inst per sequence, 0: one instance for all
+  double* cost64;                 // optional double-precision cost / violation outputs
+  double* viol64;
+  unsigned long long* t_first;    // optional: earliest wall-clock tick of a feasible finish
+  const int* order;               // queue order of the sequences (null = identity)
+  unsigned long long* qhead;      // work-queue head
+  unsigned* err;
+  DevParams prm;
+  double inv_scale[NTYPES];
+};
+
+// One evaluation launch: inputs, outputs and where the batch size lives.
+struct EvalLaunch {
+  int64_t B = 0;                   // host batch size (ignored if B_dev is set)
+  const int64_t* B_dev = nullptr;  // device batch size (for captured graphs)
+  int64_t B_max = 0;               // upper bound of the batch size (grid sizing)
+  const float *x0 = nullptr, *goal = nullptr, *inst = nullptr;
+  int inst_stride = 1;
+  const int32_t *nseg = nullptr, *modes = nullptr, *knots = nullptr;
+  const float* warm = nullptr;
+  int refine = 0;
+  float *cost = nullptr, *viol = nullptr;
+  uint8_t* feas = nullptr;
+  float* traj = nullptr;
+  int32_t* stats = nullptr;
+  double *cost64 = nullptr, *viol64 = nullptr;
+  unsigned long long* t_first = nullptr;
+};
+
+}  // namespace comet
+
+struct comet_expand_ws;  // expansion work space (expand.hip)
+
+struct comet_ctx {
+  int task;
+  comet_solver_params prm;
+  int64_t max_batch, S;
+  int max_segments, max_intervals;
+  int device;
+  double scale[comet::push::NTYPES];
+  double* zd = nullptr;
+  float* lam = nullptr;
+  float* nu = nullptr;
+  float* gains = nullptr;
+  float* dz = nullptr;
+  uint8_t* code = nullptr;
+  unsigned* err = nullptr;
+  unsigned long long* qhead = nullptr;
+  int* hist = nullptr;
+  int* order = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+  int n_cu = 0, occ_blocks_per_cu = 1;
+  comet_schedule sched{0, 0};
+  hipStream_t gstream = nullptr;   // internal stream for captured graphs
+  comet_expand_ws* xws = nullptr;
+  std::string msg;
+};
+
+
+namespace comet {
+comet_status launch_evaluate(comet_ctx* c, hipStream_t s, const EvalLaunch& L);
+comet_status fail_msg(comet_ctx* c, comet_status st, const std::string& m);
+void destroy_expand_ws(comet_ctx* c);
+}  // namespace comet

@@ -31,6 +31,36 @@ class ScheduleC(C.Structure):
     _fields_ = [("waves_per_cu", C.c_int32), ("sort_by_length", C.c_int32)]
 
 
+class ExpandParamsC(C.Structure):
+    _fields_ = [("kcap", C.c_int32), ("seed_max_segments", C.c_int32), ("radius", C.c_int32), ("rounds", C.c_int32),
+                ("frontier_W", C.c_int32), ("knots_per_segment", C.c_int32), ("k_ref", C.c_int32),
+                ("n_total", C.c_int32), ("batch_B", C.c_int64), ("eval_budget", C.c_int64), ("mu_merit", C.c_double)]
+
+
+class ExpandStatsC(C.Structure):
+    _fields_ = [("evaluated", C.c_int64), ("rounds_done", C.c_int32), ("n_feasible", C.c_int32),
+                ("first_feasible_index", C.c_int64), ("t_first_feasible_ms", C.c_double),
+                ("t_total_ms", C.c_double), ("n_refined", C.c_int32), ("reserved", C.c_int32)]
+
+
+@dataclass
+class ExpandParams:
+    kcap: int = 3
+    seed_max_segments: int = 2
+    radius: int = 1
+    rounds: int = 8
+    frontier_W: int = 4096
+    knots_per_segment: int = 8
+    k_ref: int = 64
+    n_total: int = 24
+    batch_B: int = 131072
+    eval_budget: int = 200000
+    mu_merit: float = 100.0
+
+    def c(self) -> ExpandParamsC:
+        return ExpandParamsC(*[getattr(self, f.name) for f in fields(self)])
+
+
 class CometError(RuntimeError):
     pass
 
@@ -69,6 +99,13 @@ def lib():
         L.comet_get_schedule.restype = C.c_int
         L.comet_autotune.argtypes = [P, P, C.c_int64] + [P] * 11 + [C.POINTER(ScheduleC), C.POINTER(C.c_float)]
         L.comet_autotune.restype = C.c_int
+        L.comet_expand.argtypes = [P, P, P, P, P, C.POINTER(ExpandParamsC), P, P, P, P, P, P, P,
+                                   C.POINTER(ExpandStatsC)]
+        L.comet_expand.restype = C.c_int
+        L.comet_expand_next.argtypes = [P, P, C.c_int64, P, P, C.POINTER(ExpandParamsC), C.c_int64, P, P]
+        L.comet_expand_next.restype = C.c_int
+        L.comet_expand_trace.argtypes = [P, P, C.c_int64, P, P, P, P]
+        L.comet_expand_trace.restype = C.c_int
         L.comet_last_kernel_ms.argtypes = [P, C.POINTER(C.c_float)]
         L.comet_last_kernel_ms.restype = C.c_int
         _lib = L
@@ -215,6 +252,48 @@ class Context:
                                   _ptr(feasible), _ptr(traj), _ptr(stats))
         check(rc, self._h)
         return dict(cost=cost, viol=viol, feasible=feasible, traj=traj, stats=stats)
+
+
+def expand(ctx: "Context", x0, goal, inst, params: ExpandParams, learned=None, stream=None):
+    """Greedy expansion on one instance (device tensors x0 [4], goal [3], inst [1])."""
+    import torch
+    dev = x0.device
+    S, N = ctx.max_segments, ctx.max_intervals
+    o = dict(nseg=torch.zeros(1, dtype=torch.int32, device=dev), modes=torch.zeros(S, dtype=torch.int32, device=dev),
+             knots=torch.zeros(S, dtype=torch.int32, device=dev), cost=torch.zeros(1, device=dev),
+             viol=torch.zeros(1, device=dev), traj=torch.zeros((N + 1, 7), device=dev))
+    st = ExpandStatsC()
+    pc = params.c()
+    rc = lib().comet_expand(ctx._h, _stream(stream), _ptr(x0), _ptr(goal), _ptr(inst), C.byref(pc),
+                            None if learned is None else learned.handle(), _ptr(o["nseg"]), _ptr(o["modes"]),
+                            _ptr(o["knots"]), _ptr(o["cost"]), _ptr(o["viol"]), _ptr(o["traj"]), C.byref(st))
+    check(rc, ctx._h)
+    stats = {f: getattr(st, f) for f, _ in ExpandStatsC._fields_}
+    return o, stats
+
+
+def expand_next(ctx: "Context", keys, merit, params: ExpandParams, room: int, stream=None):
+    """One batch-construction step on device tensors keys (uint64 as int64) and merit (float64)."""
+    import torch
+    dev = merit.device
+    out = torch.zeros(max(int(room), 1), dtype=torch.int64, device=dev)
+    n = torch.zeros(1, dtype=torch.int64, device=dev)
+    pc = params.c()
+    rc = lib().comet_expand_next(ctx._h, _stream(stream), int(keys.shape[0]), _ptr(keys), _ptr(merit), C.byref(pc),
+                                 int(room), _ptr(out), _ptr(n))
+    check(rc, ctx._h)
+    return out[: int(n.item())]
+
+
+def expand_trace(ctx: "Context", cap: int = 1 << 20, stream=None):
+    import torch
+    keys = torch.zeros(cap, dtype=torch.int64, device="cuda")
+    J = torch.zeros(cap, dtype=torch.float64, device="cuda")
+    v = torch.zeros(cap, dtype=torch.float64, device="cuda")
+    n = torch.zeros(1, dtype=torch.int64, device="cuda")
+    check(lib().comet_expand_trace(ctx._h, _stream(stream), cap, _ptr(keys), _ptr(J), _ptr(v), _ptr(n)), ctx._h)
+    k = int(n.item())
+    return keys[:k], J[:k], v[:k]
 
 
 def to_device(batch: dict, device="cuda"):
