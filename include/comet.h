@@ -216,6 +216,53 @@ comet_status comet_expand_next(comet_ctx* ctx, void* stream, int64_t n, const ui
 comet_status comet_expand_trace(comet_ctx* ctx, void* stream, int64_t cap, uint64_t* keys, double* J, double* v,
                                 int64_t* n_out);
 
+/* ---------------------------------------------------------------------------------
+ * Learned proposal / warm-start network (BF16 matrix-core kernels, FP32 accumulation).
+ * in_dim -> `layers` hidden layers of width `hidden` (exact-erf GELU) -> out_dim.  Output
+ * row: [0] feasibility logit, [1] predicted log(1 + J), [2 .. 2 + 720) warm start: for
+ * each of 6 segment slots, 15 samples at normalised times i/14 of 8 channels (the 7
+ * trajectory channels (x, y, theta, s, F_n, F_t, v_s) and a zero channel).  Flat parameter
+ * layout: for each linear layer in order, W [out][in] row-major then b [out] (FP32).
+ * Initialisation: W ~ U(-1/sqrt(in), 1/sqrt(in)) from a counter-based hash of (seed, index),
+ * b = 0.  Training: AdamW (beta 0.9 / 0.999, eps 1e-8) on FP32 masters; GEMM operands
+ * (weights, inputs, activations, back-propagated gradients) are rounded to BF16. */
+comet_status comet_mlp_create(int32_t in_dim, int32_t hidden, int32_t layers, int32_t out_dim, int64_t max_batch,
+                              uint64_t seed, comet_mlp** out);
+void comet_mlp_destroy(comet_mlp* mlp);
+comet_status comet_mlp_num_params(const comet_mlp* mlp, int64_t* n);
+/* get (set = 0) or set (set = 1) the FP32 master parameters from / to a device buffer of
+ * num_params floats; setting also resets the optimiser state.  Asynchronous on `stream`. */
+comet_status comet_mlp_params(comet_mlp* mlp, void* stream, int32_t set, float* flat);
+/* gradients of the last train step (device buffer of num_params floats) */
+comet_status comet_mlp_grads(comet_mlp* mlp, void* stream, float* flat);
+/* out [B, out_dim] = network(x [B, in_dim] BF16 bits), B <= max_batch */
+comet_status comet_mlp_forward(comet_mlp* mlp, void* stream, int64_t B, const uint16_t* x_bf16, float* out);
+/* One AdamW step on a batch: y_feas [B] in {0,1}, y_cost [B] (log(1+J), used where feasible),
+ * y_traj / traj_mask [B, 720] (outputs beyond 2 + 720 get no gradient).  out_dim >= 722.
+ * loss (device, 3 floats, may be NULL): mean BCE,
+ * cost MSE over feasible samples, warm-start MSE over the mask, before the step. */
+comet_status comet_mlp_train_step(comet_mlp* mlp, void* stream, int64_t B, const uint16_t* x_bf16,
+                                  const float* y_feas, const float* y_cost, const float* y_traj,
+                                  const float* traj_mask, float lr, float weight_decay, float* loss);
+/* Input encoding of planar-pushing orders (same arguments as comet_evaluate, Smax = smax)
+ * into in_dim (>= 400) BF16 values per order: pose block (start and goal x, y, cos, sin,
+ * goal - start, friction) then 6 segment slots of 64 (one-hot id, intervals / 15, present). */
+comet_status comet_mlp_encode(comet_task task, void* stream, int64_t B, const float* x0, const float* goal,
+                              const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
+                              int32_t smax, int32_t in_dim, uint16_t* x_bf16);
+/* Training targets from evaluator results (traj [B, nmax+1, 7], feasible, cost):
+ * y_feas, y_cost = log(1 + J) (0 if infeasible), y_traj [B, 720] per-segment samples at
+ * normalised times i/14 (linear interpolation of the rows), traj_mask [B, 720] = 1 on the
+ * 7 trajectory channels of present segments of feasible orders. */
+comet_status comet_mlp_targets(void* stream, int64_t B, const float* traj, int32_t nmax, const int32_t* nseg,
+                               const int32_t* knots, int32_t smax, const uint8_t* feasible, const float* cost,
+                               float* y_feas, float* y_cost, float* y_traj, float* traj_mask);
+/* Warm-start trajectories [B, nmax+1, 7] (comet_evaluate's warm layout) from network
+ * outputs [B, out_dim]: each segment's samples interpolated to its intervals; row 0 takes
+ * x0 (one start per order), the last row's controls are zero. */
+comet_status comet_mlp_decode_warm(void* stream, int64_t B, const float* out, int32_t out_dim, const float* x0,
+                                   const int32_t* nseg, const int32_t* knots, int32_t smax, int32_t nmax, float* warm);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,187 @@
+"""NumPy FP64 oracle of the learned proposal / warm-start network.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Written from the network's
+definition: in_dim -> `layers` hidden layers (exact-erf GELU) -> out_dim; heads
+[0] feasibility logit, [1] log(1 + J), [2:] warm start (6 segments x 15 samples x 8
+channels); loss = mean BCE + MSE of the cost head over feasible samples + MSE of the warm
+start over its mask; AdamW.
+
+With quantize=True the tensors that the matrix-core kernels take as BF16 operands are
+rounded to BF16 (round to nearest even) at the same places -- inputs, weights, hidden
+activations, back-propagated gradients -- and everything else is FP64.  With
+quantize=False the network is plain FP64 (used by the finite-difference and autograd pins).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+WS_SLOTS, WS_CH, N_SEG = 15, 8, 6
+POSE_DIMS, SEG_SLOT, N_MODES = 16, 64, 12
+
+
+def bf16_round(x) -> np.ndarray:
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    f = np.atleast_1d(np.asarray(x, np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    nan = np.isnan(f)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    u = (u << 16).astype(np.uint32)
+    out = u.view(np.float32).astype(np.float64)
+    out[nan] = np.nan
+    return out.reshape(np.shape(x)) if np.ndim(x) else out[0]
+
+
+def bf16_bits(x) -> np.ndarray:
+    f = np.asarray(bf16_round(x), np.float32)
+    return (f.view(np.uint32) >> 16).astype(np.uint16)
+
+
+def _erf(x):
+    return np.vectorize(math.erf, otypes=[float])(x)
+
+
+def gelu(z):
+    return 0.5 * z * (1.0 + _erf(z / math.sqrt(2.0)))
+
+
+def gelu_grad(z):
+    return 0.5 * (1.0 + _erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+
+
+class Net:
+    def __init__(self, in_dim, hidden, layers, out_dim):
+        self.dims = [in_dim] + [hidden] * layers + [out_dim]
+        self.nl = layers + 1
+        self.shapes = [(self.dims[l + 1], self.dims[l]) for l in range(self.nl)]
+        self.n_params = sum(n * k + n for n, k in self.shapes)
+
+    def unpack(self, flat):
+        out, o = [], 0
+        for n, k in self.shapes:
+            W = flat[o:o + n * k].reshape(n, k)
+            o += n * k
+            b = flat[o:o + n]
+            o += n
+            out.append((W, b))
+        return out
+
+    def pack(self, parts):
+        return np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in parts])
+
+    def init(self, seed):
+        rng = np.random.default_rng(seed)
+        parts = [(rng.uniform(-1, 1, (n, k)) / math.sqrt(k), np.zeros(n)) for n, k in self.shapes]
+        return self.pack(parts)
+
+    def forward(self, flat, X, quantize=True):
+        q = bf16_round if quantize else (lambda a: np.asarray(a, np.float64))
+        H = [q(X)]
+        Z = []
+        P = self.unpack(flat)
+        for l, (W, b) in enumerate(P):
+            z = H[-1] @ q(W).T + b
+            if l < self.nl - 1:
+                Z.append(z)
+                H.append(q(gelu(z)))
+            else:
+                Y = z
+        return Y, (H, Z)
+
+    def loss_grad(self, Y, y_feas, y_cost, y_traj, mask):
+        """Losses (3,) and dL/dY of the combined objective."""
+        B = Y.shape[0]
+        x = Y[:, 0]
+        bce = np.maximum(x, 0) - x * y_feas + np.log1p(np.exp(-np.abs(x)))
+        nf = max(y_feas.sum(), 1.0)
+        nm = max(mask.sum(), 1.0)
+        dc = Y[:, 1] - y_cost
+        dw = Y[:, 2:2 + mask.shape[1]] - y_traj
+        losses = np.array([bce.mean(), (y_feas * dc * dc).sum() / nf, (mask * dw * dw).sum() / nm])
+        dY = np.zeros_like(Y)
+        dY[:, 0] = (1.0 / (1.0 + np.exp(-x)) - y_feas) / B
+        dY[:, 1] = 2.0 * y_feas * dc / nf
+        dY[:, 2:2 + mask.shape[1]] = 2.0 * mask * dw / nm
+        return losses, dY
+
+    def backward(self, flat, cache, dY, quantize=True):
+        q = bf16_round if quantize else (lambda a: np.asarray(a, np.float64))
+        H, Z = cache
+        P = self.unpack(flat)
+        grads = [None] * self.nl
+        g32 = dY
+        g = q(dY)
+        for l in range(self.nl - 1, -1, -1):
+            W, _ = P[l]
+            dW = g.T @ H[l]
+            db = g32.sum(0)
+            grads[l] = (dW, db)
+            if l > 0:
+                dX = g @ q(W)
+                dz = dX * gelu_grad(Z[l - 1])
+                g32 = dz
+                g = q(dz)
+        return self.pack(grads)
+
+    @staticmethod
+    def adamw(flat, grad, m, v, step, lr, wd, b1=0.9, b2=0.999, eps=1e-8):
+        m = b1 * m + (1 - b1) * grad
+        v = b2 * v + (1 - b2) * grad * grad
+        mh = m / (1 - b1 ** step)
+        vh = v / (1 - b2 ** step)
+        return flat - lr * (mh / (np.sqrt(vh) + eps) + wd * flat), m, v
+
+
+def encode_push(x0, goal, inst, nseg, modes, knots, in_dim=416):
+    """Input encoding of planar-pushing orders, computed in float32 then rounded to BF16."""
+    B = len(nseg)
+    X = np.zeros((B, in_dim), np.float32)
+    x0 = np.asarray(x0, np.float32)
+    goal = np.asarray(goal, np.float32)
+    inst = np.asarray(inst, np.float32).reshape(B, -1)
+    X[:, 0] = x0[:, 0]
+    X[:, 1] = x0[:, 1]
+    X[:, 2] = np.cos(x0[:, 2])
+    X[:, 3] = np.sin(x0[:, 2])
+    X[:, 4] = goal[:, 0]
+    X[:, 5] = goal[:, 1]
+    X[:, 6] = np.cos(goal[:, 2])
+    X[:, 7] = np.sin(goal[:, 2])
+    X[:, 8] = goal[:, 0] - x0[:, 0]
+    X[:, 9] = goal[:, 1] - x0[:, 1]
+    X[:, 10] = goal[:, 2] - x0[:, 2]
+    X[:, 11] = inst[:, 0]
+    for b in range(B):
+        for j in range(int(nseg[b])):
+            base = POSE_DIMS + SEG_SLOT * j
+            X[b, base + int(modes[b, j])] = 1.0
+            X[b, base + N_MODES] = np.float32(knots[b, j]) / np.float32(15.0)
+            X[b, base + N_MODES + 1] = 1.0
+    return X
+
+
+def targets(traj, nseg, knots, feas, cost):
+    """Warm-start targets: per segment, 15 samples at normalised times i/14 by linear
+    interpolation between trajectory rows; mask on present segments of feasible orders."""
+    B = len(nseg)
+    y_traj = np.zeros((B, N_SEG * WS_SLOTS * WS_CH))
+    mask = np.zeros_like(y_traj)
+    for b in range(B):
+        k0 = 0
+        for j in range(int(nseg[b])):
+            nj = int(knots[b, j])
+            for i in range(WS_SLOTS):
+                p = i / (WS_SLOTS - 1) * nj
+                k = min(int(math.floor(p)), max(nj - 1, 0))
+                fr = p - k
+                for c in range(7):
+                    a0 = traj[b, k0 + k, c]
+                    a1 = traj[b, k0 + min(k + 1, nj), c]
+                    e = (j * WS_SLOTS + i) * WS_CH + c
+                    y_traj[b, e] = a0 + fr * (a1 - a0)
+                    mask[b, e] = 1.0 if feas[b] else 0.0
+            k0 += nj
+    y_feas = np.asarray(feas, np.float64)
+    y_cost = np.where(feas, np.log1p(np.maximum(cost, 0.0)), 0.0)
+    return y_feas, y_cost, y_traj, mask

@@ -106,6 +106,26 @@ def lib():
         L.comet_expand_next.restype = C.c_int
         L.comet_expand_trace.argtypes = [P, P, C.c_int64, P, P, P, P]
         L.comet_expand_trace.restype = C.c_int
+        L.comet_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_uint64, C.POINTER(P)]
+        L.comet_mlp_create.restype = C.c_int
+        L.comet_mlp_destroy.argtypes = [P]
+        L.comet_mlp_destroy.restype = None
+        L.comet_mlp_num_params.argtypes = [P, C.POINTER(C.c_int64)]
+        L.comet_mlp_num_params.restype = C.c_int
+        L.comet_mlp_params.argtypes = [P, P, C.c_int32, P]
+        L.comet_mlp_params.restype = C.c_int
+        L.comet_mlp_grads.argtypes = [P, P, P]
+        L.comet_mlp_grads.restype = C.c_int
+        L.comet_mlp_forward.argtypes = [P, P, C.c_int64, P, P]
+        L.comet_mlp_forward.restype = C.c_int
+        L.comet_mlp_train_step.argtypes = [P, P, C.c_int64, P, P, P, P, P, C.c_float, C.c_float, P]
+        L.comet_mlp_train_step.restype = C.c_int
+        L.comet_mlp_encode.argtypes = [C.c_int, P, C.c_int64, P, P, P, P, P, P, C.c_int32, C.c_int32, P]
+        L.comet_mlp_encode.restype = C.c_int
+        L.comet_mlp_targets.argtypes = [P, C.c_int64, P, C.c_int32, P, P, C.c_int32, P, P, P, P, P, P]
+        L.comet_mlp_targets.restype = C.c_int
+        L.comet_mlp_decode_warm.argtypes = [P, C.c_int64, P, C.c_int32, P, P, P, C.c_int32, C.c_int32, P]
+        L.comet_mlp_decode_warm.restype = C.c_int
         L.comet_last_kernel_ms.argtypes = [P, C.POINTER(C.c_float)]
         L.comet_last_kernel_ms.restype = C.c_int
         _lib = L
@@ -294,6 +314,97 @@ def expand_trace(ctx: "Context", cap: int = 1 << 20, stream=None):
     check(lib().comet_expand_trace(ctx._h, _stream(stream), cap, _ptr(keys), _ptr(J), _ptr(v), _ptr(n)), ctx._h)
     k = int(n.item())
     return keys[:k], J[:k], v[:k]
+
+
+class MLP:
+    """Learned proposal / warm-start network (BF16 matrix-core kernels)."""
+    IN, HIDDEN, LAYERS, OUT = 416, 512, 4, 736
+
+    def __init__(self, max_batch=8192, seed=0, in_dim=IN, hidden=HIDDEN, layers=LAYERS, out_dim=OUT):
+        self._h = C.c_void_p()
+        rc = lib().comet_mlp_create(in_dim, hidden, layers, out_dim, int(max_batch), int(seed), C.byref(self._h))
+        if rc != COMET_OK:
+            raise CometError(f"comet_mlp_create failed with status {rc}")
+        self.in_dim, self.hidden, self.layers, self.out_dim, self.max_batch = in_dim, hidden, layers, out_dim, max_batch
+        n = C.c_int64()
+        check(lib().comet_mlp_num_params(self._h, C.byref(n)))
+        self.n_params = n.value
+
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().comet_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        import torch
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        check(lib().comet_mlp_params(self._h, _stream(), 0, _ptr(out)))
+        return out
+
+    def set_params(self, flat):
+        check(lib().comet_mlp_params(self._h, _stream(), 1, _ptr(flat)))
+
+    def grads(self):
+        import torch
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        check(lib().comet_mlp_grads(self._h, _stream(), _ptr(out)))
+        return out
+
+    def forward(self, x_bf16):
+        import torch
+        B = int(x_bf16.shape[0])
+        out = torch.empty((B, self.out_dim), dtype=torch.float32, device="cuda")
+        check(lib().comet_mlp_forward(self._h, _stream(), B, _ptr(x_bf16), _ptr(out)))
+        return out
+
+    def train_step(self, x_bf16, y_feas, y_cost, y_traj, mask, lr, weight_decay=1e-4):
+        import torch
+        loss = torch.zeros(3, dtype=torch.float32, device="cuda")
+        check(lib().comet_mlp_train_step(self._h, _stream(), int(x_bf16.shape[0]), _ptr(x_bf16), _ptr(y_feas),
+                                         _ptr(y_cost), _ptr(y_traj), _ptr(mask), float(lr), float(weight_decay),
+                                         _ptr(loss)))
+        return loss
+
+
+def mlp_encode(d: dict, in_dim=416):
+    """Encode device batches (as from to_device) for the network: [B, in_dim] BF16 bits."""
+    import torch
+    B = int(d["nseg"].shape[0])
+    smax = int(d["modes"].shape[1])
+    x = torch.empty((B, in_dim), dtype=torch.int16, device="cuda")
+    check(lib().comet_mlp_encode(TASK_PUSH, _stream(), B, _ptr(d["x0"]), _ptr(d["goal"]), _ptr(d["inst"]),
+                                 _ptr(d["nseg"]), _ptr(d["modes"]), _ptr(d["knots"]), smax, in_dim, _ptr(x)))
+    return x
+
+
+def mlp_targets(d: dict, out: dict, nmax: int):
+    import torch
+    B = int(d["nseg"].shape[0])
+    smax = int(d["modes"].shape[1])
+    f = lambda *s: torch.empty(s, dtype=torch.float32, device="cuda")
+    yf, yc, yt, m = f(B), f(B), f(B, 720), f(B, 720)
+    check(lib().comet_mlp_targets(_stream(), B, _ptr(out["traj"]), nmax, _ptr(d["nseg"]), _ptr(d["knots"]), smax,
+                                  _ptr(out["feasible"]), _ptr(out["cost"]), _ptr(yf), _ptr(yc), _ptr(yt), _ptr(m)))
+    return yf, yc, yt, m
+
+
+def mlp_decode_warm(y, d: dict, nmax: int):
+    import torch
+    B = int(d["nseg"].shape[0])
+    smax = int(d["modes"].shape[1])
+    w = torch.empty((B, nmax + 1, 7), dtype=torch.float32, device="cuda")
+    check(lib().comet_mlp_decode_warm(_stream(), B, _ptr(y), int(y.shape[1]), _ptr(d["x0"]), _ptr(d["nseg"]),
+                                      _ptr(d["knots"]), smax, nmax, _ptr(w)))
+    return w
 
 
 def to_device(batch: dict, device="cuda"):
