@@ -173,6 +173,8 @@ comet_status comet_last_kernel_ms(comet_ctx* ctx, float* ms);
  * returns the smallest refined J among refined-feasible orders (ties by key). */
 typedef struct {
   int32_t kcap, seed_max_segments, radius, rounds, frontier_W, knots_per_segment, k_ref, n_total;
+  int32_t learned_warm;   /* with a learned network: 1 = also seed initial trajectories, 0 = order only */
+  int32_t reserved;
   int64_t batch_B, eval_budget;
   double mu_merit;
 } comet_expand_params;

@@ -900,7 +900,7 @@ comet_status launch_evaluate(comet_ctx* c, hipStream_t s, const EvalLaunch& L) {
   A.cost64 = L.cost64; A.viol64 = L.viol64; A.t_first = L.t_first;
   A.zd = c->zd; A.lam = c->lam; A.nu = c->nu; A.gains = c->gains; A.dz = c->dz; A.code = c->code; A.err = c->err;
   A.qhead = c->qhead;
-  A.order = c->sched.sort_by_length ? c->order : nullptr;
+  A.order = (c->sched.sort_by_length && !L.no_sort) ? c->order : nullptr;
   const comet_solver_params& p = c->prm;
   A.prm.al_max = L.refine ? p.ref_al_max : p.al_max;
   A.prm.gn_max = L.refine ? p.ref_gn_max : p.gn_max;

@@ -475,6 +475,54 @@ __global__ void k_pick_best(ExpCfg g, ExpCounters* C, const unsigned long long* 
   C->best_row = row;
 }
 
+// learned ordering: predicted merit expm1(cost head) + mu (1 - sigmoid(logit)), ties by key
+__global__ void k_learned_keys(ExpCfg g, const ExpCounters* C, const float* Y, int O, const unsigned long long* F,
+                               unsigned long long* hi, unsigned long long* lo, unsigned* idx) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= C->nF) return;
+  const double p = 1.0 / (1.0 + exp(-(double)Y[i * O + 0]));
+  const double m = expm1(fmin((double)Y[i * O + 1], 50.0)) + g.mu_merit * (1.0 - p);
+  hi[i] = order_bits(m);
+  lo[i] = F[i];
+  idx[i] = (unsigned)i;
+}
+
+// gather the batch into queue order: tmp arrays, then back
+__global__ void k_gather_batch(const ExpCounters* C, const unsigned* perm, const unsigned long long* F,
+                               const int32_t* nseg, const int32_t* modes, const int32_t* knots, int smax,
+                               unsigned long long* F2, int32_t* nseg2, int32_t* modes2, int32_t* knots2) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= C->nF) return;
+  const long long i = perm[r];
+  F2[r] = F[i];
+  nseg2[r] = nseg[i];
+  for (int j = 0; j < smax; ++j) {
+    modes2[r * smax + j] = modes[i * smax + j];
+    knots2[r * smax + j] = knots[i * smax + j];
+  }
+}
+
+__global__ void k_copy_batch(const ExpCounters* C, const unsigned long long* F2, const int32_t* nseg2,
+                             const int32_t* modes2, const int32_t* knots2, int smax, unsigned long long* F, int32_t* nseg,
+                             int32_t* modes, int32_t* knots) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= C->nF) return;
+  F[r] = F2[r];
+  nseg[r] = nseg2[r];
+  for (int j = 0; j < smax; ++j) {
+    modes[r * smax + j] = modes2[r * smax + j];
+    knots[r * smax + j] = knots2[r * smax + j];
+  }
+}
+
+__global__ void k_gather_warm(const ExpCounters* C, const unsigned* perm, const float* src, long long row,
+                              float* dst) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long r = t / row, c = t % row;
+  if (r >= C->nF) return;
+  dst[t] = src[(long long)perm[r] * row + c];
+}
+
 __global__ void k_best_out(ExpCfg g, const ExpCounters* C, const float* rtraj, int nmax1, int32_t* best_nseg,
                            int32_t* best_modes, int32_t* best_knots, float* best_cost, float* best_viol,
                            float* best_traj, int smax) {
@@ -528,6 +576,10 @@ struct comet_expand_ws {
   int32_t *o_nseg = nullptr, *o_modes = nullptr, *o_knots = nullptr;
   float *o_cost = nullptr, *o_viol = nullptr, *o_traj = nullptr;
   long long* dev_nV = nullptr;     // scratch scalars for expand_next
+  unsigned long long* F2 = nullptr;  // learned mode: batch in predicted-merit order
+  int32_t *fnseg2 = nullptr, *fmodes2 = nullptr, *fknots2 = nullptr;
+  float *warm_tmp = nullptr, *warm = nullptr;
+  comet_mlp* learned = nullptr;      // network the captured graph uses (null = plain)
   hipGraphExec_t gexec = nullptr;
   bool graph_valid = false;
   double wall_khz = 100000.0;
@@ -543,7 +595,8 @@ void destroy_expand_ws(comet_ctx* c) {
                   w->s_idx[0], w->s_idx[1], w->rs_counts, w->ckey, w->hkeys, w->hmin, w->cflag, w->cpos,
                   w->scan.tiles, w->F, w->fnseg, w->fmodes, w->fknots, w->ecost, w->eviol, w->rtraj, w->efeas,
                   w->ecost64, w->eviol64, w->ix0, w->igoal, w->iinst, w->o_nseg, w->o_modes, w->o_knots,
-                  w->o_cost, w->o_viol, w->o_traj, w->dev_nV};
+                  w->o_cost, w->o_viol, w->o_traj, w->dev_nV, w->F2, w->fnseg2, w->fmodes2, w->fknots2,
+                  w->warm_tmp, w->warm};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete w;
@@ -669,6 +722,12 @@ comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
   A((void**)&w->o_viol, 4);
   A((void**)&w->o_traj, 4 * nmax1 * 7);
   A((void**)&w->dev_nV, 8 * 4);
+  A((void**)&w->F2, 8 * BR);
+  A((void**)&w->fnseg2, 4 * BR);
+  A((void**)&w->fmodes2, 4 * BR * c->max_segments);
+  A((void**)&w->fknots2, 4 * BR * c->max_segments);
+  A((void**)&w->warm_tmp, 4 * BR * nmax1 * 7);
+  A((void**)&w->warm, 4 * BR * nmax1 * 7);
   if (!ok) {
     (void)hipGetLastError();
     destroy_expand_ws(c);
@@ -680,13 +739,9 @@ comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
   return COMET_OK;
 }
 
-// rank V (first nV entries) into s_idx[result]; returns which buffer holds the order
-int enqueue_rank(comet_ctx* c, hipStream_t s, int refine) {
+// stable sort of s_*[0] (first *n entries) by (hi, lo); returns the buffer holding the result
+int enqueue_sort(comet_ctx* c, hipStream_t s, const long long* nV) {
   comet_expand_ws* w = c->xws;
-  const ExpCfg& g = w->cfg;
-  const long long* nV = &w->C->nV;
-  hipLaunchKernelGGL(k_rank_keys, dim3(blocks(g.Vcap, 256)), dim3(256), 0, s, g, w->C, refine, w->vkey, w->vJ, w->vv,
-                     w->vM, w->s_hi[0], w->s_lo[0], w->s_idx[0]);
   int cur = 0;
   for (int pass = 0; pass < 16; ++pass) {
     hipLaunchKernelGGL(k_rs_count, dim3((unsigned)w->ntiles_rs), dim3(RS_TILE), 0, s, w->s_hi[cur], w->s_lo[cur], nV,
@@ -698,6 +753,15 @@ int enqueue_rank(comet_ctx* c, hipStream_t s, int refine) {
     cur ^= 1;
   }
   return cur;
+}
+
+// rank V (first nV entries) into s_idx[result]; returns which buffer holds the order
+int enqueue_rank(comet_ctx* c, hipStream_t s, int refine) {
+  comet_expand_ws* w = c->xws;
+  const ExpCfg& g = w->cfg;
+  hipLaunchKernelGGL(k_rank_keys, dim3(blocks(g.Vcap, 256)), dim3(256), 0, s, g, w->C, refine, w->vkey, w->vJ, w->vv,
+                     w->vM, w->s_hi[0], w->s_lo[0], w->s_idx[0]);
+  return enqueue_sort(c, s, &w->C->nV);
 }
 
 // next batch from the ranked V: generate, first occurrences, compact (sets C->nF)
@@ -721,11 +785,32 @@ void enqueue_next_batch(comet_ctx* c, hipStream_t s) {
 }
 
 comet_status enqueue_evaluate_batch(comet_ctx* c, hipStream_t s, const long long* n_dev, long long nmax, int refine,
-                                    float* traj, unsigned long long* t_first) {
+                                    float* traj, unsigned long long* t_first, comet_mlp* learned) {
   comet_expand_ws* w = c->xws;
   hipLaunchKernelGGL(k_build, dim3(blocks(nmax, 256)), dim3(256), 0, s, w->cfg, n_dev, w->F, w->fnseg, w->fmodes,
                      w->fknots, c->max_segments);
+  const int smax = c->max_segments;
+  const long long row = (long long)(c->max_intervals + 1) * 7;
+  if (learned) {
+    // network scores and warm starts; the batch is evaluated in predicted-merit order
+    mlp_encode_dev(learned, s, nmax, n_dev, w->ix0, w->igoal, w->iinst, 0, w->fnseg, w->fmodes, w->fknots, smax);
+    mlp_forward(learned, s, (int)nmax, n_dev);
+    const int O = mlp_out_dim(learned);
+    hipLaunchKernelGGL(k_learned_keys, dim3(blocks(nmax, 256)), dim3(256), 0, s, w->cfg, w->C, mlp_output(learned), O,
+                       w->F, w->s_hi[0], w->s_lo[0], w->s_idx[0]);
+    const int cur = enqueue_sort(c, s, n_dev);
+    const unsigned* perm = w->s_idx[cur];
+    mlp_decode_warm_dev(learned, s, nmax, n_dev, w->ix0, 0, w->fnseg, w->fknots, smax, c->max_intervals, w->warm_tmp);
+    hipLaunchKernelGGL(k_gather_batch, dim3(blocks(nmax, 256)), dim3(256), 0, s, w->C, perm, w->F, w->fnseg,
+                       w->fmodes, w->fknots, smax, w->F2, w->fnseg2, w->fmodes2, w->fknots2);
+    hipLaunchKernelGGL(k_copy_batch, dim3(blocks(nmax, 256)), dim3(256), 0, s, w->C, w->F2, w->fnseg2, w->fmodes2,
+                       w->fknots2, smax, w->F, w->fnseg, w->fmodes, w->fknots);
+    hipLaunchKernelGGL(k_gather_warm, dim3(blocks(nmax * row, 256)), dim3(256), 0, s, w->C, perm, w->warm_tmp, row,
+                       w->warm);
+  }
   EvalLaunch L;
+  L.warm = (learned && w->prm.learned_warm) ? w->warm : nullptr;
+  L.no_sort = learned != nullptr;
   L.B_dev = (const int64_t*)n_dev;
   L.B_max = nmax;
   L.x0 = w->ix0; L.goal = w->igoal; L.inst = w->iinst; L.inst_stride = 0;
@@ -751,7 +836,7 @@ comet_status enqueue_expand(comet_ctx* c, hipStream_t s) {
   }
   hipLaunchKernelGGL(k_seed, dim3(blocks(n_seed, 256)), dim3(256), 0, s, g, kmax, n_seed, w->C, w->F, w->vset);
   for (int r = 0; r <= p.rounds; ++r) {
-    comet_status st = enqueue_evaluate_batch(c, s, &w->C->nF, g.Bmax, 0, nullptr, &w->C->t_first);
+    comet_status st = enqueue_evaluate_batch(c, s, &w->C->nF, g.Bmax, 0, nullptr, &w->C->t_first, w->learned);
     if (st != COMET_OK) return st;
     hipLaunchKernelGGL(k_append, dim3(blocks(g.Bmax, 256)), dim3(256), 0, s, g, w->C, w->F, w->ecost64, w->eviol64,
                        w->vkey, w->vJ, w->vv, w->vM);
@@ -763,7 +848,7 @@ comet_status enqueue_expand(comet_ctx* c, hipStream_t s) {
     const int cur = enqueue_rank(c, s, 1);
     hipLaunchKernelGGL(k_ref_batch, dim3(blocks(p.k_ref, 256)), dim3(256), 0, s, g, w->C, w->s_idx[cur], w->vkey,
                        w->vJ, w->vv, w->F);
-    comet_status st = enqueue_evaluate_batch(c, s, &w->C->nRef, p.k_ref, 1, w->rtraj, nullptr);
+    comet_status st = enqueue_evaluate_batch(c, s, &w->C->nRef, p.k_ref, 1, w->rtraj, nullptr, nullptr);
     if (st != COMET_OK) return st;
     hipLaunchKernelGGL(k_pick_best, dim3(1), dim3(1), 0, s, g, w->C, w->F, w->ecost64, w->eviol64);
   }
@@ -783,12 +868,17 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
   if (!c) return COMET_EINVAL;
   if (!x0 || !goal || !inst || !best_nseg || !best_modes || !best_knots || !best_cost || !best_viol)
     return fail_msg(c, COMET_EINVAL, "null input or output pointer");
-  if (learned) return fail_msg(c, COMET_EINVAL, "learned proposals are not attached to this context");
   comet_status st = check_expand_params(c, params);
   if (st != COMET_OK) return st;
+  if (learned && (mlp_max_batch(learned) < params->batch_B || mlp_in_dim(learned) < 400 || mlp_out_dim(learned) < 722))
+    return fail_msg(c, COMET_EINVAL, "learned network: max_batch < batch_B, in_dim < 400 or out_dim < 722");
   st = ensure_ws(c, params);
   if (st != COMET_OK) return st;
   comet_expand_ws* w = c->xws;
+  if (w->learned != learned) {
+    w->learned = learned;
+    w->graph_valid = false;
+  }
   hipStream_t us = (hipStream_t)stream;
   if (!c->gstream && hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess)
     return fail_msg(c, COMET_EHIP, "stream creation failed");

@@ -441,6 +441,25 @@ void mlp_forward(comet_mlp* m, hipStream_t s, int B, const long long* B_dev) {
   }
 }
 
+// hooks for the expansion graph (sizes on the device)
+int mlp_in_dim(const comet_mlp* m) { return m->in_dim; }
+int mlp_out_dim(const comet_mlp* m) { return m->out_dim; }
+long long mlp_max_batch(const comet_mlp* m) { return m->max_batch; }
+const float* mlp_output(const comet_mlp* m) { return m->Y; }
+
+void mlp_encode_dev(comet_mlp* m, hipStream_t s, long long Bmax, const long long* B_dev, const float* x0,
+                    const float* goal, const float* inst, int inst_stride, const int32_t* nseg, const int32_t* modes,
+                    const int32_t* knots, int smax) {
+  hipLaunchKernelGGL(k_encode_push, dim3(nblk(Bmax * m->in_dim, 256)), dim3(256), 0, s, (long)Bmax, x0, goal, inst,
+                     inst_stride, nseg, modes, knots, smax, m->in_dim, m->H[0], B_dev);
+}
+
+void mlp_decode_warm_dev(comet_mlp* m, hipStream_t s, long long Bmax, const long long* B_dev, const float* x0,
+                         int inst_stride, const int32_t* nseg, const int32_t* knots, int smax, int nmax, float* warm) {
+  hipLaunchKernelGGL(k_decode_warm, dim3(nblk(Bmax, 128)), dim3(128), 0, s, (long)Bmax, B_dev, m->Y, m->out_dim, x0,
+                     inst_stride, nseg, knots, smax, nmax, warm);
+}
+
 }  // namespace comet
 
 extern "C" {

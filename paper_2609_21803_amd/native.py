@@ -34,7 +34,8 @@ class ScheduleC(C.Structure):
 class ExpandParamsC(C.Structure):
     _fields_ = [("kcap", C.c_int32), ("seed_max_segments", C.c_int32), ("radius", C.c_int32), ("rounds", C.c_int32),
                 ("frontier_W", C.c_int32), ("knots_per_segment", C.c_int32), ("k_ref", C.c_int32),
-                ("n_total", C.c_int32), ("batch_B", C.c_int64), ("eval_budget", C.c_int64), ("mu_merit", C.c_double)]
+                ("n_total", C.c_int32), ("learned_warm", C.c_int32), ("reserved", C.c_int32), ("batch_B", C.c_int64),
+                ("eval_budget", C.c_int64), ("mu_merit", C.c_double)]
 
 
 class ExpandStatsC(C.Structure):
@@ -53,6 +54,8 @@ class ExpandParams:
     knots_per_segment: int = 8
     k_ref: int = 64
     n_total: int = 24
+    learned_warm: int = 1
+    reserved: int = 0
     batch_B: int = 131072
     eval_budget: int = 200000
     mu_merit: float = 100.0
