@@ -85,8 +85,9 @@ struct RowEval {
 
 template <bool JAC>
 __device__ inline void eval_interval(const EvalArgs& A, const double* xk, const double* uk, const double* x1,
-                                     int code, double mu, RowEval& R) {
-  rows<float>(xk, uk, x1, code, mu, R.c, JAC ? R.J : nullptr, R.en);
+                                     int code, double mu, RowEval& R, const double* sc = nullptr) {
+  if (sc) rows_sc<float>(xk, uk, x1, code, mu, sc[0], sc[1], R.c, JAC ? R.J : nullptr, R.en);
+  else rows<float>(xk, uk, x1, code, mu, R.c, JAC ? R.J : nullptr, R.en);
   const bool stick = ((code >> 2) & 3) == 0;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -133,12 +134,53 @@ struct FactorOut {
   bool ok;
 };
 
+// inputs of one interval for the backward sweep: x_k, u_k, multipliers, mode code
+struct StageIn {
+  double xk[NX], uk[NU];
+  float lm[NE], nv[NE];
+  int code;
+};
+
+__device__ inline void load_stage(const Lane& L, int k, StageIn& s) {
+  L.load_x(k, s.xk);
+#pragma unroll
+  for (int i = 0; i < NU; ++i) s.uk[i] = L.z(k, i);
+#pragma unroll
+  for (int r = 0; r < NE; ++r) {
+    s.lm[r] = L.lam(k, r);
+    s.nv[r] = L.nu(k, r);
+  }
+  s.code = L.code(k);
+}
+
+// inputs of one interval for the forward sweep: u_k, x_{k+1}, gains, multipliers, code
+struct FwdIn {
+  double uk[NU], x1[NX];
+  float g[NGAIN];
+  float lm[NE], nv[NE];
+  int code;
+};
+
+__device__ inline void load_fwd(const Lane& L, int k, FwdIn& s) {
+  L.load_w(k, s.uk, s.x1);
+#pragma unroll
+  for (int i = 0; i < NGAIN; ++i) s.g[i] = L.gain(k, i);
+#pragma unroll
+  for (int r = 0; r < NE; ++r) {
+    s.lm[r] = L.lam(k, r);
+    s.nv[r] = L.nu(k, r);
+  }
+  s.code = L.code(k);
+}
+
 // Backward sweep: gradient, merit, Riccati factorisation and gains at the current z.
 // With FACTOR = false it only returns the gradient norm (outer stationarity test),
 // together with the scaled violation and complementarity residual.
 template <bool FACTOR>
-__device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double imu, double rho, const double* lamT,
-                               FactorOut& out, double& vs, double& rc) {
+// With upd set, the first-order multiplier update (lam += c/mu, nu = [nu + c/mu]_+, at the
+// current iterate) is applied row by row before the rows are used.
+__device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double imu, double rho, double* lamT,
+                               bool upd, FactorOut& out, double& vs, double& rc) {
   const EvalArgs& A = *L.A;
   double P[NX][NX], p[NX], gx[NX];
   double xk1[NX];
@@ -163,6 +205,7 @@ __device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double
     }
 #pragma unroll
     for (int r = 0; r < NT; ++r) {
+      if (upd) lamT[r] += cT[r] * imu;
       const double y = lamT[r] + cT[r] * imu;
       out.phi0 += lamT[r] * cT[r] + cT[r] * cT[r] * (0.5 * imu);
       p[r] = y * sT[r];
@@ -173,20 +216,50 @@ __device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double
 #pragma unroll
     for (int i = 0; i < NX; ++i) xk1[i] = xN[i];
   }
+  // software pipelining: the loads of stage k-1 are issued before stage k is computed;
+  // x_{k+1} of a stage is the x_k of the stage after it
+  StageIn nxt;
+  double x1c[NX];
+  if (on) {
+    load_stage(L, L.N - 1, nxt);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) x1c[i] = xk1[i];
+  }
   for (int t = 0; t < Nw; ++t) {
     const int k = L.N - 1 - t;
     if (!on || k < 0) continue;
+    const StageIn cur = nxt;
+    if (k >= 1) load_stage(L, k - 1, nxt);
     double xk[NX], uk[NU], x1[NX];
-    L.load_x(k, xk);
-    L.load_w(k, uk, x1);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      xk[i] = cur.xk[i];
+      x1[i] = x1c[i];
+      x1c[i] = cur.xk[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NU; ++i) uk[i] = cur.uk[i];
     RowEval R;
-    const int code = L.code(k);
+    const int code = cur.code;
     eval_interval<true>(A, xk, uk, x1, code, L.mu, R);
     float lm[NE], nv[NE];
 #pragma unroll
     for (int r = 0; r < NE; ++r) {
-      lm[r] = L.lam(k, r);
-      nv[r] = L.nu(k, r);
+      lm[r] = cur.lm[r];
+      nv[r] = cur.nv[r];
+    }
+    if (upd) {
+#pragma unroll
+      for (int r = 0; r < NE; ++r) {
+        if (R.en[r]) {
+          lm[r] = float(double(lm[r]) + R.c[r] * imu);
+          L.lam(k, r) = lm[r];
+        }
+        if (R.en[NE + r]) {
+          nv[r] = float(fmax(double(nv[r]) + R.c[NE + r] * imu, 0.0));
+          L.nu(k, r) = nv[r];
+        }
+      }
     }
     // multiplier estimates y and curvature weights w
     double y[NR], w[NR];
@@ -276,10 +349,11 @@ __device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double
 #pragma unroll
       for (int q = 0; q < j; ++q) d -= Sm[j][q] * Sm[j][q];
       ok = ok && (d > 0.0) && isfinite(d);
-      const double lj = sqrt(fmax(d, 1e-300));
-      const double inv = 1.0 / lj;
+      const double dd = fmax(d, 1e-300);
+      double inv = __builtin_amdgcn_rsq(dd);
+      inv = inv * (1.5 - 0.5 * dd * inv * inv);  // one Newton step
       ipiv[j] = inv;
-      Sm[j][j] = lj;
+      Sm[j][j] = dd * inv;
 #pragma unroll
       for (int i = j + 1; i < NW; ++i) {
         double s2 = Sm[i][j];
@@ -355,30 +429,44 @@ __device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, double 
   double xk[NX];
 #pragma unroll
   for (int i = 0; i < MAX_TRIALS; ++i) phi[i] = 0.0;
-  if (on) L.load_x(0, xk);
+  FwdIn nxt;
+  if (on) {
+    L.load_x(0, xk);
+    load_fwd(L, 0, nxt);
+  }
   for (int t = 0; t < Nw; ++t) {
     const int k = t - (Nw - L.N);
     if (!on || k < 0) continue;
+    const FwdIn cur = nxt;
+    if (k + 1 < L.N) load_fwd(L, k + 1, nxt);   // next stage's loads in flight during this stage
     double uk[NU], x1[NX];
-    L.load_w(k, uk, x1);
+#pragma unroll
+    for (int i = 0; i < NU; ++i) uk[i] = cur.uk[i];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) x1[i] = cur.x1[i];
     float dw[NW];
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
-      float s = L.gain(k, i);
+      float s = cur.g[i];
 #pragma unroll
-      for (int j = 0; j < NX; ++j) s += L.gain(k, NW + i * NX + j) * dx[j];
+      for (int j = 0; j < NX; ++j) s += cur.g[NW + i * NX + j] * dx[j];
       dw[i] = s;
       L.dz(k, i) = s;
     }
     float lm[NE], nv[NE];
 #pragma unroll
     for (int r = 0; r < NE; ++r) {
-      lm[r] = L.lam(k, r);
-      nv[r] = L.nu(k, r);
+      lm[r] = cur.lm[r];
+      nv[r] = cur.nv[r];
     }
-    const int code = L.code(k);
-    double alpha = 1.0;
-    for (int i = 0; i < T; ++i) {
+    const int code = cur.code;
+    // sin / cos of theta_k + a_i, a_i = 2^-i dtheta: one sincos of theta_k and of the
+    // smallest a_i, then angle doubling towards a_0 and angle addition
+    double sb, cb, sa, ca;
+    sincos_d(xk[2], &sb, &cb);
+    double alpha = ldexp(1.0, -(T - 1));
+    sincos_d(alpha * double(dx[2]), &sa, &ca);
+    for (int i = T - 1; i >= 0; --i) {
       double xt[NX], ut[NU], x1t[NX];
 #pragma unroll
       for (int q = 0; q < NX; ++q) {
@@ -387,13 +475,17 @@ __device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, double 
       }
 #pragma unroll
       for (int q = 0; q < NU; ++q) ut[q] = uk[q] + alpha * double(dw[q]);
+      const double sc[2] = {sb * ca + cb * sa, cb * ca - sb * sa};
       RowEval R;
-      eval_interval<false>(A, xt, ut, x1t, code, L.mu, R);
+      eval_interval<false>(A, xt, ut, x1t, code, L.mu, R, sc);
       const double contrib = stage_cost(ut) + merit_rows(R, lm, nv, mu, imu);
 #pragma unroll
       for (int q = 0; q < MAX_TRIALS; ++q)
         if (q == i) phi[q] += contrib;
-      alpha *= 0.5;
+      const double s2 = 2.0 * sa * ca, c2 = ca * ca - sa * sa;
+      sa = s2;
+      ca = c2;
+      alpha *= 2.0;
     }
 #pragma unroll
     for (int q = 0; q < NX; ++q) {
@@ -420,38 +512,12 @@ __device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, double 
 }
 
 __device__ void sweep_apply(const Lane& L, int Nw, bool on, double alpha) {
+#pragma unroll 4
   for (int t = 0; t < Nw; ++t) {
     const int k = t - (Nw - L.N);
     if (!on || k < 0) continue;
 #pragma unroll
     for (int i = 0; i < NW; ++i) L.z(k, i) += alpha * double(L.dz(k, i));
-  }
-}
-
-// first-order multiplier update lam += c/mu, nu = [nu + c/mu]_+
-__device__ void sweep_duals(const Lane& L, int Nw, bool on, double imu, double* lamT) {
-  const EvalArgs& A = *L.A;
-  for (int t = 0; t < Nw; ++t) {
-    const int k = t - (Nw - L.N);
-    if (!on || k < 0) continue;
-    double xk[NX], uk[NU], x1[NX];
-    L.load_x(k, xk);
-    L.load_w(k, uk, x1);
-    RowEval R;
-    eval_interval<false>(A, xk, uk, x1, L.code(k), L.mu, R);
-#pragma unroll
-    for (int r = 0; r < NE; ++r)
-      if (R.en[r]) L.lam(k, r) = float(double(L.lam(k, r)) + R.c[r] * imu);
-#pragma unroll
-    for (int r = 0; r < NE; ++r)
-      if (R.en[NE + r]) L.nu(k, r) = float(fmax(double(L.nu(k, r)) + R.c[NE + r] * imu, 0.0));
-  }
-  if (on) {
-    double xN[NX], cT[NT];
-    L.load_x(L.N, xN);
-    eval_terminal(A, xN, L.goal, cT);
-#pragma unroll
-    for (int r = 0; r < NT; ++r) lamT[r] += cT[r] * imu;
   }
 }
 
@@ -587,6 +653,7 @@ __device__ bool load_sequence(Lane& L, int64_t b) {
 struct SolverState {
   double mu, imu, eta, omega, rho, lamT[NT];
   int al, gn_in, gn_tot, rejects, tries, cfails, status;
+  bool upd, outer_pending;   // multiplier update to apply in the next sweep; outer test due next sweep
   __device__ void reset(const DevParams& prm) {
     mu = prm.mu0;
     imu = 1.0 / mu;
@@ -595,6 +662,7 @@ struct SolverState {
     rho = prm.rho0;
     lamT[0] = lamT[1] = lamT[2] = 0.0;
     al = gn_in = gn_tot = rejects = tries = cfails = status = 0;
+    upd = outer_pending = false;
   }
 };
 
@@ -640,14 +708,22 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
     if (!wave_any(active)) break;
     const int Nw = wave_max(active ? L.N : 0);
 
+    // One backward sweep per trip: gradient, merit, factorisation -- and, at the same
+    // iterate, the scaled violation, complementarity and stationarity that the outer test
+    // needs (pending multiplier updates are applied inside the sweep).
     FactorOut fo;
-    double vs_unused, rc_unused;
-    sweep_backward<true>(L, Nw, active, st.mu, st.imu, st.rho, st.lamT, fo, vs_unused, rc_unused);
-    bool step = false, inner_end = false, accepted = false;
+    double vsv, rcv;
+    sweep_backward<true>(L, Nw, active, st.mu, st.imu, st.rho, st.lamT, active && st.upd, fo, vsv, rcv);
+    if (active) st.upd = false;
+    bool step = false, outer_now = false, accepted = false;
     double alpha_acc = 0.0;
     if (active) {
-      if (fo.gnorm <= st.omega) {
-        inner_end = true;
+      if (st.outer_pending) {
+        // the inner loop ended with an accepted step: this sweep saw the new iterate
+        st.outer_pending = false;
+        outer_now = true;
+      } else if (fo.gnorm <= st.omega) {
+        outer_now = true;
       } else if (!fo.ok) {
         ++st.cfails;
         if (st.tries < prm.chol_retries) {
@@ -658,7 +734,7 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
           ++st.gn_in;
           ++st.gn_tot;
           st.rho = fmin(10.0 * st.rho, prm.rho_max);
-          if (++st.rejects >= prm.max_rejects || st.gn_in >= prm.gn_max) inner_end = true;
+          if (++st.rejects >= prm.max_rejects || st.gn_in >= prm.gn_max) outer_now = true;
         }
       } else {
         st.tries = 0;
@@ -668,7 +744,7 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
           step = true;
         } else {
           st.rho = fmin(10.0 * st.rho, prm.rho_max);
-          if (++st.rejects >= prm.max_rejects || st.gn_in >= prm.gn_max) inner_end = true;
+          if (++st.rejects >= prm.max_rejects || st.gn_in >= prm.gn_max) outer_now = true;
         }
       }
     }
@@ -694,49 +770,44 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
           alpha_acc = a_best;
           st.rho = fmax(st.rho / 3.0, prm.rho_min);
           st.rejects = 0;
+          if (st.gn_in >= prm.gn_max) st.outer_pending = true;  // outer test at the new iterate, next trip
         } else {
           st.rho = fmin(10.0 * st.rho, prm.rho_max);
           ++st.rejects;
+          if (st.rejects >= prm.max_rejects || st.gn_in >= prm.gn_max) outer_now = true;  // iterate unchanged
         }
-        if (st.rejects >= prm.max_rejects || st.gn_in >= prm.gn_max) inner_end = true;
       }
     }
     if (wave_any(accepted)) sweep_apply(L, Nw, accepted, alpha_acc);
-    bool upd = false, fin = false;
-    if (wave_any(inner_end)) {
-      FactorOut go;
-      double vsv, rcv;
-      sweep_backward<false>(L, Nw, inner_end, st.mu, st.imu, st.rho, st.lamT, go, vsv, rcv);
-      if (inner_end) {
-        ++st.al;
-        st.gn_in = 0;
-        st.rejects = 0;
-        if (!isfinite(vsv) || !isfinite(go.gnorm)) {
-          st.status = 2;
+    bool fin = false;
+    if (outer_now) {
+      ++st.al;
+      st.gn_in = 0;
+      st.rejects = 0;
+      if (!isfinite(vsv) || !isfinite(fo.gnorm)) {
+        st.status = 2;
+        fin = true;
+      } else if (vsv <= st.eta) {
+        if (vsv <= prm.eta_star && fo.gnorm <= prm.omega_star && rcv <= prm.rc_star) {
+          st.status = 1;
           fin = true;
-        } else if (vsv <= st.eta) {
-          if (vsv <= prm.eta_star && go.gnorm <= prm.omega_star && rcv <= prm.rc_star) {
-            st.status = 1;
-            fin = true;
-          } else {
-            upd = true;
-            st.eta = fmax(st.eta * pow(st.mu, 0.9), prm.eta_star);
-            st.omega = fmax(st.omega * st.mu, prm.omega_star);
-          }
         } else {
-          st.mu = fmax(0.1 * st.mu, prm.mu_min);
-          st.imu = 1.0 / st.mu;
-          st.eta = fmax(pow(st.mu, 0.1), prm.eta_star);
-          st.omega = fmax(st.mu, prm.omega_star);
+          st.upd = true;
+          st.eta = fmax(st.eta * pow(st.mu, 0.9), prm.eta_star);
+          st.omega = fmax(st.omega * st.mu, prm.omega_star);
         }
-        if (!fin && st.al >= prm.al_max) {
-          st.status = 0;
-          fin = true;
-          upd = false;
-        }
+      } else {
+        st.mu = fmax(0.1 * st.mu, prm.mu_min);
+        st.imu = 1.0 / st.mu;
+        st.eta = fmax(pow(st.mu, 0.1), prm.eta_star);
+        st.omega = fmax(st.mu, prm.omega_star);
+      }
+      if (!fin && st.al >= prm.al_max) {
+        st.status = 0;
+        fin = true;
+        st.upd = false;
       }
     }
-    if (wave_any(upd)) sweep_duals(L, Nw, upd, st.imu, st.lamT);
     if (wave_any(fin)) {
       double J, v;
       sweep_score(L, Nw, fin, J, v);

@@ -75,8 +75,22 @@ __host__ __device__ inline void face_dirs(int f, T& nx, T& ny) {
 // divides them by the penalty parameter, so their rounding error sets the floor of the
 // stationarity measure.
 template <typename T>
+__host__ __device__ inline void rows_sc(const double* xk, const double* uk, const double* x1, int code, double mu,
+                                        double st, double ct, double* c, T (*J)[NV], int* en);
+
+// rows() with sin and cos of theta_k computed here
+template <typename T>
 __host__ __device__ inline void rows(const double* xk, const double* uk, const double* x1, int code, double mu,
                                      double* c, T (*J)[NV], int* en) {
+  double st, ct;
+  sincos_d(xk[2], &st, &ct);
+  rows_sc<T>(xk, uk, x1, code, mu, st, ct, c, J, en);
+}
+
+// rows() given st = sin(theta_k), ct = cos(theta_k)
+template <typename T>
+__host__ __device__ inline void rows_sc(const double* xk, const double* uk, const double* x1, int code, double mu,
+                                        double st, double ct, double* c, T (*J)[NV], int* en) {
   const int face = code & 3, slip = (code >> 2) & 3, smask = (code >> 4) & 1;
   const bool stick = (slip == 0);
   const double sg = (slip == 1) ? 1.0 : ((slip == 2) ? -1.0 : 0.0);
@@ -86,8 +100,7 @@ __host__ __device__ inline void rows(const double* xk, const double* uk, const d
   const double th = xk[2], s = xk[3], Fn = uk[0], Ft = uk[1];
   const double Fbx = -Fn * nx + Ft * tx, Fby = -Fn * ny + Ft * ty;
   const double M = HALF * Ft + s * Fn;
-  double st, ct;
-  sincos_d(th, &st, &ct);
+  (void)th;
   const double xi_x = K1 * Fbx, xi_y = K1 * Fby, xi_t = KM * M;
   const double vx = ct * xi_x - st * xi_y, vy = st * xi_x + ct * xi_y;
   c[0] = (x1[0] - xk[0]) - DT * vx;
