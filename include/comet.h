@@ -57,12 +57,17 @@ typedef struct comet_mlp comet_mlp; /* opaque: learned proposal / warm-start net
  *   armijo_c1               sufficient-decrease constant of the trial steps
  *   eta_star, omega_star,   scaled feasibility, stationarity and complementarity
  *   rc_star                 tolerances of the stopping test
- *   eps_feas                feasibility tolerance of the physical-unit score, Eq. (4)   */
+ *   eps_feas                feasibility tolerance of the physical-unit score, Eq. (4)
+ *   mu0_warm                initial penalty parameter of a solve that starts from a caller
+ *                           or learned warm start (the primal is taken to be near a solution,
+ *                           so the outer loop starts with a tight penalty; multipliers start
+ *                           at zero either way)                                          */
 typedef struct {
   int32_t al_max, gn_max, ref_al_max, ref_gn_max;
   int32_t chol_retries, ls_trials, max_rejects, reserved;
   double mu0, mu_min, rho0, rho_min, rho_max, armijo_c1;
   double eta_star, omega_star, rc_star, eps_feas;
+  double mu0_warm;
 } comet_solver_params;
 
 void comet_default_params(comet_solver_params* p);

@@ -41,7 +41,8 @@ class SolverParams(C.Structure):
                 ("ls_trials", C.c_int32), ("max_rejects", C.c_int32), ("pad_", C.c_int32), ("mu0", C.c_double), ("mu_min", C.c_double),
                 ("rho0", C.c_double), ("rho_min", C.c_double), ("rho_max", C.c_double),
                 ("armijo_c1", C.c_double), ("eta_star", C.c_double), ("omega_star", C.c_double),
-                ("rc_star", C.c_double), ("eps_feas", C.c_double)]
+                ("rc_star", C.c_double), ("eps_feas", C.c_double),
+                ("mu0_warm", C.c_double)]
 
 
 class ExpandParams(C.Structure):
@@ -70,6 +71,7 @@ class Params:
     omega_star: float = 1e-4
     rc_star: float = 1e-6
     eps_feas: float = 1e-5
+    mu0_warm: float = 1e-4
 
     def c(self) -> SolverParams:
         return SolverParams(*[getattr(self, f) for f, _ in SolverParams._fields_])

@@ -64,6 +64,7 @@ typedef struct {
   int32_t al_max, gn_max, chol_retries, ls_trials, max_rejects, pad_;
   double mu0, mu_min, rho0, rho_min, rho_max, armijo_c1;
   double eta_star, omega_star, rc_star, eps_feas;
+  double mu0_warm; /* initial penalty of a solve started from a given (warm) primal */
 } OracleParams;
 
 /* one mode-conditioned problem (one candidate order on one instance) */
@@ -611,7 +612,7 @@ static int all_finite(const double *a, int n) {
   return 1;
 }
 
-static void solve(const PushProb *P, const OracleParams *prm, double *z, SolveStats *st) {
+static void solve(const PushProb *P, const OracleParams *prm, int warm, double *z, SolveStats *st) {
   const int N = P->N, nz = N * PNW;
   double *g = (double *)malloc(sizeof(double) * nz);
   double *dz = (double *)malloc(sizeof(double) * nz);
@@ -623,7 +624,7 @@ static void solve(const PushProb *P, const OracleParams *prm, double *z, SolveSt
   D.lam = (double *)calloc((size_t)N * PNE, sizeof(double));
   D.nu = (double *)calloc((size_t)N * PNE, sizeof(double));
   D.lamT[0] = D.lamT[1] = D.lamT[2] = 0.0;
-  D.mu = prm->mu0;
+  D.mu = warm ? prm->mu0_warm : prm->mu0;
   eta = pow(D.mu, 0.1);
   omega = D.mu;
   st->al_iters = st->gn_iters = st->chol_fails = 0;
@@ -759,7 +760,7 @@ static void eval_one(EvalJob *E, int64_t b) {
   } else {
     initial_guess(P, z);
   }
-  solve(P, E->prm, z, &st);
+  solve(P, E->prm, E->warm != NULL, z, &st);
   if (st.status != 2) score(P, z, &J, &v);
   if (!isfinite(J) || !isfinite(v)) {
     J = NAN;

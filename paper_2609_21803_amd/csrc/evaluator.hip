@@ -654,8 +654,8 @@ struct SolverState {
   double mu, imu, eta, omega, rho, lamT[NT];
   int al, gn_in, gn_tot, rejects, tries, cfails, status;
   bool upd, outer_pending;   // multiplier update to apply in the next sweep; outer test due next sweep
-  __device__ void reset(const DevParams& prm) {
-    mu = prm.mu0;
+  __device__ void reset(const DevParams& prm, bool warm) {
+    mu = warm ? prm.mu0_warm : prm.mu0;
     imu = 1.0 / mu;
     eta = pow(mu, 0.1);
     omega = mu;
@@ -679,7 +679,7 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
   L.N = 0;
   L.off = A.nmax;
   SolverState st;
-  st.reset(prm);
+  st.reset(prm, false);
   bool exhausted = false;
   const int64_t Bn = A.Bdev ? *A.Bdev : A.B;
   const int T = min(max(prm.ls_trials, 1), MAX_TRIALS);
@@ -700,7 +700,7 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
           exhausted = true;
         } else {
           const int64_t b = A.order ? (int64_t)A.order[q] : (int64_t)q;
-          if (load_sequence(L, b)) st.reset(prm);
+          if (load_sequence(L, b)) st.reset(prm, A.warm != nullptr);
         }
       }
     }
@@ -981,6 +981,7 @@ comet_status launch_evaluate(comet_ctx* c, hipStream_t s, const EvalLaunch& L) {
   A.prm.mu0 = p.mu0; A.prm.mu_min = p.mu_min; A.prm.rho0 = p.rho0; A.prm.rho_min = p.rho_min;
   A.prm.rho_max = p.rho_max; A.prm.armijo_c1 = p.armijo_c1; A.prm.eta_star = p.eta_star;
   A.prm.omega_star = p.omega_star; A.prm.rc_star = p.rc_star; A.prm.eps_feas = p.eps_feas;
+  A.prm.mu0_warm = p.mu0_warm;
   for (int t = 0; t < NTYPES; ++t) A.inv_scale[t] = 1.0 / c->scale[t];
   const int64_t Bmax = L.B_dev ? L.B_max : L.B;
   const int64_t blocks_needed = (Bmax + WAVE - 1) / WAVE;
@@ -1030,6 +1031,7 @@ void comet_default_params(comet_solver_params* p) {
   p->omega_star = 1e-4;
   p->rc_star = 1e-6;
   p->eps_feas = 1e-5;
+  p->mu0_warm = 1e-4;
 }
 
 comet_status comet_create(comet_task task, const comet_solver_params* params, int64_t max_batch,
@@ -1044,7 +1046,7 @@ comet_status comet_create(comet_task task, const comet_solver_params* params, in
   if (params) c->prm = *params;
   else comet_default_params(&c->prm);
   if (c->prm.ls_trials < 1 || c->prm.ls_trials > comet::MAX_TRIALS || c->prm.al_max < 1 || c->prm.gn_max < 1 ||
-      !(c->prm.mu0 > 0) || !(c->prm.mu_min > 0)) {
+      !(c->prm.mu0 > 0) || !(c->prm.mu_min > 0) || !(c->prm.mu0_warm > 0)) {
     delete c;
     return COMET_EINVAL;
   }

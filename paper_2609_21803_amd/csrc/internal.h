@@ -19,6 +19,7 @@ constexpr int WAVE = 64;
 struct DevParams {
   int al_max, gn_max, chol_retries, ls_trials, max_rejects;
   double mu0, mu_min, rho0, rho_min, rho_max, armijo_c1, eta_star, omega_star, rc_star, eps_feas;
+  double mu0_warm;
 };
 
 struct EvalArgs {

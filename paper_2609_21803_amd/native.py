@@ -24,7 +24,7 @@ class SolverParamsC(C.Structure):
                 ("reserved", C.c_int32), ("mu0", C.c_double), ("mu_min", C.c_double), ("rho0", C.c_double),
                 ("rho_min", C.c_double), ("rho_max", C.c_double), ("armijo_c1", C.c_double),
                 ("eta_star", C.c_double), ("omega_star", C.c_double), ("rc_star", C.c_double),
-                ("eps_feas", C.c_double)]
+                ("eps_feas", C.c_double), ("mu0_warm", C.c_double)]
 
 
 class ScheduleC(C.Structure):
@@ -155,6 +155,7 @@ class SolverParams:
     omega_star: float = 1e-4
     rc_star: float = 1e-6
     eps_feas: float = 1e-5
+    mu0_warm: float = 1e-4
 
     def c(self) -> SolverParamsC:
         return SolverParamsC(*[getattr(self, f.name) for f in fields(self)])

@@ -33,7 +33,7 @@ def test_default_params_agree_with_binding_and_oracle():
     assert lib_defaults == native.SolverParams()
     o = oracle.Params()
     for f in ("al_max", "gn_max", "chol_retries", "ls_trials", "max_rejects", "mu0", "mu_min", "rho0", "rho_min",
-              "rho_max", "armijo_c1", "eta_star", "omega_star", "rc_star", "eps_feas"):
+              "rho_max", "armijo_c1", "eta_star", "omega_star", "rc_star", "eps_feas", "mu0_warm"):
         assert getattr(o, f) == getattr(lib_defaults, f), f
     assert (lib_defaults.ref_al_max, lib_defaults.ref_gn_max) == (oracle.REFINE["al_max"], oracle.REFINE["gn_max"])
 

@@ -337,3 +337,33 @@ def test_invalid_inputs_score_as_infeasible(orc):
     assert r["feasible"][0] == 1
     assert np.isnan(r["cost"][1]) and np.isinf(r["viol"][1]) and r["feasible"][1] == 0
     assert np.isnan(r["cost"][2]) and np.isinf(r["viol"][2]) and r["feasible"][2] == 0
+
+
+def test_warm_start_at_a_kkt_point_stays_there(orc):
+    """A solve started from a converged point with the tight warm-start penalty returns that
+    point: the straight sticking push (closed-form optimum d^2 / (v_ref^2 T)) warm-started at
+    its own solution keeps the closed-form cost, and a warm start does not cost more
+    Gauss-Newton iterations than the schedule-derived start on converged orders."""
+    d, N = 0.05, 10
+    x0 = np.zeros((1, 4))
+    goal = np.array([[d, 0.0, 0.0]])
+    inst = np.array([[0.4]])
+    modes = np.zeros((1, 6), np.int32)
+    knots = np.zeros((1, 6), np.int32)
+    modes[0, 0], knots[0, 0] = 6, N
+    tight = orc.Params(**TIGHT)
+    r = orc.evaluate(x0, goal, inst, np.ones(1, np.int32), modes, knots, params=tight)
+    rw = orc.evaluate(x0, goal, inst, np.ones(1, np.int32), modes, knots, warm=r["traj"], params=tight)
+    closed = d * d / (N * DT)
+    assert rw["feasible"][0] == 1 and rw["stats"][0, 3] == 1
+    assert abs(rw["cost"][0] - closed) <= 1e-8 * closed
+    assert rw["stats"][0, 1] < r["stats"][0, 1]
+    b = I.subset(I.push_tiny(), np.arange(0, 1152, 9))
+    p = orc.evaluate(b["x0"], b["goal"], b["inst"], b["nseg"], b["modes"], b["knots"])
+    w = orc.evaluate(b["x0"], b["goal"], b["inst"], b["nseg"], b["modes"], b["knots"], warm=p["traj"])
+    conv = (p["stats"][:, 3] == 1) & (w["stats"][:, 3] == 1)
+    assert conv.sum() >= 20
+    assert w["stats"][conv, 1].mean() < p["stats"][conv, 1].mean()
+    both = conv & (p["feasible"] == 1) & (w["feasible"] == 1)
+    rel = np.abs(w["cost"][both] - p["cost"][both]) / np.maximum(np.abs(p["cost"][both]), 1e-12)
+    assert np.median(rel) < 1e-4 and np.quantile(rel, 0.9) < 1e-3   # same optimum, default tolerances
