@@ -6,7 +6,12 @@ augmented-Lagrangian outer loop <= 20, Gauss-Newton inner loop <= 10), inputs re
 HBM.  Prints one JSON line with solves/s, the roofline of the solver kernel and the FP64
 CPU oracle timed on a bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu]
+The learned leg trains the proposal / warm-start network on evaluator results (BF16 matrix
+cores), times its training step and batched inference against the BF16 matrix-core peak,
+and compares the device time to the first feasible plan of the plain and the learned
+expansion on held-out instances.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu] [--no-learned]
 """
 from __future__ import annotations
 
@@ -28,6 +33,7 @@ sys.path.insert(0, ROOT)
 FLOP_PER_INTERVAL_GN = 2400.0
 FLOP_PER_INTERVAL_AL = 40.0
 PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak
+PEAK_BF16_TFLOPS = 2500.0    # MI355X published dense BF16 matrix-core peak
 HBM_PEAK_GBS = 8000.0
 
 
@@ -82,12 +88,91 @@ def cpu_baseline(batch, seconds_target=15.0):
                 sample=f"{n2} of {B} TOs, evenly strided over the batch, FP64, {n_threads} threads, {dt:.1f} s")
 
 
+def mlp_flops(B, dims, train):
+    """Matrix-core flops of one forward (or forward + backward) pass over B samples."""
+    layers = list(zip(dims[:-1], dims[1:]))
+    f = sum(2.0 * B * k * n for k, n in layers)                  # forward products
+    if train:
+        f += sum(2.0 * B * k * n for k, n in layers)             # weight gradients
+        f += sum(2.0 * B * k * n for k, n in layers[1:])         # input gradients (not for the input layer)
+    return f
+
+
+def learned_leg(native, I, torch):
+    """Train the network on evaluator results, time training and inference, and compare the
+    time to the first feasible plan of the plain and the learned expansion."""
+    from paper_2609_21803_amd import learned
+    t0 = time.perf_counter()
+    data = learned.generate(1048576, seed=4000)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    mlp = native.MLP(max_batch=131072, seed=1)
+    dims = [mlp.in_dim] + [mlp.hidden] * mlp.layers + [mlp.out_dim]
+    steps, batch = 1500, 8192
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # time the bare training steps on one resident minibatch, then train on the data
+    idx = torch.arange(batch, device="cuda")
+    mb = [data[k].index_select(0, idx).contiguous() for k in ("X", "y_feas", "y_cost", "y_traj", "mask")]
+    for _ in range(3):
+        mlp.train_step(*mb, lr=0.0)
+    e0.record()
+    for _ in range(50):
+        mlp.train_step(*mb, lr=0.0)
+    e1.record()
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / 50
+    mlp.set_params(native.MLP(max_batch=16, seed=1).get_params())       # fresh weights and optimiser state
+    t0 = time.perf_counter()
+    log = learned.train(mlp, data, steps=steps, batch=batch, lr=1e-3, log_every=steps - 1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    Bf = 131072
+    xf = data["X"][:Bf].contiguous()
+    mlp.forward(xf)
+    e0.record()
+    for _ in range(10):
+        mlp.forward(xf)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 10
+    prm = native.ExpandParams(kcap=3, seed_max_segments=2, radius=1, rounds=2, frontier_W=4096, knots_per_segment=8,
+                              k_ref=64, batch_B=16384, eval_budget=20000, learned_warm=1)
+    ctx = native.Context(max_batch=16384, max_segments=6, max_intervals=24)
+    x0, goal, inst = I.push_pairs(9100, 8)
+    rows = learned.compare(ctx, mlp, prm, list(zip(x0, goal, inst)))
+    tp = [r["plain"]["t_first_ms"] for r in rows]
+    tl = [r["learned"]["t_first_ms"] for r in rows]
+    same = sum(r["plain"]["modes"] == r["learned"]["modes"] and
+               abs(r["plain"]["cost"] - r["learned"]["cost"]) <= 1e-4 * max(abs(r["plain"]["cost"]), 1e-12)
+               for r in rows)
+    tr_fl = mlp_flops(batch, dims, True)
+    fw_fl = mlp_flops(Bf, dims, False)
+    tr_tf = tr_fl / (step_ms * 1e-3) / 1e12
+    return {
+        "ttfp_ms_plain_median": float(np.median(tp)), "ttfp_ms_learned_median": float(np.median(tl)),
+        "ttfp_ratio_median": float(np.median(np.array(tl) / np.array(tp))),
+        "same_returned_plan": f"{same}/{len(rows)}",
+        "first_feasible_index_median": {"plain": float(np.median([r["plain"]["first_index"] for r in rows])),
+                                        "learned": float(np.median([r["learned"]["first_index"] for r in rows]))},
+        "instances": "8 held-out pushing start/goal pairs (seed 9100), K<=3, 8 intervals per segment, "
+                     "2 rounds, batch 16,384, budget 20,000",
+        "training": {"samples": int(data["X"].shape[0]), "steps": steps, "batch": batch, "gen_s": t_gen,
+                     "train_s": t_train, "final_loss": log[-1][1]},
+        "roofline": {"bound": "mfma", "kernel": "train step (k_gemm x 14 + loss, reductions, AdamW)",
+                     "achieved": tr_tf, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": tr_tf / PEAK_BF16_TFLOPS,
+                     "ms": step_ms, "flop": tr_fl},
+        "inference": {"batch": Bf, "ms": fwd_ms, "achieved": fw_fl / (fwd_ms * 1e-3) / 1e12, "peak": PEAK_BF16_TFLOPS,
+                      "unit": "TFLOP/s"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -169,6 +254,8 @@ def main():
                      "kernel": "k_push_solve", "kernel_ms": kms, "flop_per_launch": flops},
         "wall_s_timed": wall,
     }
+    if not args.no_learned:
+        res["learned"] = learned_leg(native, I, torch)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(batch)
     print(json.dumps(res), flush=True)

@@ -232,7 +232,9 @@ comet_status comet_expand_trace(comet_ctx* ctx, void* stream, int64_t cap, uint6
  * layout: for each linear layer in order, W [out][in] row-major then b [out] (FP32).
  * Initialisation: W ~ U(-1/sqrt(in), 1/sqrt(in)) from a counter-based hash of (seed, index),
  * b = 0.  Training: AdamW (beta 0.9 / 0.999, eps 1e-8) on FP32 masters; GEMM operands
- * (weights, inputs, activations, back-propagated gradients) are rounded to BF16. */
+ * (weights, inputs, activations, back-propagated gradients) are rounded to BF16.
+ * in_dim, hidden and out_dim must be multiples of 8 (16-byte operand vectors), else
+ * COMET_EINVAL; out_dim >= 722. */
 comet_status comet_mlp_create(int32_t in_dim, int32_t hidden, int32_t layers, int32_t out_dim, int64_t max_batch,
                               uint64_t seed, comet_mlp** out);
 void comet_mlp_destroy(comet_mlp* mlp);

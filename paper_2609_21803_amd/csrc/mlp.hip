@@ -46,116 +46,183 @@ __device__ inline float gelu_grad(float z) {
 }
 
 // ---------------------------------------------------------------------------------
-// GEMM: C(m, n) = sum_k A(m, k) B(k, n), A(m,k) = A[m*am + k*ak], B(k,n) = Bp[n*bn + k*bk],
-// BF16 operands, FP32 accumulation.  Block tile 64 x 64, K step 32, 4 waves of 32 x 32
-// (2 x 2 MFMA 16x16x32 tiles).  A_K / B_K: the contraction index is the contiguous one.
+// GEMM: C(m, n) = sum_k A(m, k) B(k, n) with BF16 operands and FP32 accumulation on the
+// matrix cores.  Operand layouts (template flags): A_K -- A(m, k) = A[m*lda + k] (the
+// contraction index is contiguous), else A(m, k) = A[k*lda + m]; B_K -- B(k, n) =
+// Bp[n*ldb + k], else B(k, n) = Bp[k*ldb + n].  Requirements (checked on the host): the
+// contiguous extent of each operand and its leading dimension are multiples of 8 and the
+// base pointers 16-byte aligned, so every global load is one 16-byte vector.
+// Block tile 128 x 64, K step 32, 256 threads = 4 waves in 2 x 2, each wave 64 x 32 (4 x 2
+// tiles of v_mfma_f32_16x16x32_bf16).  Tiles are staged through a double-buffered LDS ring
+// (one barrier per K step, the next step's global loads in flight during the products).
+// gridDim.z > 1 splits the contraction: block z sums k in [z*kc, (z+1)*kc) and writes its
+// partial sums to slab z of the output (EPI_PARTIAL).
 // ---------------------------------------------------------------------------------
-enum { EPI_HIDDEN = 0, EPI_OUT = 1, EPI_DX = 2, EPI_PLAIN = 3 };
+enum { EPI_HIDDEN = 0, EPI_OUT = 1, EPI_DX = 2, EPI_PARTIAL = 3 };
 
 struct Epi {
   const float* bias;   // [N] (EPI_HIDDEN, EPI_OUT)
-  float* z;            // FP32 pre-activation out (EPI_HIDDEN) / FP32 result (EPI_OUT, EPI_PLAIN) / dZ (EPI_DX)
+  float* z;            // FP32 pre-activation out (EPI_HIDDEN) / FP32 result (EPI_OUT, EPI_PARTIAL) / dZ (EPI_DX)
   bf16* h;             // BF16 activation (EPI_HIDDEN) / BF16 gradient (EPI_DX)
   const float* zprev;  // pre-activation of the layer below (EPI_DX)
   long ldc;            // row stride of the outputs
+  long slab;           // EPI_PARTIAL: elements between the partial-sum slabs
 };
 
-constexpr int GBM = 64, GBN = 64, GBK = 32, GPAD = 8;
+constexpr int GBM = 128, GBN = 64, GBK = 32, GLD = GBK + 8;   // LDS row: 32 bf16 + 8 pad (80 bytes)
+constexpr int MAX_SPLIT = 32;      // contraction splits of a weight-gradient GEMM
+constexpr int COLSUM_ROWS = 64;    // partial rows of the bias-gradient column sums
+
+// One operand tile of R rows (m or n) x GBK (k) into registers.  K-contiguous: vector v
+// covers row v/4, k = (v%4)*8 .. +8.  Row-contiguous: vector v covers k = v/(R/8),
+// rows ((v % (R/8))*8 .. +8).  Out-of-range vectors load zeros.
+template <int R, bool KC>
+struct TileLoader {
+  static constexpr int NV = R * GBK / 8 / 256;   // vectors per thread
+  bf16x8 v[NV];
+  __device__ void load(const bf16* __restrict__ p, long ld, int r0, int rlim, int k0, int klim, int t) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const int id = t + 256 * j;
+      int r, k;
+      if (KC) {
+        r = id >> 2;
+        k = (id & 3) * 8;
+      } else {
+        k = id / (R / 8);
+        r = (id % (R / 8)) * 8;
+      }
+      const int gr = r0 + r, gk = k0 + k;
+      const bool in = KC ? (gr < rlim && gk < klim) : (gr < rlim && gk < klim);
+      if (in) {
+        const bf16* q = KC ? p + (long)gr * ld + gk : p + (long)gk * ld + gr;
+        v[j] = *reinterpret_cast<const bf16x8*>(q);
+      } else {
+        v[j] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      }
+    }
+  }
+  __device__ void store(bf16 (*S)[GLD], int t) const {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const int id = t + 256 * j;
+      if (KC) {
+        *reinterpret_cast<bf16x8*>(&S[id >> 2][(id & 3) * 8]) = v[j];
+      } else {
+        const int k = id / (R / 8), r = (id % (R / 8)) * 8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) S[r + i][k] = (bf16)v[j][i];
+      }
+    }
+  }
+};
 
 template <bool A_K, bool B_K, int EPI>
-__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* __restrict__ A, long am, long ak,
-                                              const bf16* __restrict__ Bp, long bn, long bk, Epi ep,
-                                              const long long* M_dev) {
-  __shared__ bf16 As[GBM][GBK + GPAD];
-  __shared__ bf16 Bs[GBN][GBK + GPAD];
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* __restrict__ A, long lda,
+                                              const bf16* __restrict__ Bp, long ldb, Epi ep, const long long* M_dev,
+                                              int kc) {
+  __shared__ __attribute__((aligned(16))) bf16 As[2][GBM][GLD];
+  __shared__ __attribute__((aligned(16))) bf16 Bs[2][GBN][GLD];
   if (M_dev) M = (int)min((long long)M, *M_dev);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wm = w >> 1, wn = w & 1;
   const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
   if (m0 >= M) return;
-  f32x4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
+  const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
+  f32x4 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += GBK) {
-    // A tile -> As[m][k]
-    if (A_K) {
-      const int r = t >> 2, kc = (t & 3) * 8;
-      const int m = m0 + r;
-      for (int i = 0; i < 8; ++i) {
-        const int k = k0 + kc + i;
-        As[r][kc + i] = (m < M && k < K) ? A[(long)m * am + (long)k * ak] : (bf16)0;
-      }
-    } else {
-      const int kk = t >> 3, mc = (t & 7) * 8;
-      const int k = k0 + kk;
-      for (int i = 0; i < 8; ++i) {
-        const int m = m0 + mc + i;
-        As[mc + i][kk] = (m < M && k < K) ? A[(long)m * am + (long)k * ak] : (bf16)0;
-      }
+  TileLoader<GBM, A_K> la;
+  TileLoader<GBN, B_K> lb;
+  const int steps = (ke - kb + GBK - 1) / GBK;
+  if (steps > 0) {
+    la.load(A, lda, m0, M, kb, ke, t);
+    lb.load(Bp, ldb, n0, N, kb, ke, t);
+    la.store(As[0], t);
+    lb.store(Bs[0], t);
+  }
+  __syncthreads();
+  const int kq = (lane >> 4) * 8;
+  for (int st = 0; st < steps; ++st) {
+    const int cur = st & 1;
+    const bool more = st + 1 < steps;
+    if (more) {   // next tiles in flight while this step's products run
+      la.load(A, lda, m0, M, kb + (st + 1) * GBK, ke, t);
+      lb.load(Bp, ldb, n0, N, kb + (st + 1) * GBK, ke, t);
     }
-    // B tile -> Bs[n][k]
-    if (B_K) {
-      const int r = t >> 2, kc = (t & 3) * 8;
-      const int n = n0 + r;
-      for (int i = 0; i < 8; ++i) {
-        const int k = k0 + kc + i;
-        Bs[r][kc + i] = (n < N && k < K) ? Bp[(long)n * bn + (long)k * bk] : (bf16)0;
-      }
-    } else {
-      const int kk = t >> 3, nc = (t & 7) * 8;
-      const int k = k0 + kk;
-      for (int i = 0; i < 8; ++i) {
-        const int n = n0 + nc + i;
-        Bs[nc + i][kk] = (n < N && k < K) ? Bp[(long)n * bn + (long)k * bk] : (bf16)0;
-      }
-    }
-    __syncthreads();
-    const int kq = (lane >> 4) * 8;
-    bf16x8 a[2], b[2];
-    for (int i = 0; i < 2; ++i) {
-      const int r = wm * 32 + i * 16 + (lane & 15);
-      a[i] = *reinterpret_cast<const bf16x8*>(&As[r][kq]);
-    }
-    for (int j = 0; j < 2; ++j) {
-      const int c = wn * 32 + j * 16 + (lane & 15);
-      b[j] = *reinterpret_cast<const bf16x8*>(&Bs[c][kq]);
-    }
-    for (int i = 0; i < 2; ++i)
+    bf16x8 a[4], b[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wm * 64 + i * 16 + (lane & 15)][kq]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wn * 32 + j * 16 + (lane & 15)][kq]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (more) {
+      la.store(As[cur ^ 1], t);
+      lb.store(Bs[cur ^ 1], t);
+    }
     __syncthreads();
   }
   // accumulator layout: lane holds rows 4*(lane/16) + r, column lane%16 of each 16x16 tile
-  for (int i = 0; i < 2; ++i)
+  float* zo = ep.z + (EPI == EPI_PARTIAL ? (long)blockIdx.z * ep.slab : 0L);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
     for (int j = 0; j < 2; ++j)
+#pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + r;
+        const int m = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + r;
         const int n = n0 + wn * 32 + j * 16 + (lane & 15);
         if (m >= M || n >= N) continue;
         const float v = acc[i][j][r];
         const long o = (long)m * ep.ldc + n;
         if (EPI == EPI_HIDDEN) {
           const float z = v + ep.bias[n];
-          ep.z[o] = z;
+          zo[o] = z;
           ep.h[o] = to_bf16(gelu(z));
         } else if (EPI == EPI_OUT) {
-          ep.z[o] = v + ep.bias[n];
+          zo[o] = v + ep.bias[n];
         } else if (EPI == EPI_DX) {
           const float d = v * gelu_grad(ep.zprev[o]);
-          ep.z[o] = d;
+          zo[o] = d;
           ep.h[o] = to_bf16(d);
         } else {
-          ep.z[o] = v;
+          zo[o] = v;
         }
       }
 }
 
-// column sums of an FP32 [M][N] matrix (bias gradients)
-__global__ void k_colsum(const float* X, int M, int N, float* out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+// sum of S partial-sum slabs of n floats each
+__global__ void k_sum_slabs(const float* __restrict__ part, int S, long n, float* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
   float s = 0.f;
-  for (int m = 0; m < M; ++m) s += X[(long)m * N + n];
-  out[n] = s;
+  for (int z = 0; z < S; ++z) s += part[(long)z * n + i];
+  out[i] = s;
+}
+
+// column sums of an FP32 [M][N] matrix (bias gradients), in two deterministic stages:
+// block (x, y) covers 256 columns (64 threads x 4 consecutive columns, 16-byte loads) and
+// rows y*4 + phase + k * gridDim.y * 4 (4 row phases), writing part[y][n]; k_sum_slabs then
+// adds the gridDim.y partial rows.  N must be a multiple of 4.
+__global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ X, int M, int N,
+                                                     float* __restrict__ part) {
+  __shared__ f32x4 red[4][64];
+  const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int n = blockIdx.x * 256 + c * 4;
+  f32x4 s = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (n < N)
+    for (int m = blockIdx.y * 4 + ph; m < M; m += gridDim.y * 4) s += *reinterpret_cast<const f32x4*>(X + (long)m * N + n);
+  red[ph][c] = s;
+  __syncthreads();
+  if (ph == 0 && n < N) {
+    const f32x4 t = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+    *reinterpret_cast<f32x4*>(part + (long)blockIdx.y * N + n) = t;
+  }
 }
 
 __global__ void k_to_bf16(const float* x, bf16* y, long n) {
@@ -177,51 +244,83 @@ __global__ void k_refresh(const float* W, int N, int K, bf16* Wb, bf16* WT) {
 // loss[0] = mean BCE, loss[1] = cost MSE over feasible, loss[2] = warm MSE over mask.
 // ---------------------------------------------------------------------------------
 // cnt[0] += sum of feasible flags, cnt[1] += sum of mask entries (cnt zeroed before)
-__global__ void k_loss_counts(int B, int W, const float* y_feas, const float* mask, float* cnt) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long n = (long)B * W;
-  float c = (i < n) ? mask[i] : 0.f;
-  float a = (i < B) ? y_feas[i] : 0.f;
-  for (int o = 32; o >= 1; o >>= 1) {
-    c += __shfl_xor(c, o);
-    a += __shfl_xor(a, o);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    if (c != 0.f) atomicAdd(&cnt[1], c);
-    if (a != 0.f) atomicAdd(&cnt[0], a);
+// Loss reductions run in two deterministic stages: LOSS_BLOCKS blocks stride over the
+// elements and write one partial per block, k_reduce_partials adds them in block order.
+constexpr int LOSS_BLOCKS = 512;
+
+// sum over the 256 threads of a block; the result is valid in thread 0
+__device__ inline float block_sum(float v, float* red) {
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+// partials of the two normalisers: feasible samples, warm-start mask entries
+__global__ __launch_bounds__(256) void k_loss_counts(int B, int W, const float* y_feas, const float* mask,
+                                                     float* part) {
+  __shared__ float red[4];
+  const long n = (long)B * W, stride = (long)gridDim.x * blockDim.x;
+  float c = 0.f, a = 0.f;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) c += mask[i];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < B; i += stride) a += y_feas[i];
+  const float sa = block_sum(a, red);
+  const float sc = block_sum(c, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 4 + 0] = sa;
+    part[blockIdx.x * 4 + 1] = sc;
   }
 }
 
-__global__ void k_loss_grad(int B, int O, int Wn, const float* Y, const float* y_feas, const float* y_cost,
-                            const float* y_traj, const float* mask, const float* cnt, float* dY, bf16* dYb,
-                            float* loss_terms) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long)B * O) return;
-  const int b = (int)(i / O), o = (int)(i % O);
-  const float nf = fmaxf(cnt[0], 1.f), nm = fmaxf(cnt[1], 1.f);
-  float g = 0.f, l = 0.f;
-  int term = -1;
-  if (o == 0) {
-    const float x = Y[i], yv = y_feas[b];
-    l = fmaxf(x, 0.f) - x * yv + log1pf(expf(-fabsf(x)));
-    g = (1.f / (1.f + expf(-x)) - yv) / (float)B;
-    l /= (float)B;
-    term = 0;
-  } else if (o == 1) {
-    const float f = y_feas[b], d = Y[i] - y_cost[b];
-    l = f * d * d / nf;
-    g = 2.f * f * d / nf;
-    term = 1;
-  } else if (o - 2 < Wn) {
-    const long e = (long)b * Wn + (o - 2);
-    const float m = mask[e], d = Y[i] - y_traj[e];
-    l = m * d * d / nm;
-    g = 2.f * m * d / nm;
-    term = 2;
+// out[j] = sum over the nb block partials of component j (j < ncomp); one block of 256
+// threads, each summing a fixed stride of partials, then a fixed-order block reduction
+__global__ __launch_bounds__(256) void k_reduce_partials(const float* part, int nb, int ncomp, float* out) {
+  __shared__ float red[4];
+  for (int j = 0; j < ncomp; ++j) {
+    float s = 0.f;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b * 4 + j];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[j] = s;
   }
-  dY[i] = g;
-  dYb[i] = to_bf16(g);
-  if (term >= 0 && l != 0.f) atomicAdd(&loss_terms[term], l);
+}
+
+// dL/dY of the combined loss and per-block partials of the three loss terms
+__global__ __launch_bounds__(256) void k_loss_grad(int B, int O, int Wn, const float* Y, const float* y_feas,
+                                                   const float* y_cost, const float* y_traj, const float* mask,
+                                                   const float* cnt, float* dY, bf16* dYb, float* part) {
+  __shared__ float red[4];
+  const float nf = fmaxf(cnt[0], 1.f), nm = fmaxf(cnt[1], 1.f);
+  float acc[3] = {0.f, 0.f, 0.f};
+  for (int b = blockIdx.x; b < B; b += gridDim.x)   // one output row per block pass
+    for (int o = threadIdx.x; o < O; o += blockDim.x) {
+      const long i = (long)b * O + o;
+      float g = 0.f;
+      if (o == 0) {
+        const float x = Y[i], yv = y_feas[b];
+        acc[0] += (fmaxf(x, 0.f) - x * yv + log1pf(expf(-fabsf(x)))) / (float)B;
+        g = (1.f / (1.f + expf(-x)) - yv) / (float)B;
+      } else if (o == 1) {
+        const float f = y_feas[b], d = Y[i] - y_cost[b];
+        acc[1] += f * d * d / nf;
+        g = 2.f * f * d / nf;
+      } else if (o - 2 < Wn) {
+        const long e = (long)b * Wn + (o - 2);
+        const float m = mask[e], d = Y[i] - y_traj[e];
+        acc[2] += m * d * d / nm;
+        g = 2.f * m * d / nm;
+      }
+      dY[i] = g;
+      dYb[i] = to_bf16(g);
+    }
+  const float s0 = block_sum(acc[0], red);
+  const float s1 = block_sum(acc[1], red);
+  const float s2 = block_sum(acc[2], red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 4 + 0] = s0;
+    part[blockIdx.x * 4 + 1] = s1;
+    part[blockIdx.x * 4 + 2] = s2;
+  }
 }
 
 __global__ void k_adamw(float* w, float* m, float* v, const float* g, long n, float lr, float b1, float b2, float eps,
@@ -396,6 +495,8 @@ struct comet_mlp {
   float *dZ = nullptr;                 // FP32 gradient buffer [B][hidden]
   bf16 *dZb[2] = {nullptr, nullptr};   // BF16 gradient ping-pong [B][max(hidden, out)]
   float *cnt = nullptr, *lossd = nullptr;
+  float* part = nullptr;               // partial sums: split weight gradients / bias column sums
+  float* red = nullptr;                // per-block partials of the loss reductions [LOSS_BLOCKS][4]
   long long step = 0;
 };
 
@@ -403,11 +504,29 @@ namespace {
 
 unsigned nblk(long long n, int bs) { return (unsigned)std::max<long long>(1, (n + bs - 1) / bs); }
 
+// operand requirements of k_gemm: contiguous extents, leading dimensions and base
+// addresses allow 16-byte vector loads
+bool vec_ok(const void* p, long ld, long contiguous_extent) {
+  return ((uintptr_t)p % 16 == 0) && ld % 8 == 0 && contiguous_extent % 8 == 0;
+}
+
+// launches k_gemm; returns the number of contraction splits (partial-sum slabs) used
 template <bool A_K, bool B_K, int EPI>
-void gemm(hipStream_t s, int M, int N, int K, const bf16* A, long am, long ak, const bf16* Bp, long bn, long bk,
-          const Epi& ep, const long long* M_dev = nullptr) {
-  dim3 grid(nblk(N, GBN), nblk(M, GBM));
-  hipLaunchKernelGGL((k_gemm<A_K, B_K, EPI>), grid, dim3(256), 0, s, M, N, K, A, am, ak, Bp, bn, bk, ep, M_dev);
+int gemm(hipStream_t s, int M, int N, int K, const bf16* A, long lda, const bf16* Bp, long ldb, const Epi& ep,
+         const long long* M_dev = nullptr, int split = 1) {
+  const int kc = split > 1 ? (int)((((long)K + split - 1) / split + GBK - 1) / GBK * GBK) : std::max(K, 1);
+  const int nz = split > 1 ? (K + kc - 1) / kc : 1;
+  dim3 grid(nblk(N, GBN), nblk(M, GBM), nz);
+  hipLaunchKernelGGL((k_gemm<A_K, B_K, EPI>), grid, dim3(256), 0, s, M, N, K, A, lda, Bp, ldb, ep, M_dev, kc);
+  return nz;
+}
+
+// splits of the batch contraction of a weight-gradient GEMM: enough blocks to fill the
+// chip, at least 256 batch rows per split
+int wgrad_splits(int M, int N, int B) {
+  const long blocks = (long)nblk(N, GBN) * nblk(M, GBM);
+  const long want = (1024 + blocks - 1) / blocks;
+  return (int)std::max<long>(1, std::min<long>({want, (long)B / 256, (long)MAX_SPLIT}));
 }
 
 void refresh_weights(comet_mlp* m, hipStream_t s) {
@@ -433,10 +552,10 @@ void mlp_forward(comet_mlp* m, hipStream_t s, int B, const long long* B_dev) {
     if (l < m->nl - 1) {
       ep.z = m->Z[l];
       ep.h = m->H[l + 1];
-      gemm<true, true, EPI_HIDDEN>(s, B, N, K, m->H[l], K, 1, Wl, K, 1, ep, B_dev);
+      gemm<true, true, EPI_HIDDEN>(s, B, N, K, m->H[l], K, Wl, K, ep, B_dev);
     } else {
       ep.z = m->Y;
-      gemm<true, true, EPI_OUT>(s, B, N, K, m->H[l], K, 1, Wl, K, 1, ep, B_dev);
+      gemm<true, true, EPI_OUT>(s, B, N, K, m->H[l], K, Wl, K, ep, B_dev);
     }
   }
 }
@@ -466,8 +585,8 @@ extern "C" {
 
 comet_status comet_mlp_create(int32_t in_dim, int32_t hidden, int32_t layers, int32_t out_dim, int64_t max_batch,
                               uint64_t seed, comet_mlp** out) {
-  if (!out || in_dim < 1 || hidden < 1 || layers < 1 || layers > 16 || out_dim < 2 + 6 * WS_SLOTS * WS_CH ||
-      max_batch < 1)
+  if (!out || in_dim < 8 || hidden < 8 || layers < 1 || layers > 16 || out_dim < 2 + 6 * WS_SLOTS * WS_CH ||
+      max_batch < 1 || in_dim % 8 || hidden % 8 || out_dim % 8)
     return COMET_EINVAL;
   *out = nullptr;
   comet_mlp* m = new comet_mlp();
@@ -513,6 +632,15 @@ comet_status comet_mlp_create(int32_t in_dim, int32_t hidden, int32_t layers, in
   A((void**)&m->dZb[1], 2 * B * std::max(hidden, out_dim));
   A((void**)&m->cnt, 4 * 4);
   A((void**)&m->lossd, 4 * 4);
+  {
+    long long max_nk = 0, max_n = 0;
+    for (int l = 0; l < m->nl; ++l) {
+      max_nk = std::max(max_nk, (long long)m->N[l] * m->K[l]);
+      max_n = std::max(max_n, (long long)m->N[l]);
+    }
+    A((void**)&m->part, 4 * std::max<long long>(MAX_SPLIT * max_nk, COLSUM_ROWS * max_n));
+  }
+  A((void**)&m->red, 4 * 4 * LOSS_BLOCKS);
   if (!ok) {
     (void)hipGetLastError();
     comet_mlp_destroy(m);
@@ -539,7 +667,7 @@ comet_status comet_mlp_create(int32_t in_dim, int32_t hidden, int32_t layers, in
 void comet_mlp_destroy(comet_mlp* m) {
   if (!m) return;
   std::vector<void*> ps = {m->P, m->G, m->Mm, m->Vv, m->Wb, m->WT, m->Y, m->dY, m->dYb, m->dZ, m->dZb[0], m->dZb[1],
-                           m->cnt, m->lossd};
+                           m->cnt, m->lossd, m->part, m->red};
   for (auto* h : m->H) ps.push_back(h);
   for (auto* z : m->Z) ps.push_back(z);
   for (void* p : ps)
@@ -595,32 +723,39 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
   const int Bi = (int)B, O = m->out_dim, Wn = 6 * WS_SLOTS * WS_CH;
   if (hipMemcpyAsync(m->H[0], x_bf16, 2 * B * m->in_dim, hipMemcpyDeviceToDevice, s) != hipSuccess) return COMET_EHIP;
   mlp_forward(m, s, Bi, nullptr);
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, m->lossd, 4L);
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, m->cnt, 4L);
-  hipLaunchKernelGGL(k_loss_counts, dim3(nblk((long long)B * Wn, 256)), dim3(256), 0, s, Bi, Wn, y_feas, traj_mask,
-                     m->cnt);
-  hipLaunchKernelGGL(k_loss_grad, dim3(nblk((long long)B * O, 256)), dim3(256), 0, s, Bi, O, Wn, m->Y, y_feas, y_cost,
-                     y_traj, traj_mask, m->cnt, m->dY, m->dYb, m->lossd);
+  hipLaunchKernelGGL(k_loss_counts, dim3(LOSS_BLOCKS), dim3(256), 0, s, Bi, Wn, y_feas, traj_mask, m->red);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, m->red, LOSS_BLOCKS, 2, m->cnt);
+  hipLaunchKernelGGL(k_loss_grad, dim3(LOSS_BLOCKS), dim3(256), 0, s, Bi, O, Wn, m->Y, y_feas, y_cost, y_traj,
+                     traj_mask, m->cnt, m->dY, m->dYb, m->red);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, m->red, LOSS_BLOCKS, 3, m->lossd);
   // backward through the linear layers
   const bf16* g = m->dYb;
   const float* g32 = m->dY;
   int cur = 0;
   for (int l = m->nl - 1; l >= 0; --l) {
     const int K = m->K[l], N = m->N[l];
-    // dW_l [N][K] = G^T [N][B] . H_l [B][K]   (contraction over the batch)
+    // dW_l [N][K] = G^T [N][B] . H_l [B][K]: contraction over the batch, split into
+    // partial-sum slabs that k_sum_slabs adds
+    const int split = wgrad_splits(N, K, Bi);
     Epi ew{};
-    ew.z = m->G + m->woff[l];
+    ew.z = m->part;
     ew.ldc = K;
-    gemm<false, false, EPI_PLAIN>(s, N, K, Bi, g, 1, N, m->H[l], 1, K, ew);
-    hipLaunchKernelGGL(k_colsum, dim3(nblk(N, 256)), dim3(256), 0, s, g32, Bi, N, m->G + m->boff[l]);
+    ew.slab = (long)N * K;
+    const int nzs = gemm<false, false, EPI_PARTIAL>(s, N, K, Bi, g, N, m->H[l], K, ew, nullptr, split);
+    hipLaunchKernelGGL(k_sum_slabs, dim3(nblk((long long)N * K, 256)), dim3(256), 0, s, m->part, nzs, (long)N * K,
+                       m->G + m->woff[l]);
+    const int ry = std::max(1, std::min(COLSUM_ROWS, (Bi + 255) / 256));
+    hipLaunchKernelGGL(k_colsum_part, dim3(nblk(N, 256), ry), dim3(256), 0, s, g32, Bi, N, m->part);
+    hipLaunchKernelGGL(k_sum_slabs, dim3(nblk(N, 256)), dim3(256), 0, s, m->part, ry, (long)N, m->G + m->boff[l]);
     if (l > 0) {
-      // dZ_{l-1} [B][K] = (G [B][N] . W_l [N][K]) * gelu'(Z_{l-1})
+      // dZ_{l-1} [B][K] = (G [B][N] . W_l [N][K]) * gelu'(Z_{l-1}), W_l read through its
+      // transpose so both operands are contraction-contiguous
       Epi ex{};
       ex.z = m->dZ;
       ex.h = m->dZb[cur];
       ex.zprev = m->Z[l - 1];
       ex.ldc = K;
-      gemm<true, false, EPI_DX>(s, Bi, K, N, g, N, 1, m->Wb + m->wboff[l], 1, K, ex);
+      gemm<true, true, EPI_DX>(s, Bi, K, N, g, N, m->WT + m->wboff[l], N, ex);
       g = m->dZb[cur];
       g32 = m->dZ;
       cur ^= 1;
