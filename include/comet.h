@@ -40,7 +40,9 @@ typedef enum {
   COMET_ESTATE = -4  /* call not valid in the context's current state */
 } comet_status;
 
-typedef enum { COMET_TASK_PUSH = 0 } comet_task;
+/* Tasks: planar pushing (Sec. IV) and bimanual flipping of a box in a vertical plane
+ * (Sec. V); their dimensions and layouts are given at comet_evaluate. */
+typedef enum { COMET_TASK_PUSH = 0, COMET_TASK_FLIP = 1 } comet_task;
 
 typedef struct comet_ctx comet_ctx; /* opaque */
 typedef struct comet_mlp comet_mlp; /* opaque: learned proposal / warm-start network */
@@ -117,7 +119,27 @@ comet_status comet_check(comet_ctx* ctx, void* stream);
  *   traj  [B, Nmax+1, nx+nu] or NULL: row k = (x_k, u_k), row N has u = 0, rows > N zero
  *   stats [B, 4] or NULL: (outer iterations, inner iterations, Cholesky failures, status)
  *                      status 1 converged, 0 budget exhausted, 2 non-finite, 3 invalid input
- * B = 0 is a no-op.  B > max_batch returns COMET_EINVAL. */
+ * B = 0 is a no-op.  B > max_batch returns COMET_EINVAL.
+ *
+ * Flipping task (COMET_TASK_FLIP): box 0.2 x 0.1 m, 0.5 kg, on the table line y = 0 under
+ * gravity, pushed by two point fingers; quasi-static: the table reaction is the balance of
+ * gravity and the finger forces.
+ *   x0    [B, 8]   (px, py, th, vx, vy, om, s1, s2): centre, angle, twist, finger face
+ *                  coordinates; the start is taken at rest on face 3 (the -y face)
+ *   goal  [B, 2]   (px, th) at the final knot; the final twist is zero
+ *   inst  [B, 1]   table friction coefficient
+ *   controls (nu = 9): (ax, ay, al, f1n, f1t, sd1, f2n, f2t, sd2): accelerations of the
+ *                  twist, normal / tangential force and face-coordinate rate per finger
+ *   mode id = (f1 * 13 + f2) * 5 + g, 845 ids: finger code 0 free, 1 + 3 face + slip
+ *                  (slip 0 stick, 1 slide+, 2 slide-); table g: 0 stick, 1 slide+,
+ *                  2 slide-, 3 pivot about the left corner of the support face (counter-
+ *                  clockwise), 4 pivot about its right corner (clockwise).  A pivot run
+ *                  followed by a table-supported segment lands on the neighbouring face;
+ *                  an order whose consecutive pivots change direction is invalid.
+ *   rows are stated non-dimensionally (forces / mg, moments / (mg * 0.2 m)); viol is in
+ *                  these units; cost = sum dt (0.01 |accel|^2 + sum |f_i|^2 / (mg)^2 +
+ *                  0.01 sum sd_i^2)
+ *   traj  [B, Nmax+1, 17] rows (x_k, u_k); warm likewise. */
 comet_status comet_evaluate(comet_ctx* ctx, void* stream, int64_t B, const float* x0, const float* goal,
                             const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                             const float* warm, int32_t refine, float* cost, float* viol, uint8_t* feasible,

@@ -1038,7 +1038,8 @@ comet_status comet_create(comet_task task, const comet_solver_params* params, in
                           int32_t max_segments, int32_t max_intervals, comet_ctx** out) {
   if (!out) return COMET_EINVAL;
   *out = nullptr;
-  if (task != COMET_TASK_PUSH || max_batch < 1 || max_segments < 1 || max_segments > comet::MAXSEG ||
+  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP) || max_batch < 1 || max_segments < 1 ||
+      max_segments > comet::MAXSEG ||
       max_intervals < 1 || max_intervals > comet::MAXN)
     return COMET_EINVAL;
   comet_ctx* c = new comet_ctx();
@@ -1062,6 +1063,19 @@ comet_status comet_create(comet_task task, const comet_solver_params* params, in
     return COMET_EHIP;
   }
   c->n_cu = prop.multiProcessorCount;
+  if (task == COMET_TASK_FLIP) {
+    comet_status st = comet::flip_create_ws(c);
+    if (st == COMET_OK && (hipMalloc(&c->err, sizeof(unsigned)) != hipSuccess ||
+                           hipMemset(c->err, 0, sizeof(unsigned)) != hipSuccess ||
+                           hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess))
+      st = COMET_EHIP;
+    if (st != COMET_OK) {
+      comet_destroy(c);
+      return st;
+    }
+    *out = c;
+    return COMET_OK;
+  }
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, comet::k_push_solve, comet::WAVE, 0) != hipSuccess || nb < 1)
     nb = 1;
@@ -1095,6 +1109,7 @@ comet_status comet_create(comet_task task, const comet_solver_params* params, in
 void comet_destroy(comet_ctx* c) {
   if (!c) return;
   comet::destroy_expand_ws(c);
+  comet::flip_destroy_ws(c);
   if (c->gstream) (void)hipStreamDestroy(c->gstream);
   if (c->zd) (void)hipFree(c->zd);
   if (c->lam) (void)hipFree(c->lam);
@@ -1116,10 +1131,11 @@ const char* comet_last_error(const comet_ctx* c) { return c ? c->msg.c_str() : "
 comet_status comet_dims(const comet_ctx* c, int32_t* nx, int32_t* nu, int32_t* np, int32_t* nm, int32_t* ms,
                         int32_t* mi, int64_t* mb) {
   if (!c) return COMET_EINVAL;
-  if (nx) *nx = comet::push::NX;
-  if (nu) *nu = comet::push::NU;
+  const bool fl = (c->task == COMET_TASK_FLIP);
+  if (nx) *nx = fl ? 8 : comet::push::NX;
+  if (nu) *nu = fl ? 9 : comet::push::NU;
   if (np) *np = 1;
-  if (nm) *nm = comet::push::NMODES;
+  if (nm) *nm = fl ? 845 : comet::push::NMODES;
   if (ms) *ms = c->max_segments;
   if (mi) *mi = c->max_intervals;
   if (mb) *mb = c->max_batch;
@@ -1127,7 +1143,7 @@ comet_status comet_dims(const comet_ctx* c, int32_t* nx, int32_t* nu, int32_t* n
 }
 
 comet_status comet_row_scales(const comet_ctx* c, double* out, int32_t n) {
-  if (!c || !out || n < comet::push::NTYPES) return COMET_EINVAL;
+  if (!c || !out || n < comet::push::NTYPES || c->task != COMET_TASK_PUSH) return COMET_EINVAL;
   for (int t = 0; t < comet::push::NTYPES; ++t) out[t] = c->scale[t];
   return COMET_OK;
 }
@@ -1159,6 +1175,7 @@ comet_status comet_evaluate(comet_ctx* c, void* stream, int64_t B, const float* 
   L.x0 = x0; L.goal = goal; L.inst = inst; L.inst_stride = 1;
   L.nseg = nseg; L.modes = modes; L.knots = knots; L.warm = warm; L.refine = refine;
   L.cost = cost; L.viol = viol; L.feas = feasible; L.traj = traj; L.stats = stats;
+  if (c->task == COMET_TASK_FLIP) return comet::launch_flip(c, (hipStream_t)stream, L);
   return comet::launch_evaluate(c, (hipStream_t)stream, L);
 }
 

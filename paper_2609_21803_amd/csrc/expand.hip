@@ -866,6 +866,7 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
                           int32_t* best_modes, int32_t* best_knots, float* best_cost, float* best_viol,
                           float* best_traj, comet_expand_stats* stats) {
   if (!c) return COMET_EINVAL;
+  if (c->task != COMET_TASK_PUSH) return fail_msg(c, COMET_EINVAL, "comet_expand runs the pushing task only");
   if (!x0 || !goal || !inst || !best_nseg || !best_modes || !best_knots || !best_cost || !best_viol)
     return fail_msg(c, COMET_EINVAL, "null input or output pointer");
   comet_status st = check_expand_params(c, params);
@@ -947,6 +948,7 @@ comet_status comet_expand_next(comet_ctx* c, void* stream, int64_t n, const uint
                                const comet_expand_params* params, int64_t room, uint64_t* out_keys,
                                int64_t* out_n) {
   if (!c) return COMET_EINVAL;
+  if (c->task != COMET_TASK_PUSH) return fail_msg(c, COMET_EINVAL, "comet_expand_next runs the pushing task only");
   if (n < 0 || (n > 0 && (!keys || !merit)) || !out_keys || !out_n) return fail_msg(c, COMET_EINVAL, "bad arguments");
   comet_status st = check_expand_params(c, params);
   if (st != COMET_OK) return st;

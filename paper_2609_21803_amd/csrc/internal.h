@@ -102,12 +102,18 @@ struct comet_ctx {
   comet_schedule sched{0, 0};
   hipStream_t gstream = nullptr;   // internal stream for captured graphs
   comet_expand_ws* xws = nullptr;
+  double* fws = nullptr;      // flip task work space (FP64 per interval)
+  int* fcode = nullptr;       // flip task packed contact parameters per interval
   std::string msg;
 };
 
 
 namespace comet {
 comet_status launch_evaluate(comet_ctx* c, hipStream_t s, const EvalLaunch& L);
+// flip task (flip.hip)
+comet_status flip_create_ws(comet_ctx* c);
+void flip_destroy_ws(comet_ctx* c);
+comet_status launch_flip(comet_ctx* c, hipStream_t s, const EvalLaunch& L);
 // learned network hooks (mlp.hip)
 int mlp_in_dim(const comet_mlp* m);
 int mlp_out_dim(const comet_mlp* m);

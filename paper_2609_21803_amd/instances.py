@@ -89,3 +89,54 @@ def subset(batch: dict, idx) -> dict:
 def n_intervals(batch: dict) -> np.ndarray:
     live = np.arange(MAXSEG)[None, :] < batch["nseg"][:, None]
     return (batch["knots"] * live).sum(1)
+
+
+# ---------------------------------------------------------------------------------
+# Bimanual flipping (box 0.2 x 0.1 m at rest on its long face at the origin)
+# ---------------------------------------------------------------------------------
+FLIP_MODES = 845         # id = (f1 * 13 + f2) * 5 + g
+FLIP_X0 = (0.0, 0.05, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0)
+
+
+def flip_pairs(seed: int, n: int):
+    """n start/goal pairs: x0 [n,8] at rest, goal [n,2] = (px ~ U[-0.2, 0.2] m,
+    th ~ U[pi/2, pi]), inst [n,1] = table friction ~ U[0.62, 0.78]."""
+    rng = np.random.default_rng(seed)
+    goal = np.empty((n, 2))
+    goal[:, 0] = rng.uniform(-0.2, 0.2, n)
+    goal[:, 1] = rng.uniform(np.pi / 2, np.pi, n)
+    mu = rng.uniform(0.62, 0.78, n)
+    x0 = np.tile(np.array(FLIP_X0), (n, 1))
+    return x0, goal, mu.reshape(n, 1)
+
+
+def flip_orders(rng, B: int, kmin: int, kmax: int):
+    """B i.i.d. flip orders: K ~ U{kmin..kmax}, finger codes ~ U{0..12}, table mode ~
+    U{0..4}, except that a pivot directly after a pivot keeps its direction (an order
+    whose pivot run changes corner is not a valid problem)."""
+    K = rng.integers(kmin, kmax + 1, B)
+    f1 = rng.integers(0, 13, (B, MAXSEG))
+    f2 = rng.integers(0, 13, (B, MAXSEG))
+    g = rng.integers(0, 5, (B, MAXSEG))
+    for j in range(1, MAXSEG):
+        run = (g[:, j] >= 3) & (g[:, j - 1] >= 3)
+        g[run, j] = g[run, j - 1]
+    modes = ((f1 * 13 + f2) * 5 + g).astype(np.int32)
+    modes[np.arange(MAXSEG)[None, :] >= K[:, None]] = 0
+    return K.astype(np.int32), modes
+
+
+def flip_batch(seed: int, B: int, n_pairs: int = 32, kmin: int = 1, kmax: int = 6, knots: int = 10) -> dict:
+    """Ragged flipping batch: B orders spread over n_pairs start/goal pairs, `knots`
+    intervals per segment."""
+    rng = np.random.default_rng(seed)
+    x0, goal, inst = flip_pairs(seed + 1, n_pairs)
+    pair = rng.integers(0, n_pairs, B)
+    nseg, modes = flip_orders(rng, B, kmin, kmax)
+    kn = np.where(np.arange(MAXSEG)[None, :] < nseg[:, None], knots, 0).astype(np.int32)
+    return dict(x0=x0[pair], goal=goal[pair], inst=inst[pair], nseg=nseg, modes=modes, knots=kn)
+
+
+def flip_tiny(seed: int = 3000, B: int = 512) -> dict:
+    """Small flipping batch for parity: K ~ U{1..3}, 5 intervals per segment."""
+    return flip_batch(seed, B, n_pairs=8, kmin=1, kmax=3, knots=5)

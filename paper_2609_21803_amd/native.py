@@ -15,7 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcomet.so")
 
 COMET_OK, COMET_EINVAL, COMET_EHIP, COMET_ENOMEM, COMET_ESTATE = 0, -1, -2, -3, -4
-TASK_PUSH = 0
+TASK_PUSH, TASK_FLIP = 0, 1
+ROW_WIDTH = {TASK_PUSH: 7, TASK_FLIP: 17}   # trajectory row (x_k, u_k)
 
 
 class SolverParamsC(C.Structure):
@@ -181,6 +182,14 @@ def _stream(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
+def _torch_device_first():
+    """Initialise torch's device runtime before the library's first device call: torch
+    owns the device memory and streams handed to the library, and its runtime must be
+    the first to open the device in the process."""
+    import torch
+    torch.cuda.current_device()
+
+
 def check(rc: int, ctx=None):
     if rc != COMET_OK:
         msg = lib().comet_last_error(ctx).decode() if ctx else ""
@@ -192,6 +201,7 @@ class Context:
 
     def __init__(self, max_batch: int, max_segments: int = 6, max_intervals: int = 24,
                  params: SolverParams | None = None, task: int = TASK_PUSH):
+        _torch_device_first()
         self._h = C.c_void_p()
         self.params = params or SolverParams()
         p = self.params.c()
@@ -199,6 +209,7 @@ class Context:
                                 C.byref(self._h))
         if rc != COMET_OK:
             raise CometError(f"comet_create failed with status {rc}")
+        self.task = int(task)
         self.max_batch, self.max_segments, self.max_intervals = int(max_batch), int(max_segments), int(max_intervals)
 
     def close(self):
@@ -268,7 +279,7 @@ class Context:
         if feasible is None:
             feasible = torch.empty(B, dtype=torch.uint8, device=dev)
         if traj is None and want_traj:
-            traj = torch.empty((B, self.max_intervals + 1, 7), dtype=torch.float32, device=dev)
+            traj = torch.empty((B, self.max_intervals + 1, ROW_WIDTH[self.task]), dtype=torch.float32, device=dev)
         if stats is None and want_stats:
             stats = torch.empty((B, 4), dtype=torch.int32, device=dev)
         rc = lib().comet_evaluate(self._h, _stream(stream), B, _ptr(x0), _ptr(goal), _ptr(inst), _ptr(nseg),
@@ -325,6 +336,7 @@ class MLP:
     IN, HIDDEN, LAYERS, OUT = 416, 512, 4, 736
 
     def __init__(self, max_batch=8192, seed=0, in_dim=IN, hidden=HIDDEN, layers=LAYERS, out_dim=OUT):
+        _torch_device_first()
         self._h = C.c_void_p()
         rc = lib().comet_mlp_create(in_dim, hidden, layers, out_dim, int(max_batch), int(seed), C.byref(self._h))
         if rc != COMET_OK:
