@@ -43,7 +43,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        from . import SolverParams
+        from . import ExpandParams, SolverParams
         L = C.CDLL(build())
         P = C.c_void_p
         L.flip_evaluate.argtypes = [C.c_int64, C.c_int32, C.c_int32, P, P, P, P, P, P, P,
@@ -56,6 +56,12 @@ def lib():
                                            P, P, P]
         L.flip_score.argtypes = [C.c_int32, P, P, P, P, C.c_double, P, P, P]
         L.flip_admissible.argtypes = [C.c_int32, P]
+        L.flip_seed.argtypes = [C.c_int32, C.c_int64, P]
+        L.flip_seed.restype = C.c_int64
+        L.flip_expand_next.argtypes = [C.c_int64, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int64, P]
+        L.flip_expand_next.restype = C.c_int64
+        L.flip_expand.argtypes = [P, P, C.c_double, C.POINTER(ExpandParams), C.POINTER(SolverParams),
+                                  C.POINTER(SolverParams), C.c_int32, P, P, P, P, P, P, P, C.c_int64]
         _lib = L
     return _lib
 
@@ -170,3 +176,47 @@ class Seq:
 def admissible(modes) -> bool:
     m = _i32(list(modes))
     return bool(lib().flip_admissible(len(m), _p(m)))
+
+
+def key_make(modes) -> int:
+    k = len(modes) << 60
+    for i, m in enumerate(modes):
+        k |= int(m) << (50 - 10 * i)
+    return k
+
+
+def key_modes(k: int):
+    return [(k >> (50 - 10 * i)) & 1023 for i in range(k >> 60)]
+
+
+def seed(kmax: int, cap: int = 10 ** 7) -> np.ndarray:
+    out = np.zeros(min(cap, 10 ** 7), np.uint64)
+    n = lib().flip_seed(kmax, len(out), _p(out))
+    return out[:n]
+
+
+def expand_next(keys, merit, kcap, radius, W, room) -> np.ndarray:
+    keys = np.ascontiguousarray(keys, np.uint64)
+    merit = _f64(merit)
+    out = np.zeros(max(room, 1), np.uint64)
+    n = lib().flip_expand_next(len(keys), _p(keys), _p(merit), kcap, radius, W, room, _p(out))
+    return out[:n]
+
+
+def expand(x0, goal, mu_g, ep, params=None, ref_params=None, nthreads=None, eval_cap=200000):
+    """Greedy expansion with refinement on one instance; returns (best_key, J, v,
+    counters, evaluated keys, their J, v)."""
+    from . import REFINE, Params
+    params = params or Params()
+    ref_params = ref_params or Params(**{**params.__dict__, **REFINE})
+    bk = C.c_uint64()
+    bJ, bv = C.c_double(), C.c_double()
+    cnt = np.zeros(4, np.int64)
+    ek = np.zeros(eval_cap, np.uint64)
+    eJ, ev = np.zeros(eval_cap), np.zeros(eval_cap)
+    pe, pr, epc = params.c(), ref_params.c(), ep.c()
+    lib().flip_expand(_p(_f64(x0)), _p(_f64(goal)), float(mu_g), C.byref(epc), C.byref(pe), C.byref(pr),
+                      nthreads or default_threads(), C.byref(bk), C.byref(bJ), C.byref(bv), _p(cnt), _p(ek), _p(eJ),
+                      _p(ev), eval_cap)
+    n = int(min(cnt[0], eval_cap))
+    return bk.value, bJ.value, bv.value, cnt, ek[:n], eJ[:n], ev[:n]

@@ -1051,3 +1051,328 @@ int flip_admissible(int32_t K, const int32_t *modes) {
   }
   return 1;
 }
+
+/* ================================================================================ */
+/* Greedy contact-mode expansion (Alg. 1) over the flip language.                    */
+/* ================================================================================ */
+/* key = K << 60 | m_0 << 50 | ... | m_5 << 0 (10 bits per id): comparing keys       */
+/* compares (K, m_0, m_1, ...) lexicographically.                                    */
+typedef uint64_t FKey;
+
+static FKey fkey_make(int K, const int *m) {
+  FKey k = (FKey)K << 60;
+  int i;
+  for (i = 0; i < K; ++i) k |= (FKey)m[i] << (50 - 10 * i);
+  return k;
+}
+static int fkey_len(FKey k) { return (int)(k >> 60); }
+static int fkey_mode(FKey k, int i) { return (int)((k >> (50 - 10 * i)) & 1023u); }
+
+static int admissible_key(FKey k) {
+  int32_t m[FMAXSEG];
+  int i, K = fkey_len(k);
+  for (i = 0; i < K; ++i) m[i] = fkey_mode(k, i);
+  return flip_admissible(K, m);
+}
+
+typedef struct {
+  FKey *slot;
+  int64_t cap;
+} FSet;
+
+static void fset_init(FSet *S, int64_t n) {
+  int64_t c = 16;
+  while (c < 2 * n + 16) c <<= 1;
+  S->cap = c;
+  S->slot = (FKey *)calloc((size_t)c, sizeof(FKey));
+}
+static uint64_t fmix(uint64_t x) {
+  x ^= x >> 33; x *= 0xff51afd7ed558ccdULL;
+  x ^= x >> 33; x *= 0xc4ceb9fe1a85ec53ULL;
+  x ^= x >> 33;
+  return x;
+}
+static int fset_has(const FSet *S, FKey k) {
+  int64_t i = (int64_t)(fmix(k) & (uint64_t)(S->cap - 1));
+  while (S->slot[i]) {
+    if (S->slot[i] == k) return 1;
+    i = (i + 1) & (S->cap - 1);
+  }
+  return 0;
+}
+static void fset_add(FSet *S, FKey k) {
+  int64_t i = (int64_t)(fmix(k) & (uint64_t)(S->cap - 1));
+  while (S->slot[i]) {
+    if (S->slot[i] == k) return;
+    i = (i + 1) & (S->cap - 1);
+  }
+  S->slot[i] = k;
+}
+
+/* one-edit list in enumeration order: substitutions (position, then id, skipping   */
+/* the current id), deletions (position; K > 1), insertions (position 0..K, then id; */
+/* K < kcap); in-list repeats kept                                                   */
+static int64_t fneigh1(FKey p, int kcap, FKey *out) {
+  int K = fkey_len(p), m[FMAXSEG], q[FMAXSEG], i, j, id;
+  int64_t n = 0;
+  for (i = 0; i < K; ++i) m[i] = fkey_mode(p, i);
+  for (i = 0; i < K; ++i)
+    for (id = 0; id < FNMODES; ++id) {
+      if (id == m[i]) continue;
+      for (j = 0; j < K; ++j) q[j] = m[j];
+      q[i] = id;
+      out[n++] = fkey_make(K, q);
+    }
+  if (K > 1)
+    for (i = 0; i < K; ++i) {
+      int t = 0;
+      for (j = 0; j < K; ++j)
+        if (j != i) q[t++] = m[j];
+      out[n++] = fkey_make(K - 1, q);
+    }
+  if (K < kcap)
+    for (i = 0; i <= K; ++i)
+      for (id = 0; id < FNMODES; ++id) {
+        int t = 0;
+        for (j = 0; j < i; ++j) q[t++] = m[j];
+        q[t++] = id;
+        for (j = i; j < K; ++j) q[t++] = m[j];
+        out[n++] = fkey_make(K + 1, q);
+      }
+  return n;
+}
+
+/* r-edit neighbourhood (r in {1, 2}): the one-edit list, then the one-edit lists of  */
+/* its entries in order; first occurrence wins, the order itself excluded; only      */
+/* admissible orders are returned (intermediate orders of r = 2 need not be)          */
+static int64_t fneigh(FKey p, int kcap, int r, FKey *out) {
+  int64_t cap1 = (int64_t)(2 * kcap + 2) * FNMODES + 16;
+  FKey *l1 = (FKey *)malloc(sizeof(FKey) * (size_t)cap1);
+  FKey *l2 = (FKey *)malloc(sizeof(FKey) * (size_t)cap1);
+  int64_t n1 = fneigh1(p, kcap, l1), n = 0, i, j;
+  FSet seen;
+  fset_init(&seen, (r >= 2) ? n1 * cap1 / 4 + n1 : n1);
+  fset_add(&seen, p);
+  for (i = 0; i < n1; ++i)
+    if (!fset_has(&seen, l1[i])) {
+      fset_add(&seen, l1[i]);
+      if (admissible_key(l1[i])) out[n++] = l1[i];
+    }
+  if (r >= 2)
+    for (i = 0; i < n1; ++i) {
+      int64_t n2 = fneigh1(l1[i], kcap, l2);
+      for (j = 0; j < n2; ++j)
+        if (!fset_has(&seen, l2[j])) {
+          fset_add(&seen, l2[j]);
+          if (admissible_key(l2[j])) out[n++] = l2[j];
+        }
+    }
+  free(l1);
+  free(l2);
+  free(seen.slot);
+  return n;
+}
+
+typedef struct {
+  FKey key;
+  double J, v, M;
+} FEntry;
+
+static int cmp_fentry(const void *a, const void *b) {
+  const FEntry *x = (const FEntry *)a, *y = (const FEntry *)b;
+  const double mx = isnan(x->M) ? INFINITY : x->M, my = isnan(y->M) ? INFINITY : y->M;
+  if (mx < my) return -1;
+  if (mx > my) return 1;
+  return (x->key < y->key) ? -1 : (x->key > y->key) ? 1 : 0;
+}
+
+/* seed: admissible orders of 1..kmax segments in key order, at most cap */
+int64_t flip_seed(int32_t kmax, int64_t cap, uint64_t *out) {
+  int64_t n = 0;
+  int K, i, q[FMAXSEG];
+  for (K = 1; K <= kmax && n < cap; ++K) {
+    int64_t total = 1, c;
+    for (i = 0; i < K; ++i) total *= FNMODES;
+    for (c = 0; c < total && n < cap; ++c) {
+      int64_t t = c;
+      for (i = K - 1; i >= 0; --i) {
+        q[i] = (int)(t % FNMODES);
+        t /= FNMODES;
+      }
+      {
+        FKey k = fkey_make(K, q);
+        if (admissible_key(k)) out[n++] = k;
+      }
+    }
+  }
+  return n;
+}
+
+/* one batch-construction step: rank V by (merit, key), traverse at most W parents,   */
+/* admit their unseen admissible r-edit neighbours in order until `room` are admitted */
+int64_t flip_expand_next(int64_t n, const uint64_t *keys, const double *merit, int32_t kcap, int32_t radius,
+                         int32_t frontier_W, int64_t room, uint64_t *out_keys) {
+  FEntry *R = (FEntry *)malloc(sizeof(FEntry) * (size_t)(n + 1));
+  int64_t cap = (radius >= 2) ? 40000000 : (int64_t)(2 * kcap + 2) * FNMODES + 16;
+  FKey *nb = (FKey *)malloc(sizeof(FKey) * (size_t)cap);
+  FSet seen;
+  int64_t i, j, nF = 0;
+  fset_init(&seen, n + room + 16);
+  for (i = 0; i < n; ++i) {
+    R[i].key = keys[i];
+    R[i].M = isnan(merit[i]) ? INFINITY : merit[i];
+    R[i].J = R[i].v = 0.0;
+    fset_add(&seen, keys[i]);
+  }
+  qsort(R, (size_t)n, sizeof(FEntry), cmp_fentry);
+  for (i = 0; i < n && i < frontier_W && nF < room; ++i) {
+    int64_t m = fneigh(R[i].key, kcap, radius, nb);
+    for (j = 0; j < m && nF < room; ++j)
+      if (!fset_has(&seen, nb[j])) {
+        fset_add(&seen, nb[j]);
+        out_keys[nF++] = nb[j];
+      }
+  }
+  free(R);
+  free(nb);
+  free(seen.slot);
+  return nF;
+}
+
+typedef struct {
+  int32_t kcap, seed_max_segments, radius, rounds, frontier_W, knots_per_segment, k_ref, n_total;
+  int64_t batch_B, eval_budget;
+  double mu_merit;
+} FlipExpandParams;
+
+static void fknots(int K, const FlipExpandParams *ep, int32_t *kn) {
+  int j;
+  for (j = 0; j < K; ++j)
+    kn[j] = (ep->knots_per_segment > 0) ? ep->knots_per_segment
+                                        : ep->n_total / K + ((j < ep->n_total % K) ? 1 : 0);
+}
+
+static void feval_keys(const FKey *keys, int64_t n, const double *x0, const double *goal, double mu_g,
+                       const FlipExpandParams *ep, const FlipParams *prm, int nthreads, double *J, double *v) {
+  int32_t *nseg = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  int32_t *modes = (int32_t *)calloc((size_t)(n + 1) * FMAXSEG, sizeof(int32_t));
+  int32_t *kn = (int32_t *)calloc((size_t)(n + 1) * FMAXSEG, sizeof(int32_t));
+  double *X0 = (double *)malloc(sizeof(double) * (size_t)(n + 1) * FNX);
+  double *G = (double *)malloc(sizeof(double) * (size_t)(n + 1) * 2);
+  double *Iv = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+  uint8_t *f = (uint8_t *)malloc((size_t)(n + 1));
+  int64_t b;
+  int i, nmax = 1;
+  for (b = 0; b < n; ++b) {
+    const int K = fkey_len(keys[b]);
+    int tot = 0;
+    nseg[b] = K;
+    for (i = 0; i < K; ++i) modes[b * FMAXSEG + i] = fkey_mode(keys[b], i);
+    fknots(K, ep, &kn[b * FMAXSEG]);
+    for (i = 0; i < K; ++i) tot += kn[b * FMAXSEG + i];
+    if (tot > nmax) nmax = tot;
+    for (i = 0; i < FNX; ++i) X0[b * FNX + i] = x0[i];
+    G[b * 2 + 0] = goal[0];
+    G[b * 2 + 1] = goal[1];
+    Iv[b] = mu_g;
+  }
+  flip_evaluate(n, FMAXSEG, nmax, X0, G, Iv, nseg, modes, kn, NULL, prm, nthreads, J, v, f, NULL, NULL);
+  free(nseg); free(modes); free(kn); free(X0); free(G); free(Iv); free(f);
+}
+
+/* Greedy expansion with refinement on one instance: counters = (evaluated, rounds,   */
+/* feasible found, 1-based evaluation index of the first feasible order); the        */
+/* evaluated keys with (J, v) in evaluation order if eval_keys_out is given.          */
+int flip_expand(const double *x0, const double *goal, double mu_g, const FlipExpandParams *ep,
+                const FlipParams *prm_exp, const FlipParams *prm_ref, int32_t nthreads, uint64_t *best_key,
+                double *best_J, double *best_v, int64_t *counters, uint64_t *eval_keys_out, double *eval_J_out,
+                double *eval_v_out, int64_t eval_cap) {
+  int64_t cap = ep->eval_budget + 16, nV = 0, nF = 0, i;
+  FEntry *V = (FEntry *)malloc(sizeof(FEntry) * (size_t)cap);
+  FEntry *R = (FEntry *)malloc(sizeof(FEntry) * (size_t)cap);
+  FKey *F = (FKey *)malloc(sizeof(FKey) * (size_t)(ep->batch_B + 16));
+  double *J = (double *)malloc(sizeof(double) * (size_t)(ep->batch_B + 16));
+  double *v = (double *)malloc(sizeof(double) * (size_t)(ep->batch_B + 16));
+  int s;
+  int64_t first_feasible = 0, n_feas = 0, rounds_run = 0;
+  {
+    const int kmax = ep->seed_max_segments < ep->kcap ? ep->seed_max_segments : ep->kcap;
+    int64_t lim = ep->batch_B < ep->eval_budget ? ep->batch_B : ep->eval_budget;
+    nF = flip_seed(kmax, lim, F);
+  }
+  for (s = 0; nF > 0 && s <= ep->rounds; ++s) {
+    int64_t room;
+    feval_keys(F, nF, x0, goal, mu_g, ep, prm_exp, nthreads, J, v);
+    ++rounds_run;
+    for (i = 0; i < nF; ++i) {
+      double M = NAN;
+      if (!isnan(J[i]) && !isnan(v[i])) M = J[i] + ep->mu_merit * fmax(v[i] - prm_exp->eps_feas, 0.0);
+      V[nV].key = F[i];
+      V[nV].J = J[i];
+      V[nV].v = v[i];
+      V[nV].M = isnan(M) ? INFINITY : M;
+      if (eval_keys_out && nV < eval_cap) {
+        eval_keys_out[nV] = F[i];
+        eval_J_out[nV] = J[i];
+        eval_v_out[nV] = v[i];
+      }
+      if (v[i] <= prm_exp->eps_feas) {
+        ++n_feas;
+        if (!first_feasible) first_feasible = nV + 1;
+      }
+      ++nV;
+    }
+    nF = 0;
+    if (s == ep->rounds) break;
+    room = ep->batch_B;
+    if (ep->eval_budget - nV < room) room = ep->eval_budget - nV;
+    if (room <= 0) break;
+    {
+      uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)nV);
+      double *mer = (double *)malloc(sizeof(double) * (size_t)nV);
+      for (i = 0; i < nV; ++i) {
+        keys[i] = V[i].key;
+        mer[i] = V[i].M;
+      }
+      nF = flip_expand_next(nV, keys, mer, ep->kcap, ep->radius, ep->frontier_W, room, F);
+      free(keys);
+      free(mer);
+    }
+  }
+  counters[0] = nV;
+  counters[1] = rounds_run;
+  counters[2] = n_feas;
+  counters[3] = first_feasible;
+  {
+    int64_t nR = 0, nref;
+    FKey *rk;
+    double *rJ, *rv;
+    for (i = 0; i < nV; ++i)
+      if (V[i].v <= prm_exp->eps_feas && isfinite(V[i].J)) {
+        R[nR] = V[i];
+        R[nR].M = V[i].J;
+        ++nR;
+      }
+    qsort(R, (size_t)nR, sizeof(FEntry), cmp_fentry);
+    nref = nR < ep->k_ref ? nR : ep->k_ref;
+    rk = (FKey *)malloc(sizeof(FKey) * (size_t)(nref + 1));
+    rJ = (double *)malloc(sizeof(double) * (size_t)(nref + 1));
+    rv = (double *)malloc(sizeof(double) * (size_t)(nref + 1));
+    for (i = 0; i < nref; ++i) rk[i] = R[i].key;
+    if (nref > 0) feval_keys(rk, nref, x0, goal, mu_g, ep, prm_ref, nthreads, rJ, rv);
+    *best_key = 0;
+    *best_J = NAN;
+    *best_v = INFINITY;
+    for (i = 0; i < nref; ++i) {
+      if (!(rv[i] <= prm_ref->eps_feas) || !isfinite(rJ[i])) continue;
+      if (*best_key == 0 || rJ[i] < *best_J || (rJ[i] == *best_J && rk[i] < *best_key)) {
+        *best_key = rk[i];
+        *best_J = rJ[i];
+        *best_v = rv[i];
+      }
+    }
+    free(rk); free(rJ); free(rv);
+  }
+  free(V); free(R); free(F); free(J); free(v);
+  return 0;
+}

@@ -316,3 +316,94 @@ def test_invalid_orders_score_as_infeasible():
     r = F.evaluate(np.stack([F.X0] * 3), np.zeros((3, 2)), np.full(3, 0.7), np.array([1, 2, 1]), mm, kk)
     assert np.isnan(r["cost"][0]) and np.isnan(r["cost"][1]) and r["stats"][1, 3] == 3
     assert r["feasible"][2] == 1
+
+
+# ---------------------------------------------------------------------------------
+# Expansion over the flip language (Alg. 1)
+# ---------------------------------------------------------------------------------
+def _neigh1_py(modes, kcap, M=F.N_MODES):
+    """one-edit list in enumeration order (substitutions, deletions, insertions)"""
+    K, out = len(modes), []
+    for i in range(K):
+        for idx in range(M):
+            if idx != modes[i]:
+                out.append(modes[:i] + [idx] + modes[i + 1:])
+    if K > 1:
+        for i in range(K):
+            out.append(modes[:i] + modes[i + 1:])
+    if K < kcap:
+        for i in range(K + 1):
+            for idx in range(M):
+                out.append(modes[:i] + [idx] + modes[i:])
+    return out
+
+
+def _expand_next_py(V, merit, kcap, W, room):
+    order = sorted(range(len(V)), key=lambda i: (merit[i], F.key_make(V[i])))
+    seen = {tuple(v) for v in V}
+    out = []
+    for i in order[:W]:
+        for nb in _neigh1_py(list(V[i]), kcap):
+            if len(out) >= room:
+                return out
+            t = tuple(nb)
+            if t in seen:
+                continue
+            seen.add(t)
+            if _admissible_py(nb):
+                out.append(nb)
+    return out
+
+
+def test_seed_is_the_admissible_single_segments_in_key_order():
+    s = F.seed(1)
+    assert [F.key_modes(int(k)) for k in s] == [[m] for m in range(F.N_MODES) if _admissible_py([m])]
+
+
+@pytest.mark.parametrize("kcap,W,room,seed", [(2, 3, 500, 0), (3, 8, 4000, 1), (2, 50, 100000, 2)])
+def test_batch_construction_matches_brute_force(kcap, W, room, seed):
+    """One batch-construction step: rank by (merit, key), traverse W parents, admit unseen
+    admissible one-edit neighbours in enumeration order (independent set-based code)."""
+    rng = np.random.default_rng(seed)
+    pool = [F.key_modes(int(k)) for k in F.seed(1)]
+    V = [pool[i] for i in rng.choice(len(pool), 60, replace=False)]
+    V += [V[i] + pool[int(rng.integers(len(pool)))] for i in range(10)]
+    V = [v for v in V if _admissible_py(v)]
+    merit = rng.choice([0.5, 1.0, 2.0, np.inf], len(V))
+    keys = np.array([F.key_make(v) for v in V], np.uint64)
+    got = F.expand_next(keys, merit, kcap, 1, W, room)
+    ref = _expand_next_py(V, list(merit), kcap, W, room)
+    assert [F.key_modes(int(k)) for k in got] == ref
+
+
+def test_expansion_over_the_whole_single_segment_space_returns_the_enumeration_argmin():
+    """With K_cap = 1 the seed is the whole admissible space: the returned plan is the
+    refined argmin over all 279 orders, computed here by direct evaluation."""
+    goal = (0.04, 0.0)
+    ep = oracle_expand_params(kcap=1, seed_max_segments=1, rounds=0, frontier_W=1, knots_per_segment=8, k_ref=4,
+                              batch_B=1000, eval_budget=1000)
+    bk, bJ, bv, cnt, ek, eJ, ev = F.expand(F.X0, goal, 0.7, ep)
+    assert cnt[0] == 279
+    ones = [m for m in range(F.N_MODES) if _admissible_py([m])]
+    B = len(ones)
+    r = F.evaluate(np.tile(F.X0, (B, 1)), np.tile(goal, (B, 1)), np.full(B, 0.7), np.ones(B, np.int32),
+                   np.array([[m, 0, 0, 0, 0, 0] for m in ones]), np.array([[8, 0, 0, 0, 0, 0]] * B))
+    assert np.array_equal(eJ, r["cost"]) and np.array_equal(ev, r["viol"])
+    feas = np.where(r["feasible"] == 1)[0]
+    assert len(feas) >= 1 and cnt[2] == len(feas)
+    best4 = sorted(feas, key=lambda i: (r["cost"][i], ones[i]))[:4]
+    import oracle
+    rr = F.evaluate(np.tile(F.X0, (len(best4), 1)), np.tile(goal, (len(best4), 1)), np.full(len(best4), 0.7),
+                    np.ones(len(best4), np.int32), np.array([[ones[i], 0, 0, 0, 0, 0] for i in best4]),
+                    np.array([[8, 0, 0, 0, 0, 0]] * len(best4)), params=oracle.Params(**oracle.REFINE))
+    ok = [j for j in range(len(best4)) if rr["feasible"][j]]
+    j = min(ok, key=lambda j: (rr["cost"][j], ones[best4[j]]))
+    assert F.key_modes(int(bk)) == [ones[best4[j]]] and bJ == rr["cost"][j]
+
+
+def oracle_expand_params(**kw):
+    import oracle
+    e = oracle.Expand()
+    for k, v in kw.items():
+        setattr(e, k, v)
+    return e
