@@ -11,7 +11,9 @@ cores), times its training step and batched inference against the BF16 matrix-co
 and compares the device time to the first feasible plan of the plain and the learned
 expansion on held-out instances.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu] [--no-learned]
+The flipping leg times one round of the bimanual-flipping workload (32,768 orders).
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu] [--no-learned] [--no-flip]
 """
 from __future__ import annotations
 
@@ -34,6 +36,12 @@ FLOP_PER_INTERVAL_GN = 2400.0
 FLOP_PER_INTERVAL_AL = 40.0
 PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak
 PEAK_BF16_TFLOPS = 2500.0    # MI355X published dense BF16 matrix-core peak
+PEAK_FP64_TFLOPS = 78.6      # MI355X published FP64 vector peak
+# Flipping task (17 stage unknowns, 32 row slots), structure-aware work per interval per
+# Gauss-Newton iteration: linearisation ~0.3 kflop, block assembly ~0.8, 17 x 17 Cholesky
+# ~1.6, the 9 right-hand sides ~5.2, value function ~2.2, forward pass ~0.3, trial steps
+# ~1.2: ~10 kflop (FP64).
+FLIP_FLOP_PER_INTERVAL_GN = 10000.0
 HBM_PEAK_GBS = 8000.0
 
 
@@ -96,6 +104,33 @@ def mlp_flops(B, dims, train):
         f += sum(2.0 * B * k * n for k, n in layers)             # weight gradients
         f += sum(2.0 * B * k * n for k, n in layers[1:])         # input gradients (not for the input layer)
     return f
+
+
+def flip_leg(native, I, torch, B=32768):
+    """One round of the bimanual-flipping workload: B orders (K ~ U{1..6}, 10 intervals per
+    segment) on 32 seeded start/goal pairs, one launch timed after one warm-up launch."""
+    b = I.flip_batch(3100, B)
+    ctx = native.Context(max_batch=B, max_intervals=60, task=native.TASK_FLIP)
+    d = native.to_device(b)
+    out = ctx.evaluate(**d)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    out = ctx.evaluate(**d)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kms = ctx.kernel_ms()
+    st = out["stats"].cpu().numpy()
+    N = I.n_intervals(b).astype(np.float64)
+    flops = float((st[:, 1] * N).sum()) * FLIP_FLOP_PER_INTERVAL_GN
+    ach = flops / (kms * 1e-3) / 1e12
+    return {"workload": f"bimanual flipping: {B} orders, K ~ U{{1..6}}, 10 intervals per segment, 32 start/goal pairs "
+                        "(goal th ~ U[pi/2, pi], px ~ U[-0.2, 0.2] m), AL<=20 x GN<=10, FP64",
+            "value": B / (ms * 1e-3), "unit": "solves/s", "ms": ms, "mean_gn_iterations": float(st[:, 1].mean()),
+            "mean_intervals": float(N.mean()), "feasible_fraction": float(out["feasible"].float().mean().item()),
+            "roofline": {"bound": "alu", "kernel": "k_flip_solve", "achieved": ach, "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "kernel_ms": kms, "flop": flops}}
 
 
 def learned_leg(native, I, torch):
@@ -173,6 +208,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal leg")
+    ap.add_argument("--no-flip", action="store_true", help="skip the flipping leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -254,6 +290,8 @@ def main():
                      "kernel": "k_push_solve", "kernel_ms": kms, "flop_per_launch": flops},
         "wall_s_timed": wall,
     }
+    if not args.no_flip:
+        res["flip"] = flip_leg(native, I, torch)
     if not args.no_learned:
         res["learned"] = learned_leg(native, I, torch)
     if not args.no_cpu:

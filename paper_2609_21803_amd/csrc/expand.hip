@@ -92,6 +92,39 @@ __host__ __device__ inline unsigned long long raw_decode(unsigned long long p, l
   return (e2 < raw1_count(key_len(k1), M, kcap)) ? raw1_decode(k1, e2, M, kcap) : EMPTY;
 }
 
+// Admissibility of a flipping order (the transition rules of Sec. V, with the readings
+// of the flip model): fingers never share a face; a finger changes face only through a
+// free segment; a pivot keeps at least one finger in contact; no two consecutive segments
+// are equal; consecutive pivots keep their direction; no finger touches the face on the
+// table (the support face while supported; the support and the landing face in a pivot).
+// Ids: (f1 * 13 + f2) * 5 + g, finger 0 free / 1 + 3 face + slip; the support starts on
+// face 3 and a pivot run followed by a supported segment lands on the next face.
+__device__ inline bool flip_admissible_key(unsigned long long k) {
+  const int K = key_len(k);
+  int fs = 3, prev_g = -1, prev_id = -1, pa = -1, pb = -1;
+  for (int j = 0; j < K; ++j) {
+    const int id = key_mode(k, j);
+    if (id >= 845 || id == prev_id) return false;
+    const int g = id % 5, c2 = (id / 5) % 13, c1 = id / 65;
+    if (g >= 3 && prev_g >= 3 && g != prev_g) return false;
+    if (g <= 2 && prev_g >= 3) fs = (fs + (prev_g == 3 ? 3 : 1)) & 3;
+    const int a = c1 ? (c1 - 1) / 3 : -1, b = c2 ? (c2 - 1) / 3 : -1;
+    if (a >= 0 && a == b) return false;
+    if (g >= 3 && a < 0 && b < 0) return false;
+    if (a == fs || b == fs) return false;
+    if (g >= 3) {
+      const int landing = (fs + (g == 3 ? 3 : 1)) & 3;
+      if (a == landing || b == landing) return false;
+    }
+    if ((pa >= 0 && a >= 0 && pa != a) || (pb >= 0 && b >= 0 && pb != b)) return false;
+    pa = a;
+    pb = b;
+    prev_g = g;
+    prev_id = id;
+  }
+  return true;
+}
+
 __device__ inline unsigned long long hash_slot(unsigned long long k, unsigned long long mask) {
   return (k * 0x9E3779B97F4A7C15ull) >> 17 & mask;
 }
@@ -309,6 +342,7 @@ struct ExpCounters {
 
 struct ExpCfg {
   int M, kcap, radius, W, raw1max, knots_per_segment, n_total, k_ref;
+  int task, row;                 // task, trajectory row width (x_k, u_k)
   long long rawmax, Bmax, budget, Vcap;
   unsigned long long vmask, cmask;
   double eps, mu_merit;
@@ -343,6 +377,36 @@ __global__ void k_seed(ExpCfg g, int kmax, long long n_seed, ExpCounters* C, uns
   const unsigned long long k = key_make(K, q);
   F[t] = k;
   set_insert(vset, g.vmask, k);
+}
+
+// seed as candidates (languages with a filter): slot t holds the t-th order of 1..kmax
+// segments in key order, or EMPTY if it is not admissible; the candidate pipeline then
+// keeps the admissible ones in order
+__global__ void k_seed_cand(ExpCfg g, int kmax, long long n_seed, ExpCounters* C, unsigned long long* ckey,
+                            unsigned long long* hkeys, unsigned* hmin) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    C->nCand = n_seed;
+    C->room = min(g.Bmax, g.budget);
+    C->kept = 0;
+  }
+  if (t >= n_seed) return;
+  long long c = t, cnt = g.M;
+  int K = 1;
+  while (K < kmax && c >= cnt) {
+    c -= cnt;
+    ++K;
+    cnt *= g.M;
+  }
+  int q[6];
+  for (int i = K - 1; i >= 0; --i) {
+    q[i] = (int)(c % g.M);
+    c /= g.M;
+  }
+  unsigned long long k = key_make(K, q);
+  if (g.task == COMET_TASK_FLIP && !flip_admissible_key(k)) k = EMPTY;
+  ckey[t] = k;
+  if (k != EMPTY) first_insert(hkeys, hmin, g.cmask, k, (unsigned)t);
 }
 
 // batch keys -> evaluator inputs (segment counts, ids, interval allocation)
@@ -413,6 +477,7 @@ __global__ void k_gen(ExpCfg g, const ExpCounters* C, const unsigned* ranked, co
   const long long p = t / g.rawmax, e = t % g.rawmax;
   const unsigned long long parent = vkey[ranked[p]];
   unsigned long long k = raw_decode(parent, e, g.M, g.kcap, g.radius, g.raw1max);
+  if (k != EMPTY && g.task == COMET_TASK_FLIP && !flip_admissible_key(k)) k = EMPTY;
   if (k != EMPTY && set_has(vset, g.vmask, k)) k = EMPTY;
   ckey[t] = k;
   if (k != EMPTY) first_insert(hkeys, hmin, g.cmask, k, (unsigned)t);
@@ -542,8 +607,8 @@ __global__ void k_best_out(ExpCfg g, const ExpCounters* C, const float* rtraj, i
                          : 0;
   }
   if (best_traj)
-    for (int i = t; i < nmax1 * 7; i += blockDim.x)
-      best_traj[i] = (C->best_row >= 0) ? rtraj[C->best_row * (long long)nmax1 * 7 + i] : 0.f;
+    for (int i = t; i < nmax1 * g.row; i += blockDim.x)
+      best_traj[i] = (C->best_row >= 0) ? rtraj[C->best_row * (long long)nmax1 * g.row + i] : 0.f;
 }
 
 }  // namespace comet
@@ -580,6 +645,7 @@ struct comet_expand_ws {
   int32_t *fnseg2 = nullptr, *fmodes2 = nullptr, *fknots2 = nullptr;
   float *warm_tmp = nullptr, *warm = nullptr;
   comet_mlp* learned = nullptr;      // network the captured graph uses (null = plain)
+  long long ccap = 0;                // candidate slots allocated (ckey, cflag, cpos)
   hipGraphExec_t gexec = nullptr;
   bool graph_valid = false;
   double wall_khz = 100000.0;
@@ -632,18 +698,27 @@ comet_status check_expand_params(comet_ctx* c, const comet_expand_params* p) {
 }
 
 comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
-  const int M = push::NMODES;
+  const bool flip = (c->task == COMET_TASK_FLIP);
+  const int M = flip ? 845 : push::NMODES;
+  const int rowW = flip ? 17 : 7;
   int raw1max = 0;
   for (int K = 1; K <= p->kcap; ++K) raw1max = std::max(raw1max, raw1_count(K, M, p->kcap));
   const long long rawmax = (p->radius >= 2) ? (long long)raw1max + (long long)raw1max * raw1max : raw1max;
-  const long long ncand = rawmax * p->frontier_W;
+  long long n_seed = 0;
+  for (long long K = 1, t = 1; K <= std::min(p->seed_max_segments, p->kcap); ++K) {
+    t *= M;
+    n_seed += t;
+  }
+  const long long ncand = std::max(rawmax * p->frontier_W, flip ? n_seed : 0ll);
   if (ncand > (1ll << 27)) return fail_msg(c, COMET_EINVAL, "frontier_W x neighbourhood size exceeds 2^27 candidates");
   const long long Vcap = p->eval_budget + p->batch_B + 16;
   comet_expand_ws* w = c->xws;
-  const bool fits = w && w->cfg.Vcap >= Vcap && w->cfg.W * w->cfg.rawmax >= ncand && w->cfg.Bmax >= p->batch_B &&
+  const bool fits = w && w->cfg.Vcap >= Vcap && w->ccap >= ncand && w->cfg.Bmax >= p->batch_B &&
                     w->cfg.k_ref >= p->k_ref;
   ExpCfg g;
   g.M = M;
+  g.task = c->task;
+  g.row = rowW;
   g.kcap = p->kcap;
   g.radius = p->radius;
   g.W = p->frontier_W;
@@ -694,6 +769,7 @@ comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
     A((void**)&w->s_idx[i], 4 * Vcap);
   }
   A((void**)&w->rs_counts, 4 * 256 * w->ntiles_rs);
+  w->ccap = ncand;
   A((void**)&w->ckey, 8 * ncand);
   A((void**)&w->cflag, 4 * ncand);
   A((void**)&w->cpos, 4 * ncand);
@@ -711,7 +787,7 @@ comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
   A((void**)&w->efeas, BR);
   A((void**)&w->ecost64, 8 * BR);
   A((void**)&w->eviol64, 8 * BR);
-  A((void**)&w->rtraj, 4 * kref * nmax1 * 7);
+  A((void**)&w->rtraj, 4 * kref * nmax1 * rowW);
   A((void**)&w->ix0, 4 * 8);
   A((void**)&w->igoal, 4 * 4);
   A((void**)&w->iinst, 4 * 4);
@@ -720,7 +796,7 @@ comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
   A((void**)&w->o_knots, 4 * c->max_segments);
   A((void**)&w->o_cost, 4);
   A((void**)&w->o_viol, 4);
-  A((void**)&w->o_traj, 4 * nmax1 * 7);
+  A((void**)&w->o_traj, 4 * nmax1 * rowW);
   A((void**)&w->dev_nV, 8 * 4);
   A((void**)&w->F2, 8 * BR);
   A((void**)&w->fnseg2, 4 * BR);
@@ -818,6 +894,7 @@ comet_status enqueue_evaluate_batch(comet_ctx* c, hipStream_t s, const long long
   L.refine = refine;
   L.cost = w->ecost; L.viol = w->eviol; L.feas = w->efeas; L.traj = traj;
   L.cost64 = w->ecost64; L.viol64 = w->eviol64; L.t_first = t_first;
+  if (c->task == COMET_TASK_FLIP) return launch_flip(c, s, L);
   return launch_evaluate(c, s, L);
 }
 
@@ -834,7 +911,24 @@ comet_status enqueue_expand(comet_ctx* c, hipStream_t s) {
     t *= g.M;
     n_seed += t;
   }
-  hipLaunchKernelGGL(k_seed, dim3(blocks(n_seed, 256)), dim3(256), 0, s, g, kmax, n_seed, w->C, w->F, w->vset);
+  if (g.task == COMET_TASK_FLIP) {
+    // the flip language filters its seed: all orders of 1..kmax segments as candidates,
+    // kept in key order by the candidate pipeline
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks(g.cmask + 1, 256 * 8)), dim3(256), 0, s, w->hkeys, EMPTY,
+                       (long long)(g.cmask + 1));
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks(g.cmask + 1, 256 * 8)), dim3(256), 0, s, w->hmin, 0xFFFFFFFFu,
+                       (long long)(g.cmask + 1));
+    hipLaunchKernelGGL(k_seed_cand, dim3(blocks(n_seed, 256)), dim3(256), 0, s, g, kmax, n_seed, w->C, w->ckey,
+                       w->hkeys, w->hmin);
+    hipLaunchKernelGGL(k_first, dim3(blocks(n_seed, 256)), dim3(256), 0, s, g, w->C, w->ckey, w->hkeys, w->hmin,
+                       w->cflag);
+    w->scan.run(s, w->cflag, w->cpos, &w->C->nCand, n_seed, &w->C->kept);
+    hipLaunchKernelGGL(k_compact, dim3(blocks(n_seed, 256)), dim3(256), 0, s, g, w->C, w->ckey, w->cflag, w->cpos,
+                       w->F, w->vset);
+    hipLaunchKernelGGL(k_set_batch, dim3(1), dim3(1), 0, s, w->C);
+  } else {
+    hipLaunchKernelGGL(k_seed, dim3(blocks(n_seed, 256)), dim3(256), 0, s, g, kmax, n_seed, w->C, w->F, w->vset);
+  }
   for (int r = 0; r <= p.rounds; ++r) {
     comet_status st = enqueue_evaluate_batch(c, s, &w->C->nF, g.Bmax, 0, nullptr, &w->C->t_first, w->learned);
     if (st != COMET_OK) return st;
@@ -866,11 +960,12 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
                           int32_t* best_modes, int32_t* best_knots, float* best_cost, float* best_viol,
                           float* best_traj, comet_expand_stats* stats) {
   if (!c) return COMET_EINVAL;
-  if (c->task != COMET_TASK_PUSH) return fail_msg(c, COMET_EINVAL, "comet_expand runs the pushing task only");
   if (!x0 || !goal || !inst || !best_nseg || !best_modes || !best_knots || !best_cost || !best_viol)
     return fail_msg(c, COMET_EINVAL, "null input or output pointer");
   comet_status st = check_expand_params(c, params);
   if (st != COMET_OK) return st;
+  const bool flip = (c->task == COMET_TASK_FLIP);
+  if (flip && learned) return fail_msg(c, COMET_EINVAL, "the learned network encodes pushing orders only");
   if (learned && (mlp_max_batch(learned) < params->batch_B || mlp_in_dim(learned) < 400 || mlp_out_dim(learned) < 722))
     return fail_msg(c, COMET_EINVAL, "learned network: max_batch < batch_B, in_dim < 400 or out_dim < 722");
   st = ensure_ws(c, params);
@@ -888,8 +983,8 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
   hipEvent_t e_in, e_t0, e_t1;
   if (hipEventCreate(&e_in) != hipSuccess || hipEventCreate(&e_t0) != hipSuccess || hipEventCreate(&e_t1) != hipSuccess)
     return fail_msg(c, COMET_EHIP, "event creation failed");
-  (void)hipMemcpyAsync(w->ix0, x0, 4 * push::NX, hipMemcpyDeviceToDevice, us);
-  (void)hipMemcpyAsync(w->igoal, goal, 4 * 3, hipMemcpyDeviceToDevice, us);
+  (void)hipMemcpyAsync(w->ix0, x0, 4 * (flip ? 8 : push::NX), hipMemcpyDeviceToDevice, us);
+  (void)hipMemcpyAsync(w->igoal, goal, 4 * (flip ? 2 : 3), hipMemcpyDeviceToDevice, us);
   (void)hipMemcpyAsync(w->iinst, inst, 4 * 1, hipMemcpyDeviceToDevice, us);
   (void)hipEventRecord(e_in, us);
   (void)hipStreamWaitEvent(gs, e_in, 0);
@@ -920,7 +1015,8 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
   (void)hipMemcpyAsync(best_cost, w->o_cost, 4, hipMemcpyDeviceToDevice, gs);
   (void)hipMemcpyAsync(best_viol, w->o_viol, 4, hipMemcpyDeviceToDevice, gs);
   if (best_traj)
-    (void)hipMemcpyAsync(best_traj, w->o_traj, 4 * (size_t)(c->max_intervals + 1) * 7, hipMemcpyDeviceToDevice, gs);
+    (void)hipMemcpyAsync(best_traj, w->o_traj, 4 * (size_t)(c->max_intervals + 1) * w->cfg.row,
+                         hipMemcpyDeviceToDevice, gs);
   ExpCounters hc;
   (void)hipMemcpyAsync(&hc, w->C, sizeof hc, hipMemcpyDeviceToHost, gs);
   const hipError_t se = hipStreamSynchronize(gs);
@@ -948,7 +1044,6 @@ comet_status comet_expand_next(comet_ctx* c, void* stream, int64_t n, const uint
                                const comet_expand_params* params, int64_t room, uint64_t* out_keys,
                                int64_t* out_n) {
   if (!c) return COMET_EINVAL;
-  if (c->task != COMET_TASK_PUSH) return fail_msg(c, COMET_EINVAL, "comet_expand_next runs the pushing task only");
   if (n < 0 || (n > 0 && (!keys || !merit)) || !out_keys || !out_n) return fail_msg(c, COMET_EINVAL, "bad arguments");
   comet_status st = check_expand_params(c, params);
   if (st != COMET_OK) return st;

@@ -87,7 +87,7 @@ struct Wrench {
   Face ff[2];
 };
 
-__device__ inline void wrench(const Stage& S, const double* v, Wrench& w) {
+__device__ __forceinline__ void wrench(const Stage& S, const double* v, Wrench& w) {
   sincos(v[2], &w.s, &w.c);
   sincos(v[V_X1 + 2], &w.s1, &w.c1);
   double Fwx = 0.0, Fwy = 0.0;
@@ -131,7 +131,8 @@ __device__ inline void d_comb(const Wrench& w, double p, double q, double* a) {
 // finger); 12..16 table equalities; 17..26 finger inequalities (five per finger); 27..31
 // table inequalities.
 template <bool JAC>
-__device__ void row(const Stage& S, const Wrench& w, int r, const double* v, double& c, double* a, int& en) {
+__device__ __forceinline__ void row(const Stage& S, const Wrench& w, int r, const double* v, double& c, double* a,
+                                    int& en) {
   c = 0.0;
   en = 0;
   if (r < 8) {
@@ -364,6 +365,8 @@ __device__ inline int term_idx(int t) { return (t == 0) ? 0 : (t == 1) ? 2 : (t 
 struct FlipArgs {
   int64_t B;
   const int64_t* Bdev;
+  int64_t inst_stride;            // 1: per-order instance, 0: one instance for the batch
+  unsigned long long* t_first;    // device timestamp of the first feasible solve (or null)
   int smax, nmax;
   const float *x0, *goal, *inst;
   const int32_t *nseg, *modes, *knots;
@@ -384,6 +387,7 @@ struct Shm {
   double Q[NV][NV + 1];
   double R[NW][NX + 2];   // right-hand sides: column 0 = q_w, 1..8 = Q_wx; then the solution
   double cr[NR], wr[NR], yr[NR];
+  unsigned nzm[NR];       // nonzero columns of each Jacobian row
   double Pm[NX][NX + 1], pv[NX];
   double h[NV];
   double v[NV];           // row arguments of the interval being linearised
@@ -396,6 +400,14 @@ struct Shm {
   double mu_g;
   int N, valid, fail;
 };
+
+// value of x in lane `src` (a compile-time or wave-uniform lane index), in every lane
+__device__ __forceinline__ double bcast(double x, int src) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 // sum over the 64 lanes (result in every lane)
 __device__ inline double wave_sum(double v) {
@@ -417,7 +429,7 @@ __device__ inline void load_args(const FlipArgs& A, const Shm& sh, int64_t b, in
 }
 
 // merit contribution of interval k (cost + rows) at v, and of the terminal rows if k = N-1
-__device__ double stage_merit(const FlipArgs& A, const Shm& sh, int64_t b, int k, const double* v, double mu,
+__device__ __forceinline__ double stage_merit(const FlipArgs& A, const Shm& sh, int64_t b, int k, const double* v, double mu,
                               const double* lamT) {
   const Stage S = unpack(A.code[b * A.nmax + k], sh.mu_g);
   Wrench w;
@@ -454,7 +466,7 @@ __device__ double stage_merit(const FlipArgs& A, const Shm& sh, int64_t b, int k
 // the merit phi and the gradient g of phi (stored per interval in A.g); with `factor`,
 // also the Riccati recursion with damping rho, storing the gains.  Returns 1 if every
 // factorisation succeeded (or factor is false).
-__device__ int sweep(const FlipArgs& A, Shm& sh, int64_t b, bool factor, double mu, double rho,
+__device__ __forceinline__ int sweep(const FlipArgs& A, Shm& sh, int64_t b, bool factor, double mu, double rho,
                      const double* lamT, double& phi_out, double& gnorm_out) {
   const int lane = threadIdx.x, N = sh.N;
   const double imu = 1.0 / mu;
@@ -518,6 +530,10 @@ __device__ int sweep(const FlipArgs& A, Shm& sh, int64_t b, bool factor, double 
       sh.cr[lane] = c;
       sh.yr[lane] = y;
       sh.wr[lane] = wt;
+      unsigned m = 0;
+      if (wt != 0.0)
+        for (int j = 0; j < NV; ++j) m |= (sh.A[lane][j] != 0.0) ? (1u << j) : 0u;
+      sh.nzm[lane] = m;
     } else if (lane < NR + NU) {
       const int i = lane - NR;
       const double u = v[NX + i];
@@ -527,7 +543,8 @@ __device__ int sweep(const FlipArgs& A, Shm& sh, int64_t b, bool factor, double 
     // stage gradient h (no value function) and the gradient of phi for w_k
     if (lane < NV) {
       double s = 0.0;
-      for (int r = 0; r < NR; ++r) s += sh.yr[r] * sh.A[r][lane];
+      for (int r = 0; r < NR; ++r)
+        if (sh.yr[r] != 0.0) s += sh.yr[r] * sh.A[r][lane];
       if (lane >= NX && lane < NX + NU) s += 2.0 * DT * cost_weight(lane - NX) * v[lane];
       sh.h[lane] = s;
     }
@@ -541,95 +558,104 @@ __device__ int sweep(const FlipArgs& A, Shm& sh, int64_t b, bool factor, double 
     if (lane < NX) sh.carry[lane] = sh.h[lane];   // x_k part goes to the previous interval's w
     if (factor && ok) {
       // Gauss-Newton block over y = (x_k, w_k): cost Hessian + (1/mu) sum of active rows
-      // + value function of x_{k+1} + rho on the w block
-      for (int e = lane; e < NV * NV; e += 64) {
-        const int i = e / NV, j = e % NV;
-        if (j < i) continue;
-        double s = 0.0;
-        for (int r = 0; r < NR; ++r) s += sh.wr[r] * sh.A[r][i] * sh.A[r][j];
-        if (i == j && i >= NX && i < NX + NU) s += 2.0 * DT * cost_weight(i - NX);
-        if (i >= NX + NU) s += sh.Pm[i - NX - NU][j - NX - NU];
-        if (i == j && i >= NX) s += rho;
-        sh.Q[i][j] = s;
-        sh.Q[j][i] = s;
+      // + value function of x_{k+1} + rho on the w block.  Lane a < 25 holds row a of the
+      // block in registers (q) and entry a of the stage gradient (hv).
+      double q[NV];
+#pragma unroll
+      for (int j = 0; j < NV; ++j) q[j] = 0.0;
+      double hv = 0.0;
+      if (lane < NV) {
+        for (int r = 0; r < NR; ++r) {
+          const unsigned m = sh.nzm[r];
+          if (!((m >> lane) & 1u)) continue;   // row r does not touch column `lane`
+          const double wa = sh.wr[r] * sh.A[r][lane];
+#pragma unroll
+          for (int j = 0; j < NV; ++j)
+            if ((m >> j) & 1u) q[j] += wa * sh.A[r][j];
+        }
+        hv = sh.h[lane];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+          if (j != lane) continue;
+          if (j >= NX && j < NX + NU) q[j] += 2.0 * DT * cost_weight(j - NX);
+          if (j >= NX) q[j] += rho;
+        }
+        if (lane >= NX + NU) {
+          const int i = lane - NX - NU;
+#pragma unroll
+          for (int j = 0; j < NX; ++j) q[NX + NU + j] += sh.Pm[i][j];
+          hv += sh.pv[i];
+        }
       }
-      if (lane < NX) sh.h[NX + NU + lane] += sh.pv[lane];
-      __syncthreads();
-      // right-hand sides [q_w | Q_wx]
-      for (int e = lane; e < NW * (NX + 1); e += 64) {
-        const int i = e / (NX + 1), j = e % (NX + 1);
-        sh.R[i][j] = (j == 0) ? sh.h[NX + i] : sh.Q[NX + i][j - 1];
-      }
-      __syncthreads();
-      // Cholesky S = L L^T of the w block (in place, lower triangle), right-looking
+      // Gaussian elimination of the w block (rows / lanes 8..24) without pivoting; its
+      // pivots are the squares of the Cholesky diagonal, so a non-positive pivot is the
+      // positive-definiteness failure.  Right-hand sides: columns 0..7 (Q_wx) and hv (q_w).
       int fail = 0;
-      for (int j = 0; j < NW; ++j) {
-        const double d = sh.Q[NX + j][NX + j];
-        if (!(d > 0.0) || !isfinite(d)) {
+#pragma unroll
+      for (int jj = 0; jj < NW; ++jj) {
+        constexpr int base = NX;
+        const int pl = base + jj;
+        const double piv = bcast(q[base + jj], pl);
+        if (!(piv > 0.0) || !isfinite(piv)) {
           fail = 1;
           break;
         }
-        const double ld = sqrt(d);
-        __syncthreads();
-        if (lane == 0) sh.Q[NX + j][NX + j] = ld;
-        for (int i = j + 1 + lane; i < NW; i += 64) sh.Q[NX + i][NX + j] /= ld;
-        __syncthreads();
-        const int m = NW - 1 - j;   // trailing size
-        for (int e = lane; e < m * m; e += 64) {
-          const int i = j + 1 + e / m, c2 = j + 1 + e % m;
-          if (c2 > i) continue;
-          sh.Q[NX + i][NX + c2] -= sh.Q[NX + i][NX + j] * sh.Q[NX + c2][NX + j];
+        const double f = (lane > pl && lane < NV) ? q[base + jj] / piv : 0.0;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+          if (c >= base && c <= pl) continue;   // eliminated / pivot columns are not used again
+          q[c] -= f * bcast(q[c], pl);
         }
-        __syncthreads();
+        hv -= f * bcast(hv, pl);
       }
       if (fail) {
         ok = 0;
       } else {
-        // X = -S^{-1} [q_w | Q_wx]: forward then backward substitution, lanes over columns
+        // back substitution: lane 8 + i ends with row i of X = S^{-1} [Q_wx | q_w]
+#pragma unroll
+        for (int jj = NW - 1; jj >= 0; --jj) {
+          const int pl = NX + jj;
+          if (lane == pl) {
+            const double d = q[NX + jj];
+#pragma unroll
+            for (int c = 0; c < NX; ++c) q[c] /= d;
+            hv /= d;
+          }
+          double xc[NX];
+#pragma unroll
+          for (int c = 0; c < NX; ++c) xc[c] = bcast(q[c], pl);
+          const double xh = bcast(hv, pl);
+          if (lane >= NX && lane < pl) {
+            const double u = q[NX + jj];
+#pragma unroll
+            for (int c = 0; c < NX; ++c) q[c] -= u * xc[c];
+            hv -= u * xh;
+          }
+        }
+        // gains k = -X[:, q_w], K = -X[:, Q_wx]
+        if (lane >= NX && lane < NV) {
+          const int i = lane - NX;
+          A.kk[(b * A.nmax + k) * NW + i] = -hv;
+          double* Kr = A.KK + ((b * A.nmax + k) * NW + i) * NX;
+#pragma unroll
+          for (int c = 0; c < NX; ++c) Kr[c] = -q[c];
+        }
+        // value function of x_k on lanes 0..7: P = Q_xx + Q_xw K, p = q_x + Q_xw k
+        double P[NX], pvn = hv;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) P[j] = q[j];
+#pragma unroll
         for (int i = 0; i < NW; ++i) {
-          if (lane < NX + 1) sh.R[i][lane] /= sh.Q[NX + i][NX + i];
-          __syncthreads();
-          for (int e = lane; e < (NW - 1 - i) * (NX + 1); e += 64) {
-            const int m = i + 1 + e / (NX + 1), cc = e % (NX + 1);
-            sh.R[m][cc] -= sh.Q[NX + m][NX + i] * sh.R[i][cc];
-          }
-          __syncthreads();
+          const double u = q[NX + i];
+#pragma unroll
+          for (int j = 0; j < NX; ++j) P[j] -= u * bcast(q[j], NX + i);
+          pvn -= u * bcast(hv, NX + i);
         }
-        for (int i = NW - 1; i >= 0; --i) {
-          if (lane < NX + 1) sh.R[i][lane] /= sh.Q[NX + i][NX + i];
-          __syncthreads();
-          for (int e = lane; e < i * (NX + 1); e += 64) {
-            const int m = e / (NX + 1), cc = e % (NX + 1);
-            sh.R[m][cc] -= sh.Q[NX + i][NX + m] * sh.R[i][cc];
-          }
-          __syncthreads();
-        }
-        // gains k = -X[:,0], K = -X[:,1..8]
-        for (int e = lane; e < NW * (NX + 1); e += 64) {
-          const int i = e / (NX + 1), j = e % (NX + 1);
-          const double gval = -sh.R[i][j];
-          sh.R[i][j] = gval;
-          if (j == 0) A.kk[(b * A.nmax + k) * NW + i] = gval;
-          else A.KK[((b * A.nmax + k) * NW + i) * NX + (j - 1)] = gval;
-        }
-        __syncthreads();
-        // value function: P = Q_xx + Q_xw K, p = q_x + Q_xw k (symmetrised)
-        double pn = 0.0;
-        if (lane < NX * NX) {
-          const int i = lane / NX, j = lane % NX;
-          double s = sh.Q[i][j];
-          for (int r = 0; r < NW; ++r) s += sh.Q[i][NX + r] * sh.R[r][1 + j];
-          pn = s;
-        }
-        double pvn = 0.0;
         if (lane < NX) {
-          double s = sh.h[lane];
-          for (int r = 0; r < NW; ++r) s += sh.Q[lane][NX + r] * sh.R[r][0];
-          pvn = s;
+#pragma unroll
+          for (int j = 0; j < NX; ++j) sh.Pm[lane][j] = P[j];
+          sh.pv[lane] = pvn;
         }
-        __syncthreads();
-        if (lane < NX * NX) sh.Pm[lane / NX][lane % NX] = pn;
-        if (lane < NX) sh.pv[lane] = pvn;
         __syncthreads();
         double ps = 0.0;
         if (lane < NX * NX) {
@@ -648,7 +674,7 @@ __device__ int sweep(const FlipArgs& A, Shm& sh, int64_t b, bool factor, double 
 }
 
 // forward pass: dw_k = k_k + K_k dx_k, dx_0 = 0
-__device__ void forward(const FlipArgs& A, Shm& sh, int64_t b) {
+__device__ __forceinline__ void forward(const FlipArgs& A, Shm& sh, int64_t b) {
   const int lane = threadIdx.x;
   if (lane < NX) sh.dx[lane] = 0.0;
   __syncthreads();
@@ -667,21 +693,17 @@ __device__ void forward(const FlipArgs& A, Shm& sh, int64_t b) {
 }
 
 // lanes over (interval, trial): phi(z + alpha_t dz) for t < T
-__device__ void trials(const FlipArgs& A, Shm& sh, int64_t b, int T, double mu, const double* lamT) {
+__device__ __forceinline__ void trials(const FlipArgs& A, Shm& sh, int64_t b, int T, double mu, const double* lamT) {
   const int lane = threadIdx.x, N = sh.N;
-  double acc[MAX_TRIALS];
-  for (int t = 0; t < T; ++t) acc[t] = 0.0;
-  for (int p = lane; p < N * T; p += 64) {
-    const int k = p / T, t = p % T;
-    const double alpha = ldexp(1.0, -t);
-    double v[NV];
-    load_args(A, sh, b, k, alpha, v);
-    const double ph = stage_merit(A, sh, b, k, v, mu, lamT);
-    for (int q = 0; q < T; ++q)
-      if (q == t) acc[q] += ph;
-  }
   for (int t = 0; t < T; ++t) {
-    const double s = wave_sum(acc[t]);
+    const double alpha = ldexp(1.0, -t);
+    double acc = 0.0;
+    for (int k = lane; k < N; k += 64) {
+      double v[NV];
+      load_args(A, sh, b, k, alpha, v);
+      acc += stage_merit(A, sh, b, k, v, mu, lamT);
+    }
+    const double s = wave_sum(acc);
     if (lane == 0) sh.trial[t] = s;
   }
   __syncthreads();
@@ -689,7 +711,7 @@ __device__ void trials(const FlipArgs& A, Shm& sh, int64_t b, int T, double mu, 
 
 // lanes over intervals: scaled feasibility and complementarity at z; optionally the
 // multiplier update lam += c/mu, nu = [nu + c/mu]_+
-__device__ void viol_pass(const FlipArgs& A, Shm& sh, int64_t b, double mu, bool update, double* lamT, double& vs,
+__device__ __forceinline__ void viol_pass(const FlipArgs& A, Shm& sh, int64_t b, double mu, bool update, double* lamT, double& vs,
                           double& rc) {
   const int lane = threadIdx.x, N = sh.N;
   double vmax = 0.0, qmax = 0.0;
@@ -731,7 +753,7 @@ __device__ void viol_pass(const FlipArgs& A, Shm& sh, int64_t b, double mu, bool
 }
 
 // Eq. (4): objective and violation of z in the task's units
-__device__ void score_pass(const FlipArgs& A, Shm& sh, int64_t b, double& J, double& vi) {
+__device__ __forceinline__ void score_pass(const FlipArgs& A, Shm& sh, int64_t b, double& J, double& vi) {
   const int lane = threadIdx.x, N = sh.N;
   double jacc = 0.0, vmax = 0.0;
   for (int k = lane; k < N; k += 64) {
@@ -763,7 +785,7 @@ __device__ void score_pass(const FlipArgs& A, Shm& sh, int64_t b, double& J, dou
 // slide it 5 cm, a pivot run turns the box about its corner to the landing angle (or the
 // goal angle if the order ends in it); twists and accelerations by finite differences;
 // contact fingers press with mg/2, sliding ones on the cone edge.
-__device__ void initial_guess(const FlipArgs& A, const Shm& sh, int64_t b) {
+__device__ __forceinline__ void initial_guess(const FlipArgs& A, const Shm& sh, int64_t b) {
   const int N = sh.N;
   double* z = A.z + (b * A.nmax) * NW;
   // pass 1: poses at knots 1..N into z's x_{k+1} slots (px, py, th)
@@ -851,7 +873,7 @@ __device__ void initial_guess(const FlipArgs& A, const Shm& sh, int64_t b) {
   }
 }
 
-__global__ __launch_bounds__(64) void k_flip_solve(FlipArgs A) {
+__global__ __launch_bounds__(64, 2) void k_flip_solve(FlipArgs A) {
   __shared__ Shm sh;
   const int lane = threadIdx.x;
   const int64_t b = blockIdx.x;
@@ -864,13 +886,14 @@ __global__ __launch_bounds__(64) void k_flip_solve(FlipArgs A) {
     int valid = 1, N = 0;
     const int K = A.nseg[b];
     if (K < 1 || K > A.smax) valid = 0;
+    const int64_t bi = b * A.inst_stride;
     for (int i = 0; i < NX; ++i) {
-      sh.xk0[i] = (double)A.x0[b * NX + i];
+      sh.xk0[i] = (double)A.x0[bi * NX + i];
       if (!isfinite(sh.xk0[i])) valid = 0;
     }
-    sh.goal[0] = (double)A.goal[b * 2 + 0];
-    sh.goal[1] = (double)A.goal[b * 2 + 1];
-    sh.mu_g = (double)A.inst[b];
+    sh.goal[0] = (double)A.goal[bi * 2 + 0];
+    sh.goal[1] = (double)A.goal[bi * 2 + 1];
+    sh.mu_g = (double)A.inst[bi];
     if (!isfinite(sh.goal[0]) || !isfinite(sh.goal[1]) || !(sh.mu_g > 0.0) || !isfinite(sh.mu_g)) valid = 0;
     int fs = 3, turns = 0, prev_g = -1;
     for (int j = 0; valid && j < K; ++j) {
@@ -1018,6 +1041,7 @@ __global__ __launch_bounds__(64) void k_flip_solve(FlipArgs A) {
     A.cost[b] = (float)J;
     A.viol[b] = (float)vi;
     A.feas[b] = (vi <= prm.eps_feas) ? 1 : 0;
+    if (A.t_first && vi <= prm.eps_feas) atomicMin(A.t_first, (unsigned long long)wall_clock64());
     if (A.cost64) A.cost64[b] = J;
     if (A.viol64) A.viol64[b] = vi;
     if (A.stats) {
@@ -1076,7 +1100,8 @@ comet_status launch_flip(comet_ctx* c, hipStream_t s, const EvalLaunch& L) {
   A.Bdev = L.B_dev;
   A.smax = c->max_segments;
   A.nmax = c->max_intervals;
-  A.x0 = L.x0; A.goal = L.goal; A.inst = L.inst;
+  A.x0 = L.x0; A.goal = L.goal; A.inst = L.inst; A.inst_stride = L.inst_stride;
+  A.t_first = L.t_first;
   A.nseg = L.nseg; A.modes = L.modes; A.knots = L.knots; A.warm = L.warm;
   A.cost = L.cost; A.viol = L.viol; A.feas = L.feas; A.traj = L.traj; A.stats = L.stats;
   A.cost64 = L.cost64; A.viol64 = L.viol64;

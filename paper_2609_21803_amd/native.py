@@ -290,13 +290,14 @@ class Context:
 
 
 def expand(ctx: "Context", x0, goal, inst, params: ExpandParams, learned=None, stream=None):
-    """Greedy expansion on one instance (device tensors x0 [4], goal [3], inst [1])."""
+    """Greedy expansion on one instance (device tensors; pushing: x0 [4], goal [3], inst [1];
+    flipping: x0 [8], goal [2], inst [1])."""
     import torch
     dev = x0.device
     S, N = ctx.max_segments, ctx.max_intervals
     o = dict(nseg=torch.zeros(1, dtype=torch.int32, device=dev), modes=torch.zeros(S, dtype=torch.int32, device=dev),
              knots=torch.zeros(S, dtype=torch.int32, device=dev), cost=torch.zeros(1, device=dev),
-             viol=torch.zeros(1, device=dev), traj=torch.zeros((N + 1, 7), device=dev))
+             viol=torch.zeros(1, device=dev), traj=torch.zeros((N + 1, ROW_WIDTH[ctx.task]), device=dev))
     st = ExpandStatsC()
     pc = params.c()
     rc = lib().comet_expand(ctx._h, _stream(stream), _ptr(x0), _ptr(goal), _ptr(inst), C.byref(pc),
