@@ -409,6 +409,14 @@ __device__ __forceinline__ double bcast(double x, int src) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// a value known to be the same in every lane, moved to scalar registers
+__device__ __forceinline__ double uniform(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // sum over the 64 lanes (result in every lane)
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
@@ -543,8 +551,10 @@ __device__ __forceinline__ int sweep(const FlipArgs& A, Shm& sh, int64_t b, bool
     // stage gradient h (no value function) and the gradient of phi for w_k
     if (lane < NV) {
       double s = 0.0;
-      for (int r = 0; r < NR; ++r)
-        if (sh.yr[r] != 0.0) s += sh.yr[r] * sh.A[r][lane];
+      for (int r = 0; r < NR; ++r) {
+        const double y = uniform(sh.yr[r]);   // same for every lane: a scalar branch skips zero rows
+        if (y != 0.0) s += y * sh.A[r][lane];
+      }
       if (lane >= NX && lane < NX + NU) s += 2.0 * DT * cost_weight(lane - NX) * v[lane];
       sh.h[lane] = s;
     }
@@ -566,9 +576,11 @@ __device__ __forceinline__ int sweep(const FlipArgs& A, Shm& sh, int64_t b, bool
       double hv = 0.0;
       if (lane < NV) {
         for (int r = 0; r < NR; ++r) {
-          const unsigned m = sh.nzm[r];
-          if (!((m >> lane) & 1u)) continue;   // row r does not touch column `lane`
-          const double wa = sh.wr[r] * sh.A[r][lane];
+          // the column mask is the same for every lane: scalar branches skip the zero
+          // columns of row r, and inactive rows (mask 0) entirely
+          const unsigned m = (unsigned)__builtin_amdgcn_readfirstlane((int)sh.nzm[r]);
+          if (m == 0u) continue;
+          const double wa = ((m >> lane) & 1u) ? sh.wr[r] * sh.A[r][lane] : 0.0;
 #pragma unroll
           for (int j = 0; j < NV; ++j)
             if ((m >> j) & 1u) q[j] += wa * sh.A[r][j];
