@@ -133,6 +133,35 @@ def flip_leg(native, I, torch, B=32768):
                          "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "kernel_ms": kms, "flop": flops}}
 
 
+def hetero_leg(native, I, torch, B=131072):
+    """Heterogeneous batch (K ~ U{1..5}, 5..15 intervals per segment, up to 75 intervals):
+    the persistent work queue in its default schedule and in the autotuner's pick."""
+    b = I.push_hetero(seed=2100, B=B)
+    ctx = native.Context(max_batch=B, max_segments=6, max_intervals=75)
+    d = native.to_device(b)
+    out = ctx.evaluate(**d)
+    torch.cuda.synchronize()
+    default_ms = []
+    for _ in range(2):
+        ctx.evaluate(**d)
+        torch.cuda.synchronize()
+        default_ms.append(ctx.kernel_ms())
+    sched, tuned_ms = ctx.autotune(**d, out=out)
+    best = []
+    for _ in range(2):
+        out = ctx.evaluate(**d)
+        torch.cuda.synchronize()
+        best.append(ctx.kernel_ms())
+    st = out["stats"].cpu().numpy()
+    N = I.n_intervals(b).astype(np.float64)
+    return {"workload": f"pushing, heterogeneous: {B} orders, K ~ U{{1..5}}, 5..15 intervals per segment, "
+                        "64 start/goal pairs (seed 2100)",
+            "mean_intervals": float(N.mean()), "mean_gn_iterations": float(st[:, 1].mean()),
+            "default_schedule": {"kernel_ms": float(np.mean(default_ms)), "solves_per_s": B / (np.mean(default_ms) * 1e-3)},
+            "autotuned_schedule": {"schedule": sched, "kernel_ms": float(np.mean(best)),
+                                   "solves_per_s": B / (np.mean(best) * 1e-3)}}
+
+
 def learned_leg(native, I, torch):
     """Train the network on evaluator results, time training and inference, and compare the
     time to the first feasible plan of the plain and the learned expansion."""
@@ -209,6 +238,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal leg")
     ap.add_argument("--no-flip", action="store_true", help="skip the flipping leg")
+    ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous-batch leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -290,6 +320,8 @@ def main():
                      "kernel": "k_push_solve", "kernel_ms": kms, "flop_per_launch": flops},
         "wall_s_timed": wall,
     }
+    if not args.no_hetero:
+        res["hetero"] = hetero_leg(native, I, torch)
     if not args.no_flip:
         res["flip"] = flip_leg(native, I, torch)
     if not args.no_learned:
