@@ -92,7 +92,9 @@ comet_status comet_dims(const comet_ctx* ctx, int32_t* nx, int32_t* nu, int32_t*
                         int32_t* max_segments, int32_t* max_intervals, int64_t* max_batch);
 
 /* Row scales of the solver's internal constraint scaling (Sec. IV-A: each row type is
- * divided by its median Jacobian-row 2-norm over sample orders).  out: host, n >= 12. */
+ * divided by its median Jacobian-row 2-norm over sample orders).  out: host, n >= 12.
+ * Pushing contexts only (the flipping rows are stated non-dimensionally): COMET_EINVAL
+ * otherwise. */
 comet_status comet_row_scales(const comet_ctx* ctx, double* out, int32_t n);
 
 /* Synchronise `stream`, read and clear the device error counter.  Returns COMET_EINVAL
@@ -217,8 +219,13 @@ typedef struct {
   int32_t n_refined, reserved;
 } comet_expand_stats;
 
-/* Run seed, s_max expansion rounds and refinement for one instance (x0 [nx], goal [3],
- * inst [n_inst]: device pointers).  The loop runs as one captured HIP graph on an internal
+/* Run seed, s_max expansion rounds and refinement for one instance (x0 [nx], goal [3]
+ * (pushing) or [2] (flipping), inst [n_inst]: device pointers).  The order language is the
+ * task's: pushing, every sequence of the 12 ids; flipping, the admissible orders (fingers
+ * never share a face, change faces only through a free segment, a pivot keeps a finger in
+ * contact, no two consecutive equal segments, consecutive pivots keep their direction, no
+ * finger on the face on the table -- the support face, and in a pivot the landing face);
+ * the seed and every generated neighbour are filtered by it.  The loop runs as one captured HIP graph on an internal
  * stream ordered after `stream`; the call synchronises and fills `stats` (host).  Outputs
  * (device): best_nseg [1] (0 = no feasible plan), best_modes / best_knots [max_segments],
  * best_cost / best_viol [1] (refined), best_traj [max_intervals+1, nx+nu] or NULL.
@@ -230,11 +237,14 @@ comet_status comet_expand(comet_ctx* ctx, void* stream, const float* x0, const f
                           const comet_expand_params* params, comet_mlp* learned, int32_t* best_nseg,
                           int32_t* best_modes, int32_t* best_knots, float* best_cost, float* best_viol,
                           float* best_traj, comet_expand_stats* stats);
+/* (learned networks encode pushing orders: a flipping context with learned != NULL is
+ * COMET_EINVAL) */
 
 /* One batch-construction step of Alg. 1 on given scores: rank the n evaluated orders
  * (keys [n] uint64, merit [n] double, device) by (merit, key), traverse at most frontier_W of
  * them and admit their unseen r-edit neighbours in enumeration order until `room` orders are
- * admitted.  Writes out_keys [room] and out_n [1] (device, int64).  Synchronises `stream`. */
+ * admitted (in the context task's language).  Writes out_keys [room] and out_n [1] (device,
+ * int64).  Synchronises `stream`. */
 comet_status comet_expand_next(comet_ctx* ctx, void* stream, int64_t n, const uint64_t* keys, const double* merit,
                                const comet_expand_params* params, int64_t room, uint64_t* out_keys,
                                int64_t* out_n);

@@ -5,12 +5,12 @@
 //
 // Mapping: one candidate order per 64-lane wavefront (one block).  With 17 stage unknowns
 // (u_k, x_{k+1}) the per-stage algebra (32 x 25 row Jacobian, 25 x 25 Gauss-Newton block,
-// 17 x 17 Cholesky with 9 right-hand sides) is too large for one lane's registers, so it is
-// staged in LDS and spread over the lanes: lanes over rows for the linearisation, lanes
-// over matrix entries for the assembly and the trailing updates of the factorisation,
-// lanes over (interval, trial step) for the line search, lanes over intervals for the
-// feasibility, multiplier and scoring passes.  All arithmetic is FP64: the blocks carry
-// 1/mu-scaled rank-deficient terms as in the pushing task.
+// 17 x 17 factorisation with 9 right-hand sides) is too large for one lane's registers, so
+// it is spread over the lanes: lanes over rows for the linearisation (Jacobian rows staged
+// in LDS), lane a holding row a of the Gauss-Newton block for the assembly, lanes 8..24
+// eliminating the block with the pivot row broadcast by readlane, lanes over intervals for
+// the trial steps and the feasibility, multiplier and scoring passes.  All arithmetic is
+// FP64: the blocks carry 1/mu-scaled rank-deficient terms as in the pushing task.
 //
 // Task model (state, controls, rows, units): see include/comet.h, COMET_TASK_FLIP.
 #include <hip/hip_runtime.h>
@@ -384,8 +384,6 @@ struct FlipArgs {
 
 struct Shm {
   double A[NR][NV + 1];
-  double Q[NV][NV + 1];
-  double R[NW][NX + 2];   // right-hand sides: column 0 = q_w, 1..8 = Q_wx; then the solution
   double cr[NR], wr[NR], yr[NR];
   unsigned nzm[NR];       // nonzero columns of each Jacobian row
   double Pm[NX][NX + 1], pv[NX];
@@ -393,7 +391,6 @@ struct Shm {
   double v[NV];           // row arguments of the interval being linearised
   double carry[NX];
   double dx[NX];
-  double red[64];
   double trial[MAX_TRIALS];
   double xk0[NX];
   double goal[2];
