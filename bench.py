@@ -106,7 +106,31 @@ def mlp_flops(B, dims, train):
     return f
 
 
-def flip_leg(native, I, torch, B=32768):
+def flip_cpu_baseline(batch, seconds_target=10.0):
+    """Flip oracle (FP64, plain C, one order per thread over all host threads) on an evenly
+    strided sample of the flipping round; returns solves/s."""
+    from oracle import flip as F
+    n_threads = os.cpu_count() or 1
+    B = len(batch["nseg"])
+    f32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+
+    def run(n):
+        idx = np.linspace(0, B - 1, n).astype(np.int64)
+        sub = {k: v[idx] for k, v in batch.items()}
+        t0 = time.perf_counter()
+        F.evaluate(f32(sub["x0"]), f32(sub["goal"]), f32(sub["inst"]), sub["nseg"], sub["modes"], sub["knots"],
+                   nthreads=n_threads)
+        return time.perf_counter() - t0
+
+    n = 4 * n_threads
+    dt = run(n)
+    n2 = int(min(B, max(n, n * seconds_target / max(dt, 1e-3))))
+    dt = run(n2)
+    return dict(value=n2 / dt, unit="solves/s", cores=n_threads, kind="oracle",
+                sample=f"{n2} of {B} orders, evenly strided over the round, FP64, {n_threads} threads, {dt:.1f} s")
+
+
+def flip_leg(native, I, torch, B=32768, cpu=True):
     """One round of the bimanual-flipping workload: B orders (K ~ U{1..6}, 10 intervals per
     segment) on 32 seeded start/goal pairs, one launch timed after one warm-up launch."""
     b = I.flip_batch(3100, B)
@@ -125,12 +149,15 @@ def flip_leg(native, I, torch, B=32768):
     N = I.n_intervals(b).astype(np.float64)
     flops = float((st[:, 1] * N).sum()) * FLIP_FLOP_PER_INTERVAL_GN
     ach = flops / (kms * 1e-3) / 1e12
-    return {"workload": f"bimanual flipping: {B} orders, K ~ U{{1..6}}, 10 intervals per segment, 32 start/goal pairs "
-                        "(goal th ~ U[pi/2, pi], px ~ U[-0.2, 0.2] m), AL<=20 x GN<=10, FP64",
-            "value": B / (ms * 1e-3), "unit": "solves/s", "ms": ms, "mean_gn_iterations": float(st[:, 1].mean()),
-            "mean_intervals": float(N.mean()), "feasible_fraction": float(out["feasible"].float().mean().item()),
-            "roofline": {"bound": "alu", "kernel": "k_flip_solve", "achieved": ach, "peak": PEAK_FP64_TFLOPS,
-                         "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "kernel_ms": kms, "flop": flops}}
+    res = {"workload": f"bimanual flipping: {B} orders, K ~ U{{1..6}}, 10 intervals per segment, 32 start/goal pairs "
+                       "(goal th ~ U[pi/2, pi], px ~ U[-0.2, 0.2] m), AL<=20 x GN<=10, FP64",
+           "value": B / (ms * 1e-3), "unit": "solves/s", "ms": ms, "mean_gn_iterations": float(st[:, 1].mean()),
+           "mean_intervals": float(N.mean()), "feasible_fraction": float(out["feasible"].float().mean().item()),
+           "roofline": {"bound": "alu", "kernel": "k_flip_solve", "achieved": ach, "peak": PEAK_FP64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "kernel_ms": kms, "flop": flops}}
+    if cpu:
+        res["cpu_baseline"] = flip_cpu_baseline(b)
+    return res
 
 
 def hetero_leg(native, I, torch, B=131072):
@@ -323,7 +350,7 @@ def main():
     if not args.no_hetero:
         res["hetero"] = hetero_leg(native, I, torch)
     if not args.no_flip:
-        res["flip"] = flip_leg(native, I, torch)
+        res["flip"] = flip_leg(native, I, torch, cpu=not args.no_cpu)
     if not args.no_learned:
         res["learned"] = learned_leg(native, I, torch)
     if not args.no_cpu:
