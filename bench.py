@@ -257,6 +257,45 @@ def learned_leg(native, I, torch):
     }
 
 
+def learned_flip_leg(native, I, torch):
+    """The learned proposal on flipping: train a network on flipping evaluator results and
+    compare the plain and the learned expansion of one batch of all admissible one- and
+    two-segment orders on held-out pivot-reachable goals."""
+    from paper_2609_21803_amd import learned
+    t0 = time.perf_counter()
+    ctx = native.Context(max_batch=32768, max_segments=6, max_intervals=20, task=native.TASK_FLIP)
+    data = learned.generate_flip(96, seed=5000, ctx=ctx)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    mlp = native.MLP(max_batch=8192, seed=1)
+    t0 = time.perf_counter()
+    log = learned.train(mlp, data, steps=800, batch=8192, lr=1e-3, log_every=799)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    prm = native.ExpandParams(kcap=2, seed_max_segments=2, radius=1, rounds=0, frontier_W=8, knots_per_segment=10,
+                              k_ref=16, batch_B=8192, eval_budget=8192, learned_warm=1)
+    ctx2 = native.Context(max_batch=8192, max_segments=6, max_intervals=20, task=native.TASK_FLIP)
+    rows = learned.compare(ctx2, mlp, prm, list(zip(*I.flip_pivot_pairs(9400, 8))))
+    tp = np.array([r["plain"]["t_first_ms"] for r in rows])
+    tl = np.array([r["learned"]["t_first_ms"] for r in rows])
+    ok = (tp > 0) & (tl > 0)
+    same_cost = sum(abs(r["plain"]["cost"] - r["learned"]["cost"]) <= 1e-4 * max(abs(r["plain"]["cost"]), 1e-12)
+                    for r in rows)
+    return {
+        "ttfp_ms_plain_median": float(np.median(tp[ok])) if ok.any() else None,
+        "ttfp_ms_learned_median": float(np.median(tl[ok])) if ok.any() else None,
+        "ttfp_ratio_median": float(np.median(tl[ok] / tp[ok])) if ok.any() else None,
+        "same_returned_cost": f"{same_cost}/{len(rows)}",
+        "identical_returned_orders": f"{sum(r['plain']['modes'] == r['learned']['modes'] for r in rows)}/{len(rows)}",
+        "first_feasible_index_median": {"plain": float(np.median([r["plain"]["first_index"] for r in rows])),
+                                        "learned": float(np.median([r["learned"]["first_index"] for r in rows]))},
+        "instances": "8 held-out pivot-reachable flipping goals (seed 9400, th ~ U[0.9, 1.5]), one batch of the "
+                     "8,192 first admissible orders of 1-2 segments, 10 intervals per segment, refinement of 16",
+        "training": {"samples": int(data["X"].shape[0]), "feasible_fraction": float(data["y_feas"].mean()),
+                     "steps": 800, "batch": 8192, "gen_s": t_gen, "train_s": t_train, "final_loss": log[-1][1]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -353,6 +392,7 @@ def main():
         res["flip"] = flip_leg(native, I, torch, cpu=not args.no_cpu)
     if not args.no_learned:
         res["learned"] = learned_leg(native, I, torch)
+        res["learned_flip"] = learned_flip_leg(native, I, torch)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(batch)
     print(json.dumps(res), flush=True)

@@ -285,24 +285,40 @@ comet_status comet_mlp_forward(comet_mlp* mlp, void* stream, int64_t B, const ui
 comet_status comet_mlp_train_step(comet_mlp* mlp, void* stream, int64_t B, const uint16_t* x_bf16,
                                   const float* y_feas, const float* y_cost, const float* y_traj,
                                   const float* traj_mask, float lr, float weight_decay, float* loss);
-/* Input encoding of planar-pushing orders (same arguments as comet_evaluate, Smax = smax)
- * into in_dim (>= 400) BF16 values per order: pose block (start and goal x, y, cos, sin,
- * goal - start, friction) then 6 segment slots of 64 (one-hot id, intervals / 15, present). */
+/* Input encoding of orders (same arguments as comet_evaluate, Smax = smax) into in_dim
+ * (>= 400) BF16 values per order, a pose block of 16 then 6 segment slots of 64 (absent
+ * segments all zero, values beyond 400 zero).
+ *   COMET_TASK_PUSH: pose = start and goal (x, y, cos, sin), goal - start (x, y, theta),
+ *     pusher friction; slot = one-hot mode id (12), intervals / 15, present flag.
+ *   COMET_TASK_FLIP: pose = start (px, py, cos, sin), goal (px, 0, cos, sin), goal - start
+ *     (px, 0, theta), table friction; slot = one-hot finger-1 code (13), one-hot finger-2
+ *     code (13), one-hot table mode (5), intervals / 15, present flag.
+ * The network proposes orders and warm starts (Sec. IV-C); its input encoding is not fixed
+ * by the paper.  Other tasks: COMET_EINVAL. */
 comet_status comet_mlp_encode(comet_task task, void* stream, int64_t B, const float* x0, const float* goal,
                               const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                               int32_t smax, int32_t in_dim, uint16_t* x_bf16);
-/* Training targets from evaluator results (traj [B, nmax+1, 7], feasible, cost):
- * y_feas, y_cost = log(1 + J) (0 if infeasible), y_traj [B, 720] per-segment samples at
- * normalised times i/14 (linear interpolation of the rows), traj_mask [B, 720] = 1 on the
- * 7 trajectory channels of present segments of feasible orders. */
-comet_status comet_mlp_targets(void* stream, int64_t B, const float* traj, int32_t nmax, const int32_t* nseg,
-                               const int32_t* knots, int32_t smax, const uint8_t* feasible, const float* cost,
-                               float* y_feas, float* y_cost, float* y_traj, float* traj_mask);
-/* Warm-start trajectories [B, nmax+1, 7] (comet_evaluate's warm layout) from network
- * outputs [B, out_dim]: each segment's samples interpolated to its intervals; row 0 takes
- * x0 (one start per order), the last row's controls are zero. */
-comet_status comet_mlp_decode_warm(void* stream, int64_t B, const float* out, int32_t out_dim, const float* x0,
-                                   const int32_t* nseg, const int32_t* knots, int32_t smax, int32_t nmax, float* warm);
+/* Training targets from evaluator results (traj [B, nmax+1, row] in comet_evaluate's
+ * layout, row = 7 pushing / 17 flipping; feasible; cost): y_feas, y_cost = log(1 + J)
+ * (0 if infeasible), y_traj [B, 720] per-segment samples (6 slots x 15 times i/14 x 8
+ * channels) by linear interpolation of the rows, traj_mask [B, 720] = 1 on the learned
+ * channels of present segments of feasible orders.  Learned channels: pushing, the 7 row
+ * entries (channel 7 zero); flipping, the 8 state entries. */
+comet_status comet_mlp_targets(comet_task task, void* stream, int64_t B, const float* traj, int32_t nmax,
+                               const int32_t* nseg, const int32_t* knots, int32_t smax, const uint8_t* feasible,
+                               const float* cost, float* y_feas, float* y_cost, float* y_traj, float* traj_mask);
+/* Warm-start trajectories [B, nmax+1, row] (comet_evaluate's warm layout) from network
+ * outputs [B, out_dim]: each segment's samples interpolated to its knots.
+ *   COMET_TASK_PUSH: all 7 entries interpolated; row 0 takes x0, the last row's controls
+ *     are zero.  `modes` may be NULL.
+ *   COMET_TASK_FLIP: the 8 states interpolated, row 0 takes x0; controls from the states
+ *     and `modes` (required): accelerations and face-coordinate rates by forward
+ *     differences over dt = 0.1 s, a contact finger pushes with mg/2 normal force (a
+ *     sliding one on its cone edge in the slip direction), a free finger zero; the last
+ *     row's controls are zero. */
+comet_status comet_mlp_decode_warm(comet_task task, void* stream, int64_t B, const float* out, int32_t out_dim,
+                                   const float* x0, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
+                                   int32_t smax, int32_t nmax, float* warm);
 
 #ifdef __cplusplus
 }

@@ -161,9 +161,44 @@ def encode_push(x0, goal, inst, nseg, modes, knots, in_dim=416):
     return X
 
 
-def targets(traj, nseg, knots, feas, cost):
+def encode_flip(x0, goal, inst, nseg, modes, knots, in_dim=416):
+    """Input encoding of flipping orders (float32, then BF16): pose block (start px, py,
+    cos, sin; goal px, 0, cos, sin; goal - start px, 0, angle; table friction); per segment
+    the finger-1 code, finger-2 code and table mode as separate one-hots (13 + 13 + 5), the
+    interval count / 15 and a presence flag."""
+    B = len(nseg)
+    X = np.zeros((B, in_dim), np.float32)
+    x0 = np.asarray(x0, np.float32)
+    goal = np.asarray(goal, np.float32)
+    inst = np.asarray(inst, np.float32).reshape(B, -1)
+    X[:, 0] = x0[:, 0]
+    X[:, 1] = x0[:, 1]
+    X[:, 2] = np.cos(x0[:, 2])
+    X[:, 3] = np.sin(x0[:, 2])
+    X[:, 4] = goal[:, 0]
+    X[:, 6] = np.cos(goal[:, 1])
+    X[:, 7] = np.sin(goal[:, 1])
+    X[:, 8] = goal[:, 0] - x0[:, 0]
+    X[:, 10] = goal[:, 1] - x0[:, 2]
+    X[:, 11] = inst[:, 0]
+    for b in range(B):
+        for j in range(int(nseg[b])):
+            base = POSE_DIMS + SEG_SLOT * j
+            m = int(modes[b, j])
+            f1, f2, g = m // 65, (m // 5) % 13, m % 5
+            X[b, base + f1] = 1.0
+            X[b, base + 13 + f2] = 1.0
+            X[b, base + 26 + g] = 1.0
+            X[b, base + 31] = np.float32(knots[b, j]) / np.float32(15.0)
+            X[b, base + 32] = 1.0
+    return X
+
+
+def targets(traj, nseg, knots, feas, cost, nch=7):
     """Warm-start targets: per segment, 15 samples at normalised times i/14 by linear
-    interpolation between trajectory rows; mask on present segments of feasible orders."""
+    interpolation between trajectory rows of the first `nch` channels (pushing: the 7
+    row entries; flipping: the 8 states); mask on those channels of present segments of
+    feasible orders."""
     B = len(nseg)
     y_traj = np.zeros((B, N_SEG * WS_SLOTS * WS_CH))
     mask = np.zeros_like(y_traj)
@@ -175,7 +210,7 @@ def targets(traj, nseg, knots, feas, cost):
                 p = i / (WS_SLOTS - 1) * nj
                 k = min(int(math.floor(p)), max(nj - 1, 0))
                 fr = p - k
-                for c in range(7):
+                for c in range(nch):
                     a0 = traj[b, k0 + k, c]
                     a1 = traj[b, k0 + min(k + 1, nj), c]
                     e = (j * WS_SLOTS + i) * WS_CH + c
@@ -185,3 +220,52 @@ def targets(traj, nseg, knots, feas, cost):
     y_feas = np.asarray(feas, np.float64)
     y_cost = np.where(feas, np.log1p(np.maximum(cost, 0.0)), 0.0)
     return y_feas, y_cost, y_traj, mask
+
+
+FLIP_MG, FLIP_MU, FLIP_DT = 0.5 * 9.81, 0.5, 0.1
+
+
+def decode_warm_flip(Y, x0, nseg, modes, knots, nmax):
+    """Flipping warm start from network outputs Y [B, >= 722]: the 8 states of every knot
+    interpolated linearly from the segment's 15 samples (knot k of n at sample position
+    14 k / n), knot 0 replaced by the start state; controls of interval k: accelerations
+    (twist rate) and face-coordinate rates as forward differences of the states over dt,
+    each finger in contact pushing with mg/2 normal force and tangential force 0 (stick) or
+    +-mu mg/2 (slide+/-), a free finger zero; the last knot's controls zero."""
+    B = len(nseg)
+    W = np.zeros((B, nmax + 1, 17))
+    for b in range(B):
+        y = np.asarray(Y[b, 2:2 + N_SEG * WS_SLOTS * WS_CH], np.float64).reshape(N_SEG, WS_SLOTS, WS_CH)
+        k0 = 0
+        for j in range(int(nseg[b])):
+            nj = int(knots[b, j])
+            for k in range(nj + 1):
+                if k0 + k > nmax:
+                    break
+                p = k / nj * (WS_SLOTS - 1) if nj > 0 else 0.0
+                i = min(int(math.floor(p)), WS_SLOTS - 2)
+                fr = p - i
+                W[b, k0 + k, :8] = y[j, i, :8] + fr * (y[j, i + 1, :8] - y[j, i, :8])
+            k0 += nj
+        N = min(k0, nmax)
+        W[b, 0, :8] = x0[b]
+        kk = 0
+        for j in range(int(nseg[b])):
+            m, nj = int(modes[b, j]), int(knots[b, j])
+            codes = (m // 65, (m // 5) % 13)
+            for _ in range(nj):
+                if kk >= N:
+                    break
+                xa, xb = W[b, kk, :8], W[b, kk + 1, :8]
+                u = W[b, kk, 8:]
+                u[0:3] = (xb[3:6] - xa[3:6]) / FLIP_DT
+                for f in range(2):
+                    fn = ft = 0.0
+                    if codes[f] != 0:
+                        slip = (codes[f] - 1) % 3
+                        fn = 0.5 * FLIP_MG
+                        ft = (0.0, FLIP_MU * fn, -FLIP_MU * fn)[slip]
+                    u[3 + 3 * f], u[4 + 3 * f] = fn, ft
+                    u[5 + 3 * f] = (xb[6 + f] - xa[6 + f]) / FLIP_DT
+                kk += 1
+    return W

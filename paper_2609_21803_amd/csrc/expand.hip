@@ -802,8 +802,8 @@ comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
   A((void**)&w->fnseg2, 4 * BR);
   A((void**)&w->fmodes2, 4 * BR * c->max_segments);
   A((void**)&w->fknots2, 4 * BR * c->max_segments);
-  A((void**)&w->warm_tmp, 4 * BR * nmax1 * 7);
-  A((void**)&w->warm, 4 * BR * nmax1 * 7);
+  A((void**)&w->warm_tmp, 4 * BR * nmax1 * rowW);
+  A((void**)&w->warm, 4 * BR * nmax1 * rowW);
   if (!ok) {
     (void)hipGetLastError();
     destroy_expand_ws(c);
@@ -866,17 +866,19 @@ comet_status enqueue_evaluate_batch(comet_ctx* c, hipStream_t s, const long long
   hipLaunchKernelGGL(k_build, dim3(blocks(nmax, 256)), dim3(256), 0, s, w->cfg, n_dev, w->F, w->fnseg, w->fmodes,
                      w->fknots, c->max_segments);
   const int smax = c->max_segments;
-  const long long row = (long long)(c->max_intervals + 1) * 7;
+  const long long row = (long long)(c->max_intervals + 1) * w->cfg.row;
   if (learned) {
     // network scores and warm starts; the batch is evaluated in predicted-merit order
-    mlp_encode_dev(learned, s, nmax, n_dev, w->ix0, w->igoal, w->iinst, 0, w->fnseg, w->fmodes, w->fknots, smax);
+    mlp_encode_dev(learned, c->task, s, nmax, n_dev, w->ix0, w->igoal, w->iinst, 0, w->fnseg, w->fmodes, w->fknots,
+                   smax);
     mlp_forward(learned, s, (int)nmax, n_dev);
     const int O = mlp_out_dim(learned);
     hipLaunchKernelGGL(k_learned_keys, dim3(blocks(nmax, 256)), dim3(256), 0, s, w->cfg, w->C, mlp_output(learned), O,
                        w->F, w->s_hi[0], w->s_lo[0], w->s_idx[0]);
     const int cur = enqueue_sort(c, s, n_dev);
     const unsigned* perm = w->s_idx[cur];
-    mlp_decode_warm_dev(learned, s, nmax, n_dev, w->ix0, 0, w->fnseg, w->fknots, smax, c->max_intervals, w->warm_tmp);
+    mlp_decode_warm_dev(learned, c->task, s, nmax, n_dev, w->ix0, 0, w->fnseg, w->fmodes, w->fknots, smax,
+                        c->max_intervals, w->warm_tmp);
     hipLaunchKernelGGL(k_gather_batch, dim3(blocks(nmax, 256)), dim3(256), 0, s, w->C, perm, w->F, w->fnseg,
                        w->fmodes, w->fknots, smax, w->F2, w->fnseg2, w->fmodes2, w->fknots2);
     hipLaunchKernelGGL(k_copy_batch, dim3(blocks(nmax, 256)), dim3(256), 0, s, w->C, w->F2, w->fnseg2, w->fmodes2,
@@ -965,7 +967,6 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
   comet_status st = check_expand_params(c, params);
   if (st != COMET_OK) return st;
   const bool flip = (c->task == COMET_TASK_FLIP);
-  if (flip && learned) return fail_msg(c, COMET_EINVAL, "the learned network encodes pushing orders only");
   if (learned && (mlp_max_batch(learned) < params->batch_B || mlp_in_dim(learned) < 400 || mlp_out_dim(learned) < 722))
     return fail_msg(c, COMET_EINVAL, "learned network: max_batch < batch_B, in_dim < 400 or out_dim < 722");
   st = ensure_ws(c, params);

@@ -120,11 +120,12 @@ int mlp_out_dim(const comet_mlp* m);
 long long mlp_max_batch(const comet_mlp* m);
 const float* mlp_output(const comet_mlp* m);
 void mlp_forward(comet_mlp* m, hipStream_t s, int B, const long long* B_dev);
-void mlp_encode_dev(comet_mlp* m, hipStream_t s, long long Bmax, const long long* B_dev, const float* x0,
+void mlp_encode_dev(comet_mlp* m, int task, hipStream_t s, long long Bmax, const long long* B_dev, const float* x0,
                     const float* goal, const float* inst, int inst_stride, const int32_t* nseg, const int32_t* modes,
                     const int32_t* knots, int smax);
-void mlp_decode_warm_dev(comet_mlp* m, hipStream_t s, long long Bmax, const long long* B_dev, const float* x0,
-                         int inst_stride, const int32_t* nseg, const int32_t* knots, int smax, int nmax, float* warm);
+void mlp_decode_warm_dev(comet_mlp* m, int task, hipStream_t s, long long Bmax, const long long* B_dev,
+                         const float* x0, int inst_stride, const int32_t* nseg, const int32_t* modes,
+                         const int32_t* knots, int smax, int nmax, float* warm);
 comet_status fail_msg(comet_ctx* c, comet_status st, const std::string& m);
 void destroy_expand_ws(comet_ctx* c);
 }  // namespace comet

@@ -409,16 +409,66 @@ __global__ void k_encode_push(long B, const float* x0, const float* goal, const 
 // trajectory rows (x_k, u_k); slot i samples normalised time i / 14 by linear
 // interpolation between neighbouring rows; channel 7 is zero.
 // ---------------------------------------------------------------------------------
-__global__ void k_targets(long B, const float* traj, int nmax, const int32_t* nseg, const int32_t* knots, int smax,
-                          const uint8_t* feas, const float* cost, float* y_feas, float* y_cost, float* y_traj,
-                          float* mask) {
+// Flipping orders: pose block (start px, py, cos, sin; goal px, 0, cos, sin; goal - start
+// px, 0, angle; table friction) then 6 segment slots of 64: factorised one-hot of the id
+// (finger 1 code 0..12, finger 2 code 13..25, table mode 26..30), intervals / 15 at 31,
+// presence flag at 32.
+constexpr int FLIP_KN = 31, FLIP_PRESENT = 32;
+__global__ void k_encode_flip(long B, const float* x0, const float* goal, const float* inst, int inst_stride,
+                              const int32_t* nseg, const int32_t* modes, const int32_t* knots, int smax, int in_dim,
+                              bf16* X, const long long* B_dev) {
+  const long Bn = B_dev ? *B_dev : B;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Bn * in_dim) return;
+  const long b = i / in_dim;
+  const int d = (int)(i % in_dim);
+  const long bi = b * inst_stride;
+  float v = 0.f;
+  if (d < POSE_DIMS) {
+    const float sx = x0[bi * 8 + 0], sy = x0[bi * 8 + 1], st = x0[bi * 8 + 2];
+    const float gx = goal[bi * 2 + 0], gt = goal[bi * 2 + 1];
+    switch (d) {
+      case 0: v = sx; break;
+      case 1: v = sy; break;
+      case 2: v = cosf(st); break;
+      case 3: v = sinf(st); break;
+      case 4: v = gx; break;
+      case 6: v = cosf(gt); break;
+      case 7: v = sinf(gt); break;
+      case 8: v = gx - sx; break;
+      case 10: v = gt - st; break;
+      case 11: v = inst[bi]; break;
+      default: v = 0.f;
+    }
+  } else if (d < POSE_DIMS + 6 * SEG_SLOT) {
+    const int j = (d - POSE_DIMS) / SEG_SLOT, q = (d - POSE_DIMS) % SEG_SLOT;
+    const int K = nseg[b];
+    if (j < K && j < smax) {
+      const int m = modes[b * smax + j];
+      const int g = m % 5, f2 = (m / 5) % 13, f1 = m / 65;
+      if (q < 13) v = (q == f1) ? 1.f : 0.f;
+      else if (q < 26) v = (q - 13 == f2) ? 1.f : 0.f;
+      else if (q < 31) v = (q - 26 == g) ? 1.f : 0.f;
+      else if (q == FLIP_KN) v = (float)knots[b * smax + j] / 15.f;
+      else if (q == FLIP_PRESENT) v = 1.f;
+    }
+  }
+  X[i] = to_bf16(v);
+}
+
+// Warm-start targets: per segment, 15 samples at normalised times i/14 by linear
+// interpolation of the trajectory rows; channels 0..nch-1 of each row (pushing: the 7
+// state and control entries, flipping: the 8 states), row width `row`.
+__global__ void k_targets(long B, const float* traj, int nmax, int row, int nch, const int32_t* nseg,
+                          const int32_t* knots, int smax, const uint8_t* feas, const float* cost, float* y_feas,
+                          float* y_cost, float* y_traj, float* mask) {
   const long b = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   const int K = nseg[b];
   const float f = feas[b] ? 1.f : 0.f;
   y_feas[b] = f;
   y_cost[b] = feas[b] ? log1pf(fmaxf(cost[b], 0.f)) : 0.f;
-  const float* T = traj + b * (long)(nmax + 1) * 7;
+  const float* T = traj + b * (long)(nmax + 1) * row;
   int k0 = 0;
   for (int j = 0; j < 6; ++j) {
     const bool live = j < K && j < smax;
@@ -430,12 +480,12 @@ __global__ void k_targets(long B, const float* traj, int nmax, const int32_t* ns
       for (int c = 0; c < WS_CH; ++c) {
         const long e = b * (6L * WS_SLOTS * WS_CH) + ((long)j * WS_SLOTS + i) * WS_CH + c;
         float val = 0.f;
-        if (live && c < 7) {
-          const float a0 = T[(k0 + k) * 7 + c], a1 = T[(k0 + min(k + 1, nj)) * 7 + c];
+        if (live && c < nch) {
+          const float a0 = T[(k0 + k) * row + c], a1 = T[(k0 + min(k + 1, nj)) * row + c];
           val = a0 + fr * (a1 - a0);
         }
         y_traj[e] = val;
-        mask[e] = (live && c < 7) ? f : 0.f;
+        mask[e] = (live && c < nch) ? f : 0.f;
       }
     }
     k0 += nj;
@@ -468,6 +518,62 @@ __global__ void k_decode_warm(long B, const long long* B_dev, const float* Y, in
   for (int c = 0; c < 4; ++c) Wr[c] = x0[b * inst_stride * 4 + c];
   if (k0 <= nmax)
     for (int c = 4; c < 7; ++c) Wr[k0 * 7 + c] = 0.f;
+}
+
+// Flipping warm start: states (8 channels) interpolated from the network samples at every
+// knot, the start state at knot 0; controls from the states and the mode: accelerations
+// and face-coordinate rates by forward differences, contact fingers pressing with mg/2
+// (sliding ones on the cone edge), free fingers zero; row N has u = 0.
+__global__ void k_decode_warm_flip(long B, const long long* B_dev, const float* Y, int O, const float* x0,
+                                   int inst_stride, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
+                                   int smax, int nmax, float* warm) {
+  constexpr int ROWF = 17;
+  constexpr float MG = 0.5f * 9.81f, MUF = 0.5f, DT = 0.1f;
+  const long Bn = B_dev ? *B_dev : B;
+  const long b = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= Bn) return;
+  const int K = nseg[b];
+  const float* y = Y + b * (long)O + 2;
+  float* Wr = warm + b * (long)(nmax + 1) * ROWF;
+  for (int r = 0; r < (nmax + 1) * ROWF; ++r) Wr[r] = 0.f;
+  int k0 = 0;
+  for (int j = 0; j < K && j < smax; ++j) {
+    const int nj = knots[b * smax + j];
+    for (int k = 0; k <= nj && k0 + k <= nmax; ++k) {
+      const float p = (nj > 0) ? (float)k / (float)nj * (WS_SLOTS - 1) : 0.f;
+      const int i = min((int)floorf(p), WS_SLOTS - 2);
+      const float fr = p - (float)i;
+      for (int c = 0; c < 8; ++c) {
+        const float a0 = y[((long)j * WS_SLOTS + i) * WS_CH + c], a1 = y[((long)j * WS_SLOTS + i + 1) * WS_CH + c];
+        Wr[(k0 + k) * ROWF + c] = a0 + fr * (a1 - a0);
+      }
+    }
+    k0 += nj;
+  }
+  const int N = min(k0, nmax);
+  for (int c = 0; c < 8; ++c) Wr[c] = x0[b * inst_stride * 8 + c];
+  int kk = 0;
+  for (int j = 0; j < K && j < smax; ++j) {
+    const int m = modes[b * smax + j], nj = knots[b * smax + j];
+    const int fc[2] = {m / 65, (m / 5) % 13};
+    for (int t = 0; t < nj && kk < N; ++t, ++kk) {
+      float* u = Wr + kk * ROWF + 8;
+      const float* xa = Wr + kk * ROWF;
+      const float* xb = Wr + (kk + 1) * ROWF;
+      for (int c = 0; c < 3; ++c) u[c] = (xb[3 + c] - xa[3 + c]) / DT;
+      for (int f = 0; f < 2; ++f) {
+        float fn = 0.f, ft = 0.f;
+        if (fc[f] != 0) {
+          const int slip = (fc[f] - 1) % 3;
+          fn = 0.5f * MG;
+          ft = (slip == 0) ? 0.f : ((slip == 1) ? MUF * fn : -MUF * fn);
+        }
+        u[3 + 3 * f] = fn;
+        u[4 + 3 * f] = ft;
+        u[5 + 3 * f] = (xb[6 + f] - xa[6 + f]) / DT;
+      }
+    }
+  }
 }
 
 }  // namespace comet
@@ -566,17 +672,26 @@ int mlp_out_dim(const comet_mlp* m) { return m->out_dim; }
 long long mlp_max_batch(const comet_mlp* m) { return m->max_batch; }
 const float* mlp_output(const comet_mlp* m) { return m->Y; }
 
-void mlp_encode_dev(comet_mlp* m, hipStream_t s, long long Bmax, const long long* B_dev, const float* x0,
+void mlp_encode_dev(comet_mlp* m, int task, hipStream_t s, long long Bmax, const long long* B_dev, const float* x0,
                     const float* goal, const float* inst, int inst_stride, const int32_t* nseg, const int32_t* modes,
                     const int32_t* knots, int smax) {
-  hipLaunchKernelGGL(k_encode_push, dim3(nblk(Bmax * m->in_dim, 256)), dim3(256), 0, s, (long)Bmax, x0, goal, inst,
-                     inst_stride, nseg, modes, knots, smax, m->in_dim, m->H[0], B_dev);
+  if (task == COMET_TASK_FLIP)
+    hipLaunchKernelGGL(k_encode_flip, dim3(nblk(Bmax * m->in_dim, 256)), dim3(256), 0, s, (long)Bmax, x0, goal, inst,
+                       inst_stride, nseg, modes, knots, smax, m->in_dim, m->H[0], B_dev);
+  else
+    hipLaunchKernelGGL(k_encode_push, dim3(nblk(Bmax * m->in_dim, 256)), dim3(256), 0, s, (long)Bmax, x0, goal, inst,
+                       inst_stride, nseg, modes, knots, smax, m->in_dim, m->H[0], B_dev);
 }
 
-void mlp_decode_warm_dev(comet_mlp* m, hipStream_t s, long long Bmax, const long long* B_dev, const float* x0,
-                         int inst_stride, const int32_t* nseg, const int32_t* knots, int smax, int nmax, float* warm) {
-  hipLaunchKernelGGL(k_decode_warm, dim3(nblk(Bmax, 128)), dim3(128), 0, s, (long)Bmax, B_dev, m->Y, m->out_dim, x0,
-                     inst_stride, nseg, knots, smax, nmax, warm);
+void mlp_decode_warm_dev(comet_mlp* m, int task, hipStream_t s, long long Bmax, const long long* B_dev,
+                         const float* x0, int inst_stride, const int32_t* nseg, const int32_t* modes,
+                         const int32_t* knots, int smax, int nmax, float* warm) {
+  if (task == COMET_TASK_FLIP)
+    hipLaunchKernelGGL(k_decode_warm_flip, dim3(nblk(Bmax, 128)), dim3(128), 0, s, (long)Bmax, B_dev, m->Y,
+                       m->out_dim, x0, inst_stride, nseg, modes, knots, smax, nmax, warm);
+  else
+    hipLaunchKernelGGL(k_decode_warm, dim3(nblk(Bmax, 128)), dim3(128), 0, s, (long)Bmax, B_dev, m->Y, m->out_dim,
+                       x0, inst_stride, nseg, knots, smax, nmax, warm);
 }
 
 }  // namespace comet
@@ -775,32 +890,50 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
 comet_status comet_mlp_encode(comet_task task, void* stream, int64_t B, const float* x0, const float* goal,
                               const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                               int32_t smax, int32_t in_dim, uint16_t* x_bf16) {
-  if (task != COMET_TASK_PUSH || !x0 || !goal || !inst || !nseg || !modes || !knots || !x_bf16) return COMET_EINVAL;
+  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP) || !x0 || !goal || !inst || !nseg || !modes || !knots ||
+      !x_bf16)
+    return COMET_EINVAL;
   if (B < 0 || smax < 1 || smax > 6 || in_dim < POSE_DIMS + 6 * SEG_SLOT) return COMET_EINVAL;
   if (B == 0) return COMET_OK;
-  hipLaunchKernelGGL(k_encode_push, dim3(nblk(B * in_dim, 256)), dim3(256), 0, (hipStream_t)stream, (long)B, x0, goal,
-                     inst, 1, nseg, modes, knots, smax, in_dim, (bf16*)x_bf16, (const long long*)nullptr);
+  if (task == COMET_TASK_FLIP)
+    hipLaunchKernelGGL(k_encode_flip, dim3(nblk(B * in_dim, 256)), dim3(256), 0, (hipStream_t)stream, (long)B, x0,
+                       goal, inst, 1, nseg, modes, knots, smax, in_dim, (bf16*)x_bf16, (const long long*)nullptr);
+  else
+    hipLaunchKernelGGL(k_encode_push, dim3(nblk(B * in_dim, 256)), dim3(256), 0, (hipStream_t)stream, (long)B, x0,
+                       goal, inst, 1, nseg, modes, knots, smax, in_dim, (bf16*)x_bf16, (const long long*)nullptr);
   return hipGetLastError() == hipSuccess ? COMET_OK : COMET_EHIP;
 }
 
-comet_status comet_mlp_targets(void* stream, int64_t B, const float* traj, int32_t nmax, const int32_t* nseg,
-                               const int32_t* knots, int32_t smax, const uint8_t* feasible, const float* cost,
-                               float* y_feas, float* y_cost, float* y_traj, float* traj_mask) {
-  if (!traj || !nseg || !knots || !feasible || !cost || !y_feas || !y_cost || !y_traj || !traj_mask) return COMET_EINVAL;
+comet_status comet_mlp_targets(comet_task task, void* stream, int64_t B, const float* traj, int32_t nmax,
+                               const int32_t* nseg, const int32_t* knots, int32_t smax, const uint8_t* feasible,
+                               const float* cost, float* y_feas, float* y_cost, float* y_traj, float* traj_mask) {
+  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP) || !traj || !nseg || !knots || !feasible || !cost ||
+      !y_feas || !y_cost || !y_traj || !traj_mask)
+    return COMET_EINVAL;
   if (B < 0 || smax < 1 || smax > 6 || nmax < 1) return COMET_EINVAL;
   if (B == 0) return COMET_OK;
-  hipLaunchKernelGGL(k_targets, dim3(nblk(B, 128)), dim3(128), 0, (hipStream_t)stream, (long)B, traj, nmax, nseg,
-                     knots, smax, feasible, cost, y_feas, y_cost, y_traj, traj_mask);
+  const bool flip = (task == COMET_TASK_FLIP);
+  hipLaunchKernelGGL(k_targets, dim3(nblk(B, 128)), dim3(128), 0, (hipStream_t)stream, (long)B, traj, nmax,
+                     flip ? 17 : 7, flip ? 8 : 7, nseg, knots, smax, feasible, cost, y_feas, y_cost, y_traj,
+                     traj_mask);
   return hipGetLastError() == hipSuccess ? COMET_OK : COMET_EHIP;
 }
 
-comet_status comet_mlp_decode_warm(void* stream, int64_t B, const float* out, int32_t out_dim, const float* x0,
-                                   const int32_t* nseg, const int32_t* knots, int32_t smax, int32_t nmax, float* warm) {
-  if (!out || !x0 || !nseg || !knots || !warm || out_dim < 2 + 6 * WS_SLOTS * WS_CH) return COMET_EINVAL;
+comet_status comet_mlp_decode_warm(comet_task task, void* stream, int64_t B, const float* out, int32_t out_dim,
+                                   const float* x0, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
+                                   int32_t smax, int32_t nmax, float* warm) {
+  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP) || !out || !x0 || !nseg || !knots || !warm ||
+      out_dim < 2 + 6 * WS_SLOTS * WS_CH)
+    return COMET_EINVAL;
+  if (task == COMET_TASK_FLIP && !modes) return COMET_EINVAL;
   if (B < 0 || smax < 1 || smax > 6 || nmax < 1) return COMET_EINVAL;
   if (B == 0) return COMET_OK;
-  hipLaunchKernelGGL(k_decode_warm, dim3(nblk(B, 128)), dim3(128), 0, (hipStream_t)stream, (long)B,
-                     (const long long*)nullptr, out, out_dim, x0, 1, nseg, knots, smax, nmax, warm);
+  if (task == COMET_TASK_FLIP)
+    hipLaunchKernelGGL(k_decode_warm_flip, dim3(nblk(B, 128)), dim3(128), 0, (hipStream_t)stream, (long)B,
+                       (const long long*)nullptr, out, out_dim, x0, 1, nseg, modes, knots, smax, nmax, warm);
+  else
+    hipLaunchKernelGGL(k_decode_warm, dim3(nblk(B, 128)), dim3(128), 0, (hipStream_t)stream, (long)B,
+                       (const long long*)nullptr, out, out_dim, x0, 1, nseg, knots, smax, nmax, warm);
   return hipGetLastError() == hipSuccess ? COMET_OK : COMET_EHIP;
 }
 

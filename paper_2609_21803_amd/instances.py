@@ -110,6 +110,18 @@ def flip_pairs(seed: int, n: int):
     return x0, goal, mu.reshape(n, 1)
 
 
+def flip_pivot_pairs(seed: int, n: int, th_lo: float = 0.9, th_hi: float = 1.5):
+    """n start/goal pairs whose goal a pivot about the bottom-left corner of the resting box
+    reaches: th ~ U[th_lo, th_hi], px the centre's displacement under that rotation, table
+    friction ~ U[0.62, 0.78]."""
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(th_lo, th_hi, n)
+    cx, cy = -0.1, -0.05                     # corner relative to the centre (box 0.2 x 0.1 m)
+    px = -0.1 - (np.cos(th) * cx - np.sin(th) * cy)
+    mu = rng.uniform(0.62, 0.78, n)
+    return np.tile(np.array(FLIP_X0), (n, 1)), np.stack([px, th], 1), mu.reshape(n, 1)
+
+
 def flip_orders(rng, B: int, kmin: int, kmax: int):
     """B i.i.d. flip orders: K ~ U{kmin..kmax}, finger codes ~ U{0..12}, table mode ~
     U{0..4}, except that a pivot directly after a pivot keeps its direction (an order

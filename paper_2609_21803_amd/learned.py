@@ -39,6 +39,71 @@ def generate(n_samples: int, seed: int = 4000, chunk: int = 65536, kmin=1, kmax=
     return dict(X=X, y_feas=yf, y_cost=yc, y_traj=yt, mask=mk)
 
 
+def flip_seed_keys(ctx: native.Context, kcap: int = 2, knots: int = 10):
+    """The filtered single-segment seed of the flipping expansion (Alg. 1's first
+    frontier), read back from a zero-round device expansion."""
+    import torch
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+    x0, goal, inst = I.flip_pairs(1, 1)
+    prm = native.ExpandParams(kcap=kcap, seed_max_segments=1, radius=1, rounds=0, frontier_W=1,
+                              knots_per_segment=knots, k_ref=0, batch_B=min(ctx.max_batch, 4096), eval_budget=4096)
+    native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm)
+    keys, _, _ = native.expand_trace(ctx)
+    return keys.clone()
+
+
+def decode_keys(keys, smax: int = 6):
+    """Order keys (3 bits K at 60, ten bits per mode from bit 50 down) -> nseg, modes."""
+    import torch
+    nseg = (keys >> 60).to(torch.int32)
+    shifts = torch.tensor([50 - 10 * j for j in range(smax)], device=keys.device, dtype=torch.int64)
+    modes = ((keys[:, None] >> shifts[None, :]) & 1023).to(torch.int32)
+    modes = torch.where(torch.arange(smax, device=keys.device)[None, :] < nseg[:, None], modes, 0)
+    return nseg, modes
+
+
+def generate_flip(n_instances: int, seed: int = 5000, ctx: native.Context | None = None, kcap: int = 2,
+                  parents: int = 16, room: int = 1024, knots: int = 10, chunk: int = 32768, pairs=I.flip_pivot_pairs):
+    """Flipping training data: on each seeded start/goal pair (``pairs(seed, n)``), the
+    expansion's seed orders plus `room` neighbours (one edit) of `parents` random seed
+    orders, built by the device batch constructor; every order is solved by the evaluator
+    and turned into (X, targets) on the GPU."""
+    import torch
+    ctx = ctx or native.Context(max_batch=chunk, max_segments=6, max_intervals=kcap * knots, task=native.TASK_FLIP)
+    seed_keys = flip_seed_keys(ctx, kcap, knots)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    prm = native.ExpandParams(kcap=kcap, seed_max_segments=1, radius=1, rounds=1, frontier_W=parents,
+                              knots_per_segment=knots, k_ref=0, batch_B=room, eval_budget=room)
+    x0, goal, inst = pairs(seed, n_instances)
+    keys, pair = [], []
+    for i in range(n_instances):
+        merit = torch.rand(seed_keys.shape[0], generator=g, device="cuda", dtype=torch.float64)
+        nb = native.expand_next(ctx, seed_keys, merit, prm, room)
+        keys.append(torch.cat([seed_keys, nb]))
+        pair.append(torch.full((keys[-1].shape[0],), i, dtype=torch.int64, device="cuda"))
+    keys, pair = torch.cat(keys), torch.cat(pair)
+    n = int(keys.shape[0])
+    nseg, modes = decode_keys(keys)
+    kn = torch.where(modes.new_ones(modes.shape).cumsum(1) <= nseg[:, None], knots, 0).to(torch.int32)
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+    X0, G, M = f32(x0)[pair], f32(goal)[pair], f32(inst)[pair]
+    X = torch.empty((n, native.MLP.IN), dtype=torch.int16, device="cuda")
+    yf = torch.empty(n, device="cuda")
+    yc = torch.empty(n, device="cuda")
+    yt = torch.empty((n, 720), device="cuda")
+    mk = torch.empty((n, 720), device="cuda")
+    for s in range(0, n, ctx.max_batch):
+        e = min(n, s + ctx.max_batch)
+        d = dict(x0=X0[s:e].contiguous(), goal=G[s:e].contiguous(), inst=M[s:e].contiguous(),
+                 nseg=nseg[s:e].contiguous(), modes=modes[s:e].contiguous(), knots=kn[s:e].contiguous())
+        out = ctx.evaluate(**d)
+        X[s:e] = native.mlp_encode(d, task=native.TASK_FLIP)
+        f, c, t, m = native.mlp_targets(d, out, ctx.max_intervals, task=native.TASK_FLIP)
+        yf[s:e], yc[s:e], yt[s:e], mk[s:e] = f, c, t, m
+    return dict(X=X, y_feas=yf, y_cost=yc, y_traj=yt, mask=mk)
+
+
 def train(mlp: native.MLP, data: dict, steps: int, batch: int = 8192, lr: float = 1e-3, seed: int = 0,
           weight_decay: float = 1e-4, log_every: int = 0):
     """AdamW with cosine learning-rate decay over random minibatches; returns the loss log."""

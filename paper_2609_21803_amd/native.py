@@ -126,9 +126,10 @@ def lib():
         L.comet_mlp_train_step.restype = C.c_int
         L.comet_mlp_encode.argtypes = [C.c_int, P, C.c_int64, P, P, P, P, P, P, C.c_int32, C.c_int32, P]
         L.comet_mlp_encode.restype = C.c_int
-        L.comet_mlp_targets.argtypes = [P, C.c_int64, P, C.c_int32, P, P, C.c_int32, P, P, P, P, P, P]
+        L.comet_mlp_targets.argtypes = [C.c_int, P, C.c_int64, P, C.c_int32, P, P, C.c_int32, P, P, P, P, P, P]
         L.comet_mlp_targets.restype = C.c_int
-        L.comet_mlp_decode_warm.argtypes = [P, C.c_int64, P, C.c_int32, P, P, P, C.c_int32, C.c_int32, P]
+        L.comet_mlp_decode_warm.argtypes = [C.c_int, P, C.c_int64, P, C.c_int32, P, P, P, P, C.c_int32, C.c_int32,
+                                            P]
         L.comet_mlp_decode_warm.restype = C.c_int
         L.comet_last_kernel_ms.argtypes = [P, C.POINTER(C.c_float)]
         L.comet_last_kernel_ms.restype = C.c_int
@@ -392,35 +393,35 @@ class MLP:
         return loss
 
 
-def mlp_encode(d: dict, in_dim=416):
+def mlp_encode(d: dict, in_dim=416, task=TASK_PUSH):
     """Encode device batches (as from to_device) for the network: [B, in_dim] BF16 bits."""
     import torch
     B = int(d["nseg"].shape[0])
     smax = int(d["modes"].shape[1])
     x = torch.empty((B, in_dim), dtype=torch.int16, device="cuda")
-    check(lib().comet_mlp_encode(TASK_PUSH, _stream(), B, _ptr(d["x0"]), _ptr(d["goal"]), _ptr(d["inst"]),
+    check(lib().comet_mlp_encode(task, _stream(), B, _ptr(d["x0"]), _ptr(d["goal"]), _ptr(d["inst"]),
                                  _ptr(d["nseg"]), _ptr(d["modes"]), _ptr(d["knots"]), smax, in_dim, _ptr(x)))
     return x
 
 
-def mlp_targets(d: dict, out: dict, nmax: int):
+def mlp_targets(d: dict, out: dict, nmax: int, task=TASK_PUSH):
     import torch
     B = int(d["nseg"].shape[0])
     smax = int(d["modes"].shape[1])
     f = lambda *s: torch.empty(s, dtype=torch.float32, device="cuda")
     yf, yc, yt, m = f(B), f(B), f(B, 720), f(B, 720)
-    check(lib().comet_mlp_targets(_stream(), B, _ptr(out["traj"]), nmax, _ptr(d["nseg"]), _ptr(d["knots"]), smax,
+    check(lib().comet_mlp_targets(task, _stream(), B, _ptr(out["traj"]), nmax, _ptr(d["nseg"]), _ptr(d["knots"]), smax,
                                   _ptr(out["feasible"]), _ptr(out["cost"]), _ptr(yf), _ptr(yc), _ptr(yt), _ptr(m)))
     return yf, yc, yt, m
 
 
-def mlp_decode_warm(y, d: dict, nmax: int):
+def mlp_decode_warm(y, d: dict, nmax: int, task=TASK_PUSH):
     import torch
     B = int(d["nseg"].shape[0])
     smax = int(d["modes"].shape[1])
-    w = torch.empty((B, nmax + 1, 7), dtype=torch.float32, device="cuda")
-    check(lib().comet_mlp_decode_warm(_stream(), B, _ptr(y), int(y.shape[1]), _ptr(d["x0"]), _ptr(d["nseg"]),
-                                      _ptr(d["knots"]), smax, nmax, _ptr(w)))
+    w = torch.empty((B, nmax + 1, ROW_WIDTH[task]), dtype=torch.float32, device="cuda")
+    check(lib().comet_mlp_decode_warm(task, _stream(), B, _ptr(y), int(y.shape[1]), _ptr(d["x0"]), _ptr(d["nseg"]),
+                                      _ptr(d["modes"]), _ptr(d["knots"]), smax, nmax, _ptr(w)))
     return w
 
 
