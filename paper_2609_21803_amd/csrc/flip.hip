@@ -385,7 +385,8 @@ struct FlipArgs {
 struct Shm {
   double A[NR][NV + 1];
   double cr[NR], wr[NR], yr[NR];
-  unsigned nzm[NR];       // nonzero columns of each Jacobian row
+  double M[NV + 1][NV + 2];   // bordered Gauss-Newton block, lower triangle (see sweep)
+  double invd[NW];            // inverse pivots
   double Pm[NX][NX + 1], pv[NX];
   double h[NV];
   double v[NV];           // row arguments of the interval being linearised
@@ -467,12 +468,74 @@ __device__ __forceinline__ double stage_merit(const FlipArgs& A, const Shm& sh, 
   return phi;
 }
 
-// Backward sweep over the intervals (lanes over rows / matrix entries).  Always computes
-// the merit phi and the gradient g of phi (stored per interval in A.g); with `factor`,
-// also the Riccati recursion with damping rho, storing the gains.  Returns 1 if every
-// factorisation succeeded (or factor is false).
-__device__ __forceinline__ int sweep(const FlipArgs& A, Shm& sh, int64_t b, bool factor, double mu, double rho,
-                     const double* lamT, double& phi_out, double& gnorm_out) {
+// Per-lane slot table of the factorisation, fixed for the whole solve: tri[t] is entry
+// e = lane + 64 t of the lower triangle of an order-25 block enumerated row by row, packed
+// as (row << 8) | column (-1 past the end); the first n (n + 1) / 2 entries of that
+// enumeration are the lower triangle of order n, so one table serves every pivot.
+struct Slots {
+  int tri[6];
+};
+__device__ inline Slots make_slots(int lane) {
+  Slots S;
+  for (int t = 0; t < 6; ++t) {
+    const int e = lane + 64 * t;
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    S.tri[t] = (e < NV * (NV + 1) / 2) ? ((i << 8) | (e - i * (i + 1) / 2)) : -1;
+  }
+  return S;
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// One pivot step of the symmetric elimination over NS slots of the trailing triangle of
+// order T = n (n + 1) / 2 (entries p+1 .. NV): M[i][j] -= M[i][p] M[j][p] / d.  The slot
+// code is straight-line: a lane whose slot lies past T reads entry (NV, NV) and stores into
+// the padding column, so every load of the step is in flight at once.  Returns the updated
+// entry (p+1, p+1) in lane 0 (slot 0 of lane 0), the next pivot.
+template <int NS>
+__device__ __forceinline__ double elim_step(double* Mf, const int* tri, int lane, int p, int T, double id) {
+  constexpr int LD = NV + 2;
+  int at[NS];
+  double mi[NS], mj[NS], mij[NS];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    const bool in = lane + 64 * t < T;
+    const int ij = tri[t];
+    const int i = in ? p + 1 + (ij >> 8) : NV;
+    const int j = in ? p + 1 + (ij & 255) : NV;
+    at[t] = in ? i * LD + j : NV * LD + NV + 1;
+    mi[t] = Mf[i * LD + p];
+    mj[t] = Mf[j * LD + p];
+    mij[t] = Mf[i * LD + j];
+  }
+  double nd = 0.0;
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    const double val = mij[t] - mi[t] * mj[t] * id;
+    Mf[at[t]] = val;
+    if (t == 0) nd = val;
+  }
+  return nd;
+}
+
+// Backward sweep over the intervals.  Always computes the merit phi and the gradient g of
+// phi (stored per interval in A.g); with `factor`, also the Riccati recursion with damping
+// rho, storing the gains.  Returns 1 if every factorisation succeeded (or factor is false).
+//
+// Factorisation of one interval.  The Gauss-Newton block over (w_k, x_k), w_k = (u_k,
+// x_{k+1}), is bordered by the gradient q and held in LDS as the lower triangle of the
+// order-26 matrix  [[S, Q_wx, q_w], [Q_xw, Q_xx, q_x], [q_w', q_x', .]]  in the variable
+// order (u_k, x_{k+1}, x_k, 1).  Its row part sum_r w_r a_r a_r' (and the row gradient
+// sum_r y_r a_r in the border row) is one dense 26 x 32 x 26 product on the FP64 matrix
+// cores.  Symmetric elimination of the 17 w pivots (lanes over the entries of the trailing
+// triangle) leaves, by the Schur complement, the value function (P, p) of x_k in the
+// trailing block and L^{-1} [Q_wx, q_w] (scaled by the pivots) in the eliminated columns;
+// a back substitution with one lane per right-hand side then gives the gains.  The
+// pivots are the squares of the Cholesky diagonal of S, so a non-positive pivot is the
+// positive-definiteness failure.
+__device__ __forceinline__ int sweep(const FlipArgs& A, Shm& sh, const Slots& SL, int64_t b, bool factor, double mu,
+                                     double rho, const double* lamT, double& phi_out, double& gnorm_out) {
   const int lane = threadIdx.x, N = sh.N;
   const double imu = 1.0 / mu;
   double phi_acc = 0.0, gmax = 0.0;
@@ -535,22 +598,54 @@ __device__ __forceinline__ int sweep(const FlipArgs& A, Shm& sh, int64_t b, bool
       sh.cr[lane] = c;
       sh.yr[lane] = y;
       sh.wr[lane] = wt;
-      unsigned m = 0;
-      if (wt != 0.0)
-        for (int j = 0; j < NV; ++j) m |= (sh.A[lane][j] != 0.0) ? (1u << j) : 0u;
-      sh.nzm[lane] = m;
     } else if (lane < NR + NU) {
       const int i = lane - NR;
       const double u = v[NX + i];
       phi_acc += DT * cost_weight(i) * u * u;
     }
     __syncthreads();
+    const bool fac = factor && ok;   // the same in every lane
+    if (fac) {
+      // row part of the block on the matrix cores: tile (I, J) of D = (W A)' A, rows of
+      // tile-row 1 include the border row y' A (index NV)
+      const int c16 = lane & 15, kq = lane >> 4;
+      const int n1 = 16 + c16;
+      const int v0 = NX + c16;                                  // variable of block index c16
+      const int v1 = (n1 < NW) ? NX + n1 : n1 - NW;             // of block index n1 (if < NV)
+      f64x4 d00 = {0.0, 0.0, 0.0, 0.0}, d10 = {0.0, 0.0, 0.0, 0.0}, d11 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+      for (int s4 = 0; s4 < NR / 4; ++s4) {
+        const int r = 4 * s4 + kq;
+        const double wr = sh.wr[r];
+        const double b0 = sh.A[r][v0];
+        const double b1 = (n1 < NV) ? sh.A[r][v1] : 0.0;
+        const double a1 = (n1 < NV) ? wr * b1 : ((n1 == NV) ? sh.yr[r] : 0.0);
+        d00 = __builtin_amdgcn_mfma_f64_16x16x4f64(wr * b0, b0, d00, 0, 0, 0);
+        d10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, d10, 0, 0, 0);
+        d11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, d11, 0, 0, 0);
+      }
+      // register q of lane l holds entry (l / 16 + 4 q, l % 16) of a tile
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = kq + 4 * q;
+        sh.M[i][c16] = d00[q];
+        if (16 + i <= NV) {
+          sh.M[16 + i][c16] = d10[q];
+          if (n1 <= NV) sh.M[16 + i][n1] = d11[q];
+        }
+      }
+      __syncthreads();
+    }
     // stage gradient h (no value function) and the gradient of phi for w_k
     if (lane < NV) {
       double s = 0.0;
-      for (int r = 0; r < NR; ++r) {
-        const double y = uniform(sh.yr[r]);   // same for every lane: a scalar branch skips zero rows
-        if (y != 0.0) s += y * sh.A[r][lane];
+      if (fac) {
+        s = sh.M[NV][(lane < NX) ? NW + lane : lane - NX];
+      } else {
+        for (int r = 0; r < NR; ++r) {
+          const double y = uniform(sh.yr[r]);   // same for every lane: a scalar branch skips zero rows
+          if (y != 0.0) s += y * sh.A[r][lane];
+        }
       }
       if (lane >= NX && lane < NX + NU) s += 2.0 * DT * cost_weight(lane - NX) * v[lane];
       sh.h[lane] = s;
@@ -563,116 +658,78 @@ __device__ __forceinline__ int sweep(const FlipArgs& A, Shm& sh, int64_t b, bool
     }
     __syncthreads();
     if (lane < NX) sh.carry[lane] = sh.h[lane];   // x_k part goes to the previous interval's w
-    if (factor && ok) {
-      // Gauss-Newton block over y = (x_k, w_k): cost Hessian + (1/mu) sum of active rows
-      // + value function of x_{k+1} + rho on the w block.  Lane a < 25 holds row a of the
-      // block in registers (q) and entry a of the stage gradient (hv).
-      double q[NV];
-#pragma unroll
-      for (int j = 0; j < NV; ++j) q[j] = 0.0;
-      double hv = 0.0;
-      if (lane < NV) {
-        for (int r = 0; r < NR; ++r) {
-          // the column mask is the same for every lane: scalar branches skip the zero
-          // columns of row r, and inactive rows (mask 0) entirely
-          const unsigned m = (unsigned)__builtin_amdgcn_readfirstlane((int)sh.nzm[r]);
-          if (m == 0u) continue;
-          const double wa = ((m >> lane) & 1u) ? sh.wr[r] * sh.A[r][lane] : 0.0;
-#pragma unroll
-          for (int j = 0; j < NV; ++j)
-            if ((m >> j) & 1u) q[j] += wa * sh.A[r][j];
-        }
-        hv = sh.h[lane];
-#pragma unroll
-        for (int j = 0; j < NV; ++j) {
-          if (j != lane) continue;
-          if (j >= NX && j < NX + NU) q[j] += 2.0 * DT * cost_weight(j - NX);
-          if (j >= NX) q[j] += rho;
-        }
-        if (lane >= NX + NU) {
-          const int i = lane - NX - NU;
-#pragma unroll
-          for (int j = 0; j < NX; ++j) q[NX + NU + j] += sh.Pm[i][j];
-          hv += sh.pv[i];
-        }
+    if (fac) {
+      // cost Hessian and damping on the w diagonal, value function of x_{k+1} (P into the
+      // x_{k+1} block, p into the border), border = stage gradient q
+      if (lane < NW) {
+        double dg = rho;
+        if (lane < NU) dg += 2.0 * DT * cost_weight(lane);
+        else dg += sh.Pm[lane - NU][lane - NU];
+        sh.M[lane][lane] += dg;
+        sh.M[NV][lane] = sh.h[NX + lane] + ((lane >= NU) ? sh.pv[lane - NU] : 0.0);
+      } else if (lane < NV) {
+        sh.M[NV][lane] = sh.h[lane - NW];
       }
-      // Gaussian elimination of the w block (rows / lanes 8..24) without pivoting; its
-      // pivots are the squares of the Cholesky diagonal, so a non-positive pivot is the
-      // positive-definiteness failure.  Right-hand sides: columns 0..7 (Q_wx) and hv (q_w).
+      {
+        const int i = lane / NX, j = lane % NX;
+        if (j < i) sh.M[NU + i][NU + j] += sh.Pm[i][j];
+      }
+      __syncthreads();
+      // symmetric elimination of the w pivots 0..16 over the trailing lower triangle; all
+      // loads of a pivot step are issued before its stores
+      // The next pivot is entry (p+1, p+1), the first of the trailing triangle: lane 0 updates
+      // it in slot 0 and passes it on by readlane, so each step costs one LDS round trip.
       int fail = 0;
-#pragma unroll
-      for (int jj = 0; jj < NW; ++jj) {
-        constexpr int base = NX;
-        const int pl = base + jj;
-        const double piv = bcast(q[base + jj], pl);
-        if (!(piv > 0.0) || !isfinite(piv)) {
+      double d = uniform(sh.M[0][0]);
+#pragma unroll 1
+      for (int p = 0; p < NW; ++p) {
+        if (!(d > 0.0) || !isfinite(d)) {
           fail = 1;
           break;
         }
-        const double f = (lane > pl && lane < NV) ? q[base + jj] / piv : 0.0;
-#pragma unroll
-        for (int c = 0; c < NV; ++c) {
-          if (c >= base && c <= pl) continue;   // eliminated / pivot columns are not used again
-          q[c] -= f * bcast(q[c], pl);
-        }
-        hv -= f * bcast(hv, pl);
+        const double id = 1.0 / d;
+        if (lane == 0) sh.invd[p] = id;
+        const int n = NV - p, T = n * (n + 1) / 2;
+        // six slots while the triangle has more than 192 entries (p < 6), then three
+        const double nd = (T > 192) ? elim_step<6>(&sh.M[0][0], SL.tri, lane, p, T, id)
+                                    : elim_step<3>(&sh.M[0][0], SL.tri, lane, p, T, id);
+        d = bcast(nd, 0);
+        __syncthreads();
       }
       if (fail) {
         ok = 0;
       } else {
-        // back substitution: lane 8 + i ends with row i of X = S^{-1} [Q_wx | q_w]
+        // gains X = S^{-1} [Q_wx, q_w]: lane c < 9 solves for column c in registers.  Column
+        // p of the eliminated block holds z_p = d_p (L^{-1} [Q_wx, q_w])[p] with L unit lower,
+        // L[i][p] = M[i][p] / d_p, so X[p] = (z_p - sum_{i>p} M[i][p] X[i]) / d_p
+        if (lane <= NX) {
+          double zc[NW];
 #pragma unroll
-        for (int jj = NW - 1; jj >= 0; --jj) {
-          const int pl = NX + jj;
-          if (lane == pl) {
-            const double d = q[NX + jj];
+          for (int pp = 0; pp < NW; ++pp) zc[pp] = sh.M[NW + lane][pp];
 #pragma unroll
-            for (int c = 0; c < NX; ++c) q[c] /= d;
-            hv /= d;
+          for (int i = NW - 1; i >= 0; --i) {
+            const double xi = zc[i] * sh.invd[i];
+            zc[i] = xi;
+#pragma unroll
+            for (int pp = 0; pp < i; ++pp) zc[pp] -= sh.M[i][pp] * xi;
           }
-          double xc[NX];
+          // k = -X[:, q_w], K = -X[:, Q_wx]
+          double* kk = A.kk + (b * A.nmax + k) * NW;
+          double* KK = A.KK + (b * A.nmax + k) * NW * NX;
 #pragma unroll
-          for (int c = 0; c < NX; ++c) xc[c] = bcast(q[c], pl);
-          const double xh = bcast(hv, pl);
-          if (lane >= NX && lane < pl) {
-            const double u = q[NX + jj];
-#pragma unroll
-            for (int c = 0; c < NX; ++c) q[c] -= u * xc[c];
-            hv -= u * xh;
+          for (int pp = 0; pp < NW; ++pp) {
+            if (lane < NX)
+              KK[pp * NX + lane] = -zc[pp];
+            else
+              kk[pp] = -zc[pp];
           }
         }
-        // gains k = -X[:, q_w], K = -X[:, Q_wx]
-        if (lane >= NX && lane < NV) {
-          const int i = lane - NX;
-          A.kk[(b * A.nmax + k) * NW + i] = -hv;
-          double* Kr = A.KK + ((b * A.nmax + k) * NW + i) * NX;
-#pragma unroll
-          for (int c = 0; c < NX; ++c) Kr[c] = -q[c];
-        }
-        // value function of x_k on lanes 0..7: P = Q_xx + Q_xw K, p = q_x + Q_xw k
-        double P[NX], pvn = hv;
-#pragma unroll
-        for (int j = 0; j < NX; ++j) P[j] = q[j];
-#pragma unroll
-        for (int i = 0; i < NW; ++i) {
-          const double u = q[NX + i];
-#pragma unroll
-          for (int j = 0; j < NX; ++j) P[j] -= u * bcast(q[j], NX + i);
-          pvn -= u * bcast(hv, NX + i);
-        }
-        if (lane < NX) {
-#pragma unroll
-          for (int j = 0; j < NX; ++j) sh.Pm[lane][j] = P[j];
-          sh.pv[lane] = pvn;
-        }
-        __syncthreads();
-        double ps = 0.0;
-        if (lane < NX * NX) {
+        // value function of x_k: the trailing block after the elimination
+        {
           const int i = lane / NX, j = lane % NX;
-          ps = 0.5 * (sh.Pm[i][j] + sh.Pm[j][i]);
+          sh.Pm[i][j] = sh.M[NW + max(i, j)][NW + min(i, j)];
         }
-        __syncthreads();
-        if (lane < NX * NX) sh.Pm[lane / NX][lane % NX] = ps;
+        if (lane < NX) sh.pv[lane] = sh.M[NV][NW + lane];
       }
     }
     __syncthreads();
@@ -961,6 +1018,7 @@ __global__ __launch_bounds__(64, 2) void k_flip_solve(FlipArgs A) {
   for (int e = lane; e < N * NI; e += 64) A.nu[b * A.nmax * NI + e] = 0.0;
   __syncthreads();
 
+  const Slots SL = make_slots(lane);
   double mu = A.warm ? prm.mu0_warm : prm.mu0;
   double eta = pow(mu, 0.1), omega = mu, rho = prm.rho0;
   double lamT[NT] = {0, 0, 0, 0, 0};
@@ -971,7 +1029,7 @@ __global__ __launch_bounds__(64, 2) void k_flip_solve(FlipArgs A) {
     al_iters = al + 1;
     for (int it = 0; it < prm.gn_max; ++it) {
       double phi0, gnorm;
-      int ok = sweep(A, sh, b, true, mu, rho, lamT, phi0, gnorm);
+      int ok = sweep(A, sh, SL, b, true, mu, rho, lamT, phi0, gnorm);
       if (gnorm <= omega) break;
       int tries = 0;
       while (!ok && tries < prm.chol_retries) {
@@ -979,7 +1037,7 @@ __global__ __launch_bounds__(64, 2) void k_flip_solve(FlipArgs A) {
         rho = fmax(10.0 * rho, 1e-8);
         ++tries;
         double p2, g2;
-        ok = sweep(A, sh, b, true, mu, rho, lamT, p2, g2);
+        ok = sweep(A, sh, SL, b, true, mu, rho, lamT, p2, g2);
       }
       if (!ok) ++cfails;
       ++gn_iters;
@@ -1016,7 +1074,7 @@ __global__ __launch_bounds__(64, 2) void k_flip_solve(FlipArgs A) {
     // outer update at the final inner iterate
     double vs, rc, phi_u, gnorm;
     viol_pass(A, sh, b, mu, false, lamT, vs, rc);
-    (void)sweep(A, sh, b, false, mu, rho, lamT, phi_u, gnorm);
+    (void)sweep(A, sh, SL, b, false, mu, rho, lamT, phi_u, gnorm);
     double zbad = 0.0;
     for (int e = lane; e < N * NW; e += 64) zbad = fmax(zbad, isfinite(z[e]) ? 0.0 : 1.0);
     zbad = wave_max(zbad);
