@@ -237,8 +237,8 @@ comet_status comet_expand(comet_ctx* ctx, void* stream, const float* x0, const f
                           const comet_expand_params* params, comet_mlp* learned, int32_t* best_nseg,
                           int32_t* best_modes, int32_t* best_knots, float* best_cost, float* best_viol,
                           float* best_traj, comet_expand_stats* stats);
-/* (learned networks encode pushing orders: a flipping context with learned != NULL is
- * COMET_EINVAL) */
+/* (a learned network encodes orders of the context's task, see comet_mlp_encode; it must
+ * have been trained on that task's results) */
 
 /* One batch-construction step of Alg. 1 on given scores: rank the n evaluated orders
  * (keys [n] uint64, merit [n] double, device) by (merit, key), traverse at most frontier_W of

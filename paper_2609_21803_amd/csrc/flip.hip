@@ -563,12 +563,25 @@ __device__ __forceinline__ int sweep(const FlipArgs& A, Shm& sh, const Slots& SL
     }
     __syncthreads();
   }
+  // interval k's row arguments (lanes < 25), row multiplier (lanes < 32) and contact code
+  // are loaded one interval ahead, so their memory latency overlaps the previous interval
+  const double* zb = A.z + (b * A.nmax) * NW;
+  double v_pre = 0.0, m_pre = 0.0;
+  int code_pre = 0;
+  auto prefetch = [&](int k) {
+    if (lane < NV) v_pre = (lane < NX) ? ((k == 0) ? sh.xk0[lane] : zb[(k - 1) * NW + NU + lane]) : zb[k * NW + lane - NX];
+    if (lane < NE)
+      m_pre = A.lam[(b * A.nmax + k) * NE + lane];
+    else if (lane < NR)
+      m_pre = A.nu[(b * A.nmax + k) * NI + lane - NE];
+    code_pre = A.code[b * A.nmax + k];
+  };
+  prefetch(N - 1);
   for (int k = N - 1; k >= 0; --k) {
-    const Stage S = unpack(A.code[b * A.nmax + k], sh.mu_g);
-    if (lane < NV) {
-      const double* z = A.z + (b * A.nmax) * NW;
-      sh.v[lane] = (lane < NX) ? ((k == 0) ? sh.xk0[lane] : z[(k - 1) * NW + NU + lane]) : z[k * NW + lane - NX];
-    }
+    const Stage S = unpack(code_pre, sh.mu_g);
+    if (lane < NV) sh.v[lane] = v_pre;
+    const double m_row = m_pre;
+    if (k > 0) prefetch(k - 1);
     if (lane < NR)
       for (int j = 0; j < NV; ++j) sh.A[lane][j] = 0.0;
     __syncthreads();
@@ -583,12 +596,12 @@ __device__ __forceinline__ int sweep(const FlipArgs& A, Shm& sh, const Slots& SL
       double y = 0.0, wt = 0.0;
       if (en) {
         if (lane < NE) {
-          const double l = A.lam[(b * A.nmax + k) * NE + lane];
+          const double l = m_row;
           y = l + c * imu;
           wt = imu;
           phi_acc += l * c + c * c / (2.0 * mu);
         } else {
-          const double n = A.nu[(b * A.nmax + k) * NI + lane - NE];
+          const double n = m_row;
           const double t = n + c * imu;
           y = (t > 0.0) ? t : 0.0;
           wt = (t > 0.0) ? imu : 0.0;
