@@ -87,9 +87,13 @@ struct Wrench {
   Face ff[2];
 };
 
-__device__ __forceinline__ void wrench(const Stage& S, const double* v, Wrench& w) {
-  sincos(v[2], &w.s, &w.c);
-  sincos(v[V_X1 + 2], &w.s1, &w.c1);
+// with the sines and cosines of th_k (s, c) and th_{k+1} (s1, c1) given
+__device__ __forceinline__ void wrench_sc(const Stage& S, const double* v, double s, double c, double s1, double c1,
+                                          Wrench& w) {
+  w.s = s;
+  w.c = c;
+  w.s1 = s1;
+  w.c1 = c1;
   double Fwx = 0.0, Fwy = 0.0;
   for (int i = 0; i < 2; ++i) {
     w.Fbx[i] = w.Fby[i] = w.tau[i] = 0.0;
@@ -113,6 +117,13 @@ __device__ __forceinline__ void wrench(const Stage& S, const double* v, Wrench& 
   w.ry = MG - Fwy;
   w.drx_dth = Fwy;
   w.dry_dth = -Fwx;
+}
+
+__device__ __forceinline__ void wrench(const Stage& S, const double* v, Wrench& w) {
+  double s, c, s1, c1;
+  sincos(v[2], &s, &c);
+  sincos(v[V_X1 + 2], &s1, &c1);
+  wrench_sc(S, v, s, c, s1, c1, w);
 }
 
 // gradient of the linear combination p rx + q ry of the table reaction into a[]
@@ -434,12 +445,14 @@ __device__ inline void load_args(const FlipArgs& A, const Shm& sh, int64_t b, in
   for (int i = 0; i < NW; ++i) v[NX + i] = z[k * NW + i] + (alpha != 0.0 ? alpha * dz[k * NW + i] : 0.0);
 }
 
-// merit contribution of interval k (cost + rows) at v, and of the terminal rows if k = N-1
-__device__ __forceinline__ double stage_merit(const FlipArgs& A, const Shm& sh, int64_t b, int k, const double* v, double mu,
-                              const double* lamT) {
+// merit contribution of interval k (cost + rows) at v, and of the terminal rows if k = N-1;
+// (s0, c0), (s1, c1): sine and cosine of th_k and th_{k+1}
+__device__ __forceinline__ double stage_merit(const FlipArgs& A, const Shm& sh, int64_t b, int k, const double* v,
+                                              double s0, double c0, double s1, double c1, double mu,
+                                              const double* lamT) {
   const Stage S = unpack(A.code[b * A.nmax + k], sh.mu_g);
   Wrench w;
-  wrench(S, v, w);
+  wrench_sc(S, v, s0, c0, s1, c1, w);
   double phi = 0.0;
   for (int i = 0; i < NU; ++i) phi += DT * cost_weight(i) * v[NX + i] * v[NX + i];
   const double* lam = A.lam + (b * A.nmax + k) * NE;
@@ -577,6 +590,9 @@ __device__ __forceinline__ int sweep(const FlipArgs& A, Shm& sh, const Slots& SL
     code_pre = A.code[b * A.nmax + k];
   };
   prefetch(N - 1);
+  // sine and cosine of th_{k+1}, carried from interval k+1 (where it was th_k)
+  double sn1, cs1;
+  sincos(zb[(N - 1) * NW + NU + 2], &sn1, &cs1);
   for (int k = N - 1; k >= 0; --k) {
     const Stage S = unpack(code_pre, sh.mu_g);
     if (lane < NV) sh.v[lane] = v_pre;
@@ -587,9 +603,11 @@ __device__ __forceinline__ int sweep(const FlipArgs& A, Shm& sh, const Slots& SL
     __syncthreads();
     const double* v = sh.v;
     // rows: lane r evaluates row r and writes its gradient into A[r]
+    double sn0, cs0;
+    sincos(v[2], &sn0, &cs0);
     if (lane < NR) {
       Wrench w;
-      wrench(S, v, w);
+      wrench_sc(S, v, sn0, cs0, sn1, cs1, w);
       double c;
       int en;
       row<true>(S, w, lane, v, c, sh.A[lane], en);
@@ -671,6 +689,8 @@ __device__ __forceinline__ int sweep(const FlipArgs& A, Shm& sh, const Slots& SL
     }
     __syncthreads();
     if (lane < NX) sh.carry[lane] = sh.h[lane];   // x_k part goes to the previous interval's w
+    sn1 = sn0;
+    cs1 = cs0;
     if (fac) {
       // cost Hessian and damping on the w diagonal, value function of x_{k+1} (P into the
       // x_{k+1} block, p into the border), border = stage gradient q
@@ -771,16 +791,33 @@ __device__ __forceinline__ void forward(const FlipArgs& A, Shm& sh, int64_t b) {
   }
 }
 
-// lanes over (interval, trial): phi(z + alpha_t dz) for t < T
+// lanes over intervals, one trial step after the other: phi(z + alpha_t dz) for t < T.
+// Each lane takes the sine and cosine of its th_{k+1}; those of th_k come from the lane
+// below (th_0 does not move: dx_0 = 0), or across a 64-interval chunk boundary from lane 63.
 __device__ __forceinline__ void trials(const FlipArgs& A, Shm& sh, int64_t b, int T, double mu, const double* lamT) {
   const int lane = threadIdx.x, N = sh.N;
+  double sx0, cx0;
+  sincos(sh.xk0[2], &sx0, &cx0);
   for (int t = 0; t < T; ++t) {
     const double alpha = ldexp(1.0, -t);
-    double acc = 0.0;
-    for (int k = lane; k < N; k += 64) {
+    double acc = 0.0, sp = sx0, cp = cx0;
+    for (int k0 = 0; k0 < N; k0 += 64) {
+      const int k = k0 + lane;
+      const bool on = k < N;
       double v[NV];
-      load_args(A, sh, b, k, alpha, v);
-      acc += stage_merit(A, sh, b, k, v, mu, lamT);
+      double s1 = 0.0, c1 = 1.0;
+      if (on) {
+        load_args(A, sh, b, k, alpha, v);
+        sincos(v[V_X1 + 2], &s1, &c1);
+      }
+      double s0 = __shfl_up(s1, 1), c0 = __shfl_up(c1, 1);
+      if (lane == 0) {
+        s0 = sp;
+        c0 = cp;
+      }
+      sp = bcast(s1, 63);
+      cp = bcast(c1, 63);
+      if (on) acc += stage_merit(A, sh, b, k, v, s0, c0, s1, c1, mu, lamT);
     }
     const double s = wave_sum(acc);
     if (lane == 0) sh.trial[t] = s;
