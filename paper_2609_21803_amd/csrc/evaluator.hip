@@ -134,23 +134,49 @@ struct FactorOut {
   bool ok;
 };
 
-// inputs of one interval for the backward sweep: x_k, u_k, multipliers, mode code
+// inputs of one interval for the backward sweep: x_k, u_k, multipliers, mode code, and the
+// step directions of x_k and u_k when a step z += ap dz is pending
 struct StageIn {
   double xk[NX], uk[NU];
+  float dxk[NX], duk[NU];
   float lm[NE], nv[NE];
   int code;
 };
 
-__device__ inline void load_stage(const Lane& L, int k, StageIn& s) {
+__device__ inline void load_stage(const Lane& L, int k, StageIn& s, double ap) {
   L.load_x(k, s.xk);
 #pragma unroll
   for (int i = 0; i < NU; ++i) s.uk[i] = L.z(k, i);
+  if (ap != 0.0) {
+#pragma unroll
+    for (int i = 0; i < NX; ++i) s.dxk[i] = (k > 0) ? L.dz(k - 1, NU + i) : 0.f;
+#pragma unroll
+    for (int i = 0; i < NU; ++i) s.duk[i] = L.dz(k, i);
+  }
 #pragma unroll
   for (int r = 0; r < NE; ++r) {
     s.lm[r] = L.lam(k, r);
     s.nv[r] = L.nu(k, r);
   }
   s.code = L.code(k);
+}
+
+// the accepted step of the previous trip, applied to the entries of z that interval k
+// reads (u_k, and x_k for k > 0) and written back: every entry of z once per sweep
+__device__ inline void apply_stage(const Lane& L, int k, StageIn& s, double ap) {
+  if (ap == 0.0) return;
+  if (k > 0) {
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      s.xk[i] += ap * double(s.dxk[i]);
+      L.z(k - 1, NU + i) = s.xk[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NU; ++i) {
+    s.uk[i] += ap * double(s.duk[i]);
+    L.z(k, i) = s.uk[i];
+  }
 }
 
 // inputs of one interval for the forward sweep: u_k, x_{k+1}, gains, multipliers, code
@@ -178,9 +204,10 @@ __device__ inline void load_fwd(const Lane& L, int k, FwdIn& s) {
 // together with the scaled violation and complementarity residual.
 template <bool FACTOR>
 // With upd set, the first-order multiplier update (lam += c/mu, nu = [nu + c/mu]_+, at the
-// current iterate) is applied row by row before the rows are used.
+// current iterate) is applied row by row before the rows are used.  A step accepted in the
+// previous trip (z += ap dz, ap != 0) is applied to z as the sweep reads it.
 __device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double imu, double rho, double* lamT,
-                               bool upd, FactorOut& out, double& vs, double& rc) {
+                               bool upd, double ap, FactorOut& out, double& vs, double& rc) {
   const EvalArgs& A = *L.A;
   double P[NX][NX], p[NX], gx[NX];
   double xk1[NX];
@@ -194,6 +221,13 @@ __device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double
     // terminal value function V_N and terminal gradient
     double xN[NX], cT[NT];
     L.load_x(L.N, xN);
+    if (ap != 0.0) {
+#pragma unroll
+      for (int i = 0; i < NX; ++i) {
+        xN[i] += ap * double(L.dz(L.N - 1, NU + i));
+        L.z(L.N - 1, NU + i) = xN[i];
+      }
+    }
     eval_terminal(A, xN, L.goal, cT);
     const double sT[NT] = {A.inv_scale[T_TXY], A.inv_scale[T_TXY], A.inv_scale[T_TTH]};
 #pragma unroll
@@ -221,15 +255,16 @@ __device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double
   StageIn nxt;
   double x1c[NX];
   if (on) {
-    load_stage(L, L.N - 1, nxt);
+    load_stage(L, L.N - 1, nxt, ap);
 #pragma unroll
     for (int i = 0; i < NX; ++i) x1c[i] = xk1[i];
   }
   for (int t = 0; t < Nw; ++t) {
     const int k = L.N - 1 - t;
     if (!on || k < 0) continue;
-    const StageIn cur = nxt;
-    if (k >= 1) load_stage(L, k - 1, nxt);
+    StageIn cur = nxt;
+    if (k >= 1) load_stage(L, k - 1, nxt, ap);
+    apply_stage(L, k, cur, ap);
     double xk[NX], uk[NU], x1[NX];
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
@@ -511,16 +546,6 @@ __device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, double 
   }
 }
 
-__device__ void sweep_apply(const Lane& L, int Nw, bool on, double alpha) {
-#pragma unroll 4
-  for (int t = 0; t < Nw; ++t) {
-    const int k = t - (Nw - L.N);
-    if (!on || k < 0) continue;
-#pragma unroll
-    for (int i = 0; i < NW; ++i) L.z(k, i) += alpha * double(L.dz(k, i));
-  }
-}
-
 // physical-unit score (Eq. 4) and trajectory output
 __device__ void sweep_score(const Lane& L, int Nw, bool on, double& J, double& v) {
   const EvalArgs& A = *L.A;
@@ -681,6 +706,7 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
   SolverState st;
   st.reset(prm, false);
   bool exhausted = false;
+  double pend = 0.0;   // step length of an accepted step not yet applied to z
   const int64_t Bn = A.Bdev ? *A.Bdev : A.B;
   const int T = min(max(prm.ls_trials, 1), MAX_TRIALS);
 
@@ -700,6 +726,7 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
           exhausted = true;
         } else {
           const int64_t b = A.order ? (int64_t)A.order[q] : (int64_t)q;
+          pend = 0.0;
           if (load_sequence(L, b)) st.reset(prm, A.warm != nullptr);
         }
       }
@@ -713,7 +740,9 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
     // needs (pending multiplier updates are applied inside the sweep).
     FactorOut fo;
     double vsv, rcv;
-    sweep_backward<true>(L, Nw, active, st.mu, st.imu, st.rho, st.lamT, active && st.upd, fo, vsv, rcv);
+    sweep_backward<true>(L, Nw, active, st.mu, st.imu, st.rho, st.lamT, active && st.upd, active ? pend : 0.0, fo,
+                         vsv, rcv);
+    pend = 0.0;
     if (active) st.upd = false;
     bool step = false, outer_now = false, accepted = false;
     double alpha_acc = 0.0;
@@ -778,7 +807,8 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
         }
       }
     }
-    if (wave_any(accepted)) sweep_apply(L, Nw, accepted, alpha_acc);
+    // an accepted step is applied by the next trip's backward sweep as it reads z
+    if (accepted) pend = alpha_acc;
     bool fin = false;
     if (outer_now) {
       ++st.al;
