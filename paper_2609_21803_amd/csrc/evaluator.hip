@@ -456,7 +456,10 @@ __device__ void sweep_backward(const Lane& L, int Nw, bool on, double mu, double
   }
 }
 
-// Forward pass: dz from the gains (stored), merit at every trial step length.
+// Forward pass: dz from the gains (stored), merit at every trial step length.  The trial
+// loop is unrolled over TU >= T slots so that each trial's merit accumulator phi[i] is a
+// fixed register (a run-time trial index would select among all accumulators per trial).
+template <int TU>
 __device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, double imu, const double* lamT, int T,
                               double* phi) {
   const EvalArgs& A = *L.A;
@@ -501,7 +504,9 @@ __device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, double 
     sincos_d(xk[2], &sb, &cb);
     double alpha = ldexp(1.0, -(T - 1));
     sincos_d(alpha * double(dx[2]), &sa, &ca);
-    for (int i = T - 1; i >= 0; --i) {
+#pragma unroll
+    for (int i = TU - 1; i >= 0; --i) {
+      if (i >= T) continue;   // the same in every lane
       double xt[NX], ut[NU], x1t[NX];
 #pragma unroll
       for (int q = 0; q < NX; ++q) {
@@ -513,10 +518,7 @@ __device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, double 
       const double sc[2] = {sb * ca + cb * sa, cb * ca - sb * sa};
       RowEval R;
       eval_interval<false>(A, xt, ut, x1t, code, L.mu, R, sc);
-      const double contrib = stage_cost(ut) + merit_rows(R, lm, nv, mu, imu);
-#pragma unroll
-      for (int q = 0; q < MAX_TRIALS; ++q)
-        if (q == i) phi[q] += contrib;
+      phi[i] += stage_cost(ut) + merit_rows(R, lm, nv, mu, imu);
       const double s2 = 2.0 * sa * ca, c2 = ca * ca - sa * sa;
       sa = s2;
       ca = c2;
@@ -530,7 +532,9 @@ __device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, double 
   }
   if (on) {
     double alpha = 1.0;
-    for (int i = 0; i < T; ++i) {
+#pragma unroll
+    for (int i = 0; i < TU; ++i) {
+      if (i >= T) break;
       double xt[NX], cT[NT];
 #pragma unroll
       for (int q = 0; q < NX; ++q) xt[q] = xk[q] + alpha * double(dx[q]);
@@ -538,9 +542,7 @@ __device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, double 
       double contrib = 0.0;
 #pragma unroll
       for (int r = 0; r < NT; ++r) contrib += lamT[r] * cT[r] + cT[r] * cT[r] * (0.5 * imu);
-#pragma unroll
-      for (int q = 0; q < MAX_TRIALS; ++q)
-        if (q == i) phi[q] += contrib;
+      phi[i] += contrib;
       alpha *= 0.5;
     }
   }
@@ -779,15 +781,18 @@ __global__ __launch_bounds__(WAVE) void k_push_solve(EvalArgs A) {
     }
     if (wave_any(step)) {
       double phi[MAX_TRIALS];
-      sweep_forward(L, Nw, step, st.mu, st.imu, st.lamT, T, phi);
+      // the default eight trials take the short unrolled variant
+      if (T <= 8)
+        sweep_forward<8>(L, Nw, step, st.mu, st.imu, st.lamT, T, phi);
+      else
+        sweep_forward<MAX_TRIALS>(L, Nw, step, st.mu, st.imu, st.lamT, T, phi);
       if (step) {
         int best = -1;
         double alpha = 1.0, a_best = 0.0;
-        for (int i = 0; i < T; ++i) {
-          double ph = 0.0;
 #pragma unroll
-          for (int q = 0; q < MAX_TRIALS; ++q)
-            if (q == i) ph = phi[q];
+        for (int i = 0; i < MAX_TRIALS; ++i) {
+          if (i >= T) break;
+          const double ph = phi[i];
           if (best < 0 && isfinite(ph) && ph <= fo.phi0 + prm.armijo_c1 * alpha * fo.D) {
             best = i;
             a_best = alpha;
