@@ -101,6 +101,14 @@ __device__ inline void eval_interval(const EvalArgs& A, const double* xk, const 
   }
 }
 
+// residuals only (no Jacobian), scaled by the given per-row factors
+__device__ inline void eval_rows_scaled(const double* xk, const double* uk, const double* x1, int code, double mu,
+                                        const double* sc, const double* isc, RowEval& R) {
+  rows_sc<float>(xk, uk, x1, code, mu, sc[0], sc[1], R.c, nullptr, R.en);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) R.c[r] *= isc[r];
+}
+
 // terminal rows, scaled
 __device__ inline void eval_terminal(const EvalArgs& A, const double* xN, const double* goal, double* c) {
   c[0] = (xN[0] - goal[0]) * A.inv_scale[T_TXY];
@@ -498,6 +506,17 @@ __device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, double 
       nv[r] = cur.nv[r];
     }
     const int code = cur.code;
+    // per-interval constants of the trial steps: row scale factors and the directions in FP64
+    double isc[NR], dxd[NX], dwd[NW];
+    {
+      const bool stick = ((code >> 2) & 3) == 0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) isc[r] = A.inv_scale[row_type(r, stick)];
+#pragma unroll
+      for (int q = 0; q < NX; ++q) dxd[q] = double(dx[q]);
+#pragma unroll
+      for (int q = 0; q < NW; ++q) dwd[q] = double(dw[q]);
+    }
     // sin / cos of theta_k + a_i, a_i = 2^-i dtheta: one sincos of theta_k and of the
     // smallest a_i, then angle doubling towards a_0 and angle addition
     double sb, cb, sa, ca;
@@ -510,14 +529,14 @@ __device__ void sweep_forward(const Lane& L, int Nw, bool on, double mu, double 
       double xt[NX], ut[NU], x1t[NX];
 #pragma unroll
       for (int q = 0; q < NX; ++q) {
-        xt[q] = xk[q] + alpha * double(dx[q]);
-        x1t[q] = x1[q] + alpha * double(dw[NU + q]);
+        xt[q] = xk[q] + alpha * dxd[q];
+        x1t[q] = x1[q] + alpha * dwd[NU + q];
       }
 #pragma unroll
-      for (int q = 0; q < NU; ++q) ut[q] = uk[q] + alpha * double(dw[q]);
+      for (int q = 0; q < NU; ++q) ut[q] = uk[q] + alpha * dwd[q];
       const double sc[2] = {sb * ca + cb * sa, cb * ca - sb * sa};
       RowEval R;
-      eval_interval<false>(A, xt, ut, x1t, code, L.mu, R, sc);
+      eval_rows_scaled(xt, ut, x1t, code, L.mu, sc, isc, R);
       phi[i] += stage_cost(ut) + merit_rows(R, lm, nv, mu, imu);
       const double s2 = 2.0 * sa * ca, c2 = ca * ca - sa * sa;
       sa = s2;
