@@ -84,6 +84,20 @@ def test_tiny_workload_all_orders_match_oracle(orc):
             assert np.argmin(gc) == order[0], p
 
 
+@pytest.mark.parametrize("trials", [3, 12])
+def test_line_search_trial_counts_match_oracle(orc, trials):
+    """Other trial-step counts than the default eight (the forward pass has a separate
+    variant for more than eight trials): the tiny workload against the oracle with the
+    same count."""
+    import oracle
+    from paper_2609_21803_amd import native
+    b = I.push_tiny()
+    g = run_gpu(b, 10, params=native.SolverParams(ls_trials=trials))
+    g["ctx"].check()
+    o = run_oracle(b, 10, params=oracle.Params(ls_trials=trials))
+    compare(g, o, f"tiny, {trials} trials", min_frac=0.995)
+
+
 def test_ragged_batch_matches_oracle(orc):
     """Uneven segment counts (1..5) and interval counts (5..15 per segment) in one launch."""
     b = I.push_hetero(B=2048, seed=77)
