@@ -296,6 +296,55 @@ def learned_flip_leg(native, I, torch):
     }
 
 
+def policy_leg(native, I, torch):
+    """Allocation policies on the same evaluator at equal evaluation budgets: Alg. 1's
+    expansion vs uniform sampling without replacement (the ablation of Sec. V), time to the
+    first feasible plan, plans found and returned cost."""
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+
+    def run(ctx, pairs, prm):
+        rows = []
+        for x0, goal, inst in pairs:
+            o, st = native.expand(ctx, t(x0), t(goal), t(inst), prm)
+            torch.cuda.synchronize()
+            rows.append((int(o["nseg"].item()), float(o["cost"].item()), st))
+        return rows
+
+    def summary(rows):
+        found = [r for r in rows if r[0] > 0]
+        tf = [r[2]["t_first_feasible_ms"] for r in rows if r[2]["t_first_feasible_ms"] > 0]
+        return {"plans_found": f"{len(found)}/{len(rows)}",
+                "ttfp_ms_median": float(np.median(tf)) if tf else None,
+                "first_feasible_index_median": float(np.median([r[2]["first_feasible_index"] for r in rows
+                                                               if r[2]["first_feasible_index"] > 0] or [0])),
+                "feasible_evaluated_median": float(np.median([r[2]["n_feasible"] for r in rows])),
+                "evaluated_median": float(np.median([r[2]["evaluated"] for r in rows])),
+                "cost": [r[1] if r[0] > 0 else None for r in rows]}
+
+    out = {}
+    # flipping: 8 pivot-reachable goals, two-segment cap, budget 2,400
+    ctx = native.Context(max_batch=2048, max_segments=6, max_intervals=20, task=native.TASK_FLIP)
+    pairs = list(zip(*I.flip_pivot_pairs(9400, 8)))
+    common = dict(kcap=2, knots_per_segment=10, k_ref=16, batch_B=2048, eval_budget=2400)
+    e = run(ctx, pairs, native.ExpandParams(**common, seed_max_segments=1, radius=1, rounds=1, frontier_W=8))
+    u = run(ctx, pairs, native.ExpandParams(**common, rounds=1, policy=native.POLICY_UNIFORM, sample_seed=1,
+                                            sample_draws=65536))
+    out["flip"] = {"instances": "8 pivot-reachable flipping goals (seed 9400), K <= 2, 10 intervals per segment, "
+                                "batch 2,048, budget 2,400 evaluations, refinement of 16",
+                   "expansion": summary(e), "uniform": summary(u)}
+    # pushing: 8 start/goal pairs, four-segment cap (22,620 orders), budget 8,000
+    ctx = native.Context(max_batch=4096, max_segments=6, max_intervals=24)
+    pairs = list(zip(*I.push_pairs(9100, 8)))
+    common = dict(kcap=4, knots_per_segment=6, k_ref=64, batch_B=4096, eval_budget=8000)
+    e = run(ctx, pairs, native.ExpandParams(**common, seed_max_segments=2, radius=1, rounds=2, frontier_W=4096))
+    u = run(ctx, pairs, native.ExpandParams(**common, rounds=2, policy=native.POLICY_UNIFORM, sample_seed=1,
+                                            sample_draws=131072))
+    out["push"] = {"instances": "8 pushing start/goal pairs (seed 9100), K <= 4 (22,620 orders), 6 intervals per "
+                                "segment, batch 4,096, budget 8,000 evaluations, refinement of 64",
+                   "expansion": summary(e), "uniform": summary(u)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,6 +354,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal leg")
     ap.add_argument("--no-flip", action="store_true", help="skip the flipping leg")
     ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous-batch leg")
+    ap.add_argument("--no-policies", action="store_true", help="skip the allocation-policy comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -390,6 +440,8 @@ def main():
         res["hetero"] = hetero_leg(native, I, torch)
     if not args.no_flip:
         res["flip"] = flip_leg(native, I, torch, cpu=not args.no_cpu)
+    if not args.no_policies:
+        res["policies"] = policy_leg(native, I, torch)
     if not args.no_learned:
         res["learned"] = learned_leg(native, I, torch)
         res["learned_flip"] = learned_flip_leg(native, I, torch)

@@ -199,13 +199,32 @@ comet_status comet_last_kernel_ms(comet_ctx* ctx, float* ms);
  *   batch_B            batch width B (<= max_batch); eval_budget caps the evaluated orders
  *   mu_merit           mu of the merit M = J + mu max(v - eps_feas, 0), Eq. (5)
  * Ranking is by (M, key) with NaN as +inf; refinement ranks feasible orders by (J, key) and
- * returns the smallest refined J among refined-feasible orders (ties by key). */
+ * returns the smallest refined J among refined-feasible orders (ties by key).
+ *   policy             COMET_POLICY_EXPAND (0): Alg. 1 as above.  COMET_POLICY_UNIFORM (1):
+ *                      the uniform-sampling allocation of the ablations (Sec. V): every batch,
+ *                      the first one included, is drawn instead of generated, complete orders
+ *                      without replacement; seed_max_segments, radius and frontier_W are
+ *                      unused.  Round s makes sample_draws draws, numbered from s *
+ *                      sample_draws; draw c takes outputs 8c .. 8c+6 of the SplitMix64 stream
+ *                      seeded with sample_seed (output i = mix(seed + (i+1) * 0x9E3779B97F4A7C15),
+ *                      mix: z ^= z >> 30, z *= 0xBF58476D1CE4E5B9, z ^= z >> 27,
+ *                      z *= 0x94D049BB133111EB, z ^= z >> 31): K = 1 + out(8c) mod kcap and
+ *                      id j = out(8c+1+j) mod (number of ids), j < K.  A draw outside the
+ *                      task's language, already evaluated, or equal to an earlier draw of the
+ *                      round is dropped; the batch is the first min(room, kept) remaining draws
+ *                      in draw order.  So each segment count is equally likely and, given the
+ *                      count, every admissible order is.  Refinement and the returned plan are
+ *                      as for the expansion.
+ *   sample_draws       draws per round (policy 1; 1 .. 2^27) */
+typedef enum { COMET_POLICY_EXPAND = 0, COMET_POLICY_UNIFORM = 1 } comet_policy;
 typedef struct {
   int32_t kcap, seed_max_segments, radius, rounds, frontier_W, knots_per_segment, k_ref, n_total;
   int32_t learned_warm;   /* with a learned network: 1 = also seed initial trajectories, 0 = order only */
-  int32_t reserved;
+  int32_t policy;         /* comet_policy */
   int64_t batch_B, eval_budget;
   double mu_merit;
+  uint64_t sample_seed;   /* policy 1 */
+  int64_t sample_draws;   /* policy 1 */
 } comet_expand_params;
 
 typedef struct {

@@ -338,11 +338,15 @@ struct ExpCounters {
   long long best_row;
   double best_J, best_v;
   long long nCand;               // candidate slots of the current generation
+  unsigned long long draw_base;  // sampling: number of the next round's first draw
 };
 
 struct ExpCfg {
   int M, kcap, radius, W, raw1max, knots_per_segment, n_total, k_ref;
   int task, row;                 // task, trajectory row width (x_k, u_k)
+  int policy;                    // 0 expansion, 1 uniform sampling
+  unsigned long long sseed;      // sampling: SplitMix64 seed
+  long long draws;               // sampling: draws per round
   long long rawmax, Bmax, budget, Vcap;
   unsigned long long vmask, cmask;
   double eps, mu_merit;
@@ -351,7 +355,7 @@ struct ExpCfg {
 __global__ void k_exp_init(ExpCounters* C) {
   C->nV = 0; C->nF = 0; C->room = 0; C->nRef = 0; C->rounds = 0; C->n_feas = 0;
   C->first_feas = ~0ull; C->kept = 0; C->t_first = ~0ull; C->best_key = 0; C->best_row = -1;
-  C->best_J = NAN; C->best_v = INFINITY; C->nCand = 0;
+  C->best_J = NAN; C->best_v = INFINITY; C->nCand = 0; C->draw_base = 0;
   C->t_start = (unsigned long long)wall_clock64();
 }
 
@@ -452,8 +456,44 @@ __global__ void k_advance(ExpCfg g, ExpCounters* C) {
   if (C->nF > 0) C->rounds += 1;
   C->nF = 0;
   C->room = max(0ll, min(g.Bmax, g.budget - C->nV));
-  C->nCand = (C->room > 0) ? (long long)min((long long)g.W, C->nV) * g.rawmax : 0;
+  C->nCand = (C->room > 0) ? (g.policy ? g.draws : (long long)min((long long)g.W, C->nV) * g.rawmax) : 0;
   C->kept = 0;
+}
+
+// output i of the SplitMix64 stream seeded with `seed`
+__device__ inline unsigned long long splitmix64_out(unsigned long long seed, unsigned long long i) {
+  unsigned long long z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// uniform sampling: draw C->draw_base + t for slot t < nCand; outside the language or
+// already evaluated -> EMPTY; first occurrences are marked as for generated candidates
+__global__ void k_sample(ExpCfg g, const ExpCounters* C, const unsigned long long* vset, unsigned long long* ckey,
+                         unsigned long long* hkeys, unsigned* hmin) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= C->nCand) return;
+  const unsigned long long c = C->draw_base + (unsigned long long)t;
+  const int K = 1 + (int)(splitmix64_out(g.sseed, 8ull * c) % (unsigned long long)g.kcap);
+  int m[6] = {0, 0, 0, 0, 0, 0};
+  for (int j = 0; j < K; ++j) m[j] = (int)(splitmix64_out(g.sseed, 8ull * c + 1ull + j) % (unsigned long long)g.M);
+  unsigned long long k = key_make(K, m);
+  if (g.task == COMET_TASK_FLIP && !flip_admissible_key(k)) k = EMPTY;
+  if (k != EMPTY && set_has(vset, g.vmask, k)) k = EMPTY;
+  ckey[t] = k;
+  if (k != EMPTY) first_insert(hkeys, hmin, g.cmask, k, (unsigned)t);
+}
+
+// first sampled batch: room and draw count; later rounds move the draw numbers on
+__global__ void k_sample_start(ExpCfg g, ExpCounters* C) {
+  C->room = min(g.Bmax, g.budget);
+  C->nCand = g.draws;
+  C->kept = 0;
+}
+__global__ void k_sample_done(ExpCfg g, ExpCounters* C) {
+  C->nF = min((long long)C->kept, C->room);
+  C->draw_base += (unsigned long long)g.draws;
 }
 
 // ranking keys: (merit, key) or, for refinement, (J if feasible else +inf, key)
@@ -694,6 +734,10 @@ comet_status check_expand_params(comet_ctx* c, const comet_expand_params* p) {
   if (N < 1 || N > c->max_intervals || (p->knots_per_segment <= 0 && p->n_total < p->kcap))
     return fail_msg(c, COMET_EINVAL, "interval allocation exceeds max_intervals (or n_total < kcap)");
   if (!(p->mu_merit >= 0)) return fail_msg(c, COMET_EINVAL, "mu_merit must be >= 0");
+  if (p->policy != COMET_POLICY_EXPAND && p->policy != COMET_POLICY_UNIFORM)
+    return fail_msg(c, COMET_EINVAL, "unknown search policy");
+  if (p->policy == COMET_POLICY_UNIFORM && (p->sample_draws < 1 || p->sample_draws > (1ll << 27)))
+    return fail_msg(c, COMET_EINVAL, "sample_draws must be in [1, 2^27]");
   return COMET_OK;
 }
 
@@ -709,7 +753,8 @@ comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
     t *= M;
     n_seed += t;
   }
-  const long long ncand = std::max(rawmax * p->frontier_W, flip ? n_seed : 0ll);
+  const bool sampling = p->policy == COMET_POLICY_UNIFORM;
+  const long long ncand = sampling ? p->sample_draws : std::max(rawmax * p->frontier_W, flip ? n_seed : 0ll);
   if (ncand > (1ll << 27)) return fail_msg(c, COMET_EINVAL, "frontier_W x neighbourhood size exceeds 2^27 candidates");
   const long long Vcap = p->eval_budget + p->batch_B + 16;
   comet_expand_ws* w = c->xws;
@@ -731,6 +776,9 @@ comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
   g.budget = p->eval_budget;
   g.eps = c->prm.eps_feas;
   g.mu_merit = p->mu_merit;
+  g.policy = p->policy;
+  g.sseed = p->sample_seed;
+  g.draws = sampling ? p->sample_draws : 0;
   if (fits) {
     g.Vcap = w->cfg.Vcap;
     g.vmask = w->cfg.vmask;
@@ -841,9 +889,32 @@ int enqueue_rank(comet_ctx* c, hipStream_t s, int refine) {
 }
 
 // next batch from the ranked V: generate, first occurrences, compact (sets C->nF)
+// next batch by uniform sampling: draw, first occurrences, compact (sets C->nF)
+void enqueue_sample_batch(comet_ctx* c, hipStream_t s) {
+  comet_expand_ws* w = c->xws;
+  const ExpCfg& g = w->cfg;
+  const long long ncand = g.draws;
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks(g.cmask + 1, 256 * 8)), dim3(256), 0, s, w->hkeys, EMPTY,
+                     (long long)(g.cmask + 1));
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks(g.cmask + 1, 256 * 8)), dim3(256), 0, s, w->hmin, 0xFFFFFFFFu,
+                     (long long)(g.cmask + 1));
+  hipLaunchKernelGGL(k_sample, dim3(blocks(ncand, 256)), dim3(256), 0, s, g, w->C, w->vset, w->ckey, w->hkeys,
+                     w->hmin);
+  hipLaunchKernelGGL(k_first, dim3(blocks(ncand, 256)), dim3(256), 0, s, g, w->C, w->ckey, w->hkeys, w->hmin,
+                     w->cflag);
+  w->scan.run(s, w->cflag, w->cpos, &w->C->nCand, ncand, &w->C->kept);
+  hipLaunchKernelGGL(k_compact, dim3(blocks(ncand, 256)), dim3(256), 0, s, g, w->C, w->ckey, w->cflag, w->cpos, w->F,
+                     w->vset);
+  hipLaunchKernelGGL(k_sample_done, dim3(1), dim3(1), 0, s, g, w->C);
+}
+
 void enqueue_next_batch(comet_ctx* c, hipStream_t s) {
   comet_expand_ws* w = c->xws;
   const ExpCfg& g = w->cfg;
+  if (g.policy == COMET_POLICY_UNIFORM) {
+    enqueue_sample_batch(c, s);
+    return;
+  }
   const long long ncand = (long long)g.W * g.rawmax;
   const int cur = enqueue_rank(c, s, 0);
   hipLaunchKernelGGL(k_fill_u64, dim3(blocks(g.cmask + 1, 256 * 8)), dim3(256), 0, s, w->hkeys, EMPTY,
@@ -913,7 +984,10 @@ comet_status enqueue_expand(comet_ctx* c, hipStream_t s) {
     t *= g.M;
     n_seed += t;
   }
-  if (g.task == COMET_TASK_FLIP) {
+  if (g.policy == COMET_POLICY_UNIFORM) {
+    hipLaunchKernelGGL(k_sample_start, dim3(1), dim3(1), 0, s, g, w->C);
+    enqueue_sample_batch(c, s);
+  } else if (g.task == COMET_TASK_FLIP) {
     // the flip language filters its seed: all orders of 1..kmax segments as candidates,
     // kept in key order by the candidate pipeline
     hipLaunchKernelGGL(k_fill_u64, dim3(blocks(g.cmask + 1, 256 * 8)), dim3(256), 0, s, w->hkeys, EMPTY,
@@ -1047,6 +1121,8 @@ comet_status comet_expand_next(comet_ctx* c, void* stream, int64_t n, const uint
   if (!c) return COMET_EINVAL;
   if (n < 0 || (n > 0 && (!keys || !merit)) || !out_keys || !out_n) return fail_msg(c, COMET_EINVAL, "bad arguments");
   comet_status st = check_expand_params(c, params);
+  if (st == COMET_OK && params->policy != COMET_POLICY_EXPAND)
+    return fail_msg(c, COMET_EINVAL, "comet_expand_next builds expansion batches (policy 0)");
   if (st != COMET_OK) return st;
   if (n > params->eval_budget + params->batch_B) return fail_msg(c, COMET_EINVAL, "n exceeds eval_budget + batch_B");
   if (room < 0 || room > params->batch_B) return fail_msg(c, COMET_EINVAL, "room outside [0, batch_B]");

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libcomet.so")
 
 COMET_OK, COMET_EINVAL, COMET_EHIP, COMET_ENOMEM, COMET_ESTATE = 0, -1, -2, -3, -4
 TASK_PUSH, TASK_FLIP = 0, 1
+POLICY_EXPAND, POLICY_UNIFORM = 0, 1
 ROW_WIDTH = {TASK_PUSH: 7, TASK_FLIP: 17}   # trajectory row (x_k, u_k)
 
 
@@ -35,8 +36,9 @@ class ScheduleC(C.Structure):
 class ExpandParamsC(C.Structure):
     _fields_ = [("kcap", C.c_int32), ("seed_max_segments", C.c_int32), ("radius", C.c_int32), ("rounds", C.c_int32),
                 ("frontier_W", C.c_int32), ("knots_per_segment", C.c_int32), ("k_ref", C.c_int32),
-                ("n_total", C.c_int32), ("learned_warm", C.c_int32), ("reserved", C.c_int32), ("batch_B", C.c_int64),
-                ("eval_budget", C.c_int64), ("mu_merit", C.c_double)]
+                ("n_total", C.c_int32), ("learned_warm", C.c_int32), ("policy", C.c_int32), ("batch_B", C.c_int64),
+                ("eval_budget", C.c_int64), ("mu_merit", C.c_double), ("sample_seed", C.c_uint64),
+                ("sample_draws", C.c_int64)]
 
 
 class ExpandStatsC(C.Structure):
@@ -56,10 +58,12 @@ class ExpandParams:
     k_ref: int = 64
     n_total: int = 24
     learned_warm: int = 1
-    reserved: int = 0
+    policy: int = 0            # 0 expansion (Alg. 1), 1 uniform sampling
     batch_B: int = 131072
     eval_budget: int = 200000
     mu_merit: float = 100.0
+    sample_seed: int = 0       # uniform sampling: SplitMix64 seed
+    sample_draws: int = 65536  # uniform sampling: draws per round
 
     def c(self) -> ExpandParamsC:
         return ExpandParamsC(*[getattr(self, f.name) for f in fields(self)])

@@ -45,3 +45,28 @@ def test_product_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 src = open(os.path.join(dp, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src and "comet_oracle" not in src, f
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Field offsets and sizes of the parameter structs: C compiler on include/comet.h vs
+    the binding's ctypes structures."""
+    import subprocess
+    from paper_2609_21803_amd import native
+    structs = {"comet_expand_params": native.ExpandParamsC, "comet_solver_params": native.SolverParamsC,
+               "comet_expand_stats": native.ExpandStatsC}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "comet.h"', 'int main(void) {']
+    for s, cls in structs.items():
+        lines.append(f'  printf("{s} size %zu\\n", sizeof({s}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{s} {f} %zu\\n", offsetof({s}, {f}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for s, cls in structs.items():
+        assert got[(s, "size")] == C.sizeof(cls), s
+        for f, _ in cls._fields_:
+            assert got[(s, f)] == getattr(cls, f).offset, (s, f)
