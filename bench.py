@@ -329,9 +329,10 @@ def policy_leg(native, I, torch):
     e = run(ctx, pairs, native.ExpandParams(**common, seed_max_segments=1, radius=1, rounds=1, frontier_W=8))
     u = run(ctx, pairs, native.ExpandParams(**common, rounds=1, policy=native.POLICY_UNIFORM, sample_seed=1,
                                             sample_draws=65536))
+    m = run(ctx, pairs, native.ExpandParams(**{**common, "batch_B": 256}, policy=native.POLICY_MCTS, sample_seed=1))
     out["flip"] = {"instances": "8 pivot-reachable flipping goals (seed 9400), K <= 2, 10 intervals per segment, "
-                                "batch 2,048, budget 2,400 evaluations, refinement of 16",
-                   "expansion": summary(e), "uniform": summary(u)}
+                                "batch 2,048 (MCTS pool 256), budget 2,400 evaluations, refinement of 16",
+                   "expansion": summary(e), "uniform": summary(u), "mcts_P256": summary(m)}
     # pushing: 8 start/goal pairs, four-segment cap (22,620 orders), budget 8,000
     ctx = native.Context(max_batch=4096, max_segments=6, max_intervals=24)
     pairs = list(zip(*I.push_pairs(9100, 8)))
@@ -339,9 +340,10 @@ def policy_leg(native, I, torch):
     e = run(ctx, pairs, native.ExpandParams(**common, seed_max_segments=2, radius=1, rounds=2, frontier_W=4096))
     u = run(ctx, pairs, native.ExpandParams(**common, rounds=2, policy=native.POLICY_UNIFORM, sample_seed=1,
                                             sample_draws=131072))
+    m = run(ctx, pairs, native.ExpandParams(**{**common, "batch_B": 1024}, policy=native.POLICY_MCTS, sample_seed=1))
     out["push"] = {"instances": "8 pushing start/goal pairs (seed 9100), K <= 4 (22,620 orders), 6 intervals per "
-                                "segment, batch 4,096, budget 8,000 evaluations, refinement of 64",
-                   "expansion": summary(e), "uniform": summary(u)}
+                                "segment, batch 4,096 (MCTS pool 1,024), budget 8,000 evaluations, refinement of 64",
+                   "expansion": summary(e), "uniform": summary(u), "mcts_P1024": summary(m)}
     return out
 
 

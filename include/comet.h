@@ -215,16 +215,38 @@ comet_status comet_last_kernel_ms(comet_ctx* ctx, float* ms);
  *                      in draw order.  So each segment count is equally likely and, given the
  *                      count, every admissible order is.  Refinement and the returned plan are
  *                      as for the expansion.
- *   sample_draws       draws per round (policy 1; 1 .. 2^27) */
-typedef enum { COMET_POLICY_EXPAND = 0, COMET_POLICY_UNIFORM = 1 } comet_policy;
+ *   sample_draws       draws per round (policy 1; 1 .. 2^27)
+ *   policy COMET_POLICY_MCTS (2): the UCT allocation of the ablations (Sec. IV-D, V) on the
+ *                      same evaluator and refinement, batch_B selections per update (the
+ *                      pool P), exploration constant uct_c (the paper's 0.8), rollouts from
+ *                      the SplitMix64 stream of sample_seed (as above).  The tree is over
+ *                      order prefixes: actions "stop" (length >= 1) then "append id"
+ *                      (length < kcap) for the ids, in order, that keep the prefix in the
+ *                      language; an untried action is expanded first (stop first), else the
+ *                      child of largest W/N + uct_c sqrt(ln N_parent / N) (first on ties);
+ *                      visits are counted at selection (virtual loss); a new "append" child
+ *                      of length d is completed to K = d + out(8r) mod (kcap - d + 1)
+ *                      segments, segment j taking admissible id number out(8r+1+j) mod
+ *                      (count) (r = rollout number).  Evaluated orders are cached and the
+ *                      budget counts distinct orders; the selection that would exceed it is
+ *                      undone and ends the batch.  Rewards after each batch: pushing J_best/J
+ *                      for feasible orders (0 otherwise), flipping M_best/M (merit, Eq. (5)).
+ *                      Ends at the budget, when nothing is untried and a batch brings no new
+ *                      order, or after 64 batches in a row without one.  Runs as a host loop
+ *                      with one device evaluation per batch (not captured); no learned
+ *                      network (EINVAL).  rounds, seed_max_segments, radius, frontier_W and
+ *                      sample_draws are unused.
+ *   uct_c              UCT exploration constant (policy 2; finite, >= 0) */
+typedef enum { COMET_POLICY_EXPAND = 0, COMET_POLICY_UNIFORM = 1, COMET_POLICY_MCTS = 2 } comet_policy;
 typedef struct {
   int32_t kcap, seed_max_segments, radius, rounds, frontier_W, knots_per_segment, k_ref, n_total;
   int32_t learned_warm;   /* with a learned network: 1 = also seed initial trajectories, 0 = order only */
   int32_t policy;         /* comet_policy */
   int64_t batch_B, eval_budget;
   double mu_merit;
-  uint64_t sample_seed;   /* policy 1 */
+  uint64_t sample_seed;   /* policy 1: draws; policy 2: rollouts */
   int64_t sample_draws;   /* policy 1 */
+  double uct_c;           /* policy 2 */
 } comet_expand_params;
 
 typedef struct {

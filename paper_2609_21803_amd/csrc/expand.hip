@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.h"
@@ -99,7 +100,7 @@ __host__ __device__ inline unsigned long long raw_decode(unsigned long long p, l
 // table (the support face while supported; the support and the landing face in a pivot).
 // Ids: (f1 * 13 + f2) * 5 + g, finger 0 free / 1 + 3 face + slip; the support starts on
 // face 3 and a pivot run followed by a supported segment lands on the next face.
-__device__ inline bool flip_admissible_key(unsigned long long k) {
+__host__ __device__ inline bool flip_admissible_key(unsigned long long k) {
   const int K = key_len(k);
   int fs = 3, prev_g = -1, prev_id = -1, pa = -1, pb = -1;
   for (int j = 0; j < K; ++j) {
@@ -734,8 +735,10 @@ comet_status check_expand_params(comet_ctx* c, const comet_expand_params* p) {
   if (N < 1 || N > c->max_intervals || (p->knots_per_segment <= 0 && p->n_total < p->kcap))
     return fail_msg(c, COMET_EINVAL, "interval allocation exceeds max_intervals (or n_total < kcap)");
   if (!(p->mu_merit >= 0)) return fail_msg(c, COMET_EINVAL, "mu_merit must be >= 0");
-  if (p->policy != COMET_POLICY_EXPAND && p->policy != COMET_POLICY_UNIFORM)
+  if (p->policy != COMET_POLICY_EXPAND && p->policy != COMET_POLICY_UNIFORM && p->policy != COMET_POLICY_MCTS)
     return fail_msg(c, COMET_EINVAL, "unknown search policy");
+  if (p->policy == COMET_POLICY_MCTS && !(p->uct_c >= 0.0 && std::isfinite(p->uct_c)))
+    return fail_msg(c, COMET_EINVAL, "uct_c must be finite and >= 0");
   if (p->policy == COMET_POLICY_UNIFORM && (p->sample_draws < 1 || p->sample_draws > (1ll << 27)))
     return fail_msg(c, COMET_EINVAL, "sample_draws must be in [1, 2^27]");
   return COMET_OK;
@@ -754,7 +757,8 @@ comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
     n_seed += t;
   }
   const bool sampling = p->policy == COMET_POLICY_UNIFORM;
-  const long long ncand = sampling ? p->sample_draws : std::max(rawmax * p->frontier_W, flip ? n_seed : 0ll);
+  const long long ncand = (p->policy == COMET_POLICY_MCTS) ? 1
+                          : sampling ? p->sample_draws : std::max(rawmax * p->frontier_W, flip ? n_seed : 0ll);
   if (ncand > (1ll << 27)) return fail_msg(c, COMET_EINVAL, "frontier_W x neighbourhood size exceeds 2^27 candidates");
   const long long Vcap = p->eval_budget + p->batch_B + 16;
   comet_expand_ws* w = c->xws;
@@ -971,6 +975,24 @@ comet_status enqueue_evaluate_batch(comet_ctx* c, hipStream_t s, const long long
   return launch_evaluate(c, s, L);
 }
 
+// refinement of the k_ref best feasible evaluated orders and the returned plan
+comet_status enqueue_refine_and_output(comet_ctx* c, hipStream_t s) {
+  comet_expand_ws* w = c->xws;
+  const ExpCfg& g = w->cfg;
+  const comet_expand_params& p = w->prm;
+  if (p.k_ref > 0) {
+    const int cur = enqueue_rank(c, s, 1);
+    hipLaunchKernelGGL(k_ref_batch, dim3(blocks(p.k_ref, 256)), dim3(256), 0, s, g, w->C, w->s_idx[cur], w->vkey,
+                       w->vJ, w->vv, w->F);
+    comet_status st = enqueue_evaluate_batch(c, s, &w->C->nRef, p.k_ref, 1, w->rtraj, nullptr, nullptr);
+    if (st != COMET_OK) return st;
+    hipLaunchKernelGGL(k_pick_best, dim3(1), dim3(1), 0, s, g, w->C, w->F, w->ecost64, w->eviol64);
+  }
+  hipLaunchKernelGGL(k_best_out, dim3(1), dim3(256), 0, s, g, w->C, w->rtraj, c->max_intervals + 1, w->o_nseg,
+                     w->o_modes, w->o_knots, w->o_cost, w->o_viol, w->o_traj, c->max_segments);
+  return hipGetLastError() == hipSuccess ? COMET_OK : fail_msg(c, COMET_EHIP, "expansion launch failed");
+}
+
 comet_status enqueue_expand(comet_ctx* c, hipStream_t s) {
   comet_expand_ws* w = c->xws;
   const ExpCfg& g = w->cfg;
@@ -1013,18 +1035,224 @@ comet_status enqueue_expand(comet_ctx* c, hipStream_t s) {
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, g, w->C);
     if (r < p.rounds) enqueue_next_batch(c, s);
   }
-  // refinement of the k_ref best feasible orders
-  if (p.k_ref > 0) {
-    const int cur = enqueue_rank(c, s, 1);
-    hipLaunchKernelGGL(k_ref_batch, dim3(blocks(p.k_ref, 256)), dim3(256), 0, s, g, w->C, w->s_idx[cur], w->vkey,
-                       w->vJ, w->vv, w->F);
-    comet_status st = enqueue_evaluate_batch(c, s, &w->C->nRef, p.k_ref, 1, w->rtraj, nullptr, nullptr);
-    if (st != COMET_OK) return st;
-    hipLaunchKernelGGL(k_pick_best, dim3(1), dim3(1), 0, s, g, w->C, w->F, w->ecost64, w->eviol64);
+  return enqueue_refine_and_output(c, s);
+}
+
+// ---------------------------------------------------------------------------------
+// MCTS allocation (policy 2): UCT over order prefixes on the host, one device evaluation
+// per batch of batch_B selections.  Actions of a prefix of length d: "stop" (d >= 1) then
+// "append id" (d < kcap) for the ids, in order, that keep it in the task's language; a
+// node with untried actions expands the first, otherwise the walk takes the child of
+// largest W/N + c sqrt(ln N_parent / N) (first on ties); every node of a path gets its
+// visit at selection time (virtual loss).  A new "append" child of length d is completed by
+// a rollout: K = d + out(8r) mod (kcap - d + 1), then for j = d .. K-1 the admissible id
+// number out(8r+1+j) mod (count), out() being the SplitMix64 stream of sample_seed and r
+// the rollout number.  Evaluated orders are cached (the budget counts distinct orders); a
+// selection whose new order would exceed the budget is undone and ends the batch.  After
+// the evaluation, the best value so far is updated and each path adds its reward: pushing
+// J_best / J for feasible orders (0 otherwise), flipping M_best / M.  The search ends at
+// the budget, when nothing is left untried and a batch brings no new order, or after 64
+// batches in a row without one; then the refinement of the expansion.
+// ---------------------------------------------------------------------------------
+struct MctsNode {
+  int len;
+  int pre[6];
+  bool stop;
+  std::vector<int> acts;   // untried actions (from `next`), -1 = stop
+  size_t next = 0;
+  std::vector<int> kids;   // child node indices in action order
+  long long N = 0;
+  double W = 0.0;
+};
+
+inline unsigned long long splitmix64_host(unsigned long long seed, unsigned long long i) {
+  unsigned long long z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+struct MctsTree {
+  int task, kcap, M;
+  double c;
+  unsigned long long seed, rollouts = 0;
+  long long untried = 0;
+  std::vector<MctsNode> nodes;
+
+  bool admissible(const int* m, int n) const {
+    if (task != COMET_TASK_FLIP) return true;
+    return flip_admissible_key(key_make(n, m));
   }
-  hipLaunchKernelGGL(k_best_out, dim3(1), dim3(256), 0, s, g, w->C, w->rtraj, c->max_intervals + 1, w->o_nseg,
-                     w->o_modes, w->o_knots, w->o_cost, w->o_viol, w->o_traj, c->max_segments);
-  return hipGetLastError() == hipSuccess ? COMET_OK : fail_msg(c, COMET_EHIP, "expansion launch failed");
+  void ids_after(const int* m, int n, std::vector<int>& out) const {
+    out.clear();
+    int q[6];
+    for (int i = 0; i < n; ++i) q[i] = m[i];
+    for (int a = 0; a < M; ++a) {
+      q[n] = a;
+      if (admissible(q, n + 1)) out.push_back(a);
+    }
+  }
+  int make(const int* pre, int len, bool stop) {
+    MctsNode nd;
+    nd.len = len;
+    for (int i = 0; i < 6; ++i) nd.pre[i] = (i < len) ? pre[i] : 0;
+    nd.stop = stop;
+    if (!stop) {
+      if (len >= 1) nd.acts.push_back(-1);
+      if (len < kcap) {
+        std::vector<int> ids;
+        ids_after(pre, len, ids);
+        nd.acts.insert(nd.acts.end(), ids.begin(), ids.end());
+      }
+    }
+    untried += (long long)nd.acts.size();
+    nodes.push_back(std::move(nd));
+    return (int)nodes.size() - 1;
+  }
+  double uct(int parent, int child) const {
+#pragma clang fp contract(off)
+    const double n = (double)nodes[child].N;
+    const double q = nodes[child].W / n;
+    const double e = c * std::sqrt(std::log((double)nodes[parent].N) / n);
+    return q + e;
+  }
+  // one selection: the path (node indices) and the order it yields
+  void select(std::vector<int>& path, int* order, int& K) {
+    path.clear();
+    int v = 0;
+    path.push_back(v);
+    for (;;) {
+      MctsNode& nd = nodes[v];
+      if (nd.next < nd.acts.size()) {
+        const int a = nd.acts[nd.next++];
+        --untried;
+        int pre[6];
+        for (int i = 0; i < nodes[v].len; ++i) pre[i] = nodes[v].pre[i];
+        int len = nodes[v].len;
+        bool stop = (a == -1);
+        if (!stop) pre[len++] = a;
+        const int ch = make(pre, len, stop);
+        nodes[v].kids.push_back(ch);
+        path.push_back(ch);
+        break;
+      }
+      if (nd.kids.empty()) break;
+      int best = -1;
+      double bval = -INFINITY;
+      for (int ch : nd.kids) {
+        const double u = uct(v, ch);
+        if (u > bval) {
+          best = ch;
+          bval = u;
+        }
+      }
+      v = best;
+      path.push_back(v);
+    }
+    const MctsNode& leaf = nodes[path.back()];
+    K = leaf.len;
+    for (int i = 0; i < K; ++i) order[i] = leaf.pre[i];
+    if (!leaf.stop) rollout(order, K);
+    for (int i : path) ++nodes[i].N;
+  }
+  void rollout(int* m, int& K) {
+    const unsigned long long r = rollouts++;
+    const int d = K;
+    if (d >= kcap) return;
+    const int target = d + (int)(splitmix64_host(seed, 8ull * r) % (unsigned long long)(kcap - d + 1));
+    std::vector<int> cand;
+    for (int j = d; j < target; ++j) {
+      ids_after(m, K, cand);
+      if (cand.empty()) break;
+      m[K++] = cand[splitmix64_host(seed, 8ull * r + 1ull + (unsigned long long)j) % cand.size()];
+    }
+  }
+};
+
+__global__ void k_set_batch_n(ExpCounters* C, long long n) { C->nF = n; }
+
+comet_status run_mcts(comet_ctx* c, hipStream_t s) {
+  comet_expand_ws* w = c->xws;
+  const ExpCfg& g = w->cfg;
+  const comet_expand_params& p = w->prm;
+  const bool flip = (g.task == COMET_TASK_FLIP);
+  const double eps = g.eps;
+  hipLaunchKernelGGL(k_exp_init, dim3(1), dim3(1), 0, s, w->C);
+  MctsTree T;
+  T.task = g.task;
+  T.kcap = g.kcap;
+  T.M = g.M;
+  T.c = p.uct_c;
+  T.seed = p.sample_seed;
+  T.make(nullptr, 0, false);
+  std::unordered_map<unsigned long long, std::pair<double, double>> cache;
+  std::vector<unsigned long long> fresh;
+  std::vector<std::pair<std::vector<int>, unsigned long long>> sel;
+  std::vector<double> hJ, hv;
+  std::vector<int> path;
+  long long nV = 0, batches = 0;
+  int stall = 0;
+  double best = INFINITY;
+  while (nV < p.eval_budget && batches < 1000000) {
+    sel.clear();
+    fresh.clear();
+    for (long long q = 0; q < p.batch_B; ++q) {
+      int order[6], K = 0;
+      T.select(path, order, K);
+      const unsigned long long k = key_make(K, order);
+      if (!cache.count(k) && std::find(fresh.begin(), fresh.end(), k) == fresh.end()) {
+        if (nV + (long long)fresh.size() >= p.eval_budget) {
+          for (int i : path) --T.nodes[i].N;   // not taken
+          break;
+        }
+        fresh.push_back(k);
+      }
+      sel.emplace_back(path, k);
+    }
+    ++batches;
+    const long long n = (long long)fresh.size();
+    if (n > 0) {
+      if (hipMemcpyAsync(w->F, fresh.data(), 8 * n, hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail_msg(c, COMET_EHIP, "MCTS batch upload failed");
+      hipLaunchKernelGGL(k_set_batch_n, dim3(1), dim3(1), 0, s, w->C, n);
+      comet_status st = enqueue_evaluate_batch(c, s, &w->C->nF, n, 0, nullptr, &w->C->t_first, nullptr);
+      if (st != COMET_OK) return st;
+      hipLaunchKernelGGL(k_append, dim3(blocks(n, 256)), dim3(256), 0, s, g, w->C, w->F, w->ecost64, w->eviol64,
+                         w->vkey, w->vJ, w->vv, w->vM);
+      hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, g, w->C);
+      hJ.resize(n);
+      hv.resize(n);
+      (void)hipMemcpyAsync(hJ.data(), w->ecost64, 8 * n, hipMemcpyDeviceToHost, s);
+      (void)hipMemcpyAsync(hv.data(), w->eviol64, 8 * n, hipMemcpyDeviceToHost, s);
+      if (hipStreamSynchronize(s) != hipSuccess) return fail_msg(c, COMET_EHIP, "MCTS evaluation failed");
+      for (long long i = 0; i < n; ++i) {
+        cache[fresh[i]] = {hJ[i], hv[i]};
+        if (flip) {
+          const double Mi = (std::isfinite(hJ[i]) && std::isfinite(hv[i])) ? hJ[i] + p.mu_merit * std::fmax(hv[i] - eps, 0.0)
+                                                                           : INFINITY;
+          best = std::fmin(best, Mi);
+        } else if (hv[i] <= eps && std::isfinite(hJ[i])) {
+          best = std::fmin(best, hJ[i]);
+        }
+      }
+      nV += n;
+    }
+    for (const auto& sp : sel) {
+      const auto& r = cache[sp.second];
+      double rew = 0.0;
+      if (flip) {
+        const double Mi = (std::isfinite(r.first) && std::isfinite(r.second)) ? r.first + p.mu_merit * std::fmax(r.second - eps, 0.0)
+                                                                               : INFINITY;
+        if (std::isfinite(Mi) && Mi > 0.0) rew = best / Mi;
+      } else if (r.second <= eps && std::isfinite(r.first) && r.first > 0.0) {
+        rew = best / r.first;
+      }
+      for (int i : sp.first) T.nodes[i].W += rew;
+    }
+    stall = (n > 0) ? 0 : stall + 1;
+    if (n == 0 && (T.untried == 0 || stall >= 64)) break;
+  }
+  return enqueue_refine_and_output(c, s);
 }
 
 }  // namespace
@@ -1043,6 +1271,8 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
   const bool flip = (c->task == COMET_TASK_FLIP);
   if (learned && (mlp_max_batch(learned) < params->batch_B || mlp_in_dim(learned) < 400 || mlp_out_dim(learned) < 722))
     return fail_msg(c, COMET_EINVAL, "learned network: max_batch < batch_B, in_dim < 400 or out_dim < 722");
+  if (learned && params->policy == COMET_POLICY_MCTS)
+    return fail_msg(c, COMET_EINVAL, "the learned network ranks expansion or sampling batches, not MCTS");
   st = ensure_ws(c, params);
   if (st != COMET_OK) return st;
   comet_expand_ws* w = c->xws;
@@ -1063,6 +1293,18 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
   (void)hipMemcpyAsync(w->iinst, inst, 4 * 1, hipMemcpyDeviceToDevice, us);
   (void)hipEventRecord(e_in, us);
   (void)hipStreamWaitEvent(gs, e_in, 0);
+  if (params->policy == COMET_POLICY_MCTS) {
+    (void)hipEventRecord(e_t0, gs);
+    const comet_status ms = run_mcts(c, gs);
+    (void)hipEventRecord(e_t1, gs);
+    if (ms != COMET_OK) {
+      (void)hipStreamSynchronize(gs);
+      (void)hipEventDestroy(e_in);
+      (void)hipEventDestroy(e_t0);
+      (void)hipEventDestroy(e_t1);
+      return ms;
+    }
+  } else {
   if (!w->graph_valid) {
     if (w->gexec) {
       (void)hipGraphExecDestroy(w->gexec);
@@ -1083,6 +1325,7 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
   (void)hipEventRecord(e_t0, gs);
   if (hipGraphLaunch(w->gexec, gs) != hipSuccess) return fail_msg(c, COMET_EHIP, "graph launch failed");
   (void)hipEventRecord(e_t1, gs);
+  }
   // outputs to the caller
   (void)hipMemcpyAsync(best_nseg, w->o_nseg, 4, hipMemcpyDeviceToDevice, gs);
   (void)hipMemcpyAsync(best_modes, w->o_modes, 4 * c->max_segments, hipMemcpyDeviceToDevice, gs);

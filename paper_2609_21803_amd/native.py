@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libcomet.so")
 
 COMET_OK, COMET_EINVAL, COMET_EHIP, COMET_ENOMEM, COMET_ESTATE = 0, -1, -2, -3, -4
 TASK_PUSH, TASK_FLIP = 0, 1
-POLICY_EXPAND, POLICY_UNIFORM = 0, 1
+POLICY_EXPAND, POLICY_UNIFORM, POLICY_MCTS = 0, 1, 2
 ROW_WIDTH = {TASK_PUSH: 7, TASK_FLIP: 17}   # trajectory row (x_k, u_k)
 
 
@@ -38,7 +38,7 @@ class ExpandParamsC(C.Structure):
                 ("frontier_W", C.c_int32), ("knots_per_segment", C.c_int32), ("k_ref", C.c_int32),
                 ("n_total", C.c_int32), ("learned_warm", C.c_int32), ("policy", C.c_int32), ("batch_B", C.c_int64),
                 ("eval_budget", C.c_int64), ("mu_merit", C.c_double), ("sample_seed", C.c_uint64),
-                ("sample_draws", C.c_int64)]
+                ("sample_draws", C.c_int64), ("uct_c", C.c_double)]
 
 
 class ExpandStatsC(C.Structure):
@@ -64,6 +64,7 @@ class ExpandParams:
     mu_merit: float = 100.0
     sample_seed: int = 0       # uniform sampling: SplitMix64 seed
     sample_draws: int = 65536  # uniform sampling: draws per round
+    uct_c: float = 0.8         # MCTS exploration constant
 
     def c(self) -> ExpandParamsC:
         return ExpandParamsC(*[getattr(self, f.name) for f in fields(self)])

@@ -1,0 +1,81 @@
+"""GPU MCTS allocation (UCT with virtual loss and random rollouts, Sec. IV-D / V) against the
+MCTS oracle: the first batch (before any reward) is the oracle's selection bit for bit on
+both tasks; a whole search evaluates distinct orders of the language within the budget and
+returns a plan the oracle confirms.  Later batches depend on rewards computed from each
+side's own evaluations, which agree to rounding, so only the first batch is compared
+exactly."""
+import numpy as np
+import pytest
+
+from paper_2609_21803_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    import torch
+    return torch.as_tensor(np.asarray(a, np.float32)).cuda()
+
+
+@pytest.mark.parametrize("task,kcap,P,seed", [(0, 3, 64, 5), (0, 2, 200, 8), (1, 2, 64, 3), (1, 3, 256, 12)])
+def test_first_batch_is_the_oracle_selection(task, kcap, P, seed):
+    import torch
+    from oracle import mcts as T
+    from paper_2609_21803_amd import native
+    ctx = native.Context(max_batch=max(P, 64), max_segments=6, max_intervals=kcap * 5, task=task)
+    prm = native.ExpandParams(kcap=kcap, knots_per_segment=5, k_ref=4, batch_B=P, eval_budget=P,
+                              policy=native.POLICY_MCTS, sample_seed=seed)
+    pairs = I.flip_pivot_pairs(seed, 1) if task == 1 else I.push_pairs(seed, 1)
+    o, st = native.expand(ctx, _t(pairs[0][0]), _t(pairs[1][0]), _t(pairs[2][0]), prm)
+    torch.cuda.synchronize()
+    got = native.expand_trace(ctx)[0].cpu().numpy().view(np.uint64)
+    ref = np.array(T.first_batch(task, kcap, P, seed, eval_budget=P), np.uint64)
+    # repeated selections leave room in the budget: a second, reward-dependent batch follows
+    print(f"task {task}: evaluated {len(got)} orders, first batch of the oracle {len(ref)}")
+    assert len(got) <= P and np.array_equal(got[:len(ref)], ref)
+
+
+def test_push_mcts_search_plan_confirmed_by_oracle():
+    import torch
+    import oracle
+    from oracle import mcts as T
+    from oracle.sample import key_modes
+    from paper_2609_21803_amd import native
+    x0, goal, inst = I.push_pairs(9100, 1)
+    ep = dict(kcap=3, knots_per_segment=8, k_ref=32, batch_B=64, eval_budget=1500)
+    ctx = native.Context(max_batch=64, max_segments=6, max_intervals=24)
+    prm = native.ExpandParams(**ep, policy=native.POLICY_MCTS, sample_seed=7)
+    o, st = native.expand(ctx, _t(x0[0]), _t(goal[0]), _t(inst[0]), prm)
+    torch.cuda.synchronize()
+    keys = native.expand_trace(ctx)[0].cpu().numpy().view(np.uint64)
+    bk, bJ, bv, okeys, J, v, nb, _ = T.mcts_search(0, x0[0], goal[0], inst[0], ep["kcap"], ep["batch_B"],
+                                                   ep["eval_budget"], 7, ep["knots_per_segment"], ep["k_ref"])
+    K = int(o["nseg"].item())
+    print("device", st, o["modes"].cpu().numpy()[:K], float(o["cost"].item()), "oracle", len(okeys), nb,
+          key_modes(bk), bJ, "common orders", len(set(keys.tolist()) & set(okeys)))
+    assert len(keys) == st["evaluated"] <= ep["eval_budget"] and len(set(keys.tolist())) == len(keys)
+    fb = T.first_batch(0, ep["kcap"], ep["batch_B"], 7)
+    assert np.array_equal(keys[:len(fb)], np.array(fb, np.uint64)) and okeys[:len(fb)] == fb   # the first batch
+    assert K >= 1
+    m = list(o["modes"].cpu().numpy()[:K])
+    r = oracle.evaluate(np.asarray(x0[:1], np.float32).astype(np.float64),
+                        np.asarray(goal[:1], np.float32).astype(np.float64),
+                        np.asarray(inst[:1], np.float32).astype(np.float64), np.array([K]),
+                        np.array([m + [0] * (6 - K)]), np.array([[8] * K + [0] * (6 - K)]),
+                        params=oracle.Params(**oracle.REFINE))
+    assert r["feasible"][0] == 1 and abs(r["cost"][0] - float(o["cost"].item())) <= 1e-4 * abs(r["cost"][0])
+    # both searches return plans of comparable cost (their trees part after the first rewards)
+    assert abs(bJ - float(o["cost"].item())) <= 0.05 * abs(bJ)
+
+
+def test_mcts_parameters_are_checked():
+    from paper_2609_21803_amd import native
+    ctx = native.Context(max_batch=64, max_segments=6, max_intervals=10)
+    x0, goal, inst = I.push_pairs(1, 1)
+    with pytest.raises(native.CometError):
+        native.expand(ctx, _t(x0[0]), _t(goal[0]), _t(inst[0]), native.ExpandParams(
+            kcap=2, knots_per_segment=5, batch_B=64, eval_budget=100, policy=native.POLICY_MCTS, uct_c=-1.0))
+    mlp = native.MLP(max_batch=64, seed=1)
+    with pytest.raises(native.CometError):
+        native.expand(ctx, _t(x0[0]), _t(goal[0]), _t(inst[0]), native.ExpandParams(
+            kcap=2, knots_per_segment=5, batch_B=64, eval_budget=100, policy=native.POLICY_MCTS), learned=mlp)

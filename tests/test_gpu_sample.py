@@ -90,7 +90,7 @@ def test_sampling_parameters_are_checked():
         native.expand(ctx, _t(x0[0]), _t(goal[0]), _t(inst[0]), bad)
     with pytest.raises(native.CometError):
         native.expand(ctx, _t(x0[0]), _t(goal[0]), _t(inst[0]), native.ExpandParams(
-            kcap=2, rounds=1, knots_per_segment=5, batch_B=64, eval_budget=100, policy=2))
+            kcap=2, rounds=1, knots_per_segment=5, batch_B=64, eval_budget=100, policy=3))
     import torch
     keys = torch.zeros(4, dtype=torch.int64, device="cuda")
     merit = torch.zeros(4, dtype=torch.float64, device="cuda")
