@@ -79,3 +79,33 @@ def test_mcts_parameters_are_checked():
     with pytest.raises(native.CometError):
         native.expand(ctx, _t(x0[0]), _t(goal[0]), _t(inst[0]), native.ExpandParams(
             kcap=2, knots_per_segment=5, batch_B=64, eval_budget=100, policy=native.POLICY_MCTS), learned=mlp)
+
+
+def test_flip_mcts_search_plan_confirmed_by_oracle():
+    """Flipping (reward M_best / M): distinct orders of the language within the budget, the
+    oracle's first batch, and a returned plan the oracle re-solves to the same cost."""
+    import torch
+    import oracle
+    from oracle import flip as F
+    from oracle import mcts as T
+    from oracle.sample import key_modes
+    from paper_2609_21803_amd import native
+    x0, goal, inst = I.flip_pivot_pairs(9400, 1)
+    ep = dict(kcap=2, knots_per_segment=10, k_ref=8, batch_B=128, eval_budget=640)
+    ctx = native.Context(max_batch=128, max_segments=6, max_intervals=20, task=native.TASK_FLIP)
+    prm = native.ExpandParams(**ep, policy=native.POLICY_MCTS, sample_seed=3)
+    o, st = native.expand(ctx, _t(x0[0]), _t(goal[0]), _t(inst[0]), prm)
+    torch.cuda.synchronize()
+    keys = native.expand_trace(ctx)[0].cpu().numpy().view(np.uint64)
+    K = int(o["nseg"].item())
+    print("device", st, o["modes"].cpu().numpy()[:K], float(o["cost"].item()))
+    assert len(keys) == st["evaluated"] <= ep["eval_budget"] and len(set(keys.tolist())) == len(keys)
+    assert all(F.admissible(key_modes(int(k))) for k in keys)
+    fb = T.first_batch(1, ep["kcap"], ep["batch_B"], 3)
+    assert np.array_equal(keys[:len(fb)], np.array(fb, np.uint64))
+    assert K >= 1
+    m = list(o["modes"].cpu().numpy()[:K])
+    r = F.evaluate(np.asarray(x0[:1], np.float32).astype(np.float64), np.asarray(goal[:1], np.float32).astype(np.float64),
+                   np.asarray(inst[:1], np.float32).astype(np.float64), np.array([K]), np.array([m + [0] * (6 - K)]),
+                   np.array([[10] * K + [0] * (6 - K)]), params=oracle.Params(**oracle.REFINE))
+    assert r["feasible"][0] == 1 and abs(r["cost"][0] - float(o["cost"].item())) <= 1e-4 * abs(r["cost"][0])
