@@ -22,7 +22,7 @@ _SRC = os.path.join(_HERE, "comet_oracle.c")
 _LIB = os.path.join(_HERE, "libcomet_oracle.so")
 
 MAXSEG = 6
-N_TYPES = 12
+N_TYPES = 13
 
 
 def build(force: bool = False) -> str:
@@ -38,7 +38,7 @@ def build(force: bool = False) -> str:
 
 class SolverParams(C.Structure):
     _fields_ = [("al_max", C.c_int32), ("gn_max", C.c_int32), ("chol_retries", C.c_int32),
-                ("ls_trials", C.c_int32), ("max_rejects", C.c_int32), ("pad_", C.c_int32), ("mu0", C.c_double), ("mu_min", C.c_double),
+                ("ls_trials", C.c_int32), ("max_rejects", C.c_int32), ("timed", C.c_int32), ("mu0", C.c_double), ("mu_min", C.c_double),
                 ("rho0", C.c_double), ("rho_min", C.c_double), ("rho_max", C.c_double),
                 ("armijo_c1", C.c_double), ("eta_star", C.c_double), ("omega_star", C.c_double),
                 ("rc_star", C.c_double), ("eps_feas", C.c_double),
@@ -60,7 +60,7 @@ class Params:
     chol_retries: int = 6
     ls_trials: int = 8
     max_rejects: int = 4
-    pad_: int = 0
+    timed: int = 0          # 1: the optimised-timing pushing problem (durations are controls)
     mu0: float = 1e-2
     mu_min: float = 1e-4
     rho0: float = 1e-4
@@ -91,15 +91,16 @@ def lib():
         L.oracle_evaluate.argtypes = [C.c_int64, C.c_int32, C.c_int32, P, P, P, P, P, P, P,
                                       C.POINTER(SolverParams), C.c_int32, P, P, P, P, P]
         L.oracle_evaluate.restype = C.c_int
-        L.oracle_push_scales.argtypes = [P]
-        L.oracle_push_rows.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_double, P, P, P, P]
-        for name in ("oracle_push_initial",):
-            getattr(L, name).argtypes = [C.c_int32, P, P, P, P, C.c_double, P]
-        L.oracle_push_merit.argtypes = [C.c_int32, P, P, P, P, C.c_double, P, P, P, P, C.c_double, P, P]
-        L.oracle_push_step.argtypes = [C.c_int32, P, P, P, P, C.c_double, P, P, P, P, C.c_double,
-                                       C.c_double, P]
-        L.oracle_push_blocks.argtypes = [C.c_int32, P, P, P, P, C.c_double, P, P, P, P, P, P]
-        L.oracle_push_score.argtypes = [C.c_int32, P, P, P, P, C.c_double, P, P, P]
+        I = C.c_int32
+        L.oracle_push_scales.argtypes = [I, P]
+        L.oracle_push_rows.argtypes = [I, I, I, I, C.c_double, P, P, P, P]
+        L.oracle_push_cost.argtypes = [I, P, P, P]
+        L.oracle_push_cost.restype = C.c_double
+        L.oracle_push_initial.argtypes = [I, I, P, P, P, P, C.c_double, P]
+        L.oracle_push_merit.argtypes = [I, I, P, P, P, P, C.c_double, P, P, P, P, C.c_double, P, P]
+        L.oracle_push_step.argtypes = [I, I, P, P, P, P, C.c_double, P, P, P, P, C.c_double, C.c_double, P]
+        L.oracle_push_blocks.argtypes = [I, I, P, P, P, P, C.c_double, P, P, P, P, P, P]
+        L.oracle_push_score.argtypes = [I, I, P, P, P, P, C.c_double, P, P, P]
         L.oracle_neighbours.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, P]
         L.oracle_neighbours.restype = C.c_int64
         L.oracle_expand.argtypes = [P, P, C.c_double, C.POINTER(ExpandParams), C.POINTER(SolverParams),
@@ -146,7 +147,7 @@ def evaluate(x0, goal, inst, nseg, modes, knots, params: Params | None = None, w
     cost = np.zeros(B)
     viol = np.zeros(B)
     feas = np.zeros(B, np.uint8)
-    traj = np.zeros((B, nmax + 1, 7))
+    traj = np.zeros((B, nmax + 1, 8 if params.timed else 7))
     stats = np.zeros((B, 4), np.int32)
     w = None if warm is None else _f64(warm)
     prm = params.c()
@@ -158,25 +159,41 @@ def evaluate(x0, goal, inst, nseg, modes, knots, params: Params | None = None, w
     return dict(cost=cost, viol=viol, feasible=feas, traj=traj, stats=stats)
 
 
-def scales() -> np.ndarray:
+def scales(timed: int = 0) -> np.ndarray:
+    """Row scales of the fixed-step (timed=0) or optimised-timing (timed=1) pushing
+    problem; the last type (duration bounds) exists only with optimised timing."""
     out = np.zeros(N_TYPES)
-    lib().oracle_push_scales(_p(out))
+    lib().oracle_push_scales(int(timed), _p(out))
     return out
 
 
-def push_rows(face, slip, smask, mu, v):
+def push_rows(face, slip, smask, mu, v, timed: int = 0):
+    """Rows of one interval: v = (x_k, u_k, x_{k+1}) with 11 entries (12 with timing)."""
+    nr, nv = (12, 12) if timed else (10, 11)
     v = _f64(v)
-    c = np.zeros(10)
-    J = np.zeros((10, 11))
-    en = np.zeros(10, np.int32)
-    lib().oracle_push_rows(face, slip, smask, mu, _p(v), _p(c), _p(J), _p(en))
+    c = np.zeros(nr)
+    J = np.zeros((nr, nv))
+    en = np.zeros(nr, np.int32)
+    lib().oracle_push_rows(int(timed), face, slip, smask, mu, _p(v), _p(c), _p(J), _p(en))
     return c, J, en
+
+
+def push_cost(u, timed: int = 0):
+    """Stage cost, its gradient and its Hessian model (full nu x nu)."""
+    nu = 4 if timed else 3
+    u = _f64(u)
+    g = np.zeros(nu)
+    H = np.zeros((nu, nu))
+    J = lib().oracle_push_cost(int(timed), _p(u), _p(g), _p(H))
+    return J, g, H
 
 
 class Seq:
     """One mode-conditioned problem for the single-sequence debug entry points."""
 
-    def __init__(self, modes, knots, x0=(0, 0, 0, 0), goal=(0, 0, 0), mu=0.4):
+    def __init__(self, modes, knots, x0=(0, 0, 0, 0), goal=(0, 0, 0), mu=0.4, timed=0):
+        self.timed = int(timed)
+        self.nw, self.nr, self.nv, self.ni = (8, 12, 12, 7) if self.timed else (7, 10, 11, 5)
         self.modes = _i32(modes)
         self.knots = _i32(knots)
         self.nseg = len(self.modes)
@@ -186,34 +203,34 @@ class Seq:
         self.N = int(self.knots.sum())
 
     def _a(self):
-        return (self.nseg, _p(self.modes), _p(self.knots), _p(self.x0), _p(self.goal), self.mu)
+        return (self.timed, self.nseg, _p(self.modes), _p(self.knots), _p(self.x0), _p(self.goal), self.mu)
 
     def initial(self):
-        z = np.zeros(self.N * 7)
+        z = np.zeros(self.N * self.nw)
         lib().oracle_push_initial(*self._a(), _p(z))
         return z
 
     def duals(self):
-        return np.zeros(self.N * 5), np.zeros(self.N * 5), np.zeros(3)
+        return np.zeros(self.N * 5), np.zeros(self.N * self.ni), np.zeros(3)
 
     def merit(self, z, lam, nu, lamT, mu_al):
         phi = C.c_double()
-        g = np.zeros(self.N * 7)
+        g = np.zeros(self.N * self.nw)
         z, lam, nu, lamT = _f64(z), _f64(lam), _f64(nu), _f64(lamT)
         lib().oracle_push_merit(*self._a(), _p(z), _p(lam), _p(nu), _p(lamT), mu_al, C.byref(phi), _p(g))
         return phi.value, g
 
     def step(self, z, lam, nu, lamT, mu_al, rho):
-        dz = np.zeros(self.N * 7)
+        dz = np.zeros(self.N * self.nw)
         z, lam, nu, lamT = _f64(z), _f64(lam), _f64(nu), _f64(lamT)
         ok = lib().oracle_push_step(*self._a(), _p(z), _p(lam), _p(nu), _p(lamT), mu_al, rho, _p(dz))
         return (dz if ok > 0 else None)
 
     def blocks(self, z):
         N = self.N
-        c = np.zeros((N, 10))
-        J = np.zeros((N, 10, 11))
-        en = np.zeros((N, 10), np.int32)
+        c = np.zeros((N, self.nr))
+        J = np.zeros((N, self.nr, self.nv))
+        en = np.zeros((N, self.nr), np.int32)
         cT = np.zeros(3)
         JT = np.zeros((3, 4))
         z = _f64(z)

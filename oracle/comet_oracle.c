@@ -39,18 +39,23 @@
 /* mu_g (reading: 0.5), f_max = mu_g m g; ellipsoidal limit surface with the        */
 /* uniform-pressure radius c_ls = a (sqrt2 + ln(1+sqrt2)) / 6; velocity scale v_ref. */
 /* ------------------------------------------------------------------------------ */
-#define PNX 4 /* x, y, theta, s                */
-#define PNU 3 /* F_n, F_t, v_s                 */
-#define PNW 7 /* stage unknowns (u_k, x_{k+1}) */
-#define PNV 11 /* row arguments (x_k, u_k, x_{k+1}) */
-#define PNR 10 /* path rows per interval: 5 equalities then 5 inequalities */
-#define PNE 5
-#define PNT 3 /* terminal rows */
+#define PNX 4  /* x, y, theta, s                                   */
+#define PNU 4  /* at most: F_n, F_t, v_s (and h, timed)            */
+#define PNW 8  /* at most: stage unknowns (u_k, x_{k+1})            */
+#define PNV 12 /* at most: row arguments (x_k, u_k, x_{k+1})         */
+#define PNR 12 /* at most: path rows per interval, equalities first  */
+#define PNE 5  /* equality rows per interval                        */
+#define PNI 7  /* at most: inequality rows per interval              */
+#define PNT 3  /* terminal rows */
 #define MAXSEG 6
 #define MAXN 512
 
 static const double P_A = 0.1, P_MASS = 1.0, P_G = 9.81, P_MUG = 0.5;
 static const double P_VREF = 1.0, P_DT = 0.1, P_WV = 1.0;
+/* Optimised timing (reading): the interval duration h is a fourth control, bounded per   */
+/* interval by h_min <= h <= h_max, and the objective charges the elapsed time with the   */
+/* weight w_T; a fixed-step problem uses h = P_DT.                                        */
+static const double P_HMIN = 0.02, P_HMAX = 0.2, P_WT = 0.01;
 static double p_fmax(void) { return P_MUG * P_MASS * P_G; }
 static double p_cls(void) { return P_A * (sqrt(2.0) + log(1.0 + sqrt(2.0))) / 6.0; }
 
@@ -58,10 +63,11 @@ static double p_cls(void) { return P_A * (sqrt(2.0) + log(1.0 + sqrt(2.0))) / 6.
 static const double FACE_N[4][2] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
 
 /* row types for the internal scaling */
-enum { T_DX, T_DY, T_DTH, T_DS, T_STICK, T_SLIDE, T_FN, T_CONE, T_SLIP, T_FACE, T_TXY, T_TTH, NTYPES };
+enum { T_DX, T_DY, T_DTH, T_DS, T_STICK, T_SLIDE, T_FN, T_CONE, T_SLIP, T_FACE, T_TXY, T_TTH, T_DUR, NTYPES };
 
 typedef struct {
-  int32_t al_max, gn_max, chol_retries, ls_trials, max_rejects, pad_;
+  int32_t al_max, gn_max, chol_retries, ls_trials, max_rejects;
+  int32_t timed; /* 1: the optimised-timing pushing problem */
   double mu0, mu_min, rho0, rho_min, rho_max, armijo_c1;
   double eta_star, omega_star, rc_star, eps_feas;
   double mu0_warm; /* initial penalty of a solve started from a given (warm) primal */
@@ -70,6 +76,8 @@ typedef struct {
 /* one mode-conditioned problem (one candidate order on one instance) */
 typedef struct {
   int N;
+  int timed;              /* interval durations are controls                      */
+  int nu, nw, nv, nr, ni; /* controls, stage unknowns, row arguments, rows, ineqs */
   int face[MAXN], slip[MAXN], smask[MAXN]; /* slip: 0 stick, 1 slide+, 2 slide- */
   double mu;
   double x0[PNX], goal[3];
@@ -78,25 +86,29 @@ typedef struct {
 
 /* ------------------------------------------------------------------------------ */
 /* Rows of one interval, physical units.                                          */
-/* v = (x_k[4], u_k[3], x_{k+1}[4]).  Row slots:                                     */
+/* v = (x_k[4], u_k[nu], x_{k+1}[4]), u = (F_n, F_t, v_s) or, with optimised timing, */
+/* (F_n, F_t, v_s, h); the step is dt = P_DT or dt = h.  Row slots:                   */
 /*  0..3 defects x_{k+1} - x_k - dt f(x_k,u_k)   (slot 3 masked at a face change)  */
 /*  4    stick: v_s = 0 ;  slide(sigma): F_t - sigma mu F_n = 0                     */
 /*  5    -F_n <= 0                                                                  */
 /*  6    stick: F_t - mu F_n <= 0 ;  slide: -sigma v_s <= 0                         */
 /*  7    stick: -F_t - mu F_n <= 0 ; slide: disabled                                */
 /*  8,9  s_{k+1} - a/2 <= 0 ,  -s_{k+1} - a/2 <= 0                                  */
+/*  10,11 (timed only) h - h_max <= 0 ,  h_min - h <= 0                            */
 /* Quasi-static law (reading): body twist = (v_ref/f_max) (F_x, F_y, M / c_ls^2),   */
 /* contact point p = (a/2) n + s t, force on the slider F = -F_n n + F_t t, so the  */
 /* moment about the centre is M = p x F = (a/2) F_t + s F_n; explicit Euler.        */
 /* ------------------------------------------------------------------------------ */
-static void push_rows(int face, int slip, int smask, double mu, const double *v,
+static void push_rows(int timed, int face, int slip, int smask, double mu, const double *v,
                       double *c, double J[PNR][PNV], int *en, int *type) {
-  const double fmax = p_fmax(), cls2 = p_cls() * p_cls(), k1 = P_VREF / fmax, dt = P_DT;
+  const int nu = timed ? 4 : 3, nr = timed ? 12 : 10, c1 = 4 + nu; /* c1: first column of x_{k+1} */
+  const double fmax = p_fmax(), cls2 = p_cls() * p_cls(), k1 = P_VREF / fmax;
+  const double dt = timed ? v[7] : P_DT;
   const double nx = FACE_N[face][0], ny = FACE_N[face][1];
   const double tx = -ny, ty = nx;
   const double x = v[0], y = v[1], th = v[2], s = v[3];
   const double Fn = v[4], Ft = v[5], vs = v[6];
-  const double x1 = v[7], y1 = v[8], th1 = v[9], s1 = v[10];
+  const double x1 = v[c1], y1 = v[c1 + 1], th1 = v[c1 + 2], s1 = v[c1 + 3];
   const double Fbx = -Fn * nx + Ft * tx, Fby = -Fn * ny + Ft * ty;
   const double M = 0.5 * P_A * Ft + s * Fn;
   const double xi_x = k1 * Fbx, xi_y = k1 * Fby, xi_t = k1 * M / cls2;
@@ -108,18 +120,26 @@ static void push_rows(int face, int slip, int smask, double mu, const double *v,
   int r, j;
   for (r = 0; r < PNR; ++r) {
     c[r] = 0.0;
+    en[r] = 0;
+    type[r] = T_FACE;
     for (j = 0; j < PNV; ++j) J[r][j] = 0.0;
   }
-  /* defects */
+  /* defects; with optimised timing d/dh of "- h f" is "- f" */
   c[0] = x1 - x - dt * vx;
-  J[0][0] = -1; J[0][2] = dt * vy; J[0][4] = -dt * dvx_dFn; J[0][5] = -dt * dvx_dFt; J[0][7] = 1;
+  J[0][0] = -1; J[0][2] = dt * vy; J[0][4] = -dt * dvx_dFn; J[0][5] = -dt * dvx_dFt; J[0][c1] = 1;
   c[1] = y1 - y - dt * vy;
-  J[1][1] = -1; J[1][2] = -dt * vx; J[1][4] = -dt * dvy_dFn; J[1][5] = -dt * dvy_dFt; J[1][8] = 1;
+  J[1][1] = -1; J[1][2] = -dt * vx; J[1][4] = -dt * dvy_dFn; J[1][5] = -dt * dvy_dFt; J[1][c1 + 1] = 1;
   c[2] = th1 - th - dt * xi_t;
   J[2][2] = -1; J[2][3] = -dt * k1 * Fn / cls2; J[2][4] = -dt * k1 * s / cls2;
-  J[2][5] = -dt * k1 * 0.5 * P_A / cls2; J[2][9] = 1;
+  J[2][5] = -dt * k1 * 0.5 * P_A / cls2; J[2][c1 + 2] = 1;
   c[3] = s1 - s - dt * vs;
-  J[3][3] = -1; J[3][6] = -dt; J[3][10] = 1;
+  J[3][3] = -1; J[3][6] = -dt; J[3][c1 + 3] = 1;
+  if (timed) {
+    J[0][7] = -vx;
+    J[1][7] = -vy;
+    J[2][7] = -xi_t;
+    J[3][7] = -vs;
+  }
   en[0] = en[1] = en[2] = 1;
   en[3] = smask;
   type[0] = T_DX; type[1] = T_DY; type[2] = T_DTH; type[3] = T_DS;
@@ -141,9 +161,13 @@ static void push_rows(int face, int slip, int smask, double mu, const double *v,
     c[6] = -sg * vs; J[6][6] = -sg; en[6] = 1; type[6] = T_SLIP;
     c[7] = 0; en[7] = 0; type[7] = T_CONE;
   }
-  c[8] = s1 - 0.5 * P_A; J[8][10] = 1; en[8] = 1; type[8] = T_FACE;
-  c[9] = -s1 - 0.5 * P_A; J[9][10] = -1; en[9] = 1; type[9] = T_FACE;
-  for (r = 0; r < PNR; ++r)
+  c[8] = s1 - 0.5 * P_A; J[8][c1 + 3] = 1; en[8] = 1; type[8] = T_FACE;
+  c[9] = -s1 - 0.5 * P_A; J[9][c1 + 3] = -1; en[9] = 1; type[9] = T_FACE;
+  if (timed) {
+    c[10] = v[7] - P_HMAX; J[10][7] = 1; en[10] = 1; type[10] = T_DUR;
+    c[11] = P_HMIN - v[7]; J[11][7] = -1; en[11] = 1; type[11] = T_DUR;
+  }
+  for (r = 0; r < nr; ++r)
     if (!en[r]) {
       c[r] = 0;
       for (j = 0; j < PNV; ++j) J[r][j] = 0;
@@ -161,31 +185,47 @@ static void push_term(const double *goal, const double *xN, double *c, double J[
 }
 
 
-/* stage cost dt [ (F_n^2 + F_t^2)/f_max^2 + w_v (v_s/v_ref)^2 ] with gradient and diagonal Hessian */
-static double push_cost(const double *u, double *gu, double *hu) {
+/* Stage cost.  Fixed step: dt q(u) with q = (F_n^2 + F_t^2)/f_max^2 + w_v (v_s/v_ref)^2, */
+/* gradient and its (constant, diagonal) Hessian.  Optimised timing: h (q(u) + w_T) with   */
+/* the exact gradient; the Hessian model keeps the force/velocity block of the exact      */
+/* Hessian, 2 h diag(weights of q), taken at h_e = max(h, h_min / 2), and drops the mixed */
+/* (u, h) and (h, h) entries, with which the exact Hessian is indefinite (reading: the    */
+/* duration direction takes its curvature from the active rows and the proximal term).   */
+/* hu: [PNU][PNU], full.                                                                   */
+static double push_cost(int timed, const double *u, double *gu, double hu[PNU][PNU]) {
   const double fm2 = p_fmax() * p_fmax(), vr2 = P_VREF * P_VREF;
+  const double h = timed ? u[3] : P_DT;
+  const double q = (u[0] * u[0] + u[1] * u[1]) / fm2 + P_WV * u[2] * u[2] / vr2;
+  int i, j;
   if (gu) {
-    gu[0] = P_DT * 2.0 * u[0] / fm2;
-    gu[1] = P_DT * 2.0 * u[1] / fm2;
-    gu[2] = P_DT * 2.0 * P_WV * u[2] / vr2;
+    gu[0] = h * 2.0 * u[0] / fm2;
+    gu[1] = h * 2.0 * u[1] / fm2;
+    gu[2] = h * 2.0 * P_WV * u[2] / vr2;
+    if (timed) gu[3] = q + P_WT;
   }
   if (hu) {
-    hu[0] = P_DT * 2.0 / fm2;
-    hu[1] = P_DT * 2.0 / fm2;
-    hu[2] = P_DT * 2.0 * P_WV / vr2;
+    const double he = timed ? fmax(h, 0.5 * P_HMIN) : h;
+    for (i = 0; i < PNU; ++i)
+      for (j = 0; j < PNU; ++j) hu[i][j] = 0.0;
+    hu[0][0] = he * 2.0 / fm2;
+    hu[1][1] = he * 2.0 / fm2;
+    hu[2][2] = he * 2.0 * P_WV / vr2;
   }
-  return P_DT * ((u[0] * u[0] + u[1] * u[1]) / fm2 + P_WV * u[2] * u[2] / vr2);
+  return timed ? h * (q + P_WT) : h * q;
 }
 
 /* ------------------------------------------------------------------------------ */
-/* Primal layout: z[k*7 + 0..2] = u_k, z[k*7 + 3..6] = x_{k+1}, k = 0..N-1.          */
+/* Primal layout: z[k*nw + 0..nu-1] = u_k, z[k*nw + nu..nu+3] = x_{k+1},            */
+/* k = 0..N-1, nw = nu + 4 (nu = 3, or 4 with optimised timing).                     */
 /* ------------------------------------------------------------------------------ */
 static void stage_args(const PushProb *P, const double *z, int k, double *v) {
   int i;
-  const double *xk = (k == 0) ? P->x0 : &z[(k - 1) * PNW + PNU];
+  const int nu = P->nu, nw = P->nw;
+  const double *xk = (k == 0) ? P->x0 : &z[(k - 1) * nw + nu];
+  for (i = 0; i < PNV; ++i) v[i] = 0.0;
   for (i = 0; i < PNX; ++i) v[i] = xk[i];
-  for (i = 0; i < PNU; ++i) v[PNX + i] = z[k * PNW + i];
-  for (i = 0; i < PNX; ++i) v[PNX + PNU + i] = z[k * PNW + PNU + i];
+  for (i = 0; i < nu; ++i) v[PNX + i] = z[k * nw + i];
+  for (i = 0; i < PNX; ++i) v[PNX + nu + i] = z[k * nw + nu + i];
 }
 
 /* scaled rows of interval k: c~ = c / sigma_type, J~ likewise */
@@ -193,8 +233,8 @@ static void stage_scaled(const PushProb *P, const double *z, int k, double *c, d
   double v[PNV];
   int type[PNR], r, j;
   stage_args(P, z, k, v);
-  push_rows(P->face[k], P->slip[k], P->smask[k], P->mu, v, c, J, en, type);
-  for (r = 0; r < PNR; ++r) {
+  push_rows(P->timed, P->face[k], P->slip[k], P->smask[k], P->mu, v, c, J, en, type);
+  for (r = 0; r < P->nr; ++r) {
     const double sc = P->scale[type[r]];
     c[r] /= sc;
     for (j = 0; j < PNV; ++j) J[r][j] /= sc;
@@ -203,7 +243,7 @@ static void stage_scaled(const PushProb *P, const double *z, int k, double *c, d
 
 static void term_scaled(const PushProb *P, const double *z, double *c, double J[PNT][PNX]) {
   int type[PNT], r, j;
-  push_term(P->goal, &z[(P->N - 1) * PNW + PNU], c, J, type);
+  push_term(P->goal, &z[(P->N - 1) * P->nw + P->nu], c, J, type);
   for (r = 0; r < PNT; ++r) {
     const double sc = P->scale[type[r]];
     c[r] /= sc;
@@ -214,8 +254,8 @@ static void term_scaled(const PushProb *P, const double *z, double *c, double J[
 /* ------------------------------------------------------------------------------ */
 /* Augmented-Lagrangian merit (reading: classic PHR form, mu = 1/penalty).          */
 /*   phi = J + sum_eq (lam c + c^2/(2 mu)) + sum_in (mu/2)([nu + c/mu]_+^2 - nu^2)   */
-/* lam: [N][5] equality multipliers (slots 0..4), nu: [N][5] inequality multipliers  */
-/* (slots 5..9), lamT[3] terminal multipliers.                                        */
+/* lam: [N][5] equality multipliers (slots 0..4), nu: [N][ni] inequality multipliers */
+/* (slots 5..nr-1; ni = 5, or 7 with optimised timing), lamT[3] terminal ones.       */
 /* ------------------------------------------------------------------------------ */
 typedef struct {
   double *lam, *nu, lamT[PNT];
@@ -226,13 +266,13 @@ static double merit(const PushProb *P, const double *z, const Dual *D) {
   double phi = 0.0, c[PNR], J[PNR][PNV], cT[PNT], JT[PNT][PNX];
   int en[PNR], k, r;
   for (k = 0; k < P->N; ++k) {
-    phi += push_cost(&z[k * PNW], NULL, NULL);
+    phi += push_cost(P->timed, &z[k * P->nw], NULL, NULL);
     stage_scaled(P, z, k, c, J, en);
     for (r = 0; r < PNE; ++r)
       if (en[r]) phi += D->lam[k * PNE + r] * c[r] + c[r] * c[r] / (2.0 * D->mu);
-    for (r = PNE; r < PNR; ++r)
+    for (r = PNE; r < P->nr; ++r)
       if (en[r]) {
-        const double nu = D->nu[k * PNE + (r - PNE)];
+        const double nu = D->nu[k * P->ni + (r - PNE)];
         const double t = fmax(nu + c[r] / D->mu, 0.0);
         phi += 0.5 * D->mu * (t * t - nu * nu);
       }
@@ -260,30 +300,31 @@ static double row_weight(int r, int en, double c, double lam, double nu, double 
   }
 }
 
-/* gradient of phi w.r.t. z (size 7N) */
+/* gradient of phi w.r.t. z (size nw N) */
 static void gradient(const PushProb *P, const double *z, const Dual *D, double *g) {
   double c[PNR], J[PNR][PNV], cT[PNT], JT[PNT][PNX], gu[PNU];
+  const int nu = P->nu, nw = P->nw;
   int en[PNR], k, r, j, act;
-  memset(g, 0, sizeof(double) * PNW * P->N);
+  memset(g, 0, sizeof(double) * nw * P->N);
   for (k = 0; k < P->N; ++k) {
-    push_cost(&z[k * PNW], gu, NULL);
-    for (j = 0; j < PNU; ++j) g[k * PNW + j] += gu[j];
+    push_cost(P->timed, &z[k * nw], gu, NULL);
+    for (j = 0; j < nu; ++j) g[k * nw + j] += gu[j];
     stage_scaled(P, z, k, c, J, en);
-    for (r = 0; r < PNR; ++r) {
+    for (r = 0; r < P->nr; ++r) {
       const double lam = (r < PNE) ? D->lam[k * PNE + r] : 0.0;
-      const double nu = (r >= PNE) ? D->nu[k * PNE + r - PNE] : 0.0;
-      const double w = row_weight(r, en[r], c[r], lam, nu, D->mu, &act);
+      const double nuv = (r >= PNE) ? D->nu[k * P->ni + r - PNE] : 0.0;
+      const double w = row_weight(r, en[r], c[r], lam, nuv, D->mu, &act);
       if (w == 0.0) continue;
       /* x_k columns belong to the previous stage's x_{k+1} (x_0 is fixed) */
       if (k > 0)
-        for (j = 0; j < PNX; ++j) g[(k - 1) * PNW + PNU + j] += w * J[r][j];
-      for (j = 0; j < PNW; ++j) g[k * PNW + j] += w * J[r][PNX + j];
+        for (j = 0; j < PNX; ++j) g[(k - 1) * nw + nu + j] += w * J[r][j];
+      for (j = 0; j < nw; ++j) g[k * nw + j] += w * J[r][PNX + j];
     }
   }
   term_scaled(P, z, cT, JT);
   for (r = 0; r < PNT; ++r) {
     const double w = D->lamT[r] + cT[r] / D->mu;
-    for (j = 0; j < PNX; ++j) g[(P->N - 1) * PNW + PNU + j] += w * JT[r][j];
+    for (j = 0; j < PNX; ++j) g[(P->N - 1) * nw + nu + j] += w * JT[r][j];
   }
 }
 
@@ -330,11 +371,11 @@ static void chol_solve(int n, const double *L, int lda, double *b) {
 /* Returns 1 on success, 0 when a Cholesky factorisation fails.                     */
 /* ------------------------------------------------------------------------------ */
 static int gn_step(const PushProb *P, const double *z, const Dual *D, double rho, double *dz) {
-  const int N = P->N;
+  const int N = P->N, nu = P->nu, nw = P->nw, nv = P->nv;
   double Pm[PNX][PNX], pv[PNX];
-  double *kk = (double *)malloc(sizeof(double) * N * PNW);
-  double *KK = (double *)malloc(sizeof(double) * N * PNW * PNX);
-  double c[PNR], J[PNR][PNV], cT[PNT], JT[PNT][PNX], gu[PNU], hu[PNU];
+  double *kk = (double *)malloc(sizeof(double) * N * nw);
+  double *KK = (double *)malloc(sizeof(double) * N * nw * PNX);
+  double c[PNR], J[PNR][PNV], cT[PNT], JT[PNT][PNX], gu[PNU], hu[PNU][PNU];
   int en[PNR], k, r, i, j, act, ok = 1;
   /* terminal value function V_N */
   term_scaled(P, z, cT, JT);
@@ -353,50 +394,50 @@ static int gn_step(const PushProb *P, const double *z, const Dual *D, double rho
     double G[PNV][PNV], h[PNV], S[PNW * PNW], rhs[PNW];
     memset(G, 0, sizeof G);
     memset(h, 0, sizeof h);
-    push_cost(&z[k * PNW], gu, hu);
-    for (i = 0; i < PNU; ++i) {
+    push_cost(P->timed, &z[k * nw], gu, hu);
+    for (i = 0; i < nu; ++i) {
       h[PNX + i] += gu[i];
-      G[PNX + i][PNX + i] += hu[i];
+      for (j = 0; j < nu; ++j) G[PNX + i][PNX + j] += hu[i][j];
     }
     stage_scaled(P, z, k, c, J, en);
-    for (r = 0; r < PNR; ++r) {
+    for (r = 0; r < P->nr; ++r) {
       const double lam = (r < PNE) ? D->lam[k * PNE + r] : 0.0;
-      const double nu = (r >= PNE) ? D->nu[k * PNE + r - PNE] : 0.0;
-      const double w = row_weight(r, en[r], c[r], lam, nu, D->mu, &act);
-      for (i = 0; i < PNV; ++i) h[i] += w * J[r][i];
+      const double nuv = (r >= PNE) ? D->nu[k * P->ni + r - PNE] : 0.0;
+      const double w = row_weight(r, en[r], c[r], lam, nuv, D->mu, &act);
+      for (i = 0; i < nv; ++i) h[i] += w * J[r][i];
       if (act)
-        for (i = 0; i < PNV; ++i)
-          for (j = 0; j < PNV; ++j) G[i][j] += J[r][i] * J[r][j] / D->mu;
+        for (i = 0; i < nv; ++i)
+          for (j = 0; j < nv; ++j) G[i][j] += J[r][i] * J[r][j] / D->mu;
     }
     /* value function of x_{k+1}, the last four entries of y */
     for (i = 0; i < PNX; ++i) {
-      h[PNX + PNU + i] += pv[i];
-      for (j = 0; j < PNX; ++j) G[PNX + PNU + i][PNX + PNU + j] += Pm[i][j];
+      h[PNX + nu + i] += pv[i];
+      for (j = 0; j < PNX; ++j) G[PNX + nu + i][PNX + nu + j] += Pm[i][j];
     }
-    for (i = 0; i < PNW; ++i)
-      for (j = 0; j < PNW; ++j) S[i * PNW + j] = G[PNX + i][PNX + j] + (i == j ? rho : 0.0);
-    if (!cholesky(PNW, S, PNW)) {
+    for (i = 0; i < nw; ++i)
+      for (j = 0; j < nw; ++j) S[i * nw + j] = G[PNX + i][PNX + j] + (i == j ? rho : 0.0);
+    if (!cholesky(nw, S, nw)) {
       ok = 0;
       break;
     }
     /* gains: k = -S^-1 q_w, K = -S^-1 Q_wx */
-    for (i = 0; i < PNW; ++i) rhs[i] = -h[PNX + i];
-    chol_solve(PNW, S, PNW, rhs);
-    for (i = 0; i < PNW; ++i) kk[k * PNW + i] = rhs[i];
+    for (i = 0; i < nw; ++i) rhs[i] = -h[PNX + i];
+    chol_solve(nw, S, nw, rhs);
+    for (i = 0; i < nw; ++i) kk[k * nw + i] = rhs[i];
     for (j = 0; j < PNX; ++j) {
-      for (i = 0; i < PNW; ++i) rhs[i] = -G[PNX + i][j];
-      chol_solve(PNW, S, PNW, rhs);
-      for (i = 0; i < PNW; ++i) KK[(k * PNW + i) * PNX + j] = rhs[i];
+      for (i = 0; i < nw; ++i) rhs[i] = -G[PNX + i][j];
+      chol_solve(nw, S, nw, rhs);
+      for (i = 0; i < nw; ++i) KK[(k * nw + i) * PNX + j] = rhs[i];
     }
     /* value: P = Q_xx + Q_xw K, p = q_x + Q_xw k */
     {
       double Pn[PNX][PNX], pn[PNX];
       for (i = 0; i < PNX; ++i) {
         pn[i] = h[i];
-        for (r = 0; r < PNW; ++r) pn[i] += G[i][PNX + r] * kk[k * PNW + r];
+        for (r = 0; r < nw; ++r) pn[i] += G[i][PNX + r] * kk[k * nw + r];
         for (j = 0; j < PNX; ++j) {
           Pn[i][j] = G[i][j];
-          for (r = 0; r < PNW; ++r) Pn[i][j] += G[i][PNX + r] * KK[(k * PNW + r) * PNX + j];
+          for (r = 0; r < nw; ++r) Pn[i][j] += G[i][PNX + r] * KK[(k * nw + r) * PNX + j];
         }
       }
       for (i = 0; i < PNX; ++i) {
@@ -408,12 +449,12 @@ static int gn_step(const PushProb *P, const double *z, const Dual *D, double rho
   if (ok) {
     double dx[PNX] = {0, 0, 0, 0};
     for (k = 0; k < N; ++k) {
-      for (i = 0; i < PNW; ++i) {
-        double s = kk[k * PNW + i];
-        for (j = 0; j < PNX; ++j) s += KK[(k * PNW + i) * PNX + j] * dx[j];
-        dz[k * PNW + i] = s;
+      for (i = 0; i < nw; ++i) {
+        double s = kk[k * nw + i];
+        for (j = 0; j < PNX; ++j) s += KK[(k * nw + i) * PNX + j] * dx[j];
+        dz[k * nw + i] = s;
       }
-      for (j = 0; j < PNX; ++j) dx[j] = dz[k * PNW + PNU + j];
+      for (j = 0; j < PNX; ++j) dx[j] = dz[k * nw + nu + j];
     }
   }
   free(kk);
@@ -428,11 +469,11 @@ static void scaled_viol(const PushProb *P, const double *z, const Dual *D, doubl
   double v = 0.0, q = 0.0;
   for (k = 0; k < P->N; ++k) {
     stage_scaled(P, z, k, c, J, en);
-    for (r = 0; r < PNR; ++r) {
+    for (r = 0; r < P->nr; ++r) {
       if (!en[r]) continue;
       if (r < PNE) v = fmax(v, fabs(c[r]));
       else {
-        const double nu = D->nu[k * PNE + r - PNE];
+        const double nu = D->nu[k * P->ni + r - PNE];
         v = fmax(v, fmax(c[r], 0.0));
         q = fmax(q, fabs(fmin(-c[r], nu)));
       }
@@ -450,11 +491,11 @@ static void update_duals(const PushProb *P, const double *z, Dual *D) {
   int en[PNR], k, r;
   for (k = 0; k < P->N; ++k) {
     stage_scaled(P, z, k, c, J, en);
-    for (r = 0; r < PNR; ++r) {
+    for (r = 0; r < P->nr; ++r) {
       if (!en[r]) continue;
       if (r < PNE) D->lam[k * PNE + r] += c[r] / D->mu;
       else {
-        double *nu = &D->nu[k * PNE + r - PNE];
+        double *nu = &D->nu[k * P->ni + r - PNE];
         *nu = fmax(*nu + c[r] / D->mu, 0.0);
       }
     }
@@ -469,33 +510,36 @@ static void score(const PushProb *P, const double *z, double *Jout, double *vout
   int en[PNR], type[PNR], ttype[PNT], k, r;
   double obj = 0.0, vi = 0.0;
   for (k = 0; k < P->N; ++k) {
-    obj += push_cost(&z[k * PNW], NULL, NULL);
+    obj += push_cost(P->timed, &z[k * P->nw], NULL, NULL);
     stage_args(P, z, k, v);
-    push_rows(P->face[k], P->slip[k], P->smask[k], P->mu, v, c, J, en, type);
-    for (r = 0; r < PNR; ++r) {
+    push_rows(P->timed, P->face[k], P->slip[k], P->smask[k], P->mu, v, c, J, en, type);
+    for (r = 0; r < P->nr; ++r) {
       if (!en[r]) continue;
       vi = fmax(vi, (r < PNE) ? fabs(c[r]) : fmax(c[r], 0.0));
     }
   }
-  push_term(P->goal, &z[(P->N - 1) * PNW + PNU], cT, JT, ttype);
+  push_term(P->goal, &z[(P->N - 1) * P->nw + P->nu], cT, JT, ttype);
   for (r = 0; r < PNT; ++r) vi = fmax(vi, fabs(cT[r]));
   *Jout = obj;
   *vout = vi;
 }
 
 /* schedule-derived initial guess: pose interpolated start->goal, contact coordinate */
-/* held at its start value, F_n = 0.05 f_max, F_t on the cone edge for sliding.      */
+/* held at its start value, F_n = 0.05 f_max, F_t on the cone edge for sliding; with  */
+/* optimised timing every interval starts at the fixed step, h = P_DT.                */
 static void initial_guess(const PushProb *P, double *z) {
   const double fn = 0.05 * p_fmax();
+  const int nu = P->nu, nw = P->nw;
   int k, i;
   for (k = 0; k < P->N; ++k) {
     const double sg = (P->slip[k] == 0) ? 0.0 : ((P->slip[k] == 1) ? 1.0 : -1.0);
     const double t = (double)(k + 1) / (double)P->N;
-    z[k * PNW + 0] = fn;
-    z[k * PNW + 1] = sg * P->mu * fn;
-    z[k * PNW + 2] = 0.0;
-    for (i = 0; i < 3; ++i) z[k * PNW + PNU + i] = P->x0[i] + (P->goal[i] - P->x0[i]) * t;
-    z[k * PNW + PNU + 3] = P->x0[3];
+    z[k * nw + 0] = fn;
+    z[k * nw + 1] = sg * P->mu * fn;
+    z[k * nw + 2] = 0.0;
+    if (P->timed) z[k * nw + 3] = P_DT;
+    for (i = 0; i < 3; ++i) z[k * nw + nu + i] = P->x0[i] + (P->goal[i] - P->x0[i]) * t;
+    z[k * nw + nu + 3] = P->x0[3];
   }
 }
 
@@ -504,9 +548,15 @@ static void initial_guess(const PushProb *P, double *z) {
 /* The s-row of the last interval of a segment is masked when the next segment     */
 /* uses another face (instantaneous relocation of the pusher).                      */
 /* ------------------------------------------------------------------------------ */
-static int setup_push(PushProb *P, int nseg, const int32_t *modes, const int32_t *knots,
+static int setup_push(PushProb *P, int timed, int nseg, const int32_t *modes, const int32_t *knots,
                       const double *x0, const double *goal, double mu, const double *scale) {
   int j, i, k = 0;
+  P->timed = timed ? 1 : 0;
+  P->nu = timed ? 4 : 3;
+  P->nw = P->nu + PNX;
+  P->nv = P->nw + PNX;
+  P->nr = timed ? 12 : 10;
+  P->ni = P->nr - PNE;
   if (nseg < 1 || nseg > MAXSEG) return 0;
   for (j = 0; j < nseg; ++j) {
     if (modes[j] < 0 || modes[j] >= 12 || knots[j] < 1) return 0;
@@ -542,11 +592,11 @@ static int cmp_double(const void *a, const void *b) {
   return (x < y) ? -1 : (x > y) ? 1 : 0;
 }
 
-static double g_push_scale[NTYPES];
-static int g_push_scale_ready = 0;
+static double g_push_scale[2][NTYPES];
+static int g_push_scale_ready[2] = {0, 0};
 static pthread_mutex_t g_scale_lock = PTHREAD_MUTEX_INITIALIZER;
 
-static void compute_push_scales(double *out) {
+static void compute_push_scales(int timed, double *out) {
   static double buf[NTYPES][144 * 10 * 2 + 8];
   int cnt[NTYPES];
   double ones[NTYPES];
@@ -562,19 +612,19 @@ static void compute_push_scales(double *out) {
       int32_t modes[2] = {m1, m2}, knots[2] = {5, 5};
       double z[10 * PNW], v[PNV], c[PNR], J[PNR][PNV], cT[PNT], JT[PNT][PNX];
       int en[PNR], type[PNR], tt[PNT];
-      setup_push(&P, 2, modes, knots, x0, goal, 0.4, ones);
+      setup_push(&P, timed, 2, modes, knots, x0, goal, 0.4, ones);
       initial_guess(&P, z);
       for (k = 0; k < P.N; ++k) {
         stage_args(&P, z, k, v);
-        push_rows(P.face[k], P.slip[k], P.smask[k], P.mu, v, c, J, en, type);
-        for (r = 0; r < PNR; ++r) {
+        push_rows(timed, P.face[k], P.slip[k], P.smask[k], P.mu, v, c, J, en, type);
+        for (r = 0; r < P.nr; ++r) {
           double nrm = 0.0;
           if (!en[r]) continue;
           for (j = 0; j < PNV; ++j) nrm += J[r][j] * J[r][j];
           buf[type[r]][cnt[type[r]]++] = sqrt(nrm);
         }
       }
-      push_term(P.goal, &z[(P.N - 1) * PNW + PNU], cT, JT, tt);
+      push_term(P.goal, &z[(P.N - 1) * P.nw + P.nu], cT, JT, tt);
       for (r = 0; r < PNT; ++r) {
         double nrm = 0.0;
         for (j = 0; j < PNX; ++j) nrm += JT[r][j] * JT[r][j];
@@ -583,19 +633,24 @@ static void compute_push_scales(double *out) {
     }
   for (t = 0; t < NTYPES; ++t) {
     const int n = cnt[t];
+    if (n == 0) {           /* a type the model does not have */
+      out[t] = 1.0;
+      continue;
+    }
     qsort(buf[t], (size_t)n, sizeof(double), cmp_double);
     out[t] = (n % 2) ? buf[t][n / 2] : 0.5 * (buf[t][n / 2 - 1] + buf[t][n / 2]);
   }
 }
 
-static const double *push_scales(void) {
+static const double *push_scales(int timed) {
+  timed = timed ? 1 : 0;
   pthread_mutex_lock(&g_scale_lock);
-  if (!g_push_scale_ready) {
-    compute_push_scales(g_push_scale);
-    g_push_scale_ready = 1;
+  if (!g_push_scale_ready[timed]) {
+    compute_push_scales(timed, g_push_scale[timed]);
+    g_push_scale_ready[timed] = 1;
   }
   pthread_mutex_unlock(&g_scale_lock);
-  return g_push_scale;
+  return g_push_scale[timed];
 }
 
 /* ------------------------------------------------------------------------------ */
@@ -613,7 +668,7 @@ static int all_finite(const double *a, int n) {
 }
 
 static void solve(const PushProb *P, const OracleParams *prm, int warm, double *z, SolveStats *st) {
-  const int N = P->N, nz = N * PNW;
+  const int N = P->N, nz = N * P->nw;
   double *g = (double *)malloc(sizeof(double) * nz);
   double *dz = (double *)malloc(sizeof(double) * nz);
   double *zt = (double *)malloc(sizeof(double) * nz);
@@ -622,7 +677,7 @@ static void solve(const PushProb *P, const OracleParams *prm, int warm, double *
   double eta, omega, rho = prm->rho0;
   int al, i;
   D.lam = (double *)calloc((size_t)N * PNE, sizeof(double));
-  D.nu = (double *)calloc((size_t)N * PNE, sizeof(double));
+  D.nu = (double *)calloc((size_t)N * P->ni, sizeof(double));
   D.lamT[0] = D.lamT[1] = D.lamT[2] = 0.0;
   D.mu = warm ? prm->mu0_warm : prm->mu0;
   eta = pow(D.mu, 0.1);
@@ -714,7 +769,7 @@ static void solve(const PushProb *P, const OracleParams *prm, int warm, double *
 
 /* ------------------------------------------------------------------------------ */
 /* Batched evaluation over sequences, one sequence per thread.                      */
-/* traj: [B][nmax+1][7] rows (x_k, u_k), row N has u = 0, rows beyond N are zero.   */
+/* traj: [B][nmax+1][4+nu] rows (x_k, u_k), row N has u = 0, rows beyond N zero.    */
 /* stats: [B][4] = (AL iterations, GN iterations, Cholesky failures, status).       */
 /* ------------------------------------------------------------------------------ */
 typedef struct {
@@ -732,15 +787,16 @@ typedef struct {
 
 static void eval_one(EvalJob *E, int64_t b) {
   PushProb *P = (PushProb *)malloc(sizeof(PushProb));
-  const double *scale = push_scales();
+  const int timed = E->prm->timed != 0, rw = PNX + (timed ? 4 : 3); /* trajectory row width */
+  const double *scale = push_scales(timed);
   double *z;
   SolveStats st = {0, 0, 0, 2};
   double J = NAN, v = INFINITY;
   int k, i;
-  int ok = setup_push(P, E->nseg[b], &E->modes[b * E->smax], &E->knots[b * E->smax], &E->x0[b * PNX],
+  int ok = setup_push(P, timed, E->nseg[b], &E->modes[b * E->smax], &E->knots[b * E->smax], &E->x0[b * PNX],
                       &E->goal[b * 3], E->inst[b], scale);
   if (ok && P->N > E->nmax) ok = 0;
-  if (E->traj) memset(&E->traj[b * (E->nmax + 1) * PNW], 0, sizeof(double) * (size_t)(E->nmax + 1) * PNW);
+  if (E->traj) memset(&E->traj[b * (E->nmax + 1) * rw], 0, sizeof(double) * (size_t)(E->nmax + 1) * rw);
   if (!ok) {
     E->cost[b] = NAN;
     E->viol[b] = INFINITY;
@@ -750,12 +806,12 @@ static void eval_one(EvalJob *E, int64_t b) {
     free(P);
     return;
   }
-  z = (double *)malloc(sizeof(double) * P->N * PNW);
+  z = (double *)malloc(sizeof(double) * P->N * P->nw);
   if (E->warm) {
-    const double *w = &E->warm[b * (E->nmax + 1) * PNW];
+    const double *w = &E->warm[b * (E->nmax + 1) * rw];
     for (k = 0; k < P->N; ++k) {
-      for (i = 0; i < PNU; ++i) z[k * PNW + i] = w[k * PNW + PNX + i];
-      for (i = 0; i < PNX; ++i) z[k * PNW + PNU + i] = w[(k + 1) * PNW + i];
+      for (i = 0; i < P->nu; ++i) z[k * P->nw + i] = w[k * rw + PNX + i];
+      for (i = 0; i < PNX; ++i) z[k * P->nw + P->nu + i] = w[(k + 1) * rw + i];
     }
   } else {
     initial_guess(P, z);
@@ -777,11 +833,11 @@ static void eval_one(EvalJob *E, int64_t b) {
     E->stats[b * 4 + 3] = st.status;
   }
   if (E->traj) {
-    double *T = &E->traj[b * (E->nmax + 1) * PNW];
+    double *T = &E->traj[b * (E->nmax + 1) * rw];
     for (i = 0; i < PNX; ++i) T[i] = P->x0[i];
     for (k = 0; k < P->N; ++k) {
-      for (i = 0; i < PNU; ++i) T[k * PNW + PNX + i] = z[k * PNW + i];
-      for (i = 0; i < PNX; ++i) T[(k + 1) * PNW + i] = z[k * PNW + PNU + i];
+      for (i = 0; i < P->nu; ++i) T[k * rw + PNX + i] = z[k * P->nw + i];
+      for (i = 0; i < PNX; ++i) T[(k + 1) * rw + i] = z[k * P->nw + P->nu + i];
     }
   }
   free(z);
@@ -834,46 +890,59 @@ int oracle_evaluate(int64_t B, int32_t smax, int32_t nmax, const double *x0, con
 
 /* ------------------------------------------------------------------------------ */
 /* Debug entry points used by the pins: one sequence, given primal and duals.       */
-/* z: [N*7] in the (u_k, x_{k+1}) layout; lam [N*5], nu [N*5], lamT [3].            */
+/* z: [N*nw] in the (u_k, x_{k+1}) layout; lam [N*5], nu [N*ni], lamT [3].         */
 /* ------------------------------------------------------------------------------ */
-int oracle_push_scales(double *out) {
-  const double *s = push_scales();
+int oracle_push_scales(int32_t timed, double *out) {
+  const double *s = push_scales(timed);
   int t;
   for (t = 0; t < NTYPES; ++t) out[t] = s[t];
   return NTYPES;
 }
 
-int oracle_push_rows(int32_t face, int32_t slip, int32_t smask, double mu, const double *v, double *c,
-                     double *J, int32_t *en) {
-  double JJ[PNR][PNV];
+int oracle_push_rows(int32_t timed, int32_t face, int32_t slip, int32_t smask, double mu, const double *v,
+                     double *c, double *J, int32_t *en) {
+  double JJ[PNR][PNV], cc[PNR];
   int e[PNR], type[PNR], r, j;
-  push_rows(face, slip, smask, mu, v, c, JJ, e, type);
-  for (r = 0; r < PNR; ++r) {
+  const int nr = timed ? 12 : 10, nv = timed ? 12 : 11;
+  push_rows(timed, face, slip, smask, mu, v, cc, JJ, e, type);
+  for (r = 0; r < nr; ++r) {
+    c[r] = cc[r];
     en[r] = e[r];
-    for (j = 0; j < PNV; ++j) J[r * PNV + j] = JJ[r][j];
+    for (j = 0; j < nv; ++j) J[r * nv + j] = JJ[r][j];
   }
   return 0;
 }
 
-static int debug_setup(PushProb *P, int32_t nseg, const int32_t *modes, const int32_t *knots,
-                       const double *x0, const double *goal, double mu) {
-  return setup_push(P, nseg, modes, knots, x0, goal, mu, push_scales());
+/* stage cost, its gradient (nu) and Hessian model (nu x nu, row-major) */
+double oracle_push_cost(int32_t timed, const double *u, double *gu, double *hu) {
+  double H[PNU][PNU];
+  const int nu = timed ? 4 : 3;
+  int i, j;
+  const double J = push_cost(timed, u, gu, H);
+  for (i = 0; i < nu; ++i)
+    for (j = 0; j < nu; ++j) hu[i * nu + j] = H[i][j];
+  return J;
 }
 
-int oracle_push_initial(int32_t nseg, const int32_t *modes, const int32_t *knots, const double *x0,
+static int debug_setup(PushProb *P, int32_t timed, int32_t nseg, const int32_t *modes, const int32_t *knots,
+                       const double *x0, const double *goal, double mu) {
+  return setup_push(P, timed, nseg, modes, knots, x0, goal, mu, push_scales(timed));
+}
+
+int oracle_push_initial(int32_t timed, int32_t nseg, const int32_t *modes, const int32_t *knots, const double *x0,
                         const double *goal, double mu, double *z) {
   PushProb P;
-  if (!debug_setup(&P, nseg, modes, knots, x0, goal, mu)) return -1;
+  if (!debug_setup(&P, timed, nseg, modes, knots, x0, goal, mu)) return -1;
   initial_guess(&P, z);
   return P.N;
 }
 
-int oracle_push_merit(int32_t nseg, const int32_t *modes, const int32_t *knots, const double *x0,
+int oracle_push_merit(int32_t timed, int32_t nseg, const int32_t *modes, const int32_t *knots, const double *x0,
                       const double *goal, double mu, const double *z, const double *lam, const double *nu,
                       const double *lamT, double mu_al, double *phi_out, double *grad_out) {
   PushProb P;
   Dual D;
-  if (!debug_setup(&P, nseg, modes, knots, x0, goal, mu)) return -1;
+  if (!debug_setup(&P, timed, nseg, modes, knots, x0, goal, mu)) return -1;
   D.lam = (double *)lam;
   D.nu = (double *)nu;
   D.lamT[0] = lamT[0]; D.lamT[1] = lamT[1]; D.lamT[2] = lamT[2];
@@ -883,12 +952,12 @@ int oracle_push_merit(int32_t nseg, const int32_t *modes, const int32_t *knots, 
   return P.N;
 }
 
-int oracle_push_step(int32_t nseg, const int32_t *modes, const int32_t *knots, const double *x0,
+int oracle_push_step(int32_t timed, int32_t nseg, const int32_t *modes, const int32_t *knots, const double *x0,
                      const double *goal, double mu, const double *z, const double *lam, const double *nu,
                      const double *lamT, double mu_al, double rho, double *dz) {
   PushProb P;
   Dual D;
-  if (!debug_setup(&P, nseg, modes, knots, x0, goal, mu)) return -1;
+  if (!debug_setup(&P, timed, nseg, modes, knots, x0, goal, mu)) return -1;
   D.lam = (double *)lam;
   D.nu = (double *)nu;
   D.lamT[0] = lamT[0]; D.lamT[1] = lamT[1]; D.lamT[2] = lamT[2];
@@ -897,20 +966,20 @@ int oracle_push_step(int32_t nseg, const int32_t *modes, const int32_t *knots, c
 }
 
 /* scaled rows and Jacobians per stage (for the dense-KKT pin):                     */
-/* c [N*10], J [N*10*11], en [N*10], cT [3], JT [3*4]                                */
-int oracle_push_blocks(int32_t nseg, const int32_t *modes, const int32_t *knots, const double *x0,
+/* c [N*nr], J [N*nr*nv], en [N*nr], cT [3], JT [3*4]                                */
+int oracle_push_blocks(int32_t timed, int32_t nseg, const int32_t *modes, const int32_t *knots, const double *x0,
                        const double *goal, double mu, const double *z, double *c, double *J, int32_t *en,
                        double *cT, double *JT) {
   PushProb P;
   double cc[PNR], JJ[PNR][PNV], ct[PNT], Jt[PNT][PNX];
   int e[PNR], k, r, j;
-  if (!debug_setup(&P, nseg, modes, knots, x0, goal, mu)) return -1;
+  if (!debug_setup(&P, timed, nseg, modes, knots, x0, goal, mu)) return -1;
   for (k = 0; k < P.N; ++k) {
     stage_scaled(&P, z, k, cc, JJ, e);
-    for (r = 0; r < PNR; ++r) {
-      c[k * PNR + r] = cc[r];
-      en[k * PNR + r] = e[r];
-      for (j = 0; j < PNV; ++j) J[(k * PNR + r) * PNV + j] = JJ[r][j];
+    for (r = 0; r < P.nr; ++r) {
+      c[k * P.nr + r] = cc[r];
+      en[k * P.nr + r] = e[r];
+      for (j = 0; j < P.nv; ++j) J[(k * P.nr + r) * P.nv + j] = JJ[r][j];
     }
   }
   term_scaled(&P, z, ct, Jt);
@@ -921,10 +990,10 @@ int oracle_push_blocks(int32_t nseg, const int32_t *modes, const int32_t *knots,
   return P.N;
 }
 
-int oracle_push_score(int32_t nseg, const int32_t *modes, const int32_t *knots, const double *x0,
+int oracle_push_score(int32_t timed, int32_t nseg, const int32_t *modes, const int32_t *knots, const double *x0,
                       const double *goal, double mu, const double *z, double *J, double *v) {
   PushProb P;
-  if (!debug_setup(&P, nseg, modes, knots, x0, goal, mu)) return -1;
+  if (!debug_setup(&P, timed, nseg, modes, knots, x0, goal, mu)) return -1;
   score(&P, z, J, v);
   return P.N;
 }
