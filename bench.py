@@ -11,9 +11,10 @@ cores), times its training step and batched inference against the BF16 matrix-co
 and compares the device time to the first feasible plan of the plain and the learned
 expansion on held-out instances.
 
-The flipping leg times one round of the bimanual-flipping workload (32,768 orders).
+The flipping leg times one round of the bimanual-flipping workload (32,768 orders); the
+timed leg runs the headline orders with optimised timing (interval durations as controls).
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu] [--no-learned] [--no-flip]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu] [--no-learned] [--no-flip] [--no-timed]
 """
 from __future__ import annotations
 
@@ -42,23 +43,29 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X published FP64 vector peak
 # ~1.6, the 9 right-hand sides ~5.2, value function ~2.2, forward pass ~0.3, trial steps
 # ~1.2: ~10 kflop (FP64).
 FLIP_FLOP_PER_INTERVAL_GN = 10000.0
+# Pushing with optimised timing (8 stage unknowns, 12 row slots): the same count with the
+# duration column and the two bound rows: linearisation ~180, block assembly ~620 (the
+# squared row fill grows from 109 to 151 entries), 8x8 Cholesky ~200, gains ~640, value
+# update ~230, forward pass ~70 and ~130 per trial step length (8 trials): ~3.0 kflop.
+TIMED_FLOP_PER_INTERVAL_GN = 3000.0
 HBM_PEAK_GBS = 8000.0
 
 
-KERNEL_SOURCES = ["paper_2609_21803_amd/csrc/evaluator.hip", "paper_2609_21803_amd/csrc/push_model.h",
-                  "paper_2609_21803_amd/csrc/dmath.h"]
+KERNEL_SOURCES = ["paper_2609_21803_amd/csrc/evaluator.hip", "paper_2609_21803_amd/csrc/push_solver.inc",
+                  "paper_2609_21803_amd/csrc/push_model.h", "paper_2609_21803_amd/csrc/dmath.h"]
 PROFILE = os.path.join(ROOT, "profiles", "k_push_solve_push_plain_110592.txt")
+PROFILE_TIMED = os.path.join(ROOT, "profiles", "k_push_solve_timed_push_plain_110592.txt")
 
 
-def profiled_traffic():
+def profiled_traffic(path=PROFILE):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
     kernel sources changed after those counters were taken."""
     import hashlib
-    if not os.path.exists(PROFILE):
+    if not os.path.exists(path):
         return None
     h = hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read() for s in KERNEL_SOURCES)).hexdigest()
     fields = {}
-    for line in open(PROFILE):
+    for line in open(path):
         if ":" in line:
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip().split()[0] if v.strip() else ""
@@ -70,10 +77,11 @@ def profiled_traffic():
         return None
 
 
-def cpu_baseline(batch, seconds_target=15.0):
+def cpu_baseline(batch, seconds_target=15.0, timed=0):
     """Oracle (FP64, plain C, one sequence per thread over all host threads) on a
     strided sample of the workload; returns solves/s."""
     import oracle
+    prm = oracle.Params(timed=timed)
     n_threads = os.cpu_count() or 1
     B = len(batch["nseg"])
     f32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
@@ -83,14 +91,14 @@ def cpu_baseline(batch, seconds_target=15.0):
     sub = {k: v[idx] for k, v in batch.items()}
     t0 = time.perf_counter()
     oracle.evaluate(f32(sub["x0"]), f32(sub["goal"]), f32(sub["inst"]), sub["nseg"], sub["modes"], sub["knots"],
-                    nthreads=n_threads)
+                    params=prm, nthreads=n_threads)
     dt = time.perf_counter() - t0
     n2 = int(min(B, max(n, n * seconds_target / max(dt, 1e-3))))
     idx = np.linspace(0, B - 1, n2).astype(np.int64)
     sub = {k: v[idx] for k, v in batch.items()}
     t0 = time.perf_counter()
     oracle.evaluate(f32(sub["x0"]), f32(sub["goal"]), f32(sub["inst"]), sub["nseg"], sub["modes"], sub["knots"],
-                    nthreads=n_threads)
+                    params=prm, nthreads=n_threads)
     dt = time.perf_counter() - t0
     return dict(value=n2 / dt, unit="solves/s", cores=n_threads, kind="oracle",
                 sample=f"{n2} of {B} TOs, evenly strided over the batch, FP64, {n_threads} threads, {dt:.1f} s")
@@ -157,6 +165,47 @@ def flip_leg(native, I, torch, B=32768, cpu=True):
                         "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "kernel_ms": kms, "flop": flops}}
     if cpu:
         res["cpu_baseline"] = flip_cpu_baseline(b)
+    return res
+
+
+def timed_leg(native, I, torch, cpu=True):
+    """Pushing with optimised timing (interval durations as controls) on the headline
+    workload's orders: one launch after a warm-up launch, then two more for the kernel
+    average."""
+    b = I.push_plain()
+    B, N = len(b["nseg"]), 24
+    ctx = native.Context(max_batch=B, max_segments=6, max_intervals=N, task=native.TASK_PUSH_TIMED)
+    d = native.to_device(b)
+    out = ctx.evaluate(**d)
+    torch.cuda.synchronize()
+    ctx.check()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    out = ctx.evaluate(**d)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kms = [ctx.kernel_ms()]
+    for _ in range(2):
+        out = ctx.evaluate(**d)
+        torch.cuda.synchronize()
+        kms.append(ctx.kernel_ms())
+    kms = float(np.mean(kms))
+    st = out["stats"].cpu().numpy()
+    flops = float((st[:, 1].astype(np.float64) * N).sum()) * TIMED_FLOP_PER_INTERVAL_GN + \
+        float((st[:, 0].astype(np.float64) * N).sum()) * FLOP_PER_INTERVAL_AL
+    ach = flops / (kms * 1e-3) / 1e12
+    res = {"workload": "planar pushing with optimised timing (duration of every interval a control, "
+                       "0.02 <= h <= 0.2 s, time weight 0.01): the headline's 110,592 orders, 24 intervals, "
+                       "AL<=20 x GN<=10",
+           "value": B / (ms * 1e-3), "unit": "solves/s", "ms": ms,
+           "feasible_fraction": float(out["feasible"].float().mean().item()),
+           "mean_gn_iterations": float(st[:, 1].mean()), "mean_al_iterations": float(st[:, 0].mean()),
+           "roofline": {"bound": "alu", "kernel": "k_push_solve (timed)", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
+                        "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS, "kernel_ms": kms, "flop_per_launch": flops,
+                        "traffic": profiled_traffic(PROFILE_TIMED)}}
+    if cpu:
+        res["cpu_baseline"] = cpu_baseline(b, seconds_target=10.0, timed=1)
     return res
 
 
@@ -357,6 +406,7 @@ def main():
     ap.add_argument("--no-flip", action="store_true", help="skip the flipping leg")
     ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous-batch leg")
     ap.add_argument("--no-policies", action="store_true", help="skip the allocation-policy comparison")
+    ap.add_argument("--no-timed", action="store_true", help="skip the optimised-timing pushing leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -438,6 +488,8 @@ def main():
                      "kernel": "k_push_solve", "kernel_ms": kms, "flop_per_launch": flops},
         "wall_s_timed": wall,
     }
+    if not args.no_timed:
+        res["timed"] = timed_leg(native, I, torch, cpu=not args.no_cpu)
     if not args.no_hetero:
         res["hetero"] = hetero_leg(native, I, torch)
     if not args.no_flip:

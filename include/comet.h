@@ -40,9 +40,11 @@ typedef enum {
   COMET_ESTATE = -4  /* call not valid in the context's current state */
 } comet_status;
 
-/* Tasks: planar pushing (Sec. IV) and bimanual flipping of a box in a vertical plane
- * (Sec. V); their dimensions and layouts are given at comet_evaluate. */
-typedef enum { COMET_TASK_PUSH = 0, COMET_TASK_FLIP = 1 } comet_task;
+/* Tasks: planar pushing (Sec. IV) with a fixed step, bimanual flipping of a box in a
+ * vertical plane (Sec. V), and planar pushing with optimised timing (Sec. III-C: the
+ * interval durations become controls; Sec. IV-A runs pushing with an optimised time step
+ * under a duration bound); their dimensions and layouts are given at comet_evaluate. */
+typedef enum { COMET_TASK_PUSH = 0, COMET_TASK_FLIP = 1, COMET_TASK_PUSH_TIMED = 2 } comet_task;
 
 typedef struct comet_ctx comet_ctx; /* opaque */
 typedef struct comet_mlp comet_mlp; /* opaque: learned proposal / warm-start network */
@@ -92,7 +94,8 @@ comet_status comet_dims(const comet_ctx* ctx, int32_t* nx, int32_t* nu, int32_t*
                         int32_t* max_segments, int32_t* max_intervals, int64_t* max_batch);
 
 /* Row scales of the solver's internal constraint scaling (Sec. IV-A: each row type is
- * divided by its median Jacobian-row 2-norm over sample orders).  out: host, n >= 12.
+ * divided by its median Jacobian-row 2-norm over sample orders).  out: host, n >= 12
+ * (fixed-step pushing) or n >= 13 (optimised timing: type 12 is the duration bound).
  * Pushing contexts only (the flipping rows are stated non-dimensionally): COMET_EINVAL
  * otherwise. */
 comet_status comet_row_scales(const comet_ctx* ctx, double* out, int32_t n);
@@ -141,7 +144,15 @@ comet_status comet_check(comet_ctx* ctx, void* stream);
  *   rows are stated non-dimensionally (forces / mg, moments / (mg * 0.2 m)); viol is in
  *                  these units; cost = sum dt (0.01 |accel|^2 + sum |f_i|^2 / (mg)^2 +
  *                  0.01 sum sd_i^2)
- *   traj  [B, Nmax+1, 17] rows (x_k, u_k); warm likewise. */
+ *   traj  [B, Nmax+1, 17] rows (x_k, u_k); warm likewise.
+ *
+ * Pushing with optimised timing (COMET_TASK_PUSH_TIMED): the pushing task with the
+ * duration h_k of every interval as a fourth control, nu = 4 (F_n, F_t, v_s, h); every
+ * defect steps by h_k instead of 0.1 s, each interval carries the bounds
+ * 0.02 s <= h_k <= 0.2 s, and cost = sum h_k ((F_n^2 + F_t^2) / f_max^2 + (v_s / v_ref)^2
+ * + 0.01) charges the elapsed time; the schedule-derived start has h_k = 0.1 s.
+ *   traj  [B, Nmax+1, 8] rows (x_k, u_k); warm likewise.  The learned network serves the
+ *                  fixed-step tasks only. */
 comet_status comet_evaluate(comet_ctx* ctx, void* stream, int64_t B, const float* x0, const float* goal,
                             const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                             const float* warm, int32_t refine, float* cost, float* viol, uint8_t* feasible,

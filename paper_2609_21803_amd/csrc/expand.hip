@@ -747,7 +747,7 @@ comet_status check_expand_params(comet_ctx* c, const comet_expand_params* p) {
 comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
   const bool flip = (c->task == COMET_TASK_FLIP);
   const int M = flip ? 845 : push::NMODES;
-  const int rowW = flip ? 17 : 7;
+  const int rowW = flip ? 17 : (c->task == COMET_TASK_PUSH_TIMED ? 8 : 7);
   int raw1max = 0;
   for (int K = 1; K <= p->kcap; ++K) raw1max = std::max(raw1max, raw1_count(K, M, p->kcap));
   const long long rawmax = (p->radius >= 2) ? (long long)raw1max + (long long)raw1max * raw1max : raw1max;
@@ -1271,6 +1271,8 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
   const bool flip = (c->task == COMET_TASK_FLIP);
   if (learned && (mlp_max_batch(learned) < params->batch_B || mlp_in_dim(learned) < 400 || mlp_out_dim(learned) < 722))
     return fail_msg(c, COMET_EINVAL, "learned network: max_batch < batch_B, in_dim < 400 or out_dim < 722");
+  if (learned && c->task == COMET_TASK_PUSH_TIMED)
+    return fail_msg(c, COMET_EINVAL, "the learned network serves the fixed-step tasks only");
   if (learned && params->policy == COMET_POLICY_MCTS)
     return fail_msg(c, COMET_EINVAL, "the learned network ranks expansion or sampling batches, not MCTS");
   st = ensure_ws(c, params);

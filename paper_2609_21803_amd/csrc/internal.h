@@ -9,12 +9,11 @@
 
 namespace comet {
 
-using namespace push;
-
 constexpr int MAXSEG = 6;
 constexpr int MAXN = 512;
 constexpr int MAX_TRIALS = 16;
 constexpr int WAVE = 64;
+constexpr int MAX_TYPES = 16;   // row-scale types of any pushing model
 
 struct DevParams {
   int al_max, gn_max, chol_retries, ls_trials, max_rejects;
@@ -38,11 +37,11 @@ struct EvalArgs {
   uint8_t* feas;
   float* traj;
   int* stats;
-  double* zd;                     // [row][7][S]  (u_k, x_{k+1})
-  float* lam;                     // [row][5][S]
-  float* nu;                      // [row][5][S]
-  float* gains;                   // [row][35][S] (k, K row-major 7x4)
-  float* dz;                      // [row][7][S]
+  double* zd;                     // [row][NW][S]  (u_k, x_{k+1})
+  float* lam;                     // [row][NE][S]
+  float* nu;                      // [row][NI][S]
+  float* gains;                   // [row][NW + NW NX][S] (k, K row-major NW x NX)
+  float* dz;                      // [row][NW][S]
   uint8_t* code;                  // [row][S]
   const int64_t* Bdev;            // batch size read from device memory (graph capture), or null
   int inst_stride;                // 1: x0/goal/inst per sequence, 0: one instance for all
@@ -53,7 +52,7 @@ struct EvalArgs {
   unsigned long long* qhead;      // work-queue head
   unsigned* err;
   DevParams prm;
-  double inv_scale[NTYPES];
+  double inv_scale[MAX_TYPES];
 };
 
 // One evaluation launch: inputs, outputs and where the batch size lives.
@@ -85,7 +84,7 @@ struct comet_ctx {
   int64_t max_batch, S;
   int max_segments, max_intervals;
   int device;
-  double scale[comet::push::NTYPES];
+  double scale[comet::MAX_TYPES];
   double* zd = nullptr;
   float* lam = nullptr;
   float* nu = nullptr;

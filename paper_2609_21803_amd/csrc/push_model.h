@@ -32,7 +32,7 @@
 namespace comet {
 namespace push {
 
-constexpr int NX = 4, NU = 3, NW = 7, NV = 11, NR = 10, NE = 5, NT = 3;
+constexpr int NX = 4, NU = 3, NW = 7, NV = 11, NR = 10, NE = 5, NI = NR - NE, NT = 3;
 constexpr int NMODES = 12, NTYPES = 12, NGAIN = NW + NW * NX;
 constexpr double SIDE = 0.1, MASS = 1.0, GRAV = 9.81, MU_G = 0.5, VREF = 1.0, DT = 0.1, WV = 1.0;
 constexpr double FMAX = MU_G * MASS * GRAV;
@@ -160,5 +160,166 @@ __host__ __device__ inline double stage_cost(const double* u) {
 }
 constexpr double HF = DT * 2.0 / (FMAX * FMAX), HV = DT * 2.0 * WV / (VREF * VREF);
 
+// cost gradient added into the gradient over v, and the (constant) cost Hessian into the
+// lower triangle of the block over v
+__host__ __device__ inline void add_cost_grad(const double* u, double* h) {
+  h[VFN] += HF * u[0];
+  h[VFT] += HF * u[1];
+  h[VVS] += HV * u[2];
+}
+__host__ __device__ inline void add_cost_hess(const double* u, double (*G)[NV]) {
+  (void)u;
+  G[VFN][VFN] += HF;
+  G[VFT][VFT] += HF;
+  G[VVS][VVS] += HV;
+}
+
+// schedule-derived initial controls: normal force fn, tangential force on the cone edge
+// (sg = +-1 sliding, 0 sticking), no slip
+__host__ __device__ inline void initial_u(double fn, double sg, double mu, double* u) {
+  u[0] = fn;
+  u[1] = sg * mu * fn;
+  u[2] = 0.0;
+}
+
 }  // namespace push
+
+// --------------------------------------------------------------------------------------
+// Optimised timing (Sec. III-C: the interval durations become controls; the pushing
+// configuration of Sec. IV-A optimises the time step under a duration bound).  Readings:
+// the duration h_k of every interval is a fourth control, bounded per interval by
+// h_min <= h_k <= h_max, every defect steps by h_k instead of dt, and the objective
+// charges sum_k h_k [ (F_n^2 + F_t^2) / f_max^2 + w_v (v_s / v_ref)^2 + w_T ].  Its
+// Hessian model keeps the exact force/velocity block 2 h diag(...) (at max(h, h_min / 2))
+// and drops the (u, h) and (h, h) entries, with which the exact Hessian is indefinite;
+// the duration direction takes its curvature from the rows and the proximal term.
+// Rows 0..9 are those of the fixed-step model; rows 10, 11 are h - h_max <= 0 and
+// h_min - h <= 0.
+// --------------------------------------------------------------------------------------
+namespace push_timed {
+
+constexpr int NX = 4, NU = 4, NW = 8, NV = 12, NR = 12, NE = 5, NI = NR - NE, NT = 3;
+constexpr int NMODES = 12, NTYPES = 13, NGAIN = NW + NW * NX;
+using push::SIDE;
+using push::MASS;
+using push::GRAV;
+using push::MU_G;
+using push::VREF;
+using push::DT;
+using push::WV;
+using push::FMAX;
+using push::CLS;
+using push::K1;
+using push::KM;
+using push::HALF;
+using push::make_code;
+using push::face_dirs;
+constexpr double H_MIN = 0.02, H_MAX = 0.2, W_T = 0.01;
+
+// column indices of v = (x_k, u_k, x_{k+1}), u_k = (F_n, F_t, v_s, h)
+enum { VX = 0, VY, VTH, VS_, VFN, VFT, VVS, VH, VX1, VY1, VTH1, VS1 };
+// row types of the internal scaling: those of the fixed-step model, then the duration rows
+enum { T_DX, T_DY, T_DTH, T_DS, T_STICK, T_SLIDE, T_FN, T_CONE, T_SLIP, T_FACE, T_TXY, T_TTH, T_DUR };
+
+__host__ __device__ constexpr bool nz(int r, int i) {
+  return (r == 0) ? (i == VX || i == VTH || i == VFN || i == VFT || i == VH || i == VX1)
+       : (r == 1) ? (i == VY || i == VTH || i == VFN || i == VFT || i == VH || i == VY1)
+       : (r == 2) ? (i == VTH || i == VS_ || i == VFN || i == VFT || i == VH || i == VTH1)
+       : (r == 3) ? (i == VS_ || i == VVS || i == VH || i == VS1)
+       : (r == 4 || r == 6) ? (i == VFN || i == VFT || i == VVS)
+       : (r == 5) ? (i == VFN)
+       : (r == 7) ? (i == VFN || i == VFT)
+       : (r == 8 || r == 9) ? (i == VS1)
+       : (i == VH);
+}
+
+template <typename T>
+__host__ __device__ inline void rows_sc(const double* xk, const double* uk, const double* x1, int code, double mu,
+                                        double st, double ct, double* c, T (*J)[NV], int* en) {
+  const int face = code & 3, slip = (code >> 2) & 3, smask = (code >> 4) & 1;
+  const bool stick = (slip == 0);
+  const double sg = (slip == 1) ? 1.0 : ((slip == 2) ? -1.0 : 0.0);
+  double nx, ny;
+  face_dirs<double>(face, nx, ny);
+  const double tx = -ny, ty = nx;
+  const double s = xk[3], Fn = uk[0], Ft = uk[1], h = uk[3];
+  const double Fbx = -Fn * nx + Ft * tx, Fby = -Fn * ny + Ft * ty;
+  const double M = HALF * Ft + s * Fn;
+  const double xi_x = K1 * Fbx, xi_y = K1 * Fby, xi_t = KM * M;
+  const double vx = ct * xi_x - st * xi_y, vy = st * xi_x + ct * xi_y;
+  c[0] = (x1[0] - xk[0]) - h * vx;
+  c[1] = (x1[1] - xk[1]) - h * vy;
+  c[2] = (x1[2] - xk[2]) - h * xi_t;
+  c[3] = smask ? (x1[3] - xk[3]) - h * uk[2] : 0.0;
+  c[4] = stick ? uk[2] : uk[1] - sg * mu * uk[0];
+  c[5] = -uk[0];
+  c[6] = stick ? uk[1] - mu * uk[0] : -sg * uk[2];
+  c[7] = stick ? -uk[1] - mu * uk[0] : 0.0;
+  c[8] = x1[3] - HALF;
+  c[9] = -x1[3] - HALF;
+  c[10] = h - H_MAX;
+  c[11] = H_MIN - h;
+  en[0] = en[1] = en[2] = 1;
+  en[3] = smask;
+  en[4] = en[5] = en[6] = 1;
+  en[7] = stick ? 1 : 0;
+  en[8] = en[9] = en[10] = en[11] = 1;
+  if (J) {
+    const T k1 = T(K1), km = T(KM), hT = T(h), half = T(HALF);
+    const T stT = T(st), ctT = T(ct), nxT = T(nx), nyT = T(ny), txT = T(tx), tyT = T(ty);
+    const T muT = T(mu), sgT = T(sg), vxT = T(vx), vyT = T(vy), FnT = T(Fn), sT = T(s);
+    const T dvx_dFn = k1 * (ctT * (-nxT) - stT * (-nyT)), dvy_dFn = k1 * (stT * (-nxT) + ctT * (-nyT));
+    const T dvx_dFt = k1 * (ctT * txT - stT * tyT), dvy_dFt = k1 * (stT * txT + ctT * tyT);
+    J[0][VX] = T(-1); J[0][VTH] = hT * vyT; J[0][VFN] = -hT * dvx_dFn; J[0][VFT] = -hT * dvx_dFt;
+    J[0][VH] = -vxT; J[0][VX1] = T(1);
+    J[1][VY] = T(-1); J[1][VTH] = -hT * vxT; J[1][VFN] = -hT * dvy_dFn; J[1][VFT] = -hT * dvy_dFt;
+    J[1][VH] = -vyT; J[1][VY1] = T(1);
+    J[2][VTH] = T(-1); J[2][VS_] = -hT * km * FnT; J[2][VFN] = -hT * km * sT; J[2][VFT] = -hT * km * half;
+    J[2][VH] = -T(xi_t); J[2][VTH1] = T(1);
+    const T sm = smask ? T(1) : T(0);
+    J[3][VS_] = -sm; J[3][VVS] = -hT * sm; J[3][VH] = -sm * T(uk[2]); J[3][VS1] = sm;
+    J[4][VFN] = stick ? T(0) : -sgT * muT; J[4][VFT] = stick ? T(0) : T(1); J[4][VVS] = stick ? T(1) : T(0);
+    J[5][VFN] = T(-1);
+    J[6][VFN] = stick ? -muT : T(0); J[6][VFT] = stick ? T(1) : T(0); J[6][VVS] = stick ? T(0) : -sgT;
+    J[7][VFN] = stick ? -muT : T(0); J[7][VFT] = stick ? T(-1) : T(0);
+    J[8][VS1] = T(1);
+    J[9][VS1] = T(-1);
+    J[10][VH] = T(1);
+    J[11][VH] = T(-1);
+  }
+}
+
+template <typename T>
+__host__ __device__ inline void rows(const double* xk, const double* uk, const double* x1, int code, double mu,
+                                     double* c, T (*J)[NV], int* en) {
+  double st, ct;
+  sincos_d(xk[2], &st, &ct);
+  rows_sc<T>(xk, uk, x1, code, mu, st, ct, c, J, en);
+}
+
+__host__ __device__ inline int row_type(int r, bool stick) { return r >= 10 ? T_DUR : push::row_type(r, stick); }
+
+constexpr double CF = 1.0 / (FMAX * FMAX), CV = WV / (VREF * VREF);
+
+__host__ __device__ inline double stage_cost(const double* u) {
+  return u[3] * ((u[0] * u[0] + u[1] * u[1]) * CF + CV * u[2] * u[2] + W_T);
+}
+__host__ __device__ inline void add_cost_grad(const double* u, double* h) {
+  h[VFN] += 2.0 * CF * u[3] * u[0];
+  h[VFT] += 2.0 * CF * u[3] * u[1];
+  h[VVS] += 2.0 * CV * u[3] * u[2];
+  h[VH] += (u[0] * u[0] + u[1] * u[1]) * CF + CV * u[2] * u[2] + W_T;
+}
+__host__ __device__ inline void add_cost_hess(const double* u, double (*G)[NV]) {
+  const double he = fmax(u[3], 0.5 * H_MIN);
+  G[VFN][VFN] += 2.0 * CF * he;
+  G[VFT][VFT] += 2.0 * CF * he;
+  G[VVS][VVS] += 2.0 * CV * he;
+}
+__host__ __device__ inline void initial_u(double fn, double sg, double mu, double* u) {
+  push::initial_u(fn, sg, mu, u);
+  u[3] = DT;
+}
+
+}  // namespace push_timed
 }  // namespace comet
