@@ -34,6 +34,9 @@ namespace push {
 
 constexpr int NX = 4, NU = 3, NW = 7, NV = 11, NR = 10, NE = 5, NI = NR - NE, NT = 3;
 constexpr int NMODES = 12, NTYPES = 12, NGAIN = NW + NW * NX;
+// the forward sweep loads an interval's gains one interval ahead (they stay in registers
+// while the trial steps of the current interval run)
+constexpr bool PREFETCH_GAINS = true;
 constexpr double SIDE = 0.1, MASS = 1.0, GRAV = 9.81, MU_G = 0.5, VREF = 1.0, DT = 0.1, WV = 1.0;
 constexpr double FMAX = MU_G * MASS * GRAV;
 constexpr double CLS = SIDE * (1.4142135623730951 + 0.88137358701954305) / 6.0;  // sqrt2 + asinh(1)
@@ -200,6 +203,9 @@ namespace push_timed {
 
 constexpr int NX = 4, NU = 4, NW = 8, NV = 12, NR = 12, NE = 5, NI = NR - NE, NT = 3;
 constexpr int NMODES = 12, NTYPES = 13, NGAIN = NW + NW * NX;
+// the larger stage leaves no registers for gains in flight (prefetched, they spilled in
+// the trial loop and cost 20 % of the kernel time): they are loaded at use
+constexpr bool PREFETCH_GAINS = false;
 using push::SIDE;
 using push::MASS;
 using push::GRAV;
