@@ -163,3 +163,76 @@ def test_timed_row_scales_agree_with_oracle_and_learned_network_is_rejected(orc)
     prm = native.ExpandParams(kcap=2, rounds=1, knots_per_segment=5, batch_B=64, eval_budget=100, learned_warm=1)
     with pytest.raises(native.CometError):
         native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm, learned=mlp)
+
+
+def _refined_oracle_cost(x0, goal, inst, modes, knots_per_segment):
+    import oracle
+    K = len(modes)
+    r = oracle.evaluate(f32(x0[:1]), f32(goal[:1]), f32(inst[:1]), np.array([K]), np.array([list(modes) + [0] * (6 - K)]),
+                        np.array([[knots_per_segment] * K + [0] * (6 - K)]),
+                        params=oracle.Params(timed=1, **oracle.REFINE))
+    return r["feasible"][0], r["cost"][0]
+
+
+def test_timed_uniform_sampling_search_matches_oracle(orc):
+    """The ablation's uniform sampling over the timed evaluator: the sampled batches are the
+    oracle's bit for bit, the counts of evaluated and feasible orders agree, and the returned
+    plan is the oracle's (or a near tie) and re-solves to the same cost."""
+    import oracle
+    import torch
+    from oracle import sample as S
+    from paper_2609_21803_amd import native
+    x0, goal, inst = I.push_pairs(9100, 1)
+    ep = dict(kcap=3, rounds=2, knots_per_segment=8, k_ref=16, batch_B=512, eval_budget=1536)
+    ctx = native.Context(max_batch=512, max_segments=6, max_intervals=24, task=native.TASK_PUSH_TIMED)
+    prm = native.ExpandParams(**ep, policy=native.POLICY_UNIFORM, sample_seed=31, sample_draws=4096)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+    o, st = native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm)
+    torch.cuda.synchronize()
+    keys = native.expand_trace(ctx)[0].cpu().numpy().view(np.uint64)
+    bk, bJ, bv, okeys, J, v = S.uniform_search(0, f32(x0[0]), f32(goal[0]), f32(inst[0]), ep["kcap"], ep["rounds"],
+                                               ep["batch_B"], ep["eval_budget"], 4096, 31, ep["knots_per_segment"],
+                                               ep["k_ref"], params=oracle.Params(timed=1))
+    K = int(o["nseg"].item())
+    m = list(o["modes"].cpu().numpy()[:K])
+    print("timed uniform: device", st, m, float(o["cost"].item()), "oracle", S.key_modes(bk), bJ,
+          "oracle feasible", int((v <= EPS).sum()), flush=True)
+    assert np.array_equal(keys, np.array(okeys, np.uint64)) and st["evaluated"] == len(okeys)
+    # feasible flags of the same orders agree up to the timed task's sensitivity (the oracle
+    # itself moves on 1.2 % of margin orders under a one-ulp goal change)
+    assert abs(st["n_feasible"] - int((v <= EPS).sum())) <= max(3, 0.015 * len(okeys))
+    feas, cost = _refined_oracle_cost(x0, goal, inst, m, 8)
+    assert K >= 1 and feas == 1 and abs(cost - float(o["cost"].item())) <= 1e-4 * abs(cost)
+    if S.key_modes(bk) != m:
+        assert abs(bJ - float(o["cost"].item())) <= 1e-3 * abs(bJ)
+
+
+def test_timed_mcts_search_plan_confirmed_by_oracle(orc):
+    """MCTS (reward J_best / J) over the timed evaluator: distinct orders within the budget,
+    the oracle's first batch, and a returned plan the timed oracle re-solves to the same
+    cost; the oracle's own search returns a plan of comparable cost."""
+    import oracle
+    import torch
+    from oracle import mcts as T
+    from oracle.sample import key_modes
+    from paper_2609_21803_amd import native
+    x0, goal, inst = I.push_pairs(9100, 1)
+    ep = dict(kcap=3, knots_per_segment=8, k_ref=32, batch_B=64, eval_budget=1500)
+    ctx = native.Context(max_batch=64, max_segments=6, max_intervals=24, task=native.TASK_PUSH_TIMED)
+    prm = native.ExpandParams(**ep, policy=native.POLICY_MCTS, sample_seed=7)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+    o, st = native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm)
+    torch.cuda.synchronize()
+    keys = native.expand_trace(ctx)[0].cpu().numpy().view(np.uint64)
+    bk, bJ, bv, okeys, J, v, nb, _ = T.mcts_search(0, f32(x0[0]), f32(goal[0]), f32(inst[0]), ep["kcap"], ep["batch_B"],
+                                                   ep["eval_budget"], 7, ep["knots_per_segment"], ep["k_ref"],
+                                                   params=oracle.Params(timed=1))
+    K = int(o["nseg"].item())
+    m = list(o["modes"].cpu().numpy()[:K])
+    print("timed mcts: device", st, m, float(o["cost"].item()), "oracle", len(okeys), nb, key_modes(bk), bJ, flush=True)
+    assert len(keys) == st["evaluated"] <= ep["eval_budget"] and len(set(keys.tolist())) == len(keys)
+    fb = T.first_batch(0, ep["kcap"], ep["batch_B"], 7)
+    assert np.array_equal(keys[:len(fb)], np.array(fb, np.uint64))
+    feas, cost = _refined_oracle_cost(x0, goal, inst, m, 8)
+    assert K >= 1 and feas == 1 and abs(cost - float(o["cost"].item())) <= 1e-4 * abs(cost)
+    assert bk != 0 and abs(bJ - float(o["cost"].item())) <= 0.05 * abs(bJ)
