@@ -21,6 +21,7 @@ namespace comet {
 
 typedef unsigned short bf16;
 typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(short)))) short bf16x4;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int WS_SLOTS = 15, WS_CH = 8;
@@ -67,11 +68,13 @@ struct Epi {
   const float* zprev;  // pre-activation of the layer below (EPI_DX)
   long ldc;            // row stride of the outputs
   long slab;           // EPI_PARTIAL: elements between the partial-sum slabs
+  bf16* ht;            // optional (EPI_HIDDEN, EPI_DX): the BF16 output again, transposed: ht[n * ldt + m]
+  long ldt;            // row stride of ht (a multiple of 4)
 };
 
 constexpr int GBM = 128, GBN = 64, GBK = 32, GLD = GBK + 8;   // LDS row: 32 bf16 + 8 pad (80 bytes)
 constexpr int MAX_SPLIT = 32;      // contraction splits of a weight-gradient GEMM
-constexpr int COLSUM_ROWS = 64;    // partial rows of the bias-gradient column sums
+constexpr int COLSUM_ROWS = 256;   // partial rows of the bias-gradient column sums
 
 // One operand tile of R rows (m or n) x GBK (k) into registers.  K-contiguous: vector v
 // covers row v/4, k = (v%4)*8 .. +8.  Row-contiguous: vector v covers k = v/(R/8),
@@ -169,31 +172,80 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
   }
   // accumulator layout: lane holds rows 4*(lane/16) + r, column lane%16 of each 16x16 tile
   float* zo = ep.z + (EPI == EPI_PARTIAL ? (long)blockIdx.z * ep.slab : 0L);
+  constexpr bool TR = (EPI == EPI_HIDDEN || EPI == EPI_DX);
+  // transposed tile [n - n0][m - m0] over the operand ring (the loop's last barrier has
+  // passed, so no wave still reads it)
+  static_assert(GBN * (GBM + 8) <= 2 * GBM * GLD, "transposed tile exceeds the A ring");
+  bf16 (*Tt)[GBM + 8] = reinterpret_cast<bf16 (*)[GBM + 8]>(&As[0][0][0]);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 2; ++j) {
+      const int mb = m0 + wm * 64 + i * 16 + (lane >> 4) * 4;
+      const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+      if (n >= N) continue;
+      bf16x4 tv = bf16x4{0, 0, 0, 0};
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + r;
-        const int n = n0 + wn * 32 + j * 16 + (lane & 15);
-        if (m >= M || n >= N) continue;
+        const int m = mb + r;
+        if (m >= M) continue;
         const float v = acc[i][j][r];
         const long o = (long)m * ep.ldc + n;
         if (EPI == EPI_HIDDEN) {
           const float z = v + ep.bias[n];
           zo[o] = z;
-          ep.h[o] = to_bf16(gelu(z));
+          const bf16 hb = to_bf16(gelu(z));
+          ep.h[o] = hb;
+          tv[r] = (short)hb;
         } else if (EPI == EPI_OUT) {
           zo[o] = v + ep.bias[n];
         } else if (EPI == EPI_DX) {
           const float d = v * gelu_grad(ep.zprev[o]);
           zo[o] = d;
-          ep.h[o] = to_bf16(d);
+          const bf16 hb = to_bf16(d);
+          ep.h[o] = hb;
+          tv[r] = (short)hb;
         } else {
           zo[o] = v;
         }
       }
+      // the transposed copy is staged in LDS (the operand ring is free after the last step)
+      if (TR && ep.ht) *reinterpret_cast<bf16x4*>(&Tt[n - n0][mb - m0]) = tv;
+    }
+  if (TR && ep.ht) {
+    // write the 64 x 128 transposed block tile row by row, 16 bytes per thread and chunk
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < GBN * GBM / 8 / 256; ++c) {
+      const int id = t + 256 * c, row = id / (GBM / 8), col = (id % (GBM / 8)) * 8;
+      const int n = n0 + row, m = m0 + col;
+      if (n >= N || m >= M) continue;
+      bf16* q = ep.ht + (long)n * ep.ldt + m;
+      if (m + 7 < M) {
+        *reinterpret_cast<bf16x8*>(q) = *reinterpret_cast<const bf16x8*>(&Tt[row][col]);
+      } else {
+        for (int r = 0; r < M - m; ++r) q[r] = Tt[row][col + r];
+      }
+    }
+  }
+}
+
+// out[c * ldo + r] = in[r * ldi + c] for a rows x cols BF16 matrix, through 64 x 64 LDS tiles
+__global__ __launch_bounds__(256) void k_transpose_bf16(const bf16* __restrict__ in, long ldi, int rows, int cols,
+                                                        bf16* __restrict__ out, long ldo) {
+  __shared__ bf16 tile[64][66];
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64, tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int r = r0 + ty + 4 * k, c = c0 + tx;
+    if (r < rows && c < cols) tile[ty + 4 * k][tx] = in[(long)r * ldi + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int c = c0 + ty + 4 * k, r = r0 + tx;
+    if (r < rows && c < cols) out[(long)c * ldo + r] = tile[tx][ty + 4 * k];
+  }
 }
 
 // sum of S partial-sum slabs of n floats each
@@ -205,9 +257,25 @@ __global__ void k_sum_slabs(const float* __restrict__ part, int S, long n, float
   out[i] = s;
 }
 
+// out[i] = sum_z part[z * n + i] for many slabs S: 64 columns per block, the slabs split
+// over 4 thread phases (deterministic order: each phase in slab order, then phase order)
+__global__ __launch_bounds__(256) void k_sum_rows(const float* __restrict__ part, int S, long n,
+                                                  float* __restrict__ out) {
+  __shared__ float red[4][64];
+  const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const long i = (long)blockIdx.x * 64 + c;
+  float s = 0.f;
+  if (i < n)
+#pragma unroll 8
+    for (int z = ph; z < S; z += 4) s += part[(long)z * n + i];
+  red[ph][c] = s;
+  __syncthreads();
+  if (ph == 0 && i < n) out[i] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+}
+
 // column sums of an FP32 [M][N] matrix (bias gradients), in two deterministic stages:
 // block (x, y) covers 256 columns (64 threads x 4 consecutive columns, 16-byte loads) and
-// rows y*4 + phase + k * gridDim.y * 4 (4 row phases), writing part[y][n]; k_sum_slabs then
+// rows y*4 + phase + k * gridDim.y * 4 (4 row phases), writing part[y][n]; k_sum_rows then
 // adds the gridDim.y partial rows.  N must be a multiple of 4.
 __global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ X, int M, int N,
                                                      float* __restrict__ part) {
@@ -603,6 +671,11 @@ struct comet_mlp {
   float *cnt = nullptr, *lossd = nullptr;
   float* part = nullptr;               // partial sums: split weight gradients / bias column sums
   float* red = nullptr;                // per-block partials of the loss reductions [LOSS_BLOCKS][4]
+  // batch-contiguous BF16 copies for the weight-gradient products (training, B % 8 == 0):
+  // HT[l] = H[l]^T [K_l][ldt], GT = the current layer's output gradient transposed [N][ldt]
+  std::vector<bf16*> HT;
+  bf16* GT = nullptr;
+  long ldt = 0;
   long long step = 0;
 };
 
@@ -647,8 +720,13 @@ void refresh_weights(comet_mlp* m, hipStream_t s) {
 
 namespace comet {
 
+void mlp_forward_t(comet_mlp* m, hipStream_t s, int B, const long long* B_dev, bool keep_transposed);
+
 // forward for B rows of m->H[0] (at most *B_dev rows if given); Y filled.
-void mlp_forward(comet_mlp* m, hipStream_t s, int B, const long long* B_dev) {
+void mlp_forward(comet_mlp* m, hipStream_t s, int B, const long long* B_dev) { mlp_forward_t(m, s, B, B_dev, false); }
+
+// forward; with keep_transposed the hidden activations are also written transposed (HT)
+void mlp_forward_t(comet_mlp* m, hipStream_t s, int B, const long long* B_dev, bool keep_transposed) {
   for (int l = 0; l < m->nl; ++l) {
     const int K = m->K[l], N = m->N[l];
     Epi ep{};
@@ -658,6 +736,10 @@ void mlp_forward(comet_mlp* m, hipStream_t s, int B, const long long* B_dev) {
     if (l < m->nl - 1) {
       ep.z = m->Z[l];
       ep.h = m->H[l + 1];
+      if (keep_transposed) {
+        ep.ht = m->HT[l + 1];
+        ep.ldt = m->ldt;
+      }
       gemm<true, true, EPI_HIDDEN>(s, B, N, K, m->H[l], K, Wl, K, ep, B_dev);
     } else {
       ep.z = m->Y;
@@ -745,6 +827,10 @@ comet_status comet_mlp_create(int32_t in_dim, int32_t hidden, int32_t layers, in
   A((void**)&m->dZ, 4 * B * hidden);
   A((void**)&m->dZb[0], 2 * B * std::max(hidden, out_dim));
   A((void**)&m->dZb[1], 2 * B * std::max(hidden, out_dim));
+  m->ldt = (long)((B + 7) / 8 * 8);
+  m->HT.assign(m->nl, nullptr);
+  for (int l = 0; l < m->nl; ++l) A((void**)&m->HT[l], 2 * (size_t)m->K[l] * m->ldt);
+  A((void**)&m->GT, 2 * (size_t)std::max(hidden, out_dim) * m->ldt);
   A((void**)&m->cnt, 4 * 4);
   A((void**)&m->lossd, 4 * 4);
   {
@@ -785,6 +871,8 @@ void comet_mlp_destroy(comet_mlp* m) {
                            m->cnt, m->lossd, m->part, m->red};
   for (auto* h : m->H) ps.push_back(h);
   for (auto* z : m->Z) ps.push_back(z);
+  for (auto* h : m->HT) ps.push_back(h);
+  ps.push_back(m->GT);
   for (void* p : ps)
     if (p) (void)hipFree(p);
   delete m;
@@ -837,12 +925,24 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
   hipStream_t s = (hipStream_t)stream;
   const int Bi = (int)B, O = m->out_dim, Wn = 6 * WS_SLOTS * WS_CH;
   if (hipMemcpyAsync(m->H[0], x_bf16, 2 * B * m->in_dim, hipMemcpyDeviceToDevice, s) != hipSuccess) return COMET_EHIP;
-  mlp_forward(m, s, Bi, nullptr);
+  // With B a multiple of 8 the weight gradients contract over batch-contiguous copies of
+  // their operands (16-byte loads straight into the matrix-core tiles): the hidden
+  // activations and the hidden gradients are written transposed by the epilogues that
+  // produce them, the input and the output gradient by k_transpose_bf16.  Otherwise the
+  // products read the row-major tensors and transpose through LDS.
+  const bool tr = (Bi % 8 == 0);
+  if (tr)
+    hipLaunchKernelGGL(k_transpose_bf16, dim3(nblk(m->in_dim, 64), nblk(Bi, 64)), dim3(256), 0, s, m->H[0],
+                       (long)m->in_dim, Bi, m->in_dim, m->HT[0], m->ldt);
+  mlp_forward_t(m, s, Bi, nullptr, tr);
   hipLaunchKernelGGL(k_loss_counts, dim3(LOSS_BLOCKS), dim3(256), 0, s, Bi, Wn, y_feas, traj_mask, m->red);
   hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, m->red, LOSS_BLOCKS, 2, m->cnt);
   hipLaunchKernelGGL(k_loss_grad, dim3(LOSS_BLOCKS), dim3(256), 0, s, Bi, O, Wn, m->Y, y_feas, y_cost, y_traj,
                      traj_mask, m->cnt, m->dY, m->dYb, m->red);
   hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, m->red, LOSS_BLOCKS, 3, m->lossd);
+  if (tr)
+    hipLaunchKernelGGL(k_transpose_bf16, dim3(nblk(O, 64), nblk(Bi, 64)), dim3(256), 0, s, m->dYb, (long)O, Bi, O,
+                       m->GT, m->ldt);
   // backward through the linear layers
   const bf16* g = m->dYb;
   const float* g32 = m->dY;
@@ -856,12 +956,13 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
     ew.z = m->part;
     ew.ldc = K;
     ew.slab = (long)N * K;
-    const int nzs = gemm<false, false, EPI_PARTIAL>(s, N, K, Bi, g, N, m->H[l], K, ew, nullptr, split);
+    const int nzs = tr ? gemm<true, true, EPI_PARTIAL>(s, N, K, Bi, m->GT, m->ldt, m->HT[l], m->ldt, ew, nullptr, split)
+                       : gemm<false, false, EPI_PARTIAL>(s, N, K, Bi, g, N, m->H[l], K, ew, nullptr, split);
     hipLaunchKernelGGL(k_sum_slabs, dim3(nblk((long long)N * K, 256)), dim3(256), 0, s, m->part, nzs, (long)N * K,
                        m->G + m->woff[l]);
-    const int ry = std::max(1, std::min(COLSUM_ROWS, (Bi + 255) / 256));
+    const int ry = std::max(1, std::min(COLSUM_ROWS, (Bi + 31) / 32));
     hipLaunchKernelGGL(k_colsum_part, dim3(nblk(N, 256), ry), dim3(256), 0, s, g32, Bi, N, m->part);
-    hipLaunchKernelGGL(k_sum_slabs, dim3(nblk(N, 256)), dim3(256), 0, s, m->part, ry, (long)N, m->G + m->boff[l]);
+    hipLaunchKernelGGL(k_sum_rows, dim3(nblk(N, 64)), dim3(256), 0, s, m->part, ry, (long)N, m->G + m->boff[l]);
     if (l > 0) {
       // dZ_{l-1} [B][K] = (G [B][N] . W_l [N][K]) * gelu'(Z_{l-1}), W_l read through its
       // transpose so both operands are contraction-contiguous
@@ -870,6 +971,10 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
       ex.h = m->dZb[cur];
       ex.zprev = m->Z[l - 1];
       ex.ldc = K;
+      if (tr) {   // the next layer's weight gradient reads it transposed (its own product above is done)
+        ex.ht = m->GT;
+        ex.ldt = m->ldt;
+      }
       gemm<true, true, EPI_DX>(s, Bi, K, N, g, N, m->WT + m->wboff[l], N, ex);
       g = m->dZb[cur];
       g32 = m->dZ;

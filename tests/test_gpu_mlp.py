@@ -46,9 +46,12 @@ def test_forward_matches_oracle():
     assert _rel(Y, Yo) <= 3e-3, _rel(Y, Yo)
 
 
-def test_gradients_and_adamw_step_match_oracle():
+@pytest.mark.parametrize("B", [512, 300])
+def test_gradients_and_adamw_step_match_oracle(B):
+    """B = 512 takes the weight-gradient products over transposed batch-contiguous copies,
+    B = 300 (not a multiple of 8) the row-major operands."""
     from oracle.mlp import Net
-    net, flat, X, yf, yc, yt, mask, m, xb, t = _net_and_data(B=512, seed=7)
+    net, flat, X, yf, yc, yt, mask, m, xb, t = _net_and_data(B=B, seed=7)
     loss = m.train_step(xb, t(yf), t(yc), t(yt), t(mask), lr=1e-3, weight_decay=1e-4).cpu().numpy()
     g = m.grads().cpu().numpy().astype(np.float64)
     p1 = m.get_params().cpu().numpy().astype(np.float64)
