@@ -83,6 +83,28 @@ def test_timed_tiny_workload_matches_oracle(orc):
     assert np.median(np.abs(g["traj"][i, :10, 7] - o["traj"][i, :10, 7])) <= 1e-4
 
 
+def test_timed_warm_start_matches_oracle_with_same_warm_start(orc):
+    """A warm start (rows (x_k, u_k) with the durations in column 7) replaces the
+    schedule-derived primal; both sides start from the same float32 trajectory, the oracle's
+    solution, with the tight warm-start penalty.  Also run at the refinement budget."""
+    import oracle
+    import torch
+    from paper_2609_21803_amd import native
+    b = I.subset(I.push_tiny(), np.arange(0, 1152, 7))
+    o = run_oracle(b, 10)
+    warm = o["traj"].astype(np.float32)
+    assert warm.shape[-1] == 8
+    for refine, prm in ((0, oracle.Params(timed=1)), (1, oracle.Params(timed=1, **oracle.REFINE))):
+        B = len(b["nseg"])
+        ctx = native.Context(max_batch=B, max_segments=6, max_intervals=10, task=native.TASK_PUSH_TIMED)
+        out = ctx.evaluate(**native.to_device(b), warm=torch.as_tensor(warm).cuda(), refine=refine)
+        torch.cuda.synchronize()
+        g = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+        o2 = oracle.evaluate(f32(b["x0"]), f32(b["goal"]), f32(b["inst"]), b["nseg"], b["modes"], b["knots"],
+                             params=prm, nmax=10, warm=warm.astype(np.float64))
+        compare(g, o2, f"timed warm, refine={refine}", 0.97)
+
+
 def test_timed_ragged_batch_matches_oracle(orc):
     """Uneven segment counts (1..5) and interval counts (5..15 per segment) in one launch."""
     b = I.push_hetero(B=1024, seed=91)
