@@ -126,8 +126,16 @@ __host__ __device__ inline bool flip_admissible_key(unsigned long long k) {
   return true;
 }
 
+// Table slot of a key.  Keys carry their information in the high bits (segment count and
+// the leading ids), so the slot must depend on every bit: the 64-bit finaliser of
+// MurmurHash3 (Appleby) mixes them into the low bits the mask keeps.
 __device__ inline unsigned long long hash_slot(unsigned long long k, unsigned long long mask) {
-  return (k * 0x9E3779B97F4A7C15ull) >> 17 & mask;
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k & mask;
 }
 
 __device__ inline void set_insert(unsigned long long* tab, unsigned long long mask, unsigned long long k) {

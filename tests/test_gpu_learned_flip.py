@@ -3,8 +3,9 @@ flipping results (seed orders and their one-edit neighbours on pivot-reachable g
 ranks and warm-starts the expansion's first batch, all admissible orders of one and two
 segments.  Asserted: the returned plan costs match the plain planner's, the first
 feasible order moves to the front of the evaluation order, and the device time to the
-first feasible plan is not longer with the network than without it (the solves are
-latency-bound there, so the gain comes from the warm starts alone)."""
+first feasible plan drops below 0.9 of the plain planner's (about half in the bench's
+identical comparison: the ranking puts a feasible order at the head of the queue and its
+warm start shortens the solve)."""
 import numpy as np
 import pytest
 
@@ -52,6 +53,6 @@ def test_learned_flip_expansion_keeps_the_plan_and_finds_a_feasible_order_first(
     print("TTFP ratios learned/plain", ratios, "first feasible index (plain, learned)", first.tolist(),
           "identical orders", same_modes)
     assert np.median(first[:, 1]) < np.median(first[:, 0])
-    # the solves are latency-bound here: the gain is the warm start's (about 5 % with the
-    # current solver), so the bar is that the learned planner is not slower
-    assert np.median(ratios) < 1.0
+    # the learned ranking puts a feasible order first and its warm start shortens the solve
+    # (median ratio about 0.5 in the bench's identical comparison)
+    assert np.median(ratios) < 0.9
