@@ -55,15 +55,17 @@ KERNEL_SOURCES = ["paper_2609_21803_amd/csrc/evaluator.hip", "paper_2609_21803_a
                   "paper_2609_21803_amd/csrc/push_model.h", "paper_2609_21803_amd/csrc/dmath.h"]
 PROFILE = os.path.join(ROOT, "profiles", "k_push_solve_push_plain_110592.txt")
 PROFILE_TIMED = os.path.join(ROOT, "profiles", "k_push_solve_timed_push_plain_110592.txt")
+FLIP_SOURCES = ["paper_2609_21803_amd/csrc/flip.hip", "paper_2609_21803_amd/csrc/dmath.h"]
+PROFILE_FLIP = os.path.join(ROOT, "profiles", "k_flip_solve_flip_32768.txt")
 
 
-def profiled_traffic(path=PROFILE):
+def profiled_traffic(path=PROFILE, sources=KERNEL_SOURCES):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
     kernel sources changed after those counters were taken."""
     import hashlib
     if not os.path.exists(path):
         return None
-    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read() for s in KERNEL_SOURCES)).hexdigest()
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read() for s in sources)).hexdigest()
     fields = {}
     for line in open(path):
         if ":" in line:
@@ -162,7 +164,8 @@ def flip_leg(native, I, torch, B=32768, cpu=True):
            "value": B / (ms * 1e-3), "unit": "solves/s", "ms": ms, "mean_gn_iterations": float(st[:, 1].mean()),
            "mean_intervals": float(N.mean()), "feasible_fraction": float(out["feasible"].float().mean().item()),
            "roofline": {"bound": "alu", "kernel": "k_flip_solve", "achieved": ach, "peak": PEAK_FP64_TFLOPS,
-                        "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "kernel_ms": kms, "flop": flops}}
+                        "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "kernel_ms": kms, "flop": flops,
+                        "traffic": profiled_traffic(PROFILE_FLIP, FLIP_SOURCES)}}
     if cpu:
         res["cpu_baseline"] = flip_cpu_baseline(b)
     return res
