@@ -231,3 +231,44 @@ def test_fixed_step_plans_rescore_as_timed_plans_and_timed_plans_respect_the_bou
             z[k * 8 + 4:k * 8 + 8] = rt["traj"][i, k + 1, 0:4]
         J, v = seq(i).score(z)
         assert abs(J - rt["cost"][i]) <= 1e-12 * max(1.0, abs(J)) and v == rt["viol"][i]
+
+
+@pytest.mark.parametrize("modes,knots,goal", [((6, 7), (4, 4), (0.1, 0.0, 0.2)), ((6,), (10,), (0.15, 0.02, 0.1))])
+def test_timed_converged_solve_is_a_kkt_point_for_slsqp(orc, modes, knots, goal):
+    """An independent NLP solver (scipy SLSQP) started at the timed oracle's solution finds
+    no better feasible point of the same transcription (Eq. 2 with the durations as
+    controls) nearby.  The tight solve ends feasible at its iteration budget rather than at
+    the 1e-11 stationarity test: spreading the elapsed time differently over intervals that
+    move at the same speed leaves the cost unchanged, and that flat direction slows the
+    last digits of the stationarity measure."""
+    from scipy.optimize import minimize
+    N = sum(knots)
+    S = orc.Seq(list(modes), list(knots), goal=goal, mu=0.4, timed=1)
+    ma = np.zeros((1, 6), np.int32)
+    ka = np.zeros((1, 6), np.int32)
+    ma[0, :len(modes)] = modes
+    ka[0, :len(knots)] = knots
+    r = orc.evaluate(np.zeros((1, 4)), np.array([goal]), np.array([[0.4]]), np.array([len(modes)]), ma, ka,
+                     params=orc.Params(timed=1, **TIGHT))
+    print("oracle", r["cost"][0], r["viol"][0], r["stats"][0])
+    assert r["feasible"][0] == 1
+    z0 = np.zeros(N * 8)
+    for k in range(N):
+        z0[k * 8:k * 8 + 4] = r["traj"][0, k, 4:8]
+        z0[k * 8 + 4:k * 8 + 8] = r["traj"][0, k + 1, 0:4]
+
+    def eqs(z):
+        c, J, en, cT, JT = S.blocks(z)
+        return np.concatenate([c[:, :5][en[:, :5] == 1], cT])
+
+    def ineqs(z):
+        c, J, en, cT, JT = S.blocks(z)
+        return -c[:, 5:][en[:, 5:] == 1]
+
+    obj = lambda z: S.score(z)[0]
+    res = minimize(obj, z0, method="SLSQP", constraints=[dict(type="eq", fun=eqs), dict(type="ineq", fun=ineqs)],
+                   options=dict(ftol=1e-14, maxiter=200))
+    Jr, vr = S.score(res.x)
+    print("slsqp", Jr, vr, res.message)
+    assert abs(r["cost"][0] - obj(z0)) < 1e-12
+    assert not (vr <= 1e-8 and Jr < r["cost"][0] - 1e-6), (Jr, r["cost"][0])
