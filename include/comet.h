@@ -282,7 +282,7 @@ typedef struct {
  * (device): best_nseg [1] (0 = no feasible plan), best_modes / best_knots [max_segments],
  * best_cost / best_viol [1] (refined), best_traj [max_intervals+1, nx+nu] or NULL.
  * learned: NULL for the plain method, else a proposal network that ranks generated
- * neighbours and seeds their initial trajectories (the plain refinement judges every plan).
+ * neighbours and seeds their initial trajectories (the plain refinement re-solves every plan).
  * EINVAL on inconsistent parameters (see comet_expand_params), ENOMEM if the work space
  * (|V| <= eval_budget + batch_B, frontier_W x neighbourhood candidates <= 2^27) does not fit. */
 comet_status comet_expand(comet_ctx* ctx, void* stream, const float* x0, const float* goal, const float* inst,
