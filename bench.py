@@ -102,7 +102,7 @@ def cpu_baseline(batch, seconds_target=15.0, timed=0):
     oracle.evaluate(f32(sub["x0"]), f32(sub["goal"]), f32(sub["inst"]), sub["nseg"], sub["modes"], sub["knots"],
                     params=prm, nthreads=n_threads)
     dt = time.perf_counter() - t0
-    return dict(value=n2 / dt, unit="solves/s", cores=n_threads, kind="oracle",
+    return dict(value=n2 / dt, unit="solves/s", cores=n_threads, kind="oracle", value_per_core=n2 / dt / n_threads,
                 sample=f"{n2} of {B} TOs, evenly strided over the batch, FP64, {n_threads} threads, {dt:.1f} s")
 
 
@@ -136,7 +136,7 @@ def flip_cpu_baseline(batch, seconds_target=10.0):
     dt = run(n)
     n2 = int(min(B, max(n, n * seconds_target / max(dt, 1e-3))))
     dt = run(n2)
-    return dict(value=n2 / dt, unit="solves/s", cores=n_threads, kind="oracle",
+    return dict(value=n2 / dt, unit="solves/s", cores=n_threads, kind="oracle", value_per_core=n2 / dt / n_threads,
                 sample=f"{n2} of {B} orders, evenly strided over the round, FP64, {n_threads} threads, {dt:.1f} s")
 
 
@@ -423,6 +423,7 @@ def main():
     from paper_2609_21803_amd import native
 
     torch.cuda.set_device(0)
+    peaks = native.probe_peaks()        # the device's measured rates, beside the published peaks
     batch = I.push_plain()
     B = len(batch["nseg"])
     N = 24
@@ -488,7 +489,17 @@ def main():
         "mean_al_iterations": float(stats[:, 0].mean()),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": profiled_traffic(),
-                     "kernel": "k_push_solve", "kernel_ms": kms, "flop_per_launch": flops},
+                     "kernel": "k_push_solve", "kernel_ms": kms, "flop_per_launch": flops,
+                     "frac_nonpacked": achieved / PEAK_FP64_TFLOPS,
+                     "hbm_gbs": (profiled_traffic() / (kms * 1e-3) / 1e9) if profiled_traffic() else None},
+        "gn_histogram": {"bin_edges": list(range(0, 221, 20)),
+                         "counts": np.histogram(stats[:, 1], bins=list(range(0, 221, 20)))[0].tolist()},
+        "al_histogram": {"al_iterations": list(range(1, 21)),
+                         "counts": np.bincount(np.clip(stats[:, 0], 0, 20), minlength=21)[1:].tolist()},
+        "peaks_measured": {**peaks, "note": "microbenchmarks on this device (non-packed FP32 FMA chains, FP64 FMA "
+                                            "chains, register-resident BF16 matrix-core products, 1 GiB copy); "
+                                            "published: FP32 157.3, FP64 78.6, dense BF16 2500 TFLOP/s, "
+                                            "HBM 8000 GB/s"},
         "wall_s_timed": wall,
     }
     if not args.no_timed:

@@ -85,7 +85,9 @@ comet_status comet_create(comet_task task, const comet_solver_params* params, in
                           int32_t max_segments, int32_t max_intervals, comet_ctx** out);
 void comet_destroy(comet_ctx* ctx);
 
-/* Message of the last error on this context (thread-unsafe; the context owns the string). */
+/* Message of the last error on this context (thread-unsafe; the context owns the string).
+ * With ctx = NULL: the message of the calling thread's last failed call that takes no
+ * context (comet_probe_peaks), or "". */
 const char* comet_last_error(const comet_ctx* ctx);
 
 /* Task dimensions: state size nx, control size nu, instance parameters per sequence,
@@ -371,6 +373,17 @@ comet_status comet_mlp_targets(comet_task task, void* stream, int64_t B, const f
 comet_status comet_mlp_decode_warm(comet_task task, void* stream, int64_t B, const float* out, int32_t out_dim,
                                    const float* x0, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                                    int32_t smax, int32_t nmax, float* warm);
+
+/* Microbenchmarks of the device's peak rates, the denominators of roofline figures
+ * (measured on the current device and stream; synchronises; allocates 2 GiB of scratch
+ * for the copy and frees it).  out: host, 4 doubles:
+ *   [0] FP32 vector FMA rate, TFLOP/s (non-packed instructions: packed FP32 is disabled in
+ *       this library)
+ *   [1] FP64 vector FMA rate, TFLOP/s
+ *   [2] BF16 matrix-core rate (v_mfma_f32_16x16x32_bf16, dense), TFLOP/s
+ *   [3] device-to-device copy, GB/s (bytes read + written)
+ * COMET_ENOMEM if the scratch does not fit, COMET_EHIP on a runtime failure. */
+comet_status comet_probe_peaks(void* stream, double* out);
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcomet.so")
-SOURCES = ["evaluator.hip", "expand.hip", "mlp.hip", "flip.hip"]
+SOURCES = ["evaluator.hip", "expand.hip", "mlp.hip", "flip.hip", "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions stay disabled (the compiler would otherwise form them)

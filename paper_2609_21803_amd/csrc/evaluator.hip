@@ -114,6 +114,13 @@ comet_status fail_msg(comet_ctx* c, comet_status st, const std::string& m) {
   return st;
 }
 
+thread_local std::string g_msg;   // last failure of a call without a context
+
+comet_status fail_global(comet_status st, const std::string& m) {
+  g_msg = m;
+  return st;
+}
+
 comet_status launch_evaluate(comet_ctx* c, hipStream_t s, const EvalLaunch& L) {
   EvalArgs A;
   std::memset(&A, 0, sizeof A);
@@ -296,7 +303,7 @@ void comet_destroy(comet_ctx* c) {
   delete c;
 }
 
-const char* comet_last_error(const comet_ctx* c) { return c ? c->msg.c_str() : "null context"; }
+const char* comet_last_error(const comet_ctx* c) { return c ? c->msg.c_str() : comet::g_msg.c_str(); }
 
 comet_status comet_dims(const comet_ctx* c, int32_t* nx, int32_t* nu, int32_t* np, int32_t* nm, int32_t* ms,
                         int32_t* mi, int64_t* mb) {

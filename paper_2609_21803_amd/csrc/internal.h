@@ -126,5 +126,7 @@ void mlp_decode_warm_dev(comet_mlp* m, int task, hipStream_t s, long long Bmax, 
                          const float* x0, int inst_stride, const int32_t* nseg, const int32_t* modes,
                          const int32_t* knots, int smax, int nmax, float* warm);
 comet_status fail_msg(comet_ctx* c, comet_status st, const std::string& m);
+// failure of a call without a context: the message is kept per thread (comet_last_error(NULL))
+comet_status fail_global(comet_status st, const std::string& m);
 void destroy_expand_ws(comet_ctx* c);
 }  // namespace comet

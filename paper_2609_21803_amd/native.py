@@ -138,6 +138,8 @@ def lib():
         L.comet_mlp_decode_warm.restype = C.c_int
         L.comet_last_kernel_ms.argtypes = [P, C.POINTER(C.c_float)]
         L.comet_last_kernel_ms.restype = C.c_int
+        L.comet_probe_peaks.argtypes = [P, P]
+        L.comet_probe_peaks.restype = C.c_int
         _lib = L
     return _lib
 
@@ -198,7 +200,7 @@ def _torch_device_first():
 
 def check(rc: int, ctx=None):
     if rc != COMET_OK:
-        msg = lib().comet_last_error(ctx).decode() if ctx else ""
+        msg = lib().comet_last_error(ctx).decode()
         raise CometError(f"comet call failed with status {rc}: {msg}")
 
 
@@ -325,6 +327,17 @@ def expand_next(ctx: "Context", keys, merit, params: ExpandParams, room: int, st
                                  int(room), _ptr(out), _ptr(n))
     check(rc, ctx._h)
     return out[: int(n.item())]
+
+
+def probe_peaks(stream=None) -> dict:
+    """Measured peak rates of the current device (comet_probe_peaks)."""
+    import numpy as np
+    _torch_device_first()
+    out = np.zeros(4)
+    st = _stream(stream)
+    check(lib().comet_probe_peaks(st, out.ctypes.data_as(C.c_void_p)))
+    return dict(fp32_fma_tflops=float(out[0]), fp64_fma_tflops=float(out[1]), bf16_mfma_tflops=float(out[2]),
+                copy_gbs=float(out[3]))
 
 
 def expand_trace(ctx: "Context", cap: int = 1 << 20, stream=None):
