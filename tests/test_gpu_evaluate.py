@@ -251,3 +251,73 @@ def test_schedules_give_identical_results_and_autotuner_picks_one():
     assert ms > 0 and ctx.schedule()["waves_per_cu"] == sched["waves_per_cu"]
     assert np.array_equal(out["cost"].cpu().numpy(), outs[0]["cost"], equal_nan=True)
     print("autotuned schedule", sched, f"{ms:.2f} ms", ctx.schedule())
+
+
+def _max_length_batch():
+    rng = np.random.default_rng(510)
+    B = 32
+    x0, goal, inst = I.push_pairs(510, B)
+    b = dict(x0=np.asarray(x0, np.float32), goal=np.asarray(goal, np.float32), inst=np.asarray(inst, np.float32),
+             nseg=np.full(B, 6, np.int32), modes=rng.integers(0, 12, (B, 6)).astype(np.int32),
+             knots=np.full((B, 6), 85, np.int32))
+    # order 0: the straight push of 0.5 m through the face-2 centre
+    b["x0"][0] = 0.0
+    b["goal"][0] = (0.5, 0.0, 0.0)
+    b["modes"][0] = 6
+    return b
+
+
+def _max_length_run(b, task, kw):
+    import oracle
+    import torch
+    from paper_2609_21803_amd import native
+    ctx = native.Context(max_batch=len(b["nseg"]), max_segments=6, max_intervals=512, task=task,
+                         params=native.SolverParams(**kw))
+    out = ctx.evaluate(**native.to_device(b))
+    torch.cuda.synchronize()
+    ctx.check()
+    g = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    o = oracle.evaluate(f32(b["x0"]), f32(b["goal"]), f32(b["inst"]), b["nseg"], b["modes"], b["knots"],
+                        params=oracle.Params(timed=1 if task == 2 else 0, **kw), nmax=512)
+    conv = (g["stats"][:, 3] == 1) & (o["stats"][:, 3] == 1)
+    rel = np.abs(g["cost"].astype(np.float64) - o["cost"]) / np.maximum(np.abs(o["cost"]), 1e-12)
+    print(f"maximum length, task {task} {kw}: both converged {conv.sum()}, status agreement "
+          f"{(g['stats'][:, 3] == o['stats'][:, 3]).mean():.3f}, feasible gpu/oracle {g['feasible'].sum()}/"
+          f"{o['feasible'].sum()}, max rel cost on converged {rel[conv].max() if conv.any() else 0:.2e}", flush=True)
+    assert np.all(g["traj"][:, 511:] == 0) and np.all(g["traj"][:, 510, 4:] == 0)
+    return g, o, conv, rel
+
+
+@pytest.mark.parametrize("task", [0, 2])
+def test_maximum_length_sequences_match_oracle(orc, task):
+    """Orders at the longest work-space height: 6 segments x 85 intervals = 510 of the 512
+    intervals a context can hold, fixed step and optimised timing, default tolerances.  The
+    straight push reaches its closed form (d^2 / T, or d^2 / T + w_T T with T at the
+    duration bound) within 5e-3: every one of the 510 defects may sit within the stopping
+    tolerance (about 1e-6 m) and these slacks add up along the push (the FP64 oracle itself
+    lands 2.5e-3 and 1.1e-3 from it).  Where both sides converge, the flags agree and the
+    costs within 1e-3: the stopping region (stationarity 1e-4) is wide over 510 stages, and
+    the device's FP32 gains and steps end at another point of it than the oracle's FP64
+    path (tightened tolerances shrink the gap, see the next test; the oracle's own change
+    under a one-ulp goal move is at most 1.2e-6 there).  The statuses agree on most orders."""
+    b = _max_length_batch()
+    g, o, conv, rel = _max_length_run(b, task, {})
+    T = 510 * 0.1 if task == 0 else min(max(0.5 / 0.1, 510 * 0.02), 510 * 0.2)
+    Jstar = 0.25 / T + (0.01 * T if task == 2 else 0.0)
+    assert g["feasible"][0] == 1 and abs(float(g["cost"][0]) - Jstar) <= 5e-3 * Jstar, (g["cost"][0], Jstar)
+    assert conv.sum() >= 1
+    assert np.array_equal(g["feasible"][conv], o["feasible"][conv]) and np.all(rel[conv] <= 1e-3)
+    assert (g["stats"][:, 3] == o["stats"][:, 3]).mean() >= 0.8
+
+
+def test_maximum_length_tight_tolerances_match_oracle(orc):
+    """The same 510-interval orders (fixed step) with tightened stopping tolerances
+    (stationarity 1e-6, feasibility and complementarity 1e-8, refinement-size budget):
+    most converge on both sides, the costs agree within 1e-4 and the straight push is
+    within 1e-4 of d^2 / T."""
+    b = _max_length_batch()
+    kw = dict(omega_star=1e-6, eta_star=1e-8, rc_star=1e-8, al_max=40, gn_max=25)
+    g, o, conv, rel = _max_length_run(b, 0, kw)
+    assert conv.sum() >= 16
+    assert np.array_equal(g["feasible"][conv], o["feasible"][conv]) and np.all(rel[conv] <= 1e-4)
+    assert abs(float(g["cost"][0]) - 0.25 / 51.0) <= 1e-4 * 0.25 / 51.0

@@ -165,3 +165,21 @@ def test_empty_batch_and_oversized_orders():
     e = {k: v[:0] for k, v in native.to_device(b).items()}
     ctx.evaluate(**e)                                             # B = 0 is a no-op
     torch.cuda.synchronize()
+
+
+def test_maximum_length_orders_match_oracle():
+    """Six segments x 85 intervals = 510 of the 512 intervals a context holds (the work
+    space's largest per-order extent): same status as the oracle on every order, the same
+    final cost and violation on most (solved to the end of the budget), rows beyond N zero."""
+    from paper_2609_21803_amd import native
+    b = I.flip_batch(5100, 8, n_pairs=4, kmin=6, kmax=6, knots=85)
+    ctx = native.Context(max_batch=8, max_intervals=512, task=native.TASK_FLIP)
+    g = _run(ctx, b)
+    ctx.check()
+    o = _oracle(b, nmax=512)
+    scale = np.maximum(np.abs(o["cost"]), 1e-3)
+    close = (np.abs(g["cost"] - o["cost"]) <= 1e-4 * scale) & (np.abs(g["viol"] - o["viol"]) <= 1e-5 + 1e-4 * o["viol"])
+    print("maximum length: close", close.tolist(), "status", g["stats"][:, 3].tolist(), o["stats"][:, 3].tolist())
+    assert np.array_equal(g["feasible"], o["feasible"]) and np.array_equal(g["stats"][:, 3], o["stats"][:, 3])
+    assert close.sum() >= 6
+    assert np.all(g["traj"][:, 511:] == 0)
