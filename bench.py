@@ -214,17 +214,25 @@ def timed_leg(native, I, torch, cpu=True):
 
 def hetero_leg(native, I, torch, B=131072):
     """Heterogeneous batch (K ~ U{1..5}, 5..15 intervals per segment, up to 75 intervals):
-    the persistent work queue in its default schedule and in the autotuner's pick."""
+    the persistent work queue with the orders in input order, in the default schedule
+    (length-sorted queue) and in the autotuner's pick."""
     b = I.push_hetero(seed=2100, B=B)
     ctx = native.Context(max_batch=B, max_segments=6, max_intervals=75)
     d = native.to_device(b)
     out = ctx.evaluate(**d)
     torch.cuda.synchronize()
-    default_ms = []
-    for _ in range(2):
-        ctx.evaluate(**d)
-        torch.cuda.synchronize()
-        default_ms.append(ctx.kernel_ms())
+
+    def timed_runs():
+        ms = []
+        for _ in range(2):
+            ctx.evaluate(**d)
+            torch.cuda.synchronize()
+            ms.append(ctx.kernel_ms())
+        return ms
+
+    default_ms = timed_runs()
+    ctx.set_schedule(0, 0)
+    input_order_ms = timed_runs()
     sched, tuned_ms = ctx.autotune(**d, out=out)
     best = []
     for _ in range(2):
@@ -236,6 +244,8 @@ def hetero_leg(native, I, torch, B=131072):
     return {"workload": f"pushing, heterogeneous: {B} orders, K ~ U{{1..5}}, 5..15 intervals per segment, "
                         "64 start/goal pairs (seed 2100)",
             "mean_intervals": float(N.mean()), "mean_gn_iterations": float(st[:, 1].mean()),
+            "input_order": {"kernel_ms": float(np.mean(input_order_ms)),
+                            "solves_per_s": B / (np.mean(input_order_ms) * 1e-3)},
             "default_schedule": {"kernel_ms": float(np.mean(default_ms)), "solves_per_s": B / (np.mean(default_ms) * 1e-3)},
             "autotuned_schedule": {"schedule": sched, "kernel_ms": float(np.mean(best)),
                                    "solves_per_s": B / (np.mean(best) * 1e-3)}}

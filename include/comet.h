@@ -167,7 +167,8 @@ comet_status comet_evaluate(comet_ctx* ctx, void* stream, int64_t B, const float
  *                   limit of the kernel (never more than one wave per 64 sequences)
  *   sort_by_length  1 = the queue hands out orders by decreasing interval count, so the
  *                   lanes of a wave sweep similar lengths (ragged batches)
- * Results do not depend on the schedule (each order's arithmetic is the same in every lane). */
+ * A new context starts with {0, 1}.  Results do not depend on the schedule (each order's
+ * arithmetic is the same in every lane). */
 typedef struct {
   int32_t waves_per_cu, sort_by_length;
 } comet_schedule;

@@ -72,10 +72,19 @@ __device__ inline int seq_len(const EvalArgs& A, int64_t b) {
   return min(N, A.nmax + 1);
 }
 
-__global__ void k_queue_hist(EvalArgs A, int* hist) {
+// Counts per length are gathered in LDS first and added to the global bins once per block
+// and length: a batch of equal lengths would otherwise serialise every order's atomic on
+// one address.
+__global__ void k_queue_hist(EvalArgs A, int* hist, int nbins) {
+  __shared__ int lh[MAXN + 2];
+  for (int i = threadIdx.x; i < nbins; i += blockDim.x) lh[i] = 0;
+  __syncthreads();
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t Bn = A.Bdev ? *A.Bdev : A.B;
-  if (b < Bn) atomicAdd(&hist[seq_len(A, b)], 1);
+  if (b < Bn) atomicAdd(&lh[seq_len(A, b)], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+    if (lh[i]) atomicAdd(&hist[i], lh[i]);
 }
 
 // exclusive scan over bins in decreasing length order (one block)
@@ -90,10 +99,25 @@ __global__ void k_queue_scan(int* hist, int nbins) {
   }
 }
 
-__global__ void k_queue_scatter(EvalArgs A, int* hist, int* order) {
+// each block reserves one range per length in the bins' running offsets and places its
+// orders in it by their rank within the block
+__global__ void k_queue_scatter(EvalArgs A, int* hist, int* order, int nbins) {
+  __shared__ int lh[MAXN + 2];
+  __shared__ int base[MAXN + 2];
+  for (int i = threadIdx.x; i < nbins; i += blockDim.x) lh[i] = 0;
+  __syncthreads();
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t Bn = A.Bdev ? *A.Bdev : A.B;
-  if (b < Bn) order[atomicAdd(&hist[seq_len(A, b)], 1)] = (int)b;
+  int len = 0, rank = 0;
+  if (b < Bn) {
+    len = seq_len(A, b);
+    rank = atomicAdd(&lh[len], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nbins; i += blockDim.x)
+    if (lh[i]) base[i] = atomicAdd(&hist[i], lh[i]);
+  __syncthreads();
+  if (b < Bn) order[base[len] + rank] = (int)b;
 }
 
 }  // namespace comet
@@ -159,9 +183,9 @@ comet_status launch_evaluate(comet_ctx* c, hipStream_t s, const EvalLaunch& L) {
                      A.order ? c->hist : (int*)nullptr, nbins);
   if (A.order) {
     const unsigned gb = (unsigned)std::max<int64_t>(1, (Bmax + 255) / 256);
-    hipLaunchKernelGGL(k_queue_hist, dim3(gb), dim3(256), 0, s, A, c->hist);
+    hipLaunchKernelGGL(k_queue_hist, dim3(gb), dim3(256), 0, s, A, c->hist, nbins);
     hipLaunchKernelGGL(k_queue_scan, dim3(1), dim3(64), 0, s, c->hist, nbins);
-    hipLaunchKernelGGL(k_queue_scatter, dim3(gb), dim3(256), 0, s, A, c->hist, c->order);
+    hipLaunchKernelGGL(k_queue_scatter, dim3(gb), dim3(256), 0, s, A, c->hist, c->order, nbins);
   }
   if (timed) (void)hipEventRecord(c->ev0, s);
   if (c->task == COMET_TASK_PUSH_TIMED)

@@ -98,7 +98,7 @@ struct comet_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
   int n_cu = 0, occ_blocks_per_cu = 1;
-  comet_schedule sched{0, 0};
+  comet_schedule sched{0, 1};   // occupancy limit, length-sorted queue
   hipStream_t gstream = nullptr;   // internal stream for captured graphs
   comet_expand_ws* xws = nullptr;
   double* fws = nullptr;      // flip task work space (FP64 per interval)
