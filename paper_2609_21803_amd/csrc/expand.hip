@@ -448,15 +448,25 @@ __device__ inline double merit_of(double J, double v, double eps, double mu) {
 __global__ void k_append(ExpCfg g, ExpCounters* C, const unsigned long long* F, const double* J, const double* v,
                          unsigned long long* vkey, double* vJ, double* vv, double* vM) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= C->nF) return;
+  const bool in = i < C->nF;
   const long long j = C->nV + i;
-  vkey[j] = F[i];
-  vJ[j] = J[i];
-  vv[j] = v[i];
-  vM[j] = merit_of(J[i], v[i], g.eps, g.mu_merit);
-  if (v[i] <= g.eps) {
-    atomicAdd((unsigned long long*)&C->n_feas, 1ull);
-    atomicMin(&C->first_feas, (unsigned long long)(j + 1));
+  bool feas = false;
+  if (in) {
+    vkey[j] = F[i];
+    vJ[j] = J[i];
+    vv[j] = v[i];
+    vM[j] = merit_of(J[i], v[i], g.eps, g.mu_merit);
+    feas = v[i] <= g.eps;
+  }
+  // one update of the counters per wave: the feasible lanes' count, and the first of them
+  // (lanes hold consecutive positions, so the lowest feasible lane has the smallest j)
+  const unsigned long long m = __ballot(feas);
+  if (m) {
+    const int lead = __ffsll((long long)m) - 1;
+    if ((int)(threadIdx.x & 63) == lead) {
+      atomicAdd((unsigned long long*)&C->n_feas, (unsigned long long)__popcll(m));
+      atomicMin(&C->first_feas, (unsigned long long)(j + 1));
+    }
   }
 }
 
