@@ -153,8 +153,8 @@ comet_status comet_check(comet_ctx* ctx, void* stream);
  * defect steps by h_k instead of 0.1 s, each interval carries the bounds
  * 0.02 s <= h_k <= 0.2 s, and cost = sum h_k ((F_n^2 + F_t^2) / f_max^2 + (v_s / v_ref)^2
  * + 0.01) charges the elapsed time; the schedule-derived start has h_k = 0.1 s.
- *   traj  [B, Nmax+1, 8] rows (x_k, u_k); warm likewise.  The learned network serves the
- *                  fixed-step tasks only. */
+ *   traj  [B, Nmax+1, 8] rows (x_k, u_k); warm likewise.  With the learned network the
+ *                  eighth warm-start channel carries the interval duration. */
 comet_status comet_evaluate(comet_ctx* ctx, void* stream, int64_t B, const float* x0, const float* goal,
                             const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                             const float* warm, int32_t refine, float* cost, float* viol, uint8_t* feasible,
@@ -348,17 +348,19 @@ comet_status comet_mlp_train_step(comet_mlp* mlp, void* stream, int64_t B, const
  *   COMET_TASK_FLIP: pose = start (px, py, cos, sin), goal (px, 0, cos, sin), goal - start
  *     (px, 0, theta), table friction; slot = one-hot finger-1 code (13), one-hot finger-2
  *     code (13), one-hot table mode (5), intervals / 15, present flag.
+ *   COMET_TASK_PUSH_TIMED: as COMET_TASK_PUSH.
  * The network proposes orders and warm starts (Sec. IV-C); its input encoding is not fixed
  * by the paper.  Other tasks: COMET_EINVAL. */
 comet_status comet_mlp_encode(comet_task task, void* stream, int64_t B, const float* x0, const float* goal,
                               const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                               int32_t smax, int32_t in_dim, uint16_t* x_bf16);
 /* Training targets from evaluator results (traj [B, nmax+1, row] in comet_evaluate's
- * layout, row = 7 pushing / 17 flipping; feasible; cost): y_feas, y_cost = log(1 + J)
+ * layout, row = 7 pushing / 8 timed pushing / 17 flipping; feasible; cost): y_feas, y_cost = log(1 + J)
  * (0 if infeasible), y_traj [B, 720] per-segment samples (6 slots x 15 times i/14 x 8
  * channels) by linear interpolation of the rows, traj_mask [B, 720] = 1 on the learned
  * channels of present segments of feasible orders.  Learned channels: pushing, the 7 row
- * entries (channel 7 zero); flipping, the 8 state entries. */
+ * entries (channel 7 zero); timed pushing, the 8 row entries (channel 7 the duration);
+ * flipping, the 8 state entries. */
 comet_status comet_mlp_targets(comet_task task, void* stream, int64_t B, const float* traj, int32_t nmax,
                                const int32_t* nseg, const int32_t* knots, int32_t smax, const uint8_t* feasible,
                                const float* cost, float* y_feas, float* y_cost, float* y_traj, float* traj_mask);
@@ -366,6 +368,8 @@ comet_status comet_mlp_targets(comet_task task, void* stream, int64_t B, const f
  * outputs [B, out_dim]: each segment's samples interpolated to its knots.
  *   COMET_TASK_PUSH: all 7 entries interpolated; row 0 takes x0, the last row's controls
  *     are zero.  `modes` may be NULL.
+ *   COMET_TASK_PUSH_TIMED: as COMET_TASK_PUSH with 8 entries, the duration (entry 7)
+ *     clamped to [0.02, 0.2] s.
  *   COMET_TASK_FLIP: the 8 states interpolated, row 0 takes x0; controls from the states
  *     and `modes` (required): accelerations and face-coordinate rates by forward
  *     differences over dt = 0.1 s, a contact finger pushes with mg/2 normal force (a

@@ -1289,8 +1289,6 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
   const bool flip = (c->task == COMET_TASK_FLIP);
   if (learned && (mlp_max_batch(learned) < params->batch_B || mlp_in_dim(learned) < 400 || mlp_out_dim(learned) < 722))
     return fail_msg(c, COMET_EINVAL, "learned network: max_batch < batch_B, in_dim < 400 or out_dim < 722");
-  if (learned && c->task == COMET_TASK_PUSH_TIMED)
-    return fail_msg(c, COMET_EINVAL, "the learned network serves the fixed-step tasks only");
   if (learned && params->policy == COMET_POLICY_MCTS)
     return fail_msg(c, COMET_EINVAL, "the learned network ranks expansion or sampling batches, not MCTS");
   st = ensure_ws(c, params);

@@ -560,15 +560,18 @@ __global__ void k_targets(long B, const float* traj, int nmax, int row, int nch,
   }
 }
 
+// Pushing warm start: rows (x_k, u_k) interpolated from the network samples at every knot,
+// the start state at knot 0, row N with u = 0.  width 7 (fixed step) or 8 (optimised
+// timing: channel 7 is the interval duration, clamped to its bounds).
 __global__ void k_decode_warm(long B, const long long* B_dev, const float* Y, int O, const float* x0, int inst_stride,
-                              const int32_t* nseg, const int32_t* knots, int smax, int nmax, float* warm) {
+                              const int32_t* nseg, const int32_t* knots, int smax, int nmax, int width, float* warm) {
   const long Bn = B_dev ? *B_dev : B;
   const long b = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= Bn) return;
   const int K = nseg[b];
   const float* y = Y + b * (long)O + 2;
-  float* Wr = warm + b * (long)(nmax + 1) * 7;
-  for (int r = 0; r < (nmax + 1) * 7; ++r) Wr[r] = 0.f;
+  float* Wr = warm + b * (long)(nmax + 1) * width;
+  for (int r = 0; r < (nmax + 1) * width; ++r) Wr[r] = 0.f;
   int k0 = 0;
   for (int j = 0; j < K && j < smax; ++j) {
     const int nj = knots[b * smax + j];
@@ -576,16 +579,18 @@ __global__ void k_decode_warm(long B, const long long* B_dev, const float* Y, in
       const float p = (nj > 0) ? (float)k / (float)nj * (WS_SLOTS - 1) : 0.f;
       const int i = min((int)floorf(p), WS_SLOTS - 2);
       const float fr = p - (float)i;
-      for (int c = 0; c < 7; ++c) {
+      for (int c = 0; c < width; ++c) {
         const float a0 = y[((long)j * WS_SLOTS + i) * WS_CH + c], a1 = y[((long)j * WS_SLOTS + i + 1) * WS_CH + c];
-        Wr[(k0 + k) * 7 + c] = a0 + fr * (a1 - a0);
+        float val = a0 + fr * (a1 - a0);
+        if (c == 7) val = fminf(fmaxf(val, (float)push_timed::H_MIN), (float)push_timed::H_MAX);
+        Wr[(k0 + k) * width + c] = val;
       }
     }
     k0 += nj;
   }
   for (int c = 0; c < 4; ++c) Wr[c] = x0[b * inst_stride * 4 + c];
   if (k0 <= nmax)
-    for (int c = 4; c < 7; ++c) Wr[k0 * 7 + c] = 0.f;
+    for (int c = 4; c < width; ++c) Wr[k0 * width + c] = 0.f;
 }
 
 // Flipping warm start: states (8 channels) interpolated from the network samples at every
@@ -773,7 +778,7 @@ void mlp_decode_warm_dev(comet_mlp* m, int task, hipStream_t s, long long Bmax, 
                        m->out_dim, x0, inst_stride, nseg, modes, knots, smax, nmax, warm);
   else
     hipLaunchKernelGGL(k_decode_warm, dim3(nblk(Bmax, 128)), dim3(128), 0, s, (long)Bmax, B_dev, m->Y, m->out_dim,
-                       x0, inst_stride, nseg, knots, smax, nmax, warm);
+                       x0, inst_stride, nseg, knots, smax, nmax, task == COMET_TASK_PUSH_TIMED ? 8 : 7, warm);
 }
 
 }  // namespace comet
@@ -995,8 +1000,8 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
 comet_status comet_mlp_encode(comet_task task, void* stream, int64_t B, const float* x0, const float* goal,
                               const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                               int32_t smax, int32_t in_dim, uint16_t* x_bf16) {
-  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP) || !x0 || !goal || !inst || !nseg || !modes || !knots ||
-      !x_bf16)
+  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP && task != COMET_TASK_PUSH_TIMED) || !x0 || !goal ||
+      !inst || !nseg || !modes || !knots || !x_bf16)
     return COMET_EINVAL;
   if (B < 0 || smax < 1 || smax > 6 || in_dim < POSE_DIMS + 6 * SEG_SLOT) return COMET_EINVAL;
   if (B == 0) return COMET_OK;
@@ -1012,23 +1017,25 @@ comet_status comet_mlp_encode(comet_task task, void* stream, int64_t B, const fl
 comet_status comet_mlp_targets(comet_task task, void* stream, int64_t B, const float* traj, int32_t nmax,
                                const int32_t* nseg, const int32_t* knots, int32_t smax, const uint8_t* feasible,
                                const float* cost, float* y_feas, float* y_cost, float* y_traj, float* traj_mask) {
-  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP) || !traj || !nseg || !knots || !feasible || !cost ||
-      !y_feas || !y_cost || !y_traj || !traj_mask)
+  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP && task != COMET_TASK_PUSH_TIMED) || !traj || !nseg ||
+      !knots || !feasible || !cost || !y_feas || !y_cost || !y_traj || !traj_mask)
     return COMET_EINVAL;
   if (B < 0 || smax < 1 || smax > 6 || nmax < 1) return COMET_EINVAL;
   if (B == 0) return COMET_OK;
-  const bool flip = (task == COMET_TASK_FLIP);
-  hipLaunchKernelGGL(k_targets, dim3(nblk(B, 128)), dim3(128), 0, (hipStream_t)stream, (long)B, traj, nmax,
-                     flip ? 17 : 7, flip ? 8 : 7, nseg, knots, smax, feasible, cost, y_feas, y_cost, y_traj,
-                     traj_mask);
+  // trajectory row width and the channels sampled: pushing (x, u) 7, timed pushing 8 (with
+  // the duration), flipping the 8 states of a 17-wide row
+  const int row = task == COMET_TASK_FLIP ? 17 : (task == COMET_TASK_PUSH_TIMED ? 8 : 7);
+  const int nch = task == COMET_TASK_PUSH ? 7 : 8;
+  hipLaunchKernelGGL(k_targets, dim3(nblk(B, 128)), dim3(128), 0, (hipStream_t)stream, (long)B, traj, nmax, row, nch,
+                     nseg, knots, smax, feasible, cost, y_feas, y_cost, y_traj, traj_mask);
   return hipGetLastError() == hipSuccess ? COMET_OK : COMET_EHIP;
 }
 
 comet_status comet_mlp_decode_warm(comet_task task, void* stream, int64_t B, const float* out, int32_t out_dim,
                                    const float* x0, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                                    int32_t smax, int32_t nmax, float* warm) {
-  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP) || !out || !x0 || !nseg || !knots || !warm ||
-      out_dim < 2 + 6 * WS_SLOTS * WS_CH)
+  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP && task != COMET_TASK_PUSH_TIMED) || !out || !x0 || !nseg ||
+      !knots || !warm || out_dim < 2 + 6 * WS_SLOTS * WS_CH)
     return COMET_EINVAL;
   if (task == COMET_TASK_FLIP && !modes) return COMET_EINVAL;
   if (B < 0 || smax < 1 || smax > 6 || nmax < 1) return COMET_EINVAL;
@@ -1038,7 +1045,8 @@ comet_status comet_mlp_decode_warm(comet_task task, void* stream, int64_t B, con
                        (const long long*)nullptr, out, out_dim, x0, 1, nseg, modes, knots, smax, nmax, warm);
   else
     hipLaunchKernelGGL(k_decode_warm, dim3(nblk(B, 128)), dim3(128), 0, (hipStream_t)stream, (long)B,
-                       (const long long*)nullptr, out, out_dim, x0, 1, nseg, knots, smax, nmax, warm);
+                       (const long long*)nullptr, out, out_dim, x0, 1, nseg, knots, smax, nmax,
+                       task == COMET_TASK_PUSH_TIMED ? 8 : 7, warm);
   return hipGetLastError() == hipSuccess ? COMET_OK : COMET_EHIP;
 }
 

@@ -16,7 +16,8 @@ from . import native
 
 def generate(n_samples: int, seed: int = 4000, chunk: int = 65536, kmin=1, kmax=5, nmin=5, nmax=15,
              ctx: native.Context | None = None):
-    """Evaluate n_samples seeded ragged pushing orders and build (X, targets) on the GPU."""
+    """Evaluate n_samples seeded ragged pushing orders and build (X, targets) on the GPU
+    (fixed-step pushing, or optimised timing when `ctx` is a timed context)."""
     import torch
     N = 6 * nmax
     ctx = ctx or native.Context(max_batch=chunk, max_segments=6, max_intervals=N)
@@ -31,8 +32,8 @@ def generate(n_samples: int, seed: int = 4000, chunk: int = 65536, kmin=1, kmax=
         b = I.push_hetero(seed=seed + i, B=B, kmin=kmin, kmax=kmax, nmin=nmin, nmax=nmax)
         d = native.to_device(b)
         out = ctx.evaluate(**d)
-        X[done:done + B] = native.mlp_encode(d)
-        f, c, t, m = native.mlp_targets(d, out, ctx.max_intervals)
+        X[done:done + B] = native.mlp_encode(d, task=ctx.task)
+        f, c, t, m = native.mlp_targets(d, out, ctx.max_intervals, task=ctx.task)
         yf[done:done + B], yc[done:done + B], yt[done:done + B], mk[done:done + B] = f, c, t, m
         done += B
         i += 1
