@@ -314,14 +314,17 @@ comet_status comet_expand_trace(comet_ctx* ctx, void* stream, int64_t cap, uint6
  * Learned proposal / warm-start network (BF16 matrix-core kernels, FP32 accumulation).
  * in_dim -> `layers` hidden layers of width `hidden` (exact-erf GELU) -> out_dim.  Output
  * row: [0] feasibility logit, [1] predicted log(1 + J), [2 .. 2 + 720) warm start: for
- * each of 6 segment slots, 15 samples at normalised times i/14 of 8 channels (the 7
- * trajectory channels (x, y, theta, s, F_n, F_t, v_s) and a zero channel).  Flat parameter
+ * each of 6 segment slots, 15 samples at normalised times i/14 of 8 channels (pushing: the
+ * 7 trajectory channels (x, y, theta, s, F_n, F_t, v_s) and a zero channel; timed pushing:
+ * the same with the interval duration as channel 7; flipping: the 8 states).  Flat parameter
  * layout: for each linear layer in order, W [out][in] row-major then b [out] (FP32).
  * Initialisation: W ~ U(-1/sqrt(in), 1/sqrt(in)) from a counter-based hash of (seed, index),
  * b = 0.  Training: AdamW (beta 0.9 / 0.999, eps 1e-8) on FP32 masters; GEMM operands
  * (weights, inputs, activations, back-propagated gradients) are rounded to BF16.
  * in_dim, hidden and out_dim must be multiples of 8 (16-byte operand vectors), else
- * COMET_EINVAL; out_dim >= 722. */
+ * COMET_EINVAL; out_dim >= 722.  For comet_mlp_forward, _encode, _targets and
+ * _decode_warm, B = 0 is a no-op after the scalar arguments are checked (array pointers
+ * may then be NULL); comet_mlp_train_step needs 1 <= B <= max_batch. */
 comet_status comet_mlp_create(int32_t in_dim, int32_t hidden, int32_t layers, int32_t out_dim, int64_t max_batch,
                               uint64_t seed, comet_mlp** out);
 void comet_mlp_destroy(comet_mlp* mlp);

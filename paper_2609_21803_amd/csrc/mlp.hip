@@ -912,9 +912,9 @@ comet_status comet_mlp_grads(comet_mlp* m, void* stream, float* flat) {
 }
 
 comet_status comet_mlp_forward(comet_mlp* m, void* stream, int64_t B, const uint16_t* x_bf16, float* out) {
-  if (!m || !x_bf16 || !out) return COMET_EINVAL;
-  if (B < 0 || B > m->max_batch) return COMET_EINVAL;
-  if (B == 0) return COMET_OK;
+  if (!m || B < 0 || B > m->max_batch) return COMET_EINVAL;
+  if (B == 0) return COMET_OK;   // empty batch: no array is touched, pointers may be NULL
+  if (!x_bf16 || !out) return COMET_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   if (hipMemcpyAsync(m->H[0], x_bf16, 2 * B * m->in_dim, hipMemcpyDeviceToDevice, s) != hipSuccess) return COMET_EHIP;
   mlp_forward(m, s, (int)B, nullptr);
@@ -1000,11 +1000,11 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
 comet_status comet_mlp_encode(comet_task task, void* stream, int64_t B, const float* x0, const float* goal,
                               const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                               int32_t smax, int32_t in_dim, uint16_t* x_bf16) {
-  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP && task != COMET_TASK_PUSH_TIMED) || !x0 || !goal ||
-      !inst || !nseg || !modes || !knots || !x_bf16)
+  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP && task != COMET_TASK_PUSH_TIMED) || B < 0 || smax < 1 || smax > 6 ||
+      in_dim < POSE_DIMS + 6 * SEG_SLOT)
     return COMET_EINVAL;
-  if (B < 0 || smax < 1 || smax > 6 || in_dim < POSE_DIMS + 6 * SEG_SLOT) return COMET_EINVAL;
-  if (B == 0) return COMET_OK;
+  if (B == 0) return COMET_OK;   // empty batch: no array is touched, pointers may be NULL
+  if (!x0 || !goal || !inst || !nseg || !modes || !knots || !x_bf16) return COMET_EINVAL;
   if (task == COMET_TASK_FLIP)
     hipLaunchKernelGGL(k_encode_flip, dim3(nblk(B * in_dim, 256)), dim3(256), 0, (hipStream_t)stream, (long)B, x0,
                        goal, inst, 1, nseg, modes, knots, smax, in_dim, (bf16*)x_bf16, (const long long*)nullptr);
@@ -1017,11 +1017,10 @@ comet_status comet_mlp_encode(comet_task task, void* stream, int64_t B, const fl
 comet_status comet_mlp_targets(comet_task task, void* stream, int64_t B, const float* traj, int32_t nmax,
                                const int32_t* nseg, const int32_t* knots, int32_t smax, const uint8_t* feasible,
                                const float* cost, float* y_feas, float* y_cost, float* y_traj, float* traj_mask) {
-  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP && task != COMET_TASK_PUSH_TIMED) || !traj || !nseg ||
-      !knots || !feasible || !cost || !y_feas || !y_cost || !y_traj || !traj_mask)
+  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP && task != COMET_TASK_PUSH_TIMED) || B < 0 || smax < 1 || smax > 6 || nmax < 1) return COMET_EINVAL;
+  if (B == 0) return COMET_OK;   // empty batch: no array is touched, pointers may be NULL
+  if (!traj || !nseg || !knots || !feasible || !cost || !y_feas || !y_cost || !y_traj || !traj_mask)
     return COMET_EINVAL;
-  if (B < 0 || smax < 1 || smax > 6 || nmax < 1) return COMET_EINVAL;
-  if (B == 0) return COMET_OK;
   // trajectory row width and the channels sampled: pushing (x, u) 7, timed pushing 8 (with
   // the duration), flipping the 8 states of a 17-wide row
   const int row = task == COMET_TASK_FLIP ? 17 : (task == COMET_TASK_PUSH_TIMED ? 8 : 7);
@@ -1034,12 +1033,11 @@ comet_status comet_mlp_targets(comet_task task, void* stream, int64_t B, const f
 comet_status comet_mlp_decode_warm(comet_task task, void* stream, int64_t B, const float* out, int32_t out_dim,
                                    const float* x0, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                                    int32_t smax, int32_t nmax, float* warm) {
-  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP && task != COMET_TASK_PUSH_TIMED) || !out || !x0 || !nseg ||
-      !knots || !warm || out_dim < 2 + 6 * WS_SLOTS * WS_CH)
+  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP && task != COMET_TASK_PUSH_TIMED) || B < 0 || smax < 1 || smax > 6 || nmax < 1 ||
+      out_dim < 2 + 6 * WS_SLOTS * WS_CH)
     return COMET_EINVAL;
-  if (task == COMET_TASK_FLIP && !modes) return COMET_EINVAL;
-  if (B < 0 || smax < 1 || smax > 6 || nmax < 1) return COMET_EINVAL;
-  if (B == 0) return COMET_OK;
+  if (B == 0) return COMET_OK;   // empty batch: no array is touched, pointers may be NULL
+  if (!out || !x0 || !nseg || !knots || !warm || (task == COMET_TASK_FLIP && !modes)) return COMET_EINVAL;
   if (task == COMET_TASK_FLIP)
     hipLaunchKernelGGL(k_decode_warm_flip, dim3(nblk(B, 128)), dim3(128), 0, (hipStream_t)stream, (long)B,
                        (const long long*)nullptr, out, out_dim, x0, 1, nseg, modes, knots, smax, nmax, warm);

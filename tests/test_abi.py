@@ -70,3 +70,29 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(s, "size")] == C.sizeof(cls), s
         for f, _ in cls._fields_:
             assert got[(s, f)] == getattr(cls, f).offset, (s, f)
+
+
+def test_network_hooks_check_scalars_and_accept_an_empty_batch_on_the_host():
+    """The network hooks reject bad scalar arguments and treat B = 0 as a no-op with NULL
+    arrays, all before any device call (so this runs without a GPU)."""
+    from paper_2609_21803_amd import native
+    L = C.CDLL(native.LIB_PATH)
+    P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+    L.comet_mlp_encode.argtypes = [C.c_int, P, I64, P, P, P, P, P, P, I32, I32, P]
+    L.comet_mlp_targets.argtypes = [C.c_int, P, I64, P, I32, P, P, I32, P, P, P, P, P, P]
+    L.comet_mlp_decode_warm.argtypes = [C.c_int, P, I64, P, I32, P, P, P, P, I32, I32, P]
+    L.comet_mlp_forward.argtypes = [P, P, I64, P, P]
+    OK, EINVAL = 0, -1
+    enc = lambda task, B, smax=6, in_dim=416: L.comet_mlp_encode(task, None, B, *([None] * 6), smax, in_dim, None)
+    tgt = lambda task, B, nmax=24, smax=6: L.comet_mlp_targets(task, None, B, None, nmax, None, None, smax,
+                                                               *([None] * 6))
+    dec = lambda task, B, out_dim=736, nmax=24: L.comet_mlp_decode_warm(task, None, B, None, out_dim, *([None] * 4),
+                                                                        6, nmax, None)
+    for task in (native.TASK_PUSH, native.TASK_FLIP, native.TASK_PUSH_TIMED):
+        assert enc(task, 0) == OK and tgt(task, 0) == OK and dec(task, 0) == OK
+        assert enc(task, -1) == EINVAL and tgt(task, -1) == EINVAL and dec(task, -1) == EINVAL
+        assert enc(task, 0, smax=7) == EINVAL and enc(task, 0, in_dim=399) == EINVAL
+        assert tgt(task, 0, nmax=0) == EINVAL and dec(task, 0, out_dim=721) == EINVAL
+        assert enc(task, 4) == EINVAL and tgt(task, 4) == EINVAL and dec(task, 4) == EINVAL   # NULL arrays
+    assert enc(3, 0) == EINVAL and tgt(3, 0) == EINVAL and dec(3, 0) == EINVAL              # unknown task
+    assert L.comet_mlp_forward(None, None, 0, None, None) == EINVAL                          # no network

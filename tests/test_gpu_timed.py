@@ -251,3 +251,29 @@ def test_timed_mcts_search_plan_confirmed_by_oracle(orc):
     feas, cost = _refined_oracle_cost(x0, goal, inst, m, 8)
     assert K >= 1 and feas == 1 and abs(cost - float(o["cost"].item())) <= 1e-4 * abs(cost)
     assert bk != 0 and abs(bJ - float(o["cost"].item())) <= 0.05 * abs(bJ)
+
+
+def test_timed_empty_batch_and_oversized_orders():
+    """An order longer than the context's interval budget is rejected (NaN cost, status 3,
+    device error counter raised); an empty batch is a no-op for the evaluator and for the
+    network hooks of the timed task."""
+    import torch
+    from paper_2609_21803_amd import native
+    ctx = native.Context(max_batch=16, max_segments=6, max_intervals=10, task=native.TASK_PUSH_TIMED)
+    b = I.subset(I.push_tiny(), np.arange(4))
+    b["knots"][1, :] = 0
+    b["nseg"][1], b["knots"][1, :3] = 3, (5, 5, 5)               # 15 intervals > max_intervals
+    out = ctx.evaluate(**native.to_device(b))
+    torch.cuda.synchronize()
+    cost, stats = out["cost"].cpu().numpy(), out["stats"].cpu().numpy()
+    assert np.isnan(cost[1]) and stats[1, 3] == 3 and np.all(np.isfinite(cost[[0, 2, 3]]))
+    with pytest.raises(native.CometError):
+        ctx.check()
+    e = {k: v[:0] for k, v in native.to_device(b).items()}
+    o = ctx.evaluate(**e)                                         # B = 0 is a no-op
+    assert o["cost"].numel() == 0
+    x = native.mlp_encode(e, task=native.TASK_PUSH_TIMED)
+    t = native.mlp_targets(e, o, 10, task=native.TASK_PUSH_TIMED)
+    w = native.mlp_decode_warm(torch.zeros((0, 736), device="cuda"), e, 10, task=native.TASK_PUSH_TIMED)
+    torch.cuda.synchronize()
+    assert x.shape[0] == 0 and all(a.shape[0] == 0 for a in t) and w.shape == (0, 11, 8)
