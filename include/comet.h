@@ -337,7 +337,8 @@ comet_status comet_mlp_grads(comet_mlp* mlp, void* stream, float* flat);
 /* out [B, out_dim] = network(x [B, in_dim] BF16 bits), B <= max_batch */
 comet_status comet_mlp_forward(comet_mlp* mlp, void* stream, int64_t B, const uint16_t* x_bf16, float* out);
 /* One AdamW step on a batch: y_feas [B] in {0,1}, y_cost [B] (log(1+J), used where feasible),
- * y_traj / traj_mask [B, 720] (outputs beyond 2 + 720 get no gradient).  out_dim >= 722.
+ * y_traj / traj_mask [B, 720] (outputs beyond 2 + 720 get no gradient; y_traj 8-byte and
+ * traj_mask 16-byte aligned, B * out_dim < 2^31, else COMET_EINVAL).  out_dim >= 722.
  * loss (device, 3 floats, may be NULL): mean BCE,
  * cost MSE over feasible samples, warm-start MSE over the mask, before the step. */
 comet_status comet_mlp_train_step(comet_mlp* mlp, void* stream, int64_t B, const uint16_t* x_bf16,

@@ -314,7 +314,7 @@ __global__ void k_refresh(const float* W, int N, int K, bf16* Wb, bf16* WT) {
 // cnt[0] += sum of feasible flags, cnt[1] += sum of mask entries (cnt zeroed before)
 // Loss reductions run in two deterministic stages: LOSS_BLOCKS blocks stride over the
 // elements and write one partial per block, k_reduce_partials adds them in block order.
-constexpr int LOSS_BLOCKS = 512;
+constexpr int LOSS_BLOCKS = 1024;
 
 // sum over the 256 threads of a block; the result is valid in thread 0
 __device__ inline float block_sum(float v, float* red) {
@@ -325,14 +325,20 @@ __device__ inline float block_sum(float v, float* red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
-// partials of the two normalisers: feasible samples, warm-start mask entries
+// partials of the two normalisers: feasible samples, warm-start mask entries (the mask
+// [B][W] is read as float4: W is a multiple of 4)
 __global__ __launch_bounds__(256) void k_loss_counts(int B, int W, const float* y_feas, const float* mask,
                                                      float* part) {
   __shared__ float red[4];
-  const long n = (long)B * W, stride = (long)gridDim.x * blockDim.x;
+  const unsigned n4 = (unsigned)B * (unsigned)(W / 4), stride = gridDim.x * blockDim.x;
+  const unsigned t0 = blockIdx.x * blockDim.x + threadIdx.x;
+  const float4* m4 = reinterpret_cast<const float4*>(mask);
   float c = 0.f, a = 0.f;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) c += mask[i];
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < B; i += stride) a += y_feas[i];
+  for (unsigned i = t0; i < n4; i += stride) {
+    const float4 v = m4[i];
+    c += (v.x + v.y) + (v.z + v.w);
+  }
+  for (unsigned i = t0; i < (unsigned)B; i += stride) a += y_feas[i];
   const float sa = block_sum(a, red);
   const float sc = block_sum(c, red);
   if (threadIdx.x == 0) {
@@ -353,41 +359,48 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const float* part, int 
   }
 }
 
-// dL/dY of the combined loss and per-block partials of the three loss terms
+// dL/dY of the combined loss and per-block partials of the three loss terms.  Threads
+// stride over pairs of adjacent outputs: O and W are even and the warm-start block starts
+// at column 2, so every pair is 8-byte aligned in Y, dY and the targets and its two BF16
+// gradients fill one 4-byte word.  B * O < 2^31 (checked by the caller).
 __global__ __launch_bounds__(256) void k_loss_grad(int B, int O, int Wn, const float* Y, const float* y_feas,
                                                    const float* y_cost, const float* y_traj, const float* mask,
                                                    const float* cnt, float* dY, bf16* dYb, float* part) {
   __shared__ float red[4];
-  const float nf = fmaxf(cnt[0], 1.f), nm = fmaxf(cnt[1], 1.f);
-  float acc[3] = {0.f, 0.f, 0.f};
-  for (int b = blockIdx.x; b < B; b += gridDim.x)   // one output row per block pass
-    for (int o = threadIdx.x; o < O; o += blockDim.x) {
-      const long i = (long)b * O + o;
-      float g = 0.f;
-      if (o == 0) {
-        const float x = Y[i], yv = y_feas[b];
-        acc[0] += (fmaxf(x, 0.f) - x * yv + log1pf(expf(-fabsf(x)))) / (float)B;
-        g = (1.f / (1.f + expf(-x)) - yv) / (float)B;
-      } else if (o == 1) {
-        const float f = y_feas[b], d = Y[i] - y_cost[b];
-        acc[1] += f * d * d / nf;
-        g = 2.f * f * d / nf;
-      } else if (o - 2 < Wn) {
-        const long e = (long)b * Wn + (o - 2);
-        const float m = mask[e], d = Y[i] - y_traj[e];
-        acc[2] += m * d * d / nm;
-        g = 2.f * m * d / nm;
-      }
-      dY[i] = g;
-      dYb[i] = to_bf16(g);
+  const float inv_b = 1.f / (float)B, inv_f = 1.f / fmaxf(cnt[0], 1.f), inv_m = 1.f / fmaxf(cnt[1], 1.f);
+  const unsigned half = (unsigned)O / 2u, n = (unsigned)B * half, stride = gridDim.x * blockDim.x;
+  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+  for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+    const unsigned b = t / half, p = t - b * half;
+    const long i = (long)b * O + 2 * p;
+    const float2 y = *reinterpret_cast<const float2*>(Y + i);
+    float gx = 0.f, gy = 0.f;
+    if (p == 0) {                                     // feasibility logit, predicted cost
+      const float yv = y_feas[b], x = y.x;
+      acc0 += fmaxf(x, 0.f) - x * yv + log1pf(expf(-fabsf(x)));
+      gx = (1.f / (1.f + expf(-x)) - yv) * inv_b;
+      const float d = y.y - y_cost[b];
+      acc1 += yv * d * d;
+      gy = 2.f * yv * d * inv_f;
+    } else if (2 * p - 2 < (unsigned)Wn) {            // warm-start samples
+      const long e = (long)b * Wn + (2 * p - 2);
+      const float2 m = *reinterpret_cast<const float2*>(mask + e);
+      const float2 yt = *reinterpret_cast<const float2*>(y_traj + e);
+      const float d0 = y.x - yt.x, d1 = y.y - yt.y;
+      acc2 += m.x * d0 * d0 + m.y * d1 * d1;
+      gx = 2.f * m.x * d0 * inv_m;
+      gy = 2.f * m.y * d1 * inv_m;
     }
-  const float s0 = block_sum(acc[0], red);
-  const float s1 = block_sum(acc[1], red);
-  const float s2 = block_sum(acc[2], red);
+    *reinterpret_cast<float2*>(dY + i) = make_float2(gx, gy);
+    *reinterpret_cast<unsigned*>(dYb + i) = (unsigned)to_bf16(gx) | ((unsigned)to_bf16(gy) << 16);
+  }
+  const float s0 = block_sum(acc0, red);
+  const float s1 = block_sum(acc1, red);
+  const float s2 = block_sum(acc2, red);
   if (threadIdx.x == 0) {
-    part[blockIdx.x * 4 + 0] = s0;
-    part[blockIdx.x * 4 + 1] = s1;
-    part[blockIdx.x * 4 + 2] = s2;
+    part[blockIdx.x * 4 + 0] = s0 * inv_b;
+    part[blockIdx.x * 4 + 1] = s1 * inv_f;
+    part[blockIdx.x * 4 + 2] = s2 * inv_m;
   }
 }
 
@@ -926,7 +939,9 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
                                   const float* y_cost, const float* y_traj, const float* traj_mask, float lr,
                                   float weight_decay, float* loss) {
   if (!m || !x_bf16 || !y_feas || !y_cost || !y_traj || !traj_mask) return COMET_EINVAL;
-  if (B < 1 || B > m->max_batch || !(lr >= 0.f)) return COMET_EINVAL;
+  if (B < 1 || B > m->max_batch || B * (int64_t)m->out_dim >= (1ll << 31) || !(lr >= 0.f)) return COMET_EINVAL;
+  // the loss kernel reads the warm-start targets in pairs and the mask in fours
+  if ((uintptr_t)y_traj % 8 || (uintptr_t)traj_mask % 16) return COMET_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   const int Bi = (int)B, O = m->out_dim, Wn = 6 * WS_SLOTS * WS_CH;
   if (hipMemcpyAsync(m->H[0], x_bf16, 2 * B * m->in_dim, hipMemcpyDeviceToDevice, s) != hipSuccess) return COMET_EHIP;
