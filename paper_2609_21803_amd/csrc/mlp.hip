@@ -718,11 +718,13 @@ int gemm(hipStream_t s, int M, int N, int K, const bf16* A, long lda, const bf16
   return nz;
 }
 
-// splits of the batch contraction of a weight-gradient GEMM: enough blocks to fill the
-// chip, at least 256 batch rows per split
+// splits of the batch contraction of a weight-gradient GEMM: about 512 blocks (two per
+// CU), at least 256 batch rows per split.  Each split adds an FP32 slab of the gradient
+// that k_sum_slabs reads back; aiming at 1,024 blocks doubled that traffic and made the
+// 8,192-sample training step 6 % slower, aiming at 256 left the products short of blocks.
 int wgrad_splits(int M, int N, int B) {
   const long blocks = (long)nblk(N, GBN) * nblk(M, GBM);
-  const long want = (1024 + blocks - 1) / blocks;
+  const long want = (512 + blocks - 1) / blocks;
   return (int)std::max<long>(1, std::min<long>({want, (long)B / 256, (long)MAX_SPLIT}));
 }
 
