@@ -63,13 +63,15 @@ enum { EPI_HIDDEN = 0, EPI_OUT = 1, EPI_DX = 2, EPI_PARTIAL = 3 };
 
 struct Epi {
   const float* bias;   // [N] (EPI_HIDDEN, EPI_OUT)
-  float* z;            // FP32 pre-activation out (EPI_HIDDEN) / FP32 result (EPI_OUT, EPI_PARTIAL) / dZ (EPI_DX)
+  float* z;            // FP32 pre-activation out (EPI_HIDDEN) / FP32 result (EPI_OUT, EPI_PARTIAL)
   bf16* h;             // BF16 activation (EPI_HIDDEN) / BF16 gradient (EPI_DX)
   const float* zprev;  // pre-activation of the layer below (EPI_DX)
   long ldc;            // row stride of the outputs
   long slab;           // EPI_PARTIAL: elements between the partial-sum slabs
   bf16* ht;            // optional (EPI_HIDDEN, EPI_DX): the BF16 output again, transposed: ht[n * ldt + m]
   long ldt;            // row stride of ht (a multiple of 4)
+  float* colpart;      // EPI_DX: column sums of dZ over each wave's 64 rows, row 2 * blockIdx.y + wm,
+                       // stride ldc (the layer's bias gradient is their sum; dZ itself is not stored)
 };
 
 constexpr int GBM = 128, GBN = 64, GBK = 32, GLD = GBK + 8;   // LDS row: 32 bf16 + 8 pad (80 bytes)
@@ -177,6 +179,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
   // passed, so no wave still reads it)
   static_assert(GBN * (GBM + 8) <= 2 * GBM * GLD, "transposed tile exceeds the A ring");
   bf16 (*Tt)[GBM + 8] = reinterpret_cast<bf16 (*)[GBM + 8]>(&As[0][0][0]);
+  float cs[2] = {0.f, 0.f};   // EPI_DX: this lane's share of the wave's column sums (column j)
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
           zo[o] = v + ep.bias[n];
         } else if (EPI == EPI_DX) {
           const float d = v * gelu_grad(ep.zprev[o]);
-          zo[o] = d;
+          cs[j] += d;
           const bf16 hb = to_bf16(d);
           ep.h[o] = hb;
           tv[r] = (short)hb;
@@ -212,6 +215,17 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
       // the transposed copy is staged in LDS (the operand ring is free after the last step)
       if (TR && ep.ht) *reinterpret_cast<bf16x4*>(&Tt[n - n0][mb - m0]) = tv;
     }
+  if (EPI == EPI_DX) {
+    // lanes l, l^16, l^32, l^48 hold the same column over the wave's 4 row groups
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      float v = cs[j];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      const int n = n0 + wn * 32 + j * 16 + lane;
+      if (lane < 16 && n < N) ep.colpart[(long)(2 * blockIdx.y + wm) * ep.ldc + n] = v;
+    }
+  }
   if (TR && ep.ht) {
     // write the 64 x 128 transposed block tile row by row, 16 bytes per thread and chunk
     __syncthreads();
@@ -684,7 +698,7 @@ struct comet_mlp {
   std::vector<bf16*> H;                // activations (H[0] = X0) [B][dim]
   float *Y = nullptr, *dY = nullptr;   // output and its gradient [B][out]
   bf16 *dYb = nullptr;
-  float *dZ = nullptr;                 // FP32 gradient buffer [B][hidden]
+  float *dzcol = nullptr;              // per-wave column sums of a hidden gradient [2 ceil(B/128)][hidden]
   bf16 *dZb[2] = {nullptr, nullptr};   // BF16 gradient ping-pong [B][max(hidden, out)]
   float *cnt = nullptr, *lossd = nullptr;
   float* part = nullptr;               // partial sums: split weight gradients / bias column sums
@@ -844,7 +858,7 @@ comet_status comet_mlp_create(int32_t in_dim, int32_t hidden, int32_t layers, in
   A((void**)&m->Y, 4 * B * out_dim);
   A((void**)&m->dY, 4 * B * out_dim);
   A((void**)&m->dYb, 2 * B * out_dim);
-  A((void**)&m->dZ, 4 * B * hidden);
+  A((void**)&m->dzcol, 4 * 2 * ((B + GBM - 1) / GBM) * hidden);
   A((void**)&m->dZb[0], 2 * B * std::max(hidden, out_dim));
   A((void**)&m->dZb[1], 2 * B * std::max(hidden, out_dim));
   m->ldt = (long)((B + 7) / 8 * 8);
@@ -887,7 +901,7 @@ comet_status comet_mlp_create(int32_t in_dim, int32_t hidden, int32_t layers, in
 
 void comet_mlp_destroy(comet_mlp* m) {
   if (!m) return;
-  std::vector<void*> ps = {m->P, m->G, m->Mm, m->Vv, m->Wb, m->WT, m->Y, m->dY, m->dYb, m->dZ, m->dZb[0], m->dZb[1],
+  std::vector<void*> ps = {m->P, m->G, m->Mm, m->Vv, m->Wb, m->WT, m->Y, m->dY, m->dYb, m->dzcol, m->dZb[0], m->dZb[1],
                            m->cnt, m->lossd, m->part, m->red};
   for (auto* h : m->H) ps.push_back(h);
   for (auto* z : m->Z) ps.push_back(z);
@@ -982,14 +996,19 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
                        : gemm<false, false, EPI_PARTIAL>(s, N, K, Bi, g, N, m->H[l], K, ew, nullptr, split);
     hipLaunchKernelGGL(k_sum_slabs, dim3(nblk((long long)N * K, 256)), dim3(256), 0, s, m->part, nzs, (long)N * K,
                        m->G + m->woff[l]);
-    const int ry = std::max(1, std::min(COLSUM_ROWS, (Bi + 31) / 32));
-    hipLaunchKernelGGL(k_colsum_part, dim3(nblk(N, 256), ry), dim3(256), 0, s, g32, Bi, N, m->part);
-    hipLaunchKernelGGL(k_sum_rows, dim3(nblk(N, 64)), dim3(256), 0, s, m->part, ry, (long)N, m->G + m->boff[l]);
+    if (g32) {   // output layer: column sums of the FP32 loss gradient
+      const int ry = std::max(1, std::min(COLSUM_ROWS, (Bi + 31) / 32));
+      hipLaunchKernelGGL(k_colsum_part, dim3(nblk(N, 256), ry), dim3(256), 0, s, g32, Bi, N, m->part);
+      hipLaunchKernelGGL(k_sum_rows, dim3(nblk(N, 64)), dim3(256), 0, s, m->part, ry, (long)N, m->G + m->boff[l]);
+    } else {     // hidden layers: the per-wave column sums left by the input-gradient epilogue
+      hipLaunchKernelGGL(k_sum_rows, dim3(nblk(N, 64)), dim3(256), 0, s, m->dzcol, 2 * (int)nblk(Bi, GBM), (long)N,
+                         m->G + m->boff[l]);
+    }
     if (l > 0) {
       // dZ_{l-1} [B][K] = (G [B][N] . W_l [N][K]) * gelu'(Z_{l-1}), W_l read through its
       // transpose so both operands are contraction-contiguous
       Epi ex{};
-      ex.z = m->dZ;
+      ex.colpart = m->dzcol;
       ex.h = m->dZb[cur];
       ex.zprev = m->Z[l - 1];
       ex.ldc = K;
@@ -999,7 +1018,7 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
       }
       gemm<true, true, EPI_DX>(s, Bi, K, N, g, N, m->WT + m->wboff[l], N, ex);
       g = m->dZb[cur];
-      g32 = m->dZ;
+      g32 = nullptr;
       cur ^= 1;
     }
   }
