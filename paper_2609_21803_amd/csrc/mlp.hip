@@ -244,21 +244,30 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
   }
 }
 
-// out[c * ldo + r] = in[r * ldi + c] for a rows x cols BF16 matrix, through 64 x 64 LDS tiles
+// out[c * ldo + r] = in[r * ldi + c] for a rows x cols BF16 matrix, through 64 x 64 LDS tiles.
+// Both sides move pairs of BF16 values as 4-byte words: cols, ldi and ldo are even, rows a
+// multiple of 8 and the buffers 4-byte aligned (the callers' layouts).  The LDS row stride
+// of 65 values keeps the column reads on distinct banks.
 __global__ __launch_bounds__(256) void k_transpose_bf16(const bf16* __restrict__ in, long ldi, int rows, int cols,
                                                         bf16* __restrict__ out, long ldo) {
-  __shared__ bf16 tile[64][66];
-  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64, tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  __shared__ bf16 tile[64][65];
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64, p = threadIdx.x & 31, q = threadIdx.x >> 5;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int r = r0 + ty + 4 * k, c = c0 + tx;
-    if (r < rows && c < cols) tile[ty + 4 * k][tx] = in[(long)r * ldi + c];
+  for (int k = 0; k < 8; ++k) {   // row q + 8k of the tile, columns 2p, 2p + 1
+    const int r = r0 + q + 8 * k, c = c0 + 2 * p;
+    unsigned v = 0;
+    if (r < rows && c < cols) v = *reinterpret_cast<const unsigned*>(in + (long)r * ldi + c);
+    tile[q + 8 * k][2 * p] = (bf16)(v & 0xffffu);
+    tile[q + 8 * k][2 * p + 1] = (bf16)(v >> 16);
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int c = c0 + ty + 4 * k, r = r0 + tx;
-    if (r < rows && c < cols) out[(long)c * ldo + r] = tile[tx][ty + 4 * k];
+  for (int k = 0; k < 8; ++k) {   // output row c = column q + 8k of the tile, input rows 2p, 2p + 1
+    const int c = c0 + q + 8 * k, r = r0 + 2 * p;
+    if (c >= cols || r >= rows) continue;
+    const unsigned v = (unsigned)tile[2 * p][q + 8 * k] | ((unsigned)tile[2 * p + 1][q + 8 * k] << 16);
+    if (r + 1 < rows) *reinterpret_cast<unsigned*>(out + (long)c * ldo + r) = v;
+    else out[(long)c * ldo + r] = (bf16)(v & 0xffffu);
   }
 }
 
