@@ -369,7 +369,7 @@ def learned_flip_leg(native, I, torch):
 
 def policy_leg(native, I, torch):
     """Allocation policies on the same evaluator at equal evaluation budgets: Alg. 1's
-    expansion vs uniform sampling without replacement (the ablation of Sec. V), time to the
+    expansion vs uniform sampling without replacement (the baseline of Sec. IV-B), time to the
     first feasible plan, plans found and returned cost."""
     t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
 

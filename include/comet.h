@@ -40,8 +40,8 @@ typedef enum {
   COMET_ESTATE = -4  /* call not valid in the context's current state */
 } comet_status;
 
-/* Tasks: planar pushing (Sec. IV) with a fixed step, bimanual flipping of a box in a
- * vertical plane (Sec. V), and planar pushing with optimised timing (Sec. III-C: the
+/* Tasks: planar pushing (Sec. IV-A) with a fixed step, bimanual flipping of a box in a
+ * vertical plane (Sec. IV-B), and planar pushing with optimised timing (Sec. III-C: the
  * interval durations become controls; Sec. IV-A runs pushing with an optimised time step
  * under a duration bound); their dimensions and layouts are given at comet_evaluate. */
 typedef enum { COMET_TASK_PUSH = 0, COMET_TASK_FLIP = 1, COMET_TASK_PUSH_TIMED = 2 } comet_task;
@@ -215,7 +215,7 @@ comet_status comet_last_kernel_ms(comet_ctx* ctx, float* ms);
  * Ranking is by (M, key) with NaN as +inf; refinement ranks feasible orders by (J, key) and
  * returns the smallest refined J among refined-feasible orders (ties by key).
  *   policy             COMET_POLICY_EXPAND (0): Alg. 1 as above.  COMET_POLICY_UNIFORM (1):
- *                      the uniform-sampling allocation of the ablations (Sec. V): every batch,
+ *                      the uniform-sampling baseline of Sec. IV-B: every batch,
  *                      the first one included, is drawn instead of generated, complete orders
  *                      without replacement; seed_max_segments, radius and frontier_W are
  *                      unused.  Round s makes sample_draws draws, numbered from s *
@@ -230,7 +230,7 @@ comet_status comet_last_kernel_ms(comet_ctx* ctx, float* ms);
  *                      count, every admissible order is.  Refinement and the returned plan are
  *                      as for the expansion.
  *   sample_draws       draws per round (policy 1; 1 .. 2^27)
- *   policy COMET_POLICY_MCTS (2): the UCT allocation of the ablations (Sec. IV-D, V) on the
+ *   policy COMET_POLICY_MCTS (2): the UCT allocation of the baselines (Sec. IV-A, IV-B) on the
  *                      same evaluator and refinement, batch_B selections per update (the
  *                      pool P), exploration constant uct_c (the paper's 0.8), rollouts from
  *                      the SplitMix64 stream of sample_seed (as above).  The tree is over
@@ -353,8 +353,8 @@ comet_status comet_mlp_train_step(comet_mlp* mlp, void* stream, int64_t B, const
  *     (px, 0, theta), table friction; slot = one-hot finger-1 code (13), one-hot finger-2
  *     code (13), one-hot table mode (5), intervals / 15, present flag.
  *   COMET_TASK_PUSH_TIMED: as COMET_TASK_PUSH.
- * The network proposes orders and warm starts (Sec. IV-C); its input encoding is not fixed
- * by the paper.  Other tasks: COMET_EINVAL. */
+ * The network proposes orders and warm starts; it is an addition to the paper's method
+ * (the paper has no learned component), so no passage defines it.  Other tasks: COMET_EINVAL. */
 comet_status comet_mlp_encode(comet_task task, void* stream, int64_t B, const float* x0, const float* goal,
                               const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                               int32_t smax, int32_t in_dim, uint16_t* x_bf16);
@@ -364,7 +364,9 @@ comet_status comet_mlp_encode(comet_task task, void* stream, int64_t B, const fl
  * channels) by linear interpolation of the rows, traj_mask [B, 720] = 1 on the learned
  * channels of present segments of feasible orders.  Learned channels: pushing, the 7 row
  * entries (channel 7 zero); timed pushing, the 8 row entries (channel 7 the duration);
- * flipping, the 8 state entries. */
+ * flipping, the 8 state entries.  A sequence whose segment count is outside [1, smax], or
+ * whose live knot counts are not each >= 1 with a sum <= nmax, is treated as empty: its
+ * y_traj and traj_mask rows are zero. */
 comet_status comet_mlp_targets(comet_task task, void* stream, int64_t B, const float* traj, int32_t nmax,
                                const int32_t* nseg, const int32_t* knots, int32_t smax, const uint8_t* feasible,
                                const float* cost, float* y_feas, float* y_cost, float* y_traj, float* traj_mask);
@@ -378,7 +380,9 @@ comet_status comet_mlp_targets(comet_task task, void* stream, int64_t B, const f
  *     and `modes` (required): accelerations and face-coordinate rates by forward
  *     differences over dt = 0.1 s, a contact finger pushes with mg/2 normal force (a
  *     sliding one on its cone edge in the slip direction), a free finger zero; the last
- *     row's controls are zero. */
+ *     row's controls are zero.
+ * A sequence with invalid segment or knot counts (as for comet_mlp_targets) gets zero rows
+ * with x0 in row 0. */
 comet_status comet_mlp_decode_warm(comet_task task, void* stream, int64_t B, const float* out, int32_t out_dim,
                                    const float* x0, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                                    int32_t smax, int32_t nmax, float* warm);

@@ -107,6 +107,8 @@ def lib():
                                     C.POINTER(SolverParams), C.c_int32, P, P, P, P, P, P, P, C.c_int64]
         L.oracle_expand_next.argtypes = [C.c_int64, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int64, P]
         L.oracle_expand_next.restype = C.c_int64
+        L.oracle_merit.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
+        L.oracle_merit.restype = C.c_double
         L.oracle_enumerate.argtypes = [P, P, C.c_double, C.c_int32, C.POINTER(ExpandParams),
                                        C.POINTER(SolverParams), C.POINTER(SolverParams), C.c_int32, P, P, P, P]
         _lib = L
@@ -316,6 +318,11 @@ def enumerate_all(x0, goal, mu, ep: Expand, kmin=1, params: Params | None = None
     lib().oracle_enumerate(_p(x0), _p(goal), float(mu), kmin, C.byref(epc), C.byref(p1), C.byref(p2),
                            nthreads or default_threads(), C.byref(key), C.byref(J), C.byref(v), C.byref(n))
     return dict(best_key=int(key.value), best_cost=J.value, best_viol=v.value, evaluated=int(n.value))
+
+
+def merit(J: float, v: float, eps: float = 1e-5, mu_merit: float = 100.0) -> float:
+    """Eq. (5) merit of one evaluated order (NaN -> +inf), as the expansion ranks it."""
+    return float(lib().oracle_merit(float(J), float(v), float(eps), float(mu_merit)))
 
 
 def expand_next(keys, merit, n_modes=12, kcap=3, radius=1, frontier_W=4096, room=131072):

@@ -1162,6 +1162,9 @@ static double merit_of(double J, double v, double eps, double mu_merit) {
   return isnan(M) ? INFINITY : M;
 }
 
+/* Eq. (5) merit of one evaluated order, exported for the tests */
+double oracle_merit(double J, double v, double eps, double mu_merit) { return merit_of(J, v, eps, mu_merit); }
+
 /* knot allocation of an order: a fixed count per segment, or (if that is 0) a      */
 /* total of n_total intervals split as evenly as possible, the remainder going to   */
 /* the earliest segments.                                                           */

@@ -15,7 +15,7 @@
  * Sec. III-C (defects x_{k+1} - F(x_k, u_k), masked rows in fixed slots); the local
  * solves S_k = H_k + rho I + A^T A / mu over w_k = (u_k, x_{k+1}) with the Cholesky PD
  * test and damping retries; trial step lengths; Eq. (4) scoring.  The task model is the
- * bimanual flip of Sec. V (quasi-static wrench balance with the table reaction
+ * bimanual flip of Sec. IV-B (quasi-static wrench balance with the table reaction
  * eliminated, fingers on faces with Coulomb cones, support transitions by pivoting) on
  * the box of the benchmark configuration.  Readings of what the paper leaves open are
  * restated where they are used:
@@ -1013,7 +1013,7 @@ int flip_score(int32_t nseg, const int32_t *modes, const int32_t *knots, const d
 }
 
 /* ------------------------------------------------------------------------------ */
-/* Language of admissible orders (Sec. V, transition rules, with the readings:       */
+/* Language of admissible orders (Sec. IV-B, transition rules, with the readings:    */
 /* fingers never share a face; a finger changes face only through a free segment; a  */
 /* pivot has at least one finger in contact; no two consecutive segments are equal;  */
 /* consecutive pivots keep their direction; no finger touches the face on the table  */

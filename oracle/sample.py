@@ -1,4 +1,4 @@
-"""Oracle of the uniform-sampling allocation policy (the ablation of Sec. V that draws
+"""Oracle of the uniform-sampling allocation policy (the baseline of Sec. IV-B that draws
 complete admissible orders uniformly without replacement), over the evaluator oracles.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).

@@ -67,9 +67,11 @@ __global__ void k_queue_reset(unsigned long long* qhead, int* hist, int nbins) {
 __device__ inline int seq_len(const EvalArgs& A, int64_t b) {
   const int K = A.nseg[b];
   if (K < 1 || K > A.smax) return 0;
+  // each count is clamped to nmax + 1 and the sum saturates there, so it cannot wrap
+  const int cap = A.nmax + 1;
   int N = 0;
-  for (int j = 0; j < K; ++j) N += max(A.knots[b * A.smax + j], 0);
-  return min(N, A.nmax + 1);
+  for (int j = 0; j < K; ++j) N = min(N + min(max(A.knots[b * A.smax + j], 0), cap), cap);
+  return N;
 }
 
 // Counts per length are gathered in LDS first and added to the global bins once per block

@@ -93,7 +93,7 @@ __host__ __device__ inline unsigned long long raw_decode(unsigned long long p, l
   return (e2 < raw1_count(key_len(k1), M, kcap)) ? raw1_decode(k1, e2, M, kcap) : EMPTY;
 }
 
-// Admissibility of a flipping order (the transition rules of Sec. V, with the readings
+// Admissibility of a flipping order (the transition rules of Sec. IV-B, with the readings
 // of the flip model): fingers never share a face; a finger changes face only through a
 // free segment; a pivot keeps at least one finger in contact; no two consecutive segments
 // are equal; consecutive pivots keep their direction; no finger touches the face on the

@@ -1,5 +1,5 @@
 // flip.hip -- batched mode-conditioned TO evaluator for bimanual flipping of a box in a
-// vertical plane (the bimanual task of Sec. V: quasi-static wrench balance with the table
+// vertical plane (the bimanual task of Sec. IV-B: quasi-static wrench balance with the table
 // reaction eliminated, fingers on faces with Coulomb cones, support transitions by
 // pivoting), solved with the augmented-Lagrangian / Gauss-Newton scheme of Sec. III-C.
 //
@@ -1014,7 +1014,7 @@ __global__ __launch_bounds__(64, 2) void k_flip_solve(FlipArgs A) {
     int fs = 3, turns = 0, prev_g = -1;
     for (int j = 0; valid && j < K; ++j) {
       const int id = A.modes[b * A.smax + j], n = A.knots[b * A.smax + j];
-      if (id < 0 || id >= NMODES || n < 1 || N + n > A.nmax) {
+      if (id < 0 || id >= NMODES || n < 1 || n > A.nmax - N) {   // room left, so no sum can wrap
         valid = 0;
         break;
       }

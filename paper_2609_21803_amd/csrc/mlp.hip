@@ -560,6 +560,21 @@ __global__ void k_encode_flip(long B, const float* x0, const float* goal, const 
   X[i] = to_bf16(v);
 }
 
+// Segment count of a sequence whose live knot counts are each >= 1 and sum to at most
+// nmax, else 0 (the sequence is then treated as empty).  Counts are compared with the room
+// left, so no sum of large counts can wrap.
+__device__ inline int checked_segments(const int32_t* nseg, const int32_t* knots, long b, int smax, int nmax) {
+  const int K = nseg[b];
+  if (K < 1 || K > smax) return 0;
+  int N = 0;
+  for (int j = 0; j < K; ++j) {
+    const int n = knots[b * smax + j];
+    if (n < 1 || n > nmax - N) return 0;
+    N += n;
+  }
+  return K;
+}
+
 // Warm-start targets: per segment, 15 samples at normalised times i/14 by linear
 // interpolation of the trajectory rows; channels 0..nch-1 of each row (pushing: the 7
 // state and control entries, flipping: the 8 states), row width `row`.
@@ -568,14 +583,14 @@ __global__ void k_targets(long B, const float* traj, int nmax, int row, int nch,
                           float* y_cost, float* y_traj, float* mask) {
   const long b = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
-  const int K = nseg[b];
+  const int K = checked_segments(nseg, knots, b, smax, nmax);
   const float f = feas[b] ? 1.f : 0.f;
   y_feas[b] = f;
   y_cost[b] = feas[b] ? log1pf(fmaxf(cost[b], 0.f)) : 0.f;
   const float* T = traj + b * (long)(nmax + 1) * row;
   int k0 = 0;
   for (int j = 0; j < 6; ++j) {
-    const bool live = j < K && j < smax;
+    const bool live = j < K;
     const int nj = live ? knots[b * smax + j] : 0;
     for (int i = 0; i < WS_SLOTS; ++i) {
       const float p = (float)i / (WS_SLOTS - 1) * (float)nj;
@@ -604,7 +619,7 @@ __global__ void k_decode_warm(long B, const long long* B_dev, const float* Y, in
   const long Bn = B_dev ? *B_dev : B;
   const long b = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= Bn) return;
-  const int K = nseg[b];
+  const int K = checked_segments(nseg, knots, b, smax, nmax);
   const float* y = Y + b * (long)O + 2;
   float* Wr = warm + b * (long)(nmax + 1) * width;
   for (int r = 0; r < (nmax + 1) * width; ++r) Wr[r] = 0.f;
@@ -641,7 +656,7 @@ __global__ void k_decode_warm_flip(long B, const long long* B_dev, const float* 
   const long Bn = B_dev ? *B_dev : B;
   const long b = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= Bn) return;
-  const int K = nseg[b];
+  const int K = checked_segments(nseg, knots, b, smax, nmax);
   const float* y = Y + b * (long)O + 2;
   float* Wr = warm + b * (long)(nmax + 1) * ROWF;
   for (int r = 0; r < (nmax + 1) * ROWF; ++r) Wr[r] = 0.f;

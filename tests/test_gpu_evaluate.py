@@ -1,23 +1,18 @@
 """GPU parity of the HIP evaluator against the FP64 oracle (called through the C ABI).
 
-Tolerances (stated for the FP32/FP64 mixed GPU path against the FP64 oracle):
-  * identical feasible flags on margin sequences, i.e. where the oracle's violation is
-    <= 0.1 eps_feas or >= eps_feas + 1e-3;
-  * objective within 1e-4 relative and violation within 1e-5 absolute where both paths
-    return a feasible trajectory on a margin sequence;
-  * at least 99.5 % of margin sequences meet these on the two-segment workload and 98.5 %
-    on the long ragged and full-size workloads.  A finite-budget local solver on a
-    nonconvex problem can take another trial step near a tie and end in another local
-    point: the FP64 oracle itself changes its result on about 1 % of the long ragged
-    sequences when the goal is perturbed by one float32 ulp (printed by
-    test_oracle_self_sensitivity), so agreement beyond that rate is not a property of the
-    algorithm.
+Sequence by sequence (the rule of tests/parity.py): on every margin sequence (oracle
+violation <= 0.1 eps_feas or >= eps_feas + 1e-3) the device and the oracle return the same
+feasible flag, and where both are feasible the objective within 1e-4 relative and the
+violation within 1e-5 absolute.  A disagreeing margin sequence is excused only where the
+FP64 oracle itself changes its answer under one-ulp moves of the inputs (a decision
+boundary of the local solver), and each excused sequence is printed.
 Inputs are rounded to float32 before they reach the oracle, so both sides solve the same
 problem.
 """
 import numpy as np
 import pytest
 
+import parity
 from paper_2609_21803_amd import instances as I
 
 pytestmark = pytest.mark.gpu
@@ -49,21 +44,12 @@ def run_oracle(batch, nmax, params=None, warm=None):
                            batch["knots"], params=params, nmax=nmax, warm=warm)
 
 
-def compare(g, o, label, min_frac=0.985):
-    ov = o["viol"]
-    margin = (ov <= 0.1 * EPS) | (ov >= EPS + 1e-3)
-    flag_ok = g["feasible"] == o["feasible"]
-    both = (g["feasible"] == 1) & (o["feasible"] == 1)
-    rel = np.abs(g["cost"].astype(np.float64) - o["cost"]) / np.maximum(np.abs(o["cost"]), 1e-12)
-    val_ok = np.where(both, (rel <= 1e-4) & (np.abs(g["viol"] - ov) <= 1e-5), True)
-    ok = flag_ok & val_ok
-    frac = ok[margin].mean() if margin.any() else 1.0
-    print(f"[{label}] n={len(ov)} margin={margin.sum()} feasible(oracle)={o['feasible'].mean():.3f} "
-          f"feasible(gpu)={g['feasible'].mean():.3f} flag-agree={flag_ok[margin].mean():.4f} "
-          f"cost-agree(both feasible)={((rel <= 1e-4) | ~both)[margin].mean():.4f} pass={frac:.4f} "
-          f"median rel={np.median(rel[both & margin]) if (both & margin).any() else 0:.2e}")
-    assert frac >= min_frac, (label, frac)
-    return ok, margin
+def compare(g, o, batch, label, nmax, params=None, warm=None, idx=None):
+    """The per-sequence rule; excuses are checked by re-solving nudged inputs with the
+    oracle under the same parameters (and the same warm start, if any)."""
+    def solve(sub, rows):
+        return run_oracle(sub, nmax, params=params, warm=None if warm is None else warm[rows])
+    return parity.check(g, o, batch, solve, label, idx=idx)
 
 
 def test_tiny_workload_all_orders_match_oracle(orc):
@@ -72,7 +58,7 @@ def test_tiny_workload_all_orders_match_oracle(orc):
     g = run_gpu(b, 10)
     g["ctx"].check()
     o = run_oracle(b, 10)
-    compare(g, o, "tiny", min_frac=0.995)
+    compare(g, o, b, "tiny", 10)
     # brute-force mode selection over the 144 orders picks the same order per pair where
     # the best feasible cost beats the runner-up by more than 1e-3 relative
     for p in range(8):
@@ -95,7 +81,7 @@ def test_line_search_trial_counts_match_oracle(orc, trials):
     g = run_gpu(b, 10, params=native.SolverParams(ls_trials=trials))
     g["ctx"].check()
     o = run_oracle(b, 10, params=oracle.Params(ls_trials=trials))
-    compare(g, o, f"tiny, {trials} trials", min_frac=0.995)
+    compare(g, o, b, f"tiny, {trials} trials", 10, params=oracle.Params(ls_trials=trials))
 
 
 def test_ragged_batch_matches_oracle(orc):
@@ -104,7 +90,7 @@ def test_ragged_batch_matches_oracle(orc):
     nmax = int(I.n_intervals(b).max())
     g = run_gpu(b, 75)
     o = run_oracle(b, 75)
-    compare(g, o, "ragged")
+    compare(g, o, b, "ragged", 75)
     # trajectory rows beyond N are zero and row N carries u = 0
     N = I.n_intervals(b)
     for i in range(0, 2048, 97):
@@ -112,16 +98,15 @@ def test_ragged_batch_matches_oracle(orc):
     assert nmax <= 75
 
 
-def test_full_size_plain_workload_sampled(orc):
+def test_full_size_plain_workload_all_sequences(orc):
     """64 pairs x 1,728 three-segment orders (110,592 TOs) in the launch the benchmark
-    times; 384 sampled sequences checked against the oracle one by one."""
+    times; every sequence is compared with the oracle's (about a minute of the oracle on
+    16 host threads)."""
     b = I.push_plain()
     g = run_gpu(b, 24)
     g["ctx"].check()
-    idx = np.random.default_rng(11).choice(len(b["nseg"]), 384, replace=False)
-    o = run_oracle(I.subset(b, idx), 24)
-    gs = {k: g[k][idx] for k in ("cost", "viol", "feasible")}
-    compare(gs, o, "plain-sampled")
+    o = run_oracle(b, 24)
+    compare(g, o, b, "plain, all 110,592", 24)
     assert np.all(np.isfinite(g["cost"][g["feasible"] == 1]))
 
 
@@ -142,13 +127,17 @@ def test_closed_form_and_zero_goal_on_gpu(orc):
 
 def test_invalid_sequences_flagged_and_counted():
     from paper_2609_21803_amd import native
-    b = I.subset(I.push_tiny(), np.arange(6))
+    b = I.subset(I.push_tiny(), np.arange(8))
     b["modes"][1, 0] = 12           # out-of-range id
     b["nseg"][2] = 0                # no segment
     b["goal"][3, 0] = np.nan        # non-finite input
     b["knots"][4, 1] = 30           # more intervals than the context allows
+    # knot counts whose int32 sum wraps: four segments of 2^30 sum to 0 (mod 2^32), and
+    # INT32_MAX + 5 is negative; both must be rejected before any interval is written
+    b["nseg"][6], b["modes"][6, :4], b["knots"][6, :4] = 4, 3, 2 ** 30
+    b["knots"][7, :2] = (2 ** 31 - 1, 5)
     g = run_gpu(b, 10)
-    for i in (1, 2, 3, 4):
+    for i in (1, 2, 3, 4, 6, 7):
         assert np.isnan(g["cost"][i]) and np.isinf(g["viol"][i]) and g["feasible"][i] == 0
         assert g["stats"][i, 3] == 3
     assert np.isfinite(g["cost"][0]) and np.isfinite(g["cost"][5])
@@ -190,7 +179,7 @@ def test_warm_start_matches_oracle_with_same_warm_start(orc):
     warm = o["traj"].astype(np.float32)
     g = run_gpu(b, 10, warm=warm)
     o2 = run_oracle(b, 10, warm=warm.astype(np.float64))
-    compare(g, o2, "warm", min_frac=0.985)
+    compare(g, o2, b, "warm", 10, warm=warm.astype(np.float64))
 
 
 def test_refinement_budget_matches_oracle(orc):
@@ -202,12 +191,11 @@ def test_refinement_budget_matches_oracle(orc):
     g = run_gpu(b, 10, refine=1)
     prm = oracle.Params(**oracle.REFINE)
     o = run_oracle(b, 10, params=prm)
-    compare(g, o, "refine", min_frac=0.97)
-    gp = dict(b)
-    gp["goal"] = f32(b["goal"]) * (1 + 1.2e-7 * np.random.default_rng(2).choice([-1, 1], size=b["goal"].shape))
-    o2 = run_oracle(gp, 10, params=prm)
-    compare(dict(cost=o2["cost"], viol=o2["viol"], feasible=o2["feasible"]), o, "refine-oracle-vs-perturbed",
-            min_frac=0.9)
+    compare(g, o, b, "refine", 10, params=prm)
+    o2 = run_oracle(parity.nudge(b, np.random.default_rng(2)), 10, params=prm)
+    m = parity.margin_mask(o["viol"])
+    print(f"refinement budget: the oracle changes its answer on {(~parity.agrees(o2, o))[m].mean():.4f} of the "
+          f"margin sequences under one-ulp input moves")
 
 
 def test_row_scales_agree_with_oracle(orc):
@@ -217,15 +205,15 @@ def test_row_scales_agree_with_oracle(orc):
 
 
 def test_oracle_self_sensitivity(orc):
-    """Context for the bars above: how often the FP64 oracle disagrees with itself (same
-    tolerances) when the goal moves by one float32 ulp, on the long ragged workload."""
+    """Context for the excuses above: how often the FP64 oracle changes its own answer
+    when the inputs move by at most one float32 ulp, on the long ragged workload."""
     b = I.push_hetero(B=1024, seed=77)
     o = run_oracle(b, 75)
-    gp = dict(b)
-    gp["goal"] = f32(b["goal"]) * (1 + 1.2e-7 * np.random.default_rng(1).choice([-1, 1], size=b["goal"].shape))
-    o2 = run_oracle(gp, 75)
-    ok, margin = compare(dict(cost=o2["cost"], viol=o2["viol"], feasible=o2["feasible"]), o, "oracle-vs-perturbed",
-                         min_frac=0.97)
+    o2 = run_oracle(parity.nudge(b, np.random.default_rng(1)), 75)
+    m = parity.margin_mask(o["viol"])
+    frac = (~parity.agrees(o2, o))[m].mean()
+    print(f"oracle vs nudged oracle: {frac:.4f} of {m.sum()} margin sequences change")
+    assert frac < 0.05
 
 
 def test_schedules_give_identical_results_and_autotuner_picks_one():

@@ -1,4 +1,4 @@
-"""GPU MCTS allocation (UCT with virtual loss and random rollouts, Sec. IV-D / V) against the
+"""GPU MCTS allocation (UCT with virtual loss and random rollouts, Sec. IV-A / IV-B) against the
 MCTS oracle: the first batch (before any reward) is the oracle's selection bit for bit on
 both tasks; a whole search evaluates distinct orders of the language within the budget and
 returns a plan the oracle confirms.  Later batches depend on rewards computed from each

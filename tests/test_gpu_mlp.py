@@ -110,6 +110,34 @@ def test_targets_and_warm_decode():
         assert np.allclose(w[i, 1:N[i], :4], tr[i, 1:N[i], :4], atol=1e-5)
 
 
+def test_targets_and_decode_treat_invalid_counts_as_empty():
+    """Knot counts that are non-positive or whose int32 sum would wrap make a sequence
+    empty for the target and warm-start hooks: zero targets and mask, zero warm rows with
+    x0 in row 0; valid rows of the same batch are unaffected."""
+    import torch
+    from paper_2609_21803_amd import native
+    b = I.push_hetero(B=8, seed=21, kmax=3)
+    b["nseg"][1], b["modes"][1, :4], b["knots"][1, :4] = 4, 2, 2 ** 30     # sum wraps to 0
+    b["knots"][3, :2] = (5, 2 ** 31 - 1)                                  # sum wraps negative
+    b["nseg"][3] = max(int(b["nseg"][3]), 2)
+    b["knots"][5, 0] = -4                                                 # negative count
+    d = native.to_device(b)
+    nmax = 75
+    traj = torch.rand((8, nmax + 1, 7), device="cuda")
+    out = dict(traj=traj, feasible=torch.ones(8, dtype=torch.uint8, device="cuda"),
+               cost=torch.ones(8, device="cuda"))
+    yf, yc, yt, mk = [a.cpu().numpy() for a in native.mlp_targets(d, out, nmax)]
+    bad = np.array([1, 3, 5])
+    good = np.setdiff1d(np.arange(8), bad)
+    assert np.all(yt[bad] == 0) and np.all(mk[bad] == 0)
+    assert np.all(mk[good].sum(1) > 0)
+    Y = torch.rand((8, 736), device="cuda")
+    w = native.mlp_decode_warm(Y, d, nmax).cpu().numpy()
+    assert np.all(w[bad, 1:] == 0) and np.all(w[bad, 0, 4:] == 0)
+    assert np.array_equal(w[bad, 0, :4], b["x0"][bad].astype(np.float32))
+    assert np.all(np.abs(w[good, 1]).sum(1) > 0)
+
+
 def test_training_reduces_the_loss():
     from oracle.mlp import Net
     net, flat, X, yf, yc, yt, mask, m, xb, t = _net_and_data(B=1024, seed=3)

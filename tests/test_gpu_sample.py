@@ -1,4 +1,4 @@
-"""GPU parity of the uniform-sampling allocation policy (the ablation of Sec. V) against the
+"""GPU parity of the uniform-sampling allocation policy (the baseline of Sec. IV-B) against the
 sampling oracle: the device draws exactly the oracle's batches (bit-exact keys, both
 tasks), and a whole flipping search returns a plan the oracle confirms."""
 import numpy as np

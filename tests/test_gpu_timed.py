@@ -2,18 +2,17 @@
 durations as controls, Sec. III-C) against the FP64 oracle with timing switched on, called
 through the C ABI.
 
-Tolerances are those of the fixed-step pushing parity: identical feasible flags on margin
-sequences (oracle violation <= 0.1 eps_feas or >= eps_feas + 1e-3), objective within 1e-4
-relative and violation within 1e-5 where both are feasible, on at least 98.5 % of the margin
-sequences (a local solver near a tie may take another trial step and end elsewhere).  The
-timed two-segment workload is more sensitive than the fixed-step one: the FP64 oracle
-itself changes its result on 1.2 % of its margin sequences when the goals move by one
-float32 ulp (0.2 % with the fixed step), so the fixed-step bar of 99.5 % is not a property
-of the algorithm here.  Inputs are rounded to float32 before they reach the oracle.
+Sequence by sequence, with the rule of tests/parity.py: every margin sequence (oracle
+violation <= 0.1 eps_feas or >= eps_feas + 1e-3) has identical feasible flags, and where
+both are feasible the objective within 1e-4 relative and the violation within 1e-5; a
+disagreeing margin sequence is excused only where the timed FP64 oracle itself changes its
+answer under one-ulp moves of the inputs, and each excused sequence is printed.  Inputs
+are rounded to float32 before they reach the oracle.
 """
 import numpy as np
 import pytest
 
+import parity
 from paper_2609_21803_amd import instances as I
 
 pytestmark = pytest.mark.gpu
@@ -40,28 +39,20 @@ def run_gpu(batch, max_intervals, refine=0):
     return res
 
 
-def run_oracle(batch, nmax, idx=None, params=None):
+def run_oracle(batch, nmax, idx=None, params=None, warm=None):
     import oracle
     params = params or oracle.Params(timed=1)
     sel = slice(None) if idx is None else idx
     return oracle.evaluate(f32(batch["x0"][sel]), f32(batch["goal"][sel]), f32(batch["inst"][sel]), batch["nseg"][sel],
-                           batch["modes"][sel], batch["knots"][sel], params=params, nmax=nmax)
+                           batch["modes"][sel], batch["knots"][sel], params=params, nmax=nmax, warm=warm)
 
 
-def compare(g, o, label, min_frac):
-    ov = o["viol"]
-    margin = (ov <= 0.1 * EPS) | (ov >= EPS + 1e-3)
-    flag_ok = g["feasible"] == o["feasible"]
-    both = (g["feasible"] == 1) & (o["feasible"] == 1)
-    rel = np.abs(g["cost"].astype(np.float64) - o["cost"]) / np.maximum(np.abs(o["cost"]), 1e-12)
-    val_ok = np.where(both, (rel <= 1e-4) & (np.abs(g["viol"] - ov) <= 1e-5), True)
-    ok = flag_ok & val_ok
-    frac = ok[margin].mean() if margin.any() else 1.0
-    print(f"[{label}] n={len(ov)} margin={margin.sum()} feasible(oracle)={o['feasible'].mean():.3f} "
-          f"feasible(gpu)={g['feasible'].mean():.3f} flag-agree={flag_ok[margin].mean():.4f} pass={frac:.4f} "
-          f"median rel={np.median(rel[both & margin]) if (both & margin).any() else 0:.2e}", flush=True)
-    assert frac >= min_frac, (label, frac)
-    return both
+def compare(g, o, batch, label, nmax, params=None, warm=None, idx=None):
+    """The per-sequence rule; returns the margin sequences feasible on both sides."""
+    def solve(sub, rows):
+        return run_oracle(sub, nmax, params=params, warm=None if warm is None else warm[rows])
+    parity.check(g, o, batch, solve, label, idx=idx)
+    return (g["feasible"] == 1) & (o["feasible"] == 1) & parity.margin_mask(o["viol"])
 
 
 def _durations_in_bounds(g, N, rows):
@@ -75,7 +66,7 @@ def test_timed_tiny_workload_matches_oracle(orc):
     b = I.push_tiny()
     g = run_gpu(b, 10)
     o = run_oracle(b, 10)
-    both = compare(g, o, "timed tiny", 0.985)
+    both = compare(g, o, b, "timed tiny", 10)
     N = I.n_intervals(b)
     _durations_in_bounds(g, N, np.where(g["feasible"] == 1)[0])
     # trajectories of sequences feasible on both sides agree in their durations
@@ -102,7 +93,7 @@ def test_timed_warm_start_matches_oracle_with_same_warm_start(orc):
         g = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
         o2 = oracle.evaluate(f32(b["x0"]), f32(b["goal"]), f32(b["inst"]), b["nseg"], b["modes"], b["knots"],
                              params=prm, nmax=10, warm=warm.astype(np.float64))
-        compare(g, o2, f"timed warm, refine={refine}", 0.97)
+        compare(g, o2, b, f"timed warm, refine={refine}", 10, params=prm, warm=warm.astype(np.float64))
 
 
 def test_timed_ragged_batch_matches_oracle(orc):
@@ -110,7 +101,7 @@ def test_timed_ragged_batch_matches_oracle(orc):
     b = I.push_hetero(B=1024, seed=91)
     g = run_gpu(b, 75)
     o = run_oracle(b, 75)
-    compare(g, o, "timed ragged", 0.985)
+    compare(g, o, b, "timed ragged", 75)
     N = I.n_intervals(b)
     for i in range(0, 1024, 61):
         assert np.all(g["traj"][i, N[i] + 1:] == 0) and np.all(g["traj"][i, N[i], 4:] == 0)
@@ -118,12 +109,14 @@ def test_timed_ragged_batch_matches_oracle(orc):
 
 def test_timed_full_size_workload_sampled(orc):
     """64 pairs x 1,728 three-segment orders (110,592 TOs, 24 intervals) in one launch, the
-    benchmark's timed launch; 384 sampled sequences checked against the oracle one by one."""
+    benchmark's timed launch; 8,192 evenly strided sequences checked against the oracle one
+    by one (the timed oracle runs at about 1,000 solves/s on 16 threads)."""
     b = I.push_plain()
     g = run_gpu(b, 24)
-    idx = np.random.default_rng(12).choice(len(b["nseg"]), 384, replace=False)
+    idx = np.linspace(0, len(b["nseg"]) - 1, 8192).astype(np.int64)
     o = run_oracle(b, 24, idx=idx)
-    compare({k: v[idx] for k, v in g.items() if k != "ctx" and v is not None}, o, "timed full size (sampled)", 0.985)
+    compare({k: v[idx] for k, v in g.items() if k != "ctx" and v is not None}, o, I.subset(b, idx),
+            "timed full size (8,192 strided)", 24, idx=idx)
     _durations_in_bounds(g, I.n_intervals(b), np.where(g["feasible"] == 1)[0][::97])
 
 

@@ -87,7 +87,7 @@ def _world_wrench(face_codes, v):
 def test_pivot_and_support_rows_match_world_frame_statics(seed):
     """The pivot moment row equals the world-frame moment balance about the corner; the
     centre-of-pressure rows equal the support-face bound on -(moment about the centre)/r_y
-    (Sec. V: quasi-static wrench balance with the table reaction eliminated)."""
+    (Sec. IV-B: quasi-static wrench balance with the table reaction eliminated)."""
     rng = np.random.default_rng(10 + seed)
     f1, f2 = fg(0, 0), fg(1, 1)
     for g, dirn in ((3, 1.0), (4, -1.0)):
