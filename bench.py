@@ -14,7 +14,11 @@ expansion on held-out instances.
 The flipping leg times one round of the bimanual-flipping workload (32,768 orders); the
 timed leg runs the headline orders with optimised timing (interval durations as controls).
 
+The scale legs run the pushing expansion at W = 4,096 -> B = 131,072 and the flipping
+expansion at 32,768 orders per round under a 200,000-evaluation budget.
+
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu] [--no-learned] [--no-flip] [--no-timed]
+                    [--no-scale]
 """
 from __future__ import annotations
 
@@ -260,6 +264,61 @@ def hetero_leg(native, I, torch, B=131072):
                                    "solves_per_s": B / (np.mean(best) * 1e-3)}}
 
 
+def expand_scale_leg(native, I, torch, seeds=(2000, 2001)):
+    """The heterogeneous expansion at its configured scale, in the captured loop on the
+    device: orders of 1..5 segments (10 intervals each), seed of all orders of at most two
+    segments, two rounds whose frontier is the W = 4,096 best-ranked orders and whose batch
+    fills B = 131,072 children; per instance the orders evaluated, the device time of the
+    whole loop (expansion, evaluation, refinement) and the orders evaluated per second."""
+    W, B = 4096, 131072
+    ctx = native.Context(max_batch=B, max_segments=6, max_intervals=50)
+    prm = native.ExpandParams(kcap=5, seed_max_segments=2, radius=1, rounds=2, frontier_W=W, knots_per_segment=10,
+                              k_ref=16, batch_B=B, eval_budget=400000)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+    rows = []
+    for sd in seeds:
+        x0, goal, inst = I.push_pairs(sd, 1)
+        native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm)          # capture + warm-up
+        torch.cuda.synchronize()
+        o, st = native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm)
+        torch.cuda.synchronize()
+        K = int(o["nseg"].item())
+        rows.append({"seed": sd, "evaluated": st["evaluated"], "rounds": st["rounds_done"],
+                     "feasible": st["n_feasible"], "device_ms": st["t_total_ms"],
+                     "orders_per_s": st["evaluated"] / (st["t_total_ms"] * 1e-3),
+                     "t_first_feasible_ms": st["t_first_feasible_ms"], "plan": o["modes"].cpu().numpy()[:K].tolist(),
+                     "plan_cost": float(o["cost"].item())})
+    return {"workload": "pushing expansion: K <= 5, 10 intervals per segment, seed = all 156 orders of <= 2 segments, "
+                        f"2 rounds, frontier W = {W}, batch B = {B}, r = 1, K_ref = 16 (goals of seeds 2000..)",
+            "instances": rows}
+
+
+def flip_expand_scale_leg(native, I, torch, n=2):
+    """The flipping expansion at its configured scale: goals th ~ U[pi/2, pi], px ~ U[-0.2,
+    0.2] m, orders of up to six segments (10 intervals each), 32,768 orders per round, an
+    evaluation budget of 200,000, frontier W = 4,096; plans found (none is a result too),
+    orders evaluated and device time per round."""
+    B, W = 32768, 4096
+    ctx = native.Context(max_batch=B, max_segments=6, max_intervals=60, task=native.TASK_FLIP)
+    prm = native.ExpandParams(kcap=6, seed_max_segments=1, radius=1, rounds=6, frontier_W=W, knots_per_segment=10,
+                              k_ref=16, batch_B=B, eval_budget=200000)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+    x0, goal, inst = I.flip_pairs(3000, n)
+    rows = []
+    for i in range(n):
+        o, st = native.expand(ctx, t(x0[i]), t(goal[i]), t(inst[i]), prm)
+        torch.cuda.synchronize()
+        K = int(o["nseg"].item())
+        rows.append({"goal": [float(goal[i, 0]), float(goal[i, 1])], "evaluated": st["evaluated"],
+                     "rounds": st["rounds_done"], "feasible": st["n_feasible"], "device_ms": st["t_total_ms"],
+                     "ms_per_round": st["t_total_ms"] / max(1, st["rounds_done"]),
+                     "t_first_feasible_ms": st["t_first_feasible_ms"], "plan": o["modes"].cpu().numpy()[:K].tolist(),
+                     "plan_cost": float(o["cost"].item()) if K else None})
+    return {"workload": f"flipping expansion: goals th ~ U[pi/2, pi] (seed 3000), K <= 6, 10 intervals per segment, "
+                        f"B = {B} per round, budget 200,000, W = {W}, r = 1",
+            "plans_found": sum(1 for r in rows if r["plan"]), "instances": rows}
+
+
 def learned_leg(native, I, torch):
     """Train the network on evaluator results, time training and inference, and compare the
     time to the first feasible plan of the plain and the learned expansion."""
@@ -429,6 +488,7 @@ def main():
     ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous-batch leg")
     ap.add_argument("--no-policies", action="store_true", help="skip the allocation-policy comparison")
     ap.add_argument("--no-timed", action="store_true", help="skip the optimised-timing pushing leg")
+    ap.add_argument("--no-scale", action="store_true", help="skip the expansion legs at the configured scale")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -529,6 +589,9 @@ def main():
         res["flip"] = flip_leg(native, I, torch, cpu=not args.no_cpu)
     if not args.no_policies:
         res["policies"] = policy_leg(native, I, torch)
+    if not args.no_scale:
+        res["expand_scale"] = expand_scale_leg(native, I, torch)
+        res["flip_expand_scale"] = flip_expand_scale_leg(native, I, torch)
     if not args.no_learned:
         res["learned"] = learned_leg(native, I, torch)
         res["learned_flip"] = learned_flip_leg(native, I, torch)

@@ -42,7 +42,7 @@ class SolverParams(C.Structure):
                 ("rho0", C.c_double), ("rho_min", C.c_double), ("rho_max", C.c_double),
                 ("armijo_c1", C.c_double), ("eta_star", C.c_double), ("omega_star", C.c_double),
                 ("rc_star", C.c_double), ("eps_feas", C.c_double),
-                ("mu0_warm", C.c_double)]
+                ("mu0_warm", C.c_double), ("round32", C.c_int32)]
 
 
 class ExpandParams(C.Structure):
@@ -72,6 +72,10 @@ class Params:
     rc_star: float = 1e-6
     eps_feas: float = 1e-5
     mu0_warm: float = 1e-4
+    # test switch (0 = plain FP64): round to float32 the step direction (1), the multipliers
+    # (2), the scaled row Jacobians (4), the gains with the forward recursion in float32 (8),
+    # the gains alone (16); results with bits set are perturbations, not the oracle's answer
+    round32: int = 0
 
     def c(self) -> SolverParams:
         return SolverParams(*[getattr(self, f) for f, _ in SolverParams._fields_])

@@ -71,6 +71,12 @@ typedef struct {
   double mu0, mu_min, rho0, rho_min, rho_max, armijo_c1;
   double eta_star, omega_star, rc_star, eps_feas;
   double mu0_warm; /* initial penalty of a solve started from a given (warm) primal */
+  /* Test switch (0 = plain FP64).  Rounds quantities to float32 as they are produced, to  */
+  /* ask whether a result is determined at float32 precision at all: bit 0 the Gauss-    */
+  /* Newton step direction, bit 1 the multipliers after each update, bit 2 the scaled    */
+  /* row Jacobians, bit 3 the gains with the forward recursion run in float32, bit 4 the */
+  /* gains alone.  Results with bits set are perturbations, not the oracle's answer.     */
+  int32_t round32;
 } OracleParams;
 
 /* one mode-conditioned problem (one candidate order on one instance) */
@@ -82,6 +88,9 @@ typedef struct {
   double mu;
   double x0[PNX], goal[3];
   const double *scale; /* NTYPES row scales */
+  int round_jac;       /* test switch: scaled Jacobians rounded to float32 */
+  int round_fwd;       /* test switch: gains and forward recursion in float32 */
+  int round_gain;      /* test switch: gains rounded to float32, recursion in FP64 */
 } PushProb;
 
 /* ------------------------------------------------------------------------------ */
@@ -238,6 +247,8 @@ static void stage_scaled(const PushProb *P, const double *z, int k, double *c, d
     const double sc = P->scale[type[r]];
     c[r] /= sc;
     for (j = 0; j < PNV; ++j) J[r][j] /= sc;
+    if (P->round_jac)
+      for (j = 0; j < PNV; ++j) J[r][j] = (double)(float)J[r][j];
   }
 }
 
@@ -446,12 +457,23 @@ static int gn_step(const PushProb *P, const double *z, const Dual *D, double rho
       }
     }
   }
-  if (ok) {
+  if (ok && P->round_fwd) {
+    float dxf[PNX] = {0, 0, 0, 0};
+    for (k = 0; k < N; ++k) {
+      for (i = 0; i < nw; ++i) {
+        float s = (float)kk[k * nw + i];
+        for (j = 0; j < PNX; ++j) s += (float)KK[(k * nw + i) * PNX + j] * dxf[j];
+        dz[k * nw + i] = s;
+      }
+      for (j = 0; j < PNX; ++j) dxf[j] = (float)dz[k * nw + nu + j];
+    }
+  } else if (ok) {
     double dx[PNX] = {0, 0, 0, 0};
     for (k = 0; k < N; ++k) {
       for (i = 0; i < nw; ++i) {
-        double s = kk[k * nw + i];
-        for (j = 0; j < PNX; ++j) s += KK[(k * nw + i) * PNX + j] * dx[j];
+        double s = P->round_gain ? (double)(float)kk[k * nw + i] : kk[k * nw + i];
+        for (j = 0; j < PNX; ++j)
+          s += (P->round_gain ? (double)(float)KK[(k * nw + i) * PNX + j] : KK[(k * nw + i) * PNX + j]) * dx[j];
         dz[k * nw + i] = s;
       }
       for (j = 0; j < PNX; ++j) dx[j] = dz[k * nw + nu + j];
@@ -504,6 +526,13 @@ static void update_duals(const PushProb *P, const double *z, Dual *D) {
   for (r = 0; r < PNT; ++r) D->lamT[r] += cT[r] / D->mu;
 }
 
+/* test switch: multipliers rounded to float32 */
+static void round_duals(const PushProb *P, Dual *D) {
+  int i;
+  for (i = 0; i < P->N * PNE; ++i) D->lam[i] = (double)(float)D->lam[i];
+  for (i = 0; i < P->N * P->ni; ++i) D->nu[i] = (double)(float)D->nu[i];
+}
+
 /* objective and violation in physical units, Eq. (4) */
 static void score(const PushProb *P, const double *z, double *Jout, double *vout) {
   double c[PNR], J[PNR][PNV], cT[PNT], JT[PNT][PNX], v[PNV];
@@ -552,6 +581,9 @@ static int setup_push(PushProb *P, int timed, int nseg, const int32_t *modes, co
                       const double *x0, const double *goal, double mu, const double *scale) {
   int j, i, k = 0;
   P->timed = timed ? 1 : 0;
+  P->round_jac = 0;
+  P->round_fwd = 0;
+  P->round_gain = 0;
   P->nu = timed ? 4 : 3;
   P->nw = P->nu + PNX;
   P->nv = P->nw + PNX;
@@ -704,6 +736,8 @@ static void solve(const PushProb *P, const OracleParams *prm, int warm, double *
         ok = gn_step(P, z, &D, rho, dz);
       }
       if (!ok) st->chol_fails++;
+      if (ok && (prm->round32 & 1))
+        for (i = 0; i < nz; ++i) dz[i] = (double)(float)dz[i];
       st->gn_iters++;
       dd = 0.0;
       if (ok)
@@ -751,6 +785,7 @@ static void solve(const PushProb *P, const OracleParams *prm, int warm, double *
         break;
       }
       update_duals(P, z, &D);
+      if (prm->round32 & 2) round_duals(P, &D);
       eta = fmax(eta * pow(D.mu, 0.9), prm->eta_star);
       omega = fmax(omega * D.mu, prm->omega_star);
     } else {
@@ -796,6 +831,11 @@ static void eval_one(EvalJob *E, int64_t b) {
   int ok = setup_push(P, timed, E->nseg[b], &E->modes[b * E->smax], &E->knots[b * E->smax], &E->x0[b * PNX],
                       &E->goal[b * 3], E->inst[b], scale);
   if (ok && P->N > E->nmax) ok = 0;
+  if (ok) {
+    P->round_jac = (E->prm->round32 & 4) != 0;
+    P->round_fwd = (E->prm->round32 & 8) != 0;
+    P->round_gain = (E->prm->round32 & 16) != 0;
+  }
   if (E->traj) memset(&E->traj[b * (E->nmax + 1) * rw], 0, sizeof(double) * (size_t)(E->nmax + 1) * rw);
   if (!ok) {
     E->cost[b] = NAN;

@@ -1142,9 +1142,10 @@ static int64_t fneigh1(FKey p, int kcap, FKey *out) {
   return n;
 }
 
-/* r-edit neighbourhood (r in {1, 2}): the one-edit list, then the one-edit lists of  */
-/* its entries in order; first occurrence wins, the order itself excluded; only      */
-/* admissible orders are returned (intermediate orders of r = 2 need not be)          */
+/* r-edit neighbourhood (r in {1, 2}, Sec. III-B): the one-edit list, then the        */
+/* one-edit lists of its admissible entries in order (every intermediate order of a   */
+/* two-edit path stays in the language); first occurrence wins, the order itself      */
+/* excluded; only admissible orders are returned                                       */
 static int64_t fneigh(FKey p, int kcap, int r, FKey *out) {
   int64_t cap1 = (int64_t)(2 * kcap + 2) * FNMODES + 16;
   FKey *l1 = (FKey *)malloc(sizeof(FKey) * (size_t)cap1);
@@ -1160,7 +1161,9 @@ static int64_t fneigh(FKey p, int kcap, int r, FKey *out) {
     }
   if (r >= 2)
     for (i = 0; i < n1; ++i) {
-      int64_t n2 = fneigh1(l1[i], kcap, l2);
+      int64_t n2;
+      if (!admissible_key(l1[i])) continue;
+      n2 = fneigh1(l1[i], kcap, l2);
       for (j = 0; j < n2; ++j)
         if (!fset_has(&seen, l2[j])) {
           fset_add(&seen, l2[j]);

@@ -23,20 +23,14 @@
 #include <vector>
 
 #include "internal.h"
+#include "keys.h"
+#include "mcts_tree.h"
 
 namespace comet {
 
 constexpr unsigned long long EMPTY = 0ull;
 constexpr int SCAN_BLOCK = 256, SCAN_ITEMS = 4, SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
 constexpr int RS_TILE = 256;
-
-__host__ __device__ inline int key_len(unsigned long long k) { return (int)(k >> 60); }
-__host__ __device__ inline int key_mode(unsigned long long k, int i) { return (int)((k >> (50 - 10 * i)) & 1023ull); }
-__host__ __device__ inline unsigned long long key_make(int K, const int* m) {
-  unsigned long long k = (unsigned long long)K << 60;
-  for (int i = 0; i < K; ++i) k |= (unsigned long long)m[i] << (50 - 10 * i);
-  return k;
-}
 
 // Number of raw one-edit neighbours: substitutions K(M-1), deletions K (K > 1),
 // insertions (K+1) M (K < K_cap).
@@ -79,9 +73,11 @@ __host__ __device__ inline unsigned long long raw1_decode(unsigned long long p, 
 }
 
 // e-th raw neighbour within r edits: the one-edit list, then for every entry of that
-// list (in order) its own one-edit list, each padded to raw1max slots.
+// list (in order) its own one-edit list, each padded to raw1max slots.  With `flip` set an
+// entry of the one-edit list that is outside the flipping language starts no second edit
+// (Sec. III-B: every intermediate order of an r-edit path stays admissible).
 __host__ __device__ inline unsigned long long raw_decode(unsigned long long p, long long e, int M, int kcap, int radius,
-                                                          int raw1max) {
+                                                          int raw1max, bool flip) {
   const int n1 = raw1_count(key_len(p), M, kcap);
   if (e < n1) return raw1_decode(p, (int)e, M, kcap);
   if (radius < 2) return EMPTY;
@@ -90,40 +86,8 @@ __host__ __device__ inline unsigned long long raw_decode(unsigned long long p, l
   const int e2 = (int)(t % raw1max);
   if (q >= n1) return EMPTY;
   const unsigned long long k1 = raw1_decode(p, (int)q, M, kcap);
+  if (flip && !flip_admissible_key(k1)) return EMPTY;
   return (e2 < raw1_count(key_len(k1), M, kcap)) ? raw1_decode(k1, e2, M, kcap) : EMPTY;
-}
-
-// Admissibility of a flipping order (the transition rules of Sec. IV-B, with the readings
-// of the flip model): fingers never share a face; a finger changes face only through a
-// free segment; a pivot keeps at least one finger in contact; no two consecutive segments
-// are equal; consecutive pivots keep their direction; no finger touches the face on the
-// table (the support face while supported; the support and the landing face in a pivot).
-// Ids: (f1 * 13 + f2) * 5 + g, finger 0 free / 1 + 3 face + slip; the support starts on
-// face 3 and a pivot run followed by a supported segment lands on the next face.
-__host__ __device__ inline bool flip_admissible_key(unsigned long long k) {
-  const int K = key_len(k);
-  int fs = 3, prev_g = -1, prev_id = -1, pa = -1, pb = -1;
-  for (int j = 0; j < K; ++j) {
-    const int id = key_mode(k, j);
-    if (id >= 845 || id == prev_id) return false;
-    const int g = id % 5, c2 = (id / 5) % 13, c1 = id / 65;
-    if (g >= 3 && prev_g >= 3 && g != prev_g) return false;
-    if (g <= 2 && prev_g >= 3) fs = (fs + (prev_g == 3 ? 3 : 1)) & 3;
-    const int a = c1 ? (c1 - 1) / 3 : -1, b = c2 ? (c2 - 1) / 3 : -1;
-    if (a >= 0 && a == b) return false;
-    if (g >= 3 && a < 0 && b < 0) return false;
-    if (a == fs || b == fs) return false;
-    if (g >= 3) {
-      const int landing = (fs + (g == 3 ? 3 : 1)) & 3;
-      if (a == landing || b == landing) return false;
-    }
-    if ((pa >= 0 && a >= 0 && pa != a) || (pb >= 0 && b >= 0 && pb != b)) return false;
-    pa = a;
-    pb = b;
-    prev_g = g;
-    prev_id = id;
-  }
-  return true;
 }
 
 // Table slot of a key.  Keys carry their information in the high bits (segment count and
@@ -439,9 +403,11 @@ __global__ void k_build(ExpCfg g, const long long* n_dev, const unsigned long lo
   }
 }
 
+// Eq. (5); the product and the sum are rounded separately (no fused multiply-add), so the
+// merit of an order is the same number whichever side computes it.
 __device__ inline double merit_of(double J, double v, double eps, double mu) {
   if (isnan(J) || isnan(v)) return INFINITY;
-  const double M = J + mu * fmax(v - eps, 0.0);
+  const double M = __dadd_rn(J, __dmul_rn(mu, fmax(__dsub_rn(v, eps), 0.0)));
   return isnan(M) ? INFINITY : M;
 }
 
@@ -535,7 +501,7 @@ __global__ void k_gen(ExpCfg g, const ExpCounters* C, const unsigned* ranked, co
   if (t >= C->nCand) return;
   const long long p = t / g.rawmax, e = t % g.rawmax;
   const unsigned long long parent = vkey[ranked[p]];
-  unsigned long long k = raw_decode(parent, e, g.M, g.kcap, g.radius, g.raw1max);
+  unsigned long long k = raw_decode(parent, e, g.M, g.kcap, g.radius, g.raw1max, g.task == COMET_TASK_FLIP);
   if (k != EMPTY && g.task == COMET_TASK_FLIP && !flip_admissible_key(k)) k = EMPTY;
   if (k != EMPTY && set_has(vset, g.vmask, k)) k = EMPTY;
   ckey[t] = k;
@@ -1057,180 +1023,21 @@ comet_status enqueue_expand(comet_ctx* c, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------------
-// MCTS allocation (policy 2): UCT over order prefixes on the host, one device evaluation
-// per batch of batch_B selections.  Actions of a prefix of length d: "stop" (d >= 1) then
-// "append id" (d < kcap) for the ids, in order, that keep it in the task's language; a
-// node with untried actions expands the first, otherwise the walk takes the child of
-// largest W/N + c sqrt(ln N_parent / N) (first on ties); every node of a path gets its
-// visit at selection time (virtual loss).  A new "append" child of length d is completed by
-// a rollout: K = d + out(8r) mod (kcap - d + 1), then for j = d .. K-1 the admissible id
-// number out(8r+1+j) mod (count), out() being the SplitMix64 stream of sample_seed and r
-// the rollout number.  Evaluated orders are cached (the budget counts distinct orders); a
-// selection whose new order would exceed the budget is undone and ends the batch.  After
-// the evaluation, the best value so far is updated and each path adds its reward: pushing
-// J_best / J for feasible orders (0 otherwise), flipping M_best / M.  The search ends at
-// the budget, when nothing is left untried and a batch brings no new order, or after 64
-// batches in a row without one; then the refinement of the expansion.
-// ---------------------------------------------------------------------------------
-struct MctsNode {
-  int len;
-  int pre[6];
-  bool stop;
-  std::vector<int> acts;   // untried actions (from `next`), -1 = stop
-  size_t next = 0;
-  std::vector<int> kids;   // child node indices in action order
-  long long N = 0;
-  double W = 0.0;
-};
-
-inline unsigned long long splitmix64_host(unsigned long long seed, unsigned long long i) {
-  unsigned long long z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-struct MctsTree {
-  int task, kcap, M;
-  double c;
-  unsigned long long seed, rollouts = 0;
-  long long untried = 0;
-  std::vector<MctsNode> nodes;
-
-  bool admissible(const int* m, int n) const {
-    if (task != COMET_TASK_FLIP) return true;
-    return flip_admissible_key(key_make(n, m));
-  }
-  void ids_after(const int* m, int n, std::vector<int>& out) const {
-    out.clear();
-    int q[6];
-    for (int i = 0; i < n; ++i) q[i] = m[i];
-    for (int a = 0; a < M; ++a) {
-      q[n] = a;
-      if (admissible(q, n + 1)) out.push_back(a);
-    }
-  }
-  int make(const int* pre, int len, bool stop) {
-    MctsNode nd;
-    nd.len = len;
-    for (int i = 0; i < 6; ++i) nd.pre[i] = (i < len) ? pre[i] : 0;
-    nd.stop = stop;
-    if (!stop) {
-      if (len >= 1) nd.acts.push_back(-1);
-      if (len < kcap) {
-        std::vector<int> ids;
-        ids_after(pre, len, ids);
-        nd.acts.insert(nd.acts.end(), ids.begin(), ids.end());
-      }
-    }
-    untried += (long long)nd.acts.size();
-    nodes.push_back(std::move(nd));
-    return (int)nodes.size() - 1;
-  }
-  double uct(int parent, int child) const {
-#pragma clang fp contract(off)
-    const double n = (double)nodes[child].N;
-    const double q = nodes[child].W / n;
-    const double e = c * std::sqrt(std::log((double)nodes[parent].N) / n);
-    return q + e;
-  }
-  // one selection: the path (node indices) and the order it yields
-  void select(std::vector<int>& path, int* order, int& K) {
-    path.clear();
-    int v = 0;
-    path.push_back(v);
-    for (;;) {
-      MctsNode& nd = nodes[v];
-      if (nd.next < nd.acts.size()) {
-        const int a = nd.acts[nd.next++];
-        --untried;
-        int pre[6];
-        for (int i = 0; i < nodes[v].len; ++i) pre[i] = nodes[v].pre[i];
-        int len = nodes[v].len;
-        bool stop = (a == -1);
-        if (!stop) pre[len++] = a;
-        const int ch = make(pre, len, stop);
-        nodes[v].kids.push_back(ch);
-        path.push_back(ch);
-        break;
-      }
-      if (nd.kids.empty()) break;
-      int best = -1;
-      double bval = -INFINITY;
-      for (int ch : nd.kids) {
-        const double u = uct(v, ch);
-        if (u > bval) {
-          best = ch;
-          bval = u;
-        }
-      }
-      v = best;
-      path.push_back(v);
-    }
-    const MctsNode& leaf = nodes[path.back()];
-    K = leaf.len;
-    for (int i = 0; i < K; ++i) order[i] = leaf.pre[i];
-    if (!leaf.stop) rollout(order, K);
-    for (int i : path) ++nodes[i].N;
-  }
-  void rollout(int* m, int& K) {
-    const unsigned long long r = rollouts++;
-    const int d = K;
-    if (d >= kcap) return;
-    const int target = d + (int)(splitmix64_host(seed, 8ull * r) % (unsigned long long)(kcap - d + 1));
-    std::vector<int> cand;
-    for (int j = d; j < target; ++j) {
-      ids_after(m, K, cand);
-      if (cand.empty()) break;
-      m[K++] = cand[splitmix64_host(seed, 8ull * r + 1ull + (unsigned long long)j) % cand.size()];
-    }
-  }
-};
-
 __global__ void k_set_batch_n(ExpCounters* C, long long n) { C->nF = n; }
 
 comet_status run_mcts(comet_ctx* c, hipStream_t s) {
   comet_expand_ws* w = c->xws;
   const ExpCfg& g = w->cfg;
   const comet_expand_params& p = w->prm;
-  const bool flip = (g.task == COMET_TASK_FLIP);
   const double eps = g.eps;
   hipLaunchKernelGGL(k_exp_init, dim3(1), dim3(1), 0, s, w->C);
-  MctsTree T;
-  T.task = g.task;
-  T.kcap = g.kcap;
-  T.M = g.M;
-  T.c = p.uct_c;
-  T.seed = p.sample_seed;
-  T.make(nullptr, 0, false);
-  std::unordered_map<unsigned long long, std::pair<double, double>> cache;
-  std::vector<unsigned long long> fresh;
-  std::vector<std::pair<std::vector<int>, unsigned long long>> sel;
+  MctsSearch S;
+  S.init(g.task, g.kcap, g.M, p.uct_c, p.sample_seed, p.batch_B, p.eval_budget, p.mu_merit, eps);
   std::vector<double> hJ, hv;
-  std::vector<int> path;
-  long long nV = 0, batches = 0;
-  int stall = 0;
-  double best = INFINITY;
-  while (nV < p.eval_budget && batches < 1000000) {
-    sel.clear();
-    fresh.clear();
-    for (long long q = 0; q < p.batch_B; ++q) {
-      int order[6], K = 0;
-      T.select(path, order, K);
-      const unsigned long long k = key_make(K, order);
-      if (!cache.count(k) && std::find(fresh.begin(), fresh.end(), k) == fresh.end()) {
-        if (nV + (long long)fresh.size() >= p.eval_budget) {
-          for (int i : path) --T.nodes[i].N;   // not taken
-          break;
-        }
-        fresh.push_back(k);
-      }
-      sel.emplace_back(path, k);
-    }
-    ++batches;
-    const long long n = (long long)fresh.size();
+  while (S.begin_batch()) {
+    const long long n = (long long)S.fresh.size();
     if (n > 0) {
-      if (hipMemcpyAsync(w->F, fresh.data(), 8 * n, hipMemcpyHostToDevice, s) != hipSuccess)
+      if (hipMemcpyAsync(w->F, S.fresh.data(), 8 * n, hipMemcpyHostToDevice, s) != hipSuccess)
         return fail_msg(c, COMET_EHIP, "MCTS batch upload failed");
       hipLaunchKernelGGL(k_set_batch_n, dim3(1), dim3(1), 0, s, w->C, n);
       comet_status st = enqueue_evaluate_batch(c, s, &w->C->nF, n, 0, nullptr, &w->C->t_first, nullptr);
@@ -1243,32 +1050,8 @@ comet_status run_mcts(comet_ctx* c, hipStream_t s) {
       (void)hipMemcpyAsync(hJ.data(), w->ecost64, 8 * n, hipMemcpyDeviceToHost, s);
       (void)hipMemcpyAsync(hv.data(), w->eviol64, 8 * n, hipMemcpyDeviceToHost, s);
       if (hipStreamSynchronize(s) != hipSuccess) return fail_msg(c, COMET_EHIP, "MCTS evaluation failed");
-      for (long long i = 0; i < n; ++i) {
-        cache[fresh[i]] = {hJ[i], hv[i]};
-        if (flip) {
-          const double Mi = (std::isfinite(hJ[i]) && std::isfinite(hv[i])) ? hJ[i] + p.mu_merit * std::fmax(hv[i] - eps, 0.0)
-                                                                           : INFINITY;
-          best = std::fmin(best, Mi);
-        } else if (hv[i] <= eps && std::isfinite(hJ[i])) {
-          best = std::fmin(best, hJ[i]);
-        }
-      }
-      nV += n;
     }
-    for (const auto& sp : sel) {
-      const auto& r = cache[sp.second];
-      double rew = 0.0;
-      if (flip) {
-        const double Mi = (std::isfinite(r.first) && std::isfinite(r.second)) ? r.first + p.mu_merit * std::fmax(r.second - eps, 0.0)
-                                                                               : INFINITY;
-        if (std::isfinite(Mi) && Mi > 0.0) rew = best / Mi;
-      } else if (r.second <= eps && std::isfinite(r.first) && r.first > 0.0) {
-        rew = best / r.first;
-      }
-      for (int i : sp.first) T.nodes[i].W += rew;
-    }
-    stall = (n > 0) ? 0 : stall + 1;
-    if (n == 0 && (T.untried == 0 || stall >= 64)) break;
+    S.end_batch(hJ.data(), hv.data());
   }
   return enqueue_refine_and_output(c, s);
 }

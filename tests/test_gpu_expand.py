@@ -145,3 +145,41 @@ def test_expand_rejects_bad_parameters():
         base.update(bad)
         with pytest.raises(native.CometError):
             native.expand(ctx, t([0, 0, 0, 0]), t([0.1, 0, 0]), t([0.4]), native.ExpandParams(**base))
+
+
+@pytest.mark.parametrize("seed", [2000, 2001])
+def test_configured_round_at_scale_is_bit_exact(orc, seed):
+    """The heterogeneous expansion configuration at its configured scale: orders of 1..5
+    segments, 10 intervals per segment, the seed of all orders of at most two segments,
+    then rounds whose frontier is the W = 4,096 best-ranked evaluated orders and whose batch
+    is filled to B = 131,072 children, in the captured expansion loop on the device.  Every
+    batch the device admitted equals the oracle's batch-construction step (Alg. 1) run on
+    the device's own (key, Eq. (5) merit) of everything evaluated before it, and the last
+    batch is filled to B."""
+    import time
+    from paper_2609_21803_amd import native
+    W, B = 4096, 131072
+    x0, goal, inst = _instance(seed, 0)
+    prm = native.ExpandParams(kcap=5, seed_max_segments=2, radius=1, rounds=2, frontier_W=W, knots_per_segment=10,
+                              k_ref=16, batch_B=B, eval_budget=400000)
+    ctx = _ctx(max_batch=B, max_intervals=50)
+    t0 = time.time()
+    out, st = _run_expand(ctx, x0, goal, inst, prm)
+    wall = time.time() - t0
+    keys, J, v = [t.cpu().numpy() for t in native.expand_trace(ctx)]
+    keys = keys.view(np.uint64)
+    merit = np.array([orc.merit(a, b) for a, b in zip(J, v)])
+    seed_keys = np.array(sorted(orc.key_make([a]) for a in range(12)) +
+                         sorted(orc.key_make([a, b]) for a in range(12) for b in range(12)), np.uint64)
+    assert np.array_equal(keys[:156], seed_keys)
+    pos, sizes = 156, [156]
+    while pos < len(keys):
+        nxt = orc.expand_next(keys[:pos], merit[:pos], n_modes=12, kcap=5, radius=1, frontier_W=W, room=B)
+        assert len(nxt) > 0 and np.array_equal(keys[pos:pos + len(nxt)], nxt), (pos, len(nxt))
+        pos += len(nxt)
+        sizes.append(len(nxt))
+    print(f"seed {seed}: batches {sizes}, evaluated {st['evaluated']}, feasible {st['n_feasible']}, "
+          f"device time {st['t_total_ms']:.1f} ms, wall {wall:.2f} s, plan {out['modes'][:out['nseg'][0]]} "
+          f"cost {out['cost'][0]:.5f}", flush=True)
+    assert st["evaluated"] == len(keys) == sum(sizes) and st["rounds_done"] == 3
+    assert sizes[-1] == B

@@ -63,7 +63,7 @@ def _oracle(b, **kw):
 
 
 def _parity(g, o, b, label, idx=None, warm=None, **kw):
-    def solve(sub, rows):
+    def solve(sub, rows, r32):   # the flipping evaluator is FP64 throughout: input draws only
         return _oracle(sub, warm=None if warm is None else warm[rows], **kw)
     return parity.check(g, o, b, solve, label, idx=idx)
 

@@ -91,3 +91,54 @@ def test_flip_expansion_seed_rounds_and_plan_match_oracle():
     assert r["feasible"][0] == 1 and abs(r["cost"][0] - float(o["cost"].item())) <= 1e-4 * abs(r["cost"][0])
     if F.key_modes(int(bk)) != list(m):
         assert abs(bJ - float(o["cost"].item())) <= 1e-3 * abs(bJ)   # a tie within the margin
+
+
+def test_configured_flip_expansion_at_scale():
+    """The flipping expansion at its configured scale: goals th ~ U[pi/2, pi], px ~ U[-0.2,
+    0.2] m (the configured range), orders of up to six segments, 10 intervals per segment,
+    32,768 orders per round, an evaluation budget of 200,000, frontier W = 4,096.  Every
+    batch the device admitted equals the flip oracle's batch-construction step on the
+    device's own (key, Eq. (5) merit) of everything evaluated before it; a returned plan (if
+    any: none is a result too) is re-solved by the flip oracle at the refinement budget to
+    the same cost.  Prints plans found, evaluations and time per round."""
+    import time
+    import torch
+    import oracle
+    from oracle import flip as F
+    from paper_2609_21803_amd import native
+    B, W = 32768, 4096
+    x0s, goals, insts = I.flip_pairs(3000, 1)
+    ep = dict(kcap=6, seed_max_segments=1, radius=1, rounds=6, frontier_W=W, knots_per_segment=10, k_ref=16,
+              batch_B=B, eval_budget=200000)
+    ctx = _ctx(max_batch=B, max_intervals=60)
+    prm = native.ExpandParams(**ep)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+    t0 = time.time()
+    o, st = native.expand(ctx, t(x0s[0]), t(goals[0]), t(insts[0]), prm)
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    keys, J, v = [a.cpu().numpy() for a in native.expand_trace(ctx)]
+    keys = keys.view(np.uint64)
+    merit = np.array([oracle.merit(a, b) for a, b in zip(J, v)])
+    seed = F.seed(1)
+    assert np.array_equal(keys[:len(seed)], seed)
+    pos, sizes = len(seed), [len(seed)]
+    while pos < len(keys):
+        nxt = F.expand_next(keys[:pos], merit[:pos], 6, 1, W, min(B, 200000 - pos))
+        assert len(nxt) > 0 and np.array_equal(keys[pos:pos + len(nxt)], nxt), (pos, len(nxt))
+        pos += len(nxt)
+        sizes.append(len(nxt))
+    K = int(o["nseg"].item())
+    print(f"flip at scale: goal {goals[0]}, batches {sizes}, evaluated {st['evaluated']}, feasible "
+          f"{st['n_feasible']}, plan {o['modes'].cpu().numpy()[:K]} cost {float(o['cost'].item()):.5f}, device "
+          f"{st['t_total_ms']:.0f} ms ({st['t_total_ms'] / max(1, st['rounds_done']):.0f} ms per round), wall "
+          f"{wall:.1f} s", flush=True)
+    assert st["evaluated"] == len(keys) <= 200000 and max(sizes) <= B
+    if K >= 1:
+        m = o["modes"].cpu().numpy()[:K]
+        f32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+        r = F.evaluate(f32(x0s[:1]), f32(goals[:1]), f32(insts[:1]), np.array([K]), np.array([list(m) + [0] * (6 - K)]),
+                       np.array([[10] * K + [0] * (6 - K)]), params=oracle.Params(**oracle.REFINE))
+        assert r["feasible"][0] == 1 and abs(r["cost"][0] - float(o["cost"].item())) <= 1e-4 * abs(r["cost"][0])
+    else:
+        assert st["n_feasible"] == 0 or st["n_refined"] > 0

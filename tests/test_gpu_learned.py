@@ -1,11 +1,20 @@
-"""The learned proposal inside the device expansion: it changes the order in which
-candidate orders are solved, never which plan is returned.  A network trained on
-evaluator results ranks each batch (queue order) and, optionally, seeds warm starts;
-refinement re-solves the best feasible orders from the plain schedule-derived start in
-both planners.  Warm-started solves begin with the tight penalty mu0_warm, so a good warm
-start shortens every solve.  Asserted: identical returned plans, the first feasible order
-comes earlier in evaluation order, and the device time to the first feasible plan is
-shorter with the learned network than without it."""
+"""The learned proposal inside the device expansion.  A network trained on evaluator
+results ranks each batch (queue order) and, optionally, seeds warm starts; refinement
+re-solves the best feasible orders from the plain schedule-derived start in both planners.
+
+* Ranking only: the queue order never changes an order's result (each solve's arithmetic
+  is the same in every lane), so the evaluated set, the frontier, the refinement set and
+  the returned plan are the plain planner's exactly -- asserted on every instance (same
+  order, cost within 1e-4 relative) -- and the first feasible order comes earlier in the
+  queue.  When a whole batch is resident at once (here 16,384 orders on 65,536 lanes) the
+  queue order cannot make a solve end sooner, so ranking alone does not shorten the time
+  to the first plan; that is what the warm starts do.
+* Warm starts as well: a warm-started solve begins near a solution and ends sooner, which
+  shortens the device time to the first feasible plan; it may end in another local
+  optimum, so the frontier can differ; the returned plan is re-solved from the plain start
+  and is asserted feasible and no more than 1e-4 relative worse than the plain planner's on
+  every instance.
+"""
 import numpy as np
 import pytest
 
@@ -14,31 +23,52 @@ from paper_2609_21803_amd import instances as I
 pytestmark = pytest.mark.gpu
 
 
-def test_learned_expansion_returns_the_plain_plan_and_ranks_feasible_orders_first():
-    import torch
+def _trained():
     from paper_2609_21803_amd import learned, native
     data = learned.generate(262144, seed=4000)
     mlp = native.MLP(max_batch=16384, seed=1)
     log = learned.train(mlp, data, steps=800, batch=8192, lr=1e-3, log_every=200)
     print("training loss", log)
     assert log[-1][1][0] < log[0][1][0]
+    return mlp
+
+
+def _rows(mlp, warm):
+    from paper_2609_21803_amd import learned, native
     ctx = native.Context(max_batch=16384, max_segments=6, max_intervals=24)
     prm = native.ExpandParams(kcap=3, seed_max_segments=2, radius=1, rounds=2, frontier_W=4096,
-                              knots_per_segment=8, k_ref=64, batch_B=16384, eval_budget=20000, learned_warm=1)
+                              knots_per_segment=8, k_ref=64, batch_B=16384, eval_budget=20000, learned_warm=warm)
     x0, goal, inst = I.push_pairs(9100, 8)          # held out: the training seeds are 4000+
-    rows = learned.compare(ctx, mlp, prm, list(zip(x0, goal, inst)))
-    same, ratios, first = 0, [], []
+    return learned.compare(ctx, mlp, prm, list(zip(x0, goal, inst)))
+
+
+def test_learned_ranking_keeps_the_plain_plan_and_warm_starts_reach_a_plan_sooner():
+    mlp = _trained()
+    rows = _rows(mlp, warm=0)
+    ratios, first = [], []
     for r in rows:
         p, l = r["plain"], r["learned"]
         print(p, l)
-        assert p["evaluated"] == l["evaluated"]            # no batch truncation: same orders evaluated
-        if p["modes"] == l["modes"] and (not p["modes"] or abs(p["cost"] - l["cost"]) <= 1e-4 * abs(p["cost"])):
-            same += 1
+        assert p["evaluated"] == l["evaluated"] and p["n_feasible"] == l["n_feasible"]
+        assert p["modes"] == l["modes"]
+        assert (not p["modes"]) or abs(p["cost"] - l["cost"]) <= 1e-4 * abs(p["cost"])
         if p["t_first_ms"] > 0 and l["t_first_ms"] > 0:
             ratios.append(l["t_first_ms"] / p["t_first_ms"])
             first.append((p["first_index"], l["first_index"]))
-    print("TTFP ratios learned/plain", ratios, "first feasible index (plain, learned)", first)
-    assert same >= 7
+    print("ranking only: TTFP ratios learned/plain", ratios, "first feasible index (plain, learned)", first)
     first = np.array(first)
     assert len(first) >= 4 and np.median(first[:, 1]) < np.median(first[:, 0])
+
+    # warm starts as well: plans re-solved from the plain start, never worse than plain
+    rows = _rows(mlp, warm=1)
+    ratios = []
+    for r in rows:
+        p, l = r["plain"], r["learned"]
+        print("warm", p, l)
+        if p["modes"]:
+            assert l["modes"] and l["cost"] <= p["cost"] + 1e-4 * abs(p["cost"])
+        if p["t_first_ms"] > 0 and l["t_first_ms"] > 0:
+            ratios.append(l["t_first_ms"] / p["t_first_ms"])
+    print("ranking + warm starts: TTFP ratios learned/plain", ratios,
+          "identical plans", sum(r["plain"]["modes"] == r["learned"]["modes"] for r in rows))
     assert len(ratios) >= 4 and np.median(ratios) < 0.9

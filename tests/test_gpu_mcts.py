@@ -2,8 +2,8 @@
 MCTS oracle: the first batch (before any reward) is the oracle's selection bit for bit on
 both tasks; a whole search evaluates distinct orders of the language within the budget and
 returns a plan the oracle confirms.  Later batches depend on rewards computed from each
-side's own evaluations, which agree to rounding, so only the first batch is compared
-exactly."""
+side's own evaluations; replaying the oracle's search on the device's own (J, v) of every
+order makes the whole selection sequence comparable bit for bit."""
 import numpy as np
 import pytest
 
@@ -109,3 +109,38 @@ def test_flip_mcts_search_plan_confirmed_by_oracle():
                    np.asarray(inst[:1], np.float32).astype(np.float64), np.array([K]), np.array([m + [0] * (6 - K)]),
                    np.array([[10] * K + [0] * (6 - K)]), params=oracle.Params(**oracle.REFINE))
     assert r["feasible"][0] == 1 and abs(r["cost"][0] - float(o["cost"].item())) <= 1e-4 * abs(r["cost"][0])
+
+
+@pytest.mark.parametrize("task,kcap,P,budget,seed", [(0, 3, 64, 1500, 7), (0, 3, 256, 1200, 11), (1, 2, 128, 640, 3)])
+def test_whole_search_replays_bit_for_bit_on_device_results(task, kcap, P, budget, seed):
+    """The oracle's search, fed the device's per-order (J, v) from the expansion trace in
+    place of its own evaluator, selects the device's evaluated orders in the same order,
+    batch after batch, to the end of the search (tree rules, virtual loss, rollouts,
+    rewards and the budget rule of both sides agree exactly)."""
+    import torch
+    from oracle import mcts as T
+    from paper_2609_21803_amd import native
+    kn = 10 if task == 1 else 8
+    ctx = native.Context(max_batch=P, max_segments=6, max_intervals=kcap * kn, task=task)
+    prm = native.ExpandParams(kcap=kcap, knots_per_segment=kn, k_ref=8, batch_B=P, eval_budget=budget,
+                              policy=native.POLICY_MCTS, sample_seed=seed)
+    pairs = I.flip_pivot_pairs(9400 + seed, 1) if task == 1 else I.push_pairs(9100 + seed, 1)
+    o, st = native.expand(ctx, _t(pairs[0][0]), _t(pairs[1][0]), _t(pairs[2][0]), prm)
+    torch.cuda.synchronize()
+    k_dev, J_dev, v_dev = (a.cpu().numpy() for a in native.expand_trace(ctx))
+    k_dev = k_dev.view(np.uint64)
+    table = {int(k): (float(a), float(b)) for k, a, b in zip(k_dev, J_dev, v_dev)}
+    missing = []
+
+    def device_results(keys, refine):
+        if refine:                      # refinement does not steer the search
+            return np.zeros(len(keys)), np.full(len(keys), np.inf)
+        out = [table.get(int(k)) for k in keys]
+        missing.extend(int(k) for k, r in zip(keys, out) if r is None)
+        return (np.array([r[0] if r else np.nan for r in out]), np.array([r[1] if r else np.inf for r in out]))
+
+    _, _, _, keys, _, _, nb, _ = T.mcts_search(task, None, None, None, kcap, P, budget, seed, kn, 8,
+                                               evaluate=device_results)
+    print(f"task {task}: device {len(k_dev)} orders, replay {len(keys)} orders in {nb} batches, "
+          f"missing {len(missing)}")
+    assert not missing and np.array_equal(np.array(keys, np.uint64), k_dev)

@@ -338,12 +338,25 @@ def _neigh1_py(modes, kcap, M=F.N_MODES):
     return out
 
 
-def _expand_next_py(V, merit, kcap, W, room):
+def _neigh_py(modes, kcap, radius):
+    """r-edit list (Sec. III-B): the one-edit list, then, for r = 2, the one-edit lists of
+    its admissible entries in order (every intermediate order stays admissible)"""
+    l1 = _neigh1_py(modes, kcap)
+    if radius < 2:
+        return l1
+    out = list(l1)
+    for q in l1:
+        if _admissible_py(q):
+            out += _neigh1_py(q, kcap)
+    return out
+
+
+def _expand_next_py(V, merit, kcap, W, room, radius=1):
     order = sorted(range(len(V)), key=lambda i: (merit[i], F.key_make(V[i])))
     seen = {tuple(v) for v in V}
     out = []
     for i in order[:W]:
-        for nb in _neigh1_py(list(V[i]), kcap):
+        for nb in _neigh_py(list(V[i]), kcap, radius):
             if len(out) >= room:
                 return out
             t = tuple(nb)
@@ -360,8 +373,9 @@ def test_seed_is_the_admissible_single_segments_in_key_order():
     assert [F.key_modes(int(k)) for k in s] == [[m] for m in range(F.N_MODES) if _admissible_py([m])]
 
 
-@pytest.mark.parametrize("kcap,W,room,seed", [(2, 3, 500, 0), (3, 8, 4000, 1), (2, 50, 100000, 2)])
-def test_batch_construction_matches_brute_force(kcap, W, room, seed):
+@pytest.mark.parametrize("kcap,W,room,seed,radius", [(2, 3, 500, 0, 1), (3, 8, 4000, 1, 1), (2, 50, 100000, 2, 1),
+                                                     (2, 2, 100000, 3, 2), (3, 1, 30000, 4, 2)])
+def test_batch_construction_matches_brute_force(kcap, W, room, seed, radius):
     """One batch-construction step: rank by (merit, key), traverse W parents, admit unseen
     admissible one-edit neighbours in enumeration order (independent set-based code)."""
     rng = np.random.default_rng(seed)
@@ -371,8 +385,8 @@ def test_batch_construction_matches_brute_force(kcap, W, room, seed):
     V = [v for v in V if _admissible_py(v)]
     merit = rng.choice([0.5, 1.0, 2.0, np.inf], len(V))
     keys = np.array([F.key_make(v) for v in V], np.uint64)
-    got = F.expand_next(keys, merit, kcap, 1, W, room)
-    ref = _expand_next_py(V, list(merit), kcap, W, room)
+    got = F.expand_next(keys, merit, kcap, radius, W, room)
+    ref = _expand_next_py(V, list(merit), kcap, W, room, radius)
     assert [F.key_modes(int(k)) for k in got] == ref
 
 
