@@ -160,6 +160,29 @@ comet_status comet_evaluate(comet_ctx* ctx, void* stream, int64_t B, const float
                             const float* warm, int32_t refine, float* cost, float* viol, uint8_t* feasible,
                             float* traj, int32_t* stats);
 
+/* comet_evaluate without a context, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * pushing tasks only (COMET_TASK_PUSH, COMET_TASK_PUSH_TIMED; others COMET_EINVAL).  The
+ * solver's work space lives in a static device array of 64 MiB that every GPU the library
+ * runs on holds until the process ends; this call allocates nothing (its first call on a
+ * device looks up that device's copy of the array and the device's properties).
+ *   params          solver parameters, NULL = comet_default_params (exploration budget)
+ *   max_segments    column count of modes / knots (1..6)
+ *   max_intervals   row count Nmax of traj (1..512): every order must have <= Nmax intervals
+ *   other arguments as comet_evaluate (no warm start, exploration budget).
+ * Limit: the work space of B orders and max_intervals rows must fit 64 MiB -- about
+ * 265 bytes per (order rounded up to 64) x interval, e.g. 2,048 orders of up to 120
+ * intervals; larger requests return COMET_EINVAL before any launch (message from
+ * comet_last_error(NULL)).  Results equal comet_evaluate's bit for bit.  Invalid device data
+ * is reported through the outputs only (cost NaN, viol +inf, status 3): there is no error
+ * counter to read.  All calls on one GPU share its array, so calls that overlap in time on
+ * one GPU (other streams, other threads) race and must be serialised by the caller.
+ * Asynchronous on `stream`; B = 0 is a no-op. */
+comet_status comet_evaluate_noalloc(comet_task task, const comet_solver_params* params, void* stream, int64_t B,
+                                    int32_t max_segments, int32_t max_intervals, const float* x0, const float* goal,
+                                    const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
+                                    float* cost, float* viol, uint8_t* feasible, float* traj, int32_t* stats);
+
 /* Launch schedule of the solver kernel.  The kernel is persistent: each lane solves one
  * order at a time and takes the next one from a device work queue when its solve ends
  * (Sec. III-C: a reusable pool of slots with independent stopping).

@@ -29,6 +29,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -189,14 +190,67 @@ comet_status launch_evaluate(comet_ctx* c, hipStream_t s, const EvalLaunch& L) {
     hipLaunchKernelGGL(k_queue_scan, dim3(1), dim3(64), 0, s, c->hist, nbins);
     hipLaunchKernelGGL(k_queue_scatter, dim3(gb), dim3(256), 0, s, A, c->hist, c->order, nbins);
   }
-  if (timed) (void)hipEventRecord(c->ev0, s);
+  if (timed && c->ev0) (void)hipEventRecord(c->ev0, s);
   if (c->task == COMET_TASK_PUSH_TIMED)
     hipLaunchKernelGGL(timed_step::k_push_solve, dim3(grid), dim3(WAVE), 0, s, A);
   else
     hipLaunchKernelGGL(fixed_step::k_push_solve, dim3(grid), dim3(WAVE), 0, s, A);
-  if (timed) (void)hipEventRecord(c->ev1, s);
-  c->timed = timed;
+  if (timed && c->ev1) (void)hipEventRecord(c->ev1, s);
+  c->timed = timed && c->ev0;
   if (hipGetLastError() != hipSuccess) return fail_msg(c, COMET_EHIP, "kernel launch failed");
+  return COMET_OK;
+}
+
+}  // namespace comet
+
+// ==================================================================================
+// Allocation-free evaluation (pushing tasks): the work space of the solver lives in a
+// static device array of every GPU the library runs on, instead of in a context's pools.
+// ==================================================================================
+namespace comet {
+
+constexpr size_t NOALLOC_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// per device: the address of its copy of `scratch` (host code never uses the array's name
+// as an address), its CU count, the solver kernels' occupancy and both models' row scales
+struct NoallocDevice {
+  bool ready = false;
+  unsigned char* ptr = nullptr;
+  int n_cu = 0, occ[2] = {1, 1};
+  double scale[2][MAX_TYPES];
+};
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static NoallocDevice g_noalloc[NOALLOC_MAX_DEVICES];
+static std::mutex g_noalloc_lock;
+
+// Set-up of the current device, once: the symbol address, device properties, occupancy and
+// row scales.  Later calls on the device only read these.
+static comet_status noalloc_setup(int dev, NoallocDevice** out) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail_global(COMET_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> g(g_noalloc_lock);
+  NoallocDevice& d = g_noalloc[dev];
+  if (!d.ready) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+      return fail_global(COMET_EHIP, "hipGetSymbolAddress of the scratch array failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail_global(COMET_EHIP, "device properties");
+    int nb0 = 0, nb1 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb0, fixed_step::k_push_solve, WAVE, 0) != hipSuccess || nb0 < 1)
+      nb0 = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, timed_step::k_push_solve, WAVE, 0) != hipSuccess || nb1 < 1)
+      nb1 = 1;
+    for (int t = 0; t < MAX_TYPES; ++t) d.scale[0][t] = d.scale[1][t] = 1.0;
+    fixed_step::compute_scales(d.scale[0]);
+    timed_step::compute_scales(d.scale[1]);
+    d.ptr = (unsigned char*)p;
+    d.n_cu = prop.multiProcessorCount;
+    d.occ[0] = nb0;
+    d.occ[1] = nb1;
+    d.ready = true;
+  }
+  *out = &d;
   return COMET_OK;
 }
 
@@ -382,6 +436,81 @@ comet_status comet_evaluate(comet_ctx* c, void* stream, int64_t B, const float* 
   L.cost = cost; L.viol = viol; L.feas = feasible; L.traj = traj; L.stats = stats;
   if (c->task == COMET_TASK_FLIP) return comet::launch_flip(c, (hipStream_t)stream, L);
   return comet::launch_evaluate(c, (hipStream_t)stream, L);
+}
+
+comet_status comet_evaluate_noalloc(comet_task task, const comet_solver_params* params, void* stream, int64_t B,
+                                    int32_t max_segments, int32_t max_intervals, const float* x0, const float* goal,
+                                    const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
+                                    float* cost, float* viol, uint8_t* feasible, float* traj, int32_t* stats) {
+  using namespace comet;
+  if (task != COMET_TASK_PUSH && task != COMET_TASK_PUSH_TIMED)
+    return fail_global(COMET_EINVAL, "the allocation-free evaluation serves the pushing tasks");
+  if (B < 0 || max_segments < 1 || max_segments > MAXSEG || max_intervals < 1 || max_intervals > MAXN)
+    return fail_global(COMET_EINVAL, "B, max_segments or max_intervals out of range");
+  if (B == 0) return COMET_OK;
+  if (!x0 || !goal || !inst || !nseg || !modes || !knots || !cost || !viol || !feasible)
+    return fail_global(COMET_EINVAL, "null input or output pointer");
+  comet_solver_params prm;
+  if (params) prm = *params;
+  else comet_default_params(&prm);
+  if (prm.ls_trials < 1 || prm.ls_trials > MAX_TRIALS || prm.al_max < 1 || prm.gn_max < 1 || !(prm.mu0 > 0) ||
+      !(prm.mu_min > 0) || !(prm.mu0_warm > 0))
+    return fail_global(COMET_EINVAL, "bad solver parameters");
+  const bool timed = (task == COMET_TASK_PUSH_TIMED);
+  const int64_t NW = timed ? push_timed::NW : push::NW, NE = timed ? push_timed::NE : push::NE;
+  const int64_t NI = timed ? push_timed::NI : push::NI, NG = timed ? push_timed::NGAIN : push::NGAIN;
+  const int64_t S = (B + 63) / 64 * 64, R = max_intervals;
+  // layout of the scratch array, every region 256-byte aligned
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = (off + bytes + 255) / 256 * 256;
+    return at;
+  };
+  const size_t o_zd = take(sizeof(double) * R * NW * S), o_lam = take(sizeof(float) * R * NE * S);
+  const size_t o_nu = take(sizeof(float) * R * NI * S), o_gain = take(sizeof(float) * R * NG * S);
+  const size_t o_dz = take(sizeof(float) * R * NW * S), o_code = take((size_t)R * S);
+  const size_t o_q = take(sizeof(unsigned long long)), o_err = take(sizeof(unsigned));
+  const size_t o_hist = take(sizeof(int) * (R + 2)), o_order = take(sizeof(int) * B);
+  if (off > NOALLOC_BYTES)
+    return fail_global(COMET_EINVAL, "batch x intervals exceed the allocation-free work space (64 MiB)");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail_global(COMET_EHIP, "no current device");
+  NoallocDevice* nd = nullptr;
+  comet_status st = noalloc_setup(dev, &nd);
+  if (st != COMET_OK) return st;
+  // a context on the stack pointing into the device's scratch array: no pools, no events
+  comet_ctx c;
+  c.task = task;
+  c.prm = prm;
+  c.max_batch = B;
+  c.S = S;
+  c.max_segments = max_segments;
+  c.max_intervals = max_intervals;
+  c.device = dev;
+  for (int t = 0; t < MAX_TYPES; ++t) c.scale[t] = nd->scale[timed ? 1 : 0][t];
+  unsigned char* base = nd->ptr;
+  c.zd = (double*)(base + o_zd);
+  c.lam = (float*)(base + o_lam);
+  c.nu = (float*)(base + o_nu);
+  c.gains = (float*)(base + o_gain);
+  c.dz = (float*)(base + o_dz);
+  c.code = base + o_code;
+  c.qhead = (unsigned long long*)(base + o_q);
+  c.err = (unsigned*)(base + o_err);
+  c.hist = (int*)(base + o_hist);
+  c.order = (int*)(base + o_order);
+  c.n_cu = nd->n_cu;
+  c.occ_blocks_per_cu = nd->occ[timed ? 1 : 0];
+  EvalLaunch L;
+  L.B = B;
+  L.B_max = B;
+  L.x0 = x0; L.goal = goal; L.inst = inst; L.inst_stride = 1;
+  L.nseg = nseg; L.modes = modes; L.knots = knots;
+  L.cost = cost; L.viol = viol; L.feas = feasible; L.traj = traj; L.stats = stats;
+  st = launch_evaluate(&c, (hipStream_t)stream, L);
+  if (st != COMET_OK) return fail_global(st, c.msg);
+  return COMET_OK;
 }
 
 comet_status comet_set_schedule(comet_ctx* c, const comet_schedule* sc) {

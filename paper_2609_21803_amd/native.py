@@ -102,6 +102,9 @@ def lib():
         L.comet_check.restype = C.c_int
         L.comet_evaluate.argtypes = [P, P, C.c_int64] + [P] * 7 + [C.c_int32] + [P] * 5
         L.comet_evaluate.restype = C.c_int
+        L.comet_evaluate_noalloc.argtypes = [C.c_int, C.POINTER(SolverParamsC), P, C.c_int64, C.c_int32, C.c_int32] + \
+            [P] * 11
+        L.comet_evaluate_noalloc.restype = C.c_int
         L.comet_set_schedule.argtypes = [P, C.POINTER(ScheduleC)]
         L.comet_set_schedule.restype = C.c_int
         L.comet_get_schedule.argtypes = [P, C.POINTER(ScheduleC), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
@@ -441,6 +444,29 @@ def mlp_decode_warm(y, d: dict, nmax: int, task=TASK_PUSH):
     check(lib().comet_mlp_decode_warm(task, _stream(), B, _ptr(y), int(y.shape[1]), _ptr(d["x0"]), _ptr(d["nseg"]),
                                       _ptr(d["modes"]), _ptr(d["knots"]), smax, nmax, _ptr(w)))
     return w
+
+
+def evaluate_noalloc(x0, goal, inst, nseg, modes, knots, max_intervals: int, task=TASK_PUSH,
+                     params: "SolverParams | None" = None, out: dict | None = None, stream=None):
+    """comet_evaluate_noalloc: the context-free, allocation-free evaluation (pushing tasks).
+    Outputs are allocated here by torch unless given in `out` (the library call itself
+    allocates nothing)."""
+    import torch
+    B = int(nseg.shape[0])
+    dev = nseg.device
+    row = ROW_WIDTH[task]
+    if out is None:
+        out = dict(cost=torch.empty(B, dtype=torch.float32, device=dev), viol=torch.empty(B, dtype=torch.float32, device=dev),
+                   feasible=torch.empty(B, dtype=torch.uint8, device=dev),
+                   traj=torch.empty((B, max_intervals + 1, row), dtype=torch.float32, device=dev),
+                   stats=torch.empty((B, 4), dtype=torch.int32, device=dev))
+    pc = None if params is None else C.byref(params.c())
+    rc = lib().comet_evaluate_noalloc(int(task), pc, _stream(stream), B, int(modes.shape[1]), int(max_intervals),
+                                      _ptr(x0), _ptr(goal), _ptr(inst), _ptr(nseg), _ptr(modes), _ptr(knots),
+                                      _ptr(out["cost"]), _ptr(out["viol"]), _ptr(out["feasible"]), _ptr(out.get("traj")),
+                                      _ptr(out.get("stats")))
+    check(rc)
+    return out
 
 
 def to_device(batch: dict, device="cuda"):
