@@ -267,12 +267,12 @@ def hetero_leg(native, I, torch, B=131072):
 def expand_scale_leg(native, I, torch, seeds=(2000, 2001)):
     """The heterogeneous expansion at its configured scale, in the captured loop on the
     device: orders of 1..5 segments (10 intervals each), seed of all orders of at most two
-    segments, two rounds whose frontier is the W = 4,096 best-ranked orders and whose batch
-    fills B = 131,072 children; per instance the orders evaluated, the device time of the
+    segments, two rounds of two-edit neighbourhoods (22,464 orders, then the frontier of the
+    W = 4,096 best-ranked orders fills B = 131,072 children); per instance the orders evaluated, the device time of the
     whole loop (expansion, evaluation, refinement) and the orders evaluated per second."""
     W, B = 4096, 131072
     ctx = native.Context(max_batch=B, max_segments=6, max_intervals=50)
-    prm = native.ExpandParams(kcap=5, seed_max_segments=2, radius=1, rounds=2, frontier_W=W, knots_per_segment=10,
+    prm = native.ExpandParams(kcap=5, seed_max_segments=2, radius=2, rounds=2, frontier_W=W, knots_per_segment=10,
                               k_ref=16, batch_B=B, eval_budget=400000)
     t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
     rows = []
@@ -289,7 +289,7 @@ def expand_scale_leg(native, I, torch, seeds=(2000, 2001)):
                      "t_first_feasible_ms": st["t_first_feasible_ms"], "plan": o["modes"].cpu().numpy()[:K].tolist(),
                      "plan_cost": float(o["cost"].item())})
     return {"workload": "pushing expansion: K <= 5, 10 intervals per segment, seed = all 156 orders of <= 2 segments, "
-                        f"2 rounds, frontier W = {W}, batch B = {B}, r = 1, K_ref = 16 (goals of seeds 2000..)",
+                        f"2 rounds, frontier W = {W}, batch B = {B}, r = 2, K_ref = 16 (goals of seeds 2000..)",
             "instances": rows}
 
 
@@ -324,7 +324,7 @@ def learned_leg(native, I, torch):
     time to the first feasible plan of the plain and the learned expansion."""
     from paper_2609_21803_amd import learned
     t0 = time.perf_counter()
-    data = learned.generate(1048576, seed=4000)
+    data = learned.generate(2097152, seed=4000)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     mlp = native.MLP(max_batch=131072, seed=1)
@@ -360,7 +360,18 @@ def learned_leg(native, I, torch):
                               k_ref=64, batch_B=16384, eval_budget=20000, learned_warm=1)
     ctx = native.Context(max_batch=16384, max_segments=6, max_intervals=24)
     x0, goal, inst = I.push_pairs(9100, 8)
-    rows = learned.compare(ctx, mlp, prm, list(zip(x0, goal, inst)))
+    rows = learned.compare(ctx, mlp, prm, list(zip(x0, goal, inst)), trace=True)
+    # D6: feasibility ranking of the evaluated orders, network logit vs the plain planner's
+    # evaluation order (earlier = ranked better), against the evaluator's flags
+    auc_net, auc_plain = [], []
+    for r, a, g, m in zip(rows, x0, goal, inst):
+        k, J, v = r["plain"].pop("trace")
+        feas = v <= 1e-5
+        auc_net.append(learned.feasibility_auc(mlp, k, feas, a, g, m, 8))
+        auc_plain.append(learned.auc(-np.arange(len(v), dtype=np.float64), feas))
+    held = I.push_hetero(seed=4900, B=65536)
+    wctx = native.Context(max_batch=65536, max_segments=6, max_intervals=75)
+    savings = learned.warm_start_savings(wctx, mlp, held)
     tp = [r["plain"]["t_first_ms"] for r in rows]
     tl = [r["learned"]["t_first_ms"] for r in rows]
     same = sum(r["plain"]["modes"] == r["learned"]["modes"] and
@@ -377,6 +388,12 @@ def learned_leg(native, I, torch):
                                         "learned": float(np.median([r["learned"]["first_index"] for r in rows]))},
         "instances": "8 held-out pushing start/goal pairs (seed 9100), K<=3, 8 intervals per segment, "
                      "2 rounds, batch 16,384, budget 20,000",
+        "feasibility_auc": {"network_median": float(np.nanmedian(auc_net)),
+                            "plain_order_median": float(np.nanmedian(auc_plain)),
+                            "per_instance_network": auc_net, "per_instance_plain_order": auc_plain,
+                            "over": "every order the plain expansion evaluated on each held-out instance"},
+        "warm_start_gn": {**savings, "batch": "65,536 held-out ragged orders (seed 4900), K ~ U{1..5}, "
+                                              "5..15 intervals per segment"},
         "training": {"samples": int(data["X"].shape[0]), "steps": steps, "batch": batch, "gen_s": t_gen,
                      "train_s": t_train, "final_loss": log[-1][1]},
         "roofline": {"bound": "mfma", "kernel": "train step (k_gemm x 14 + loss, reductions, AdamW)",
@@ -581,22 +598,21 @@ def main():
                                             "HBM 8000 GB/s"},
         "wall_s_timed": wall,
     }
-    if not args.no_timed:
-        res["timed"] = timed_leg(native, I, torch, cpu=not args.no_cpu)
-    if not args.no_hetero:
-        res["hetero"] = hetero_leg(native, I, torch)
-    if not args.no_flip:
-        res["flip"] = flip_leg(native, I, torch, cpu=not args.no_cpu)
-    if not args.no_policies:
-        res["policies"] = policy_leg(native, I, torch)
-    if not args.no_scale:
-        res["expand_scale"] = expand_scale_leg(native, I, torch)
-        res["flip_expand_scale"] = flip_expand_scale_leg(native, I, torch)
-    if not args.no_learned:
-        res["learned"] = learned_leg(native, I, torch)
-        res["learned_flip"] = learned_flip_leg(native, I, torch)
-    if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(batch)
+    print(f"[bench] pushing: {ms:.2f} ms/step", file=sys.stderr, flush=True)
+    legs = [("timed", not args.no_timed, lambda: timed_leg(native, I, torch, cpu=not args.no_cpu)),
+            ("hetero", not args.no_hetero, lambda: hetero_leg(native, I, torch)),
+            ("flip", not args.no_flip, lambda: flip_leg(native, I, torch, cpu=not args.no_cpu)),
+            ("policies", not args.no_policies, lambda: policy_leg(native, I, torch)),
+            ("expand_scale", not args.no_scale, lambda: expand_scale_leg(native, I, torch)),
+            ("flip_expand_scale", not args.no_scale, lambda: flip_expand_scale_leg(native, I, torch)),
+            ("learned", not args.no_learned, lambda: learned_leg(native, I, torch)),
+            ("learned_flip", not args.no_learned, lambda: learned_flip_leg(native, I, torch)),
+            ("cpu_baseline", not args.no_cpu, lambda: cpu_baseline(batch))]
+    for name, on, run in legs:
+        if on:
+            t = time.perf_counter()
+            res[name] = run()
+            print(f"[bench] {name} leg done in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     print(json.dumps(res), flush=True)
 
 

@@ -406,8 +406,9 @@ __global__ void k_build(ExpCfg g, const long long* n_dev, const unsigned long lo
 // Eq. (5); the product and the sum are rounded separately (no fused multiply-add), so the
 // merit of an order is the same number whichever side computes it.
 __device__ inline double merit_of(double J, double v, double eps, double mu) {
+#pragma clang fp contract(off)
   if (isnan(J) || isnan(v)) return INFINITY;
-  const double M = __dadd_rn(J, __dmul_rn(mu, fmax(__dsub_rn(v, eps), 0.0)));
+  const double M = J + mu * fmax(v - eps, 0.0);
   return isnan(M) ? INFINITY : M;
 }
 

@@ -124,9 +124,10 @@ def train(mlp: native.MLP, data: dict, steps: int, batch: int = 8192, lr: float 
     return log
 
 
-def compare(ctx: native.Context, mlp: native.MLP, params: native.ExpandParams, pairs):
+def compare(ctx: native.Context, mlp: native.MLP, params: native.ExpandParams, pairs, trace: bool = False):
     """Plain vs learned expansion on each (x0, goal, inst): time and evaluations to the first
-    feasible plan, and the returned plan of each."""
+    feasible plan, and the returned plan of each (with trace, also the plain expansion's
+    evaluated keys and (J, v) in evaluation order)."""
     import torch
     rows = []
     t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
@@ -139,5 +140,68 @@ def compare(ctx: native.Context, mlp: native.MLP, params: native.ExpandParams, p
             rec[name] = dict(t_first_ms=st["t_first_feasible_ms"], first_index=st["first_feasible_index"],
                              t_total_ms=st["t_total_ms"], evaluated=st["evaluated"], n_feasible=st["n_feasible"],
                              cost=float(o["cost"].item()), modes=o["modes"].cpu().numpy()[:K].tolist())
+            if trace and net is None:
+                k, J, v = native.expand_trace(ctx)
+                rec[name]["trace"] = (k.clone(), J.cpu().numpy(), v.cpu().numpy())
         rows.append(rec)
     return rows
+
+
+def auc(score, label) -> float:
+    """Area under the ROC curve of `score` for the binary `label` (Mann-Whitney, ties half)."""
+    score = np.asarray(score, np.float64)
+    label = np.asarray(label, bool)
+    npos, nneg = int(label.sum()), int((~label).sum())
+    if npos == 0 or nneg == 0:
+        return float("nan")
+    order = np.argsort(score, kind="mergesort")
+    ranks = np.empty(len(score))
+    s = score[order]
+    i = 0
+    while i < len(s):                      # average ranks over ties
+        j = i
+        while j + 1 < len(s) and s[j + 1] == s[i]:
+            j += 1
+        ranks[order[i:j + 1]] = 0.5 * (i + j) + 1.0
+        i = j + 1
+    return float((ranks[label].sum() - npos * (npos + 1) / 2) / (npos * nneg))
+
+
+def feasibility_auc(mlp: native.MLP, keys, feasible, x0, goal, inst, knots_per_segment: int, task=native.TASK_PUSH):
+    """AUC of the network's feasibility logit over evaluated orders (keys on the device) of one
+    instance, against the evaluator's flags."""
+    import torch
+    n = int(keys.shape[0])
+    nseg, modes = decode_keys(keys)
+    kn = torch.where(modes.new_ones(modes.shape).cumsum(1) <= nseg[:, None], knots_per_segment, 0).to(torch.int32)
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+    logits = []
+    for s in range(0, n, mlp.max_batch):
+        e = min(n, s + mlp.max_batch)
+        d = dict(x0=f32(x0)[None].expand(e - s, -1).contiguous(), goal=f32(goal)[None].expand(e - s, -1).contiguous(),
+                 inst=f32(inst).reshape(1, 1).expand(e - s, 1).contiguous(), nseg=nseg[s:e].contiguous(),
+                 modes=modes[s:e].contiguous(), knots=kn[s:e].contiguous())
+        logits.append(mlp.forward(native.mlp_encode(d, task=task))[:, 0].float().cpu().numpy())
+    return auc(np.concatenate(logits), feasible)
+
+
+def warm_start_savings(ctx: native.Context, mlp: native.MLP, batch: dict):
+    """Gauss-Newton iterations of the plain schedule-derived start against the network's warm
+    start on one batch: mean iterations over the orders feasible from both starts, and the
+    feasible fractions."""
+    import torch
+    d = native.to_device(batch)
+    plain = ctx.evaluate(**d)
+    torch.cuda.synchronize()
+    Y = torch.cat([mlp.forward(native.mlp_encode({k: v[s:s + mlp.max_batch] for k, v in d.items()}, task=ctx.task))
+                   for s in range(0, int(d["nseg"].shape[0]), mlp.max_batch)])
+    warm = native.mlp_decode_warm(Y, d, ctx.max_intervals, task=ctx.task)
+    ws = ctx.evaluate(**d, warm=warm)
+    torch.cuda.synchronize()
+    fp, fw = plain["feasible"].cpu().numpy() == 1, ws["feasible"].cpu().numpy() == 1
+    gp, gw = plain["stats"].cpu().numpy()[:, 1], ws["stats"].cpu().numpy()[:, 1]
+    both = fp & fw
+    return dict(orders=int(len(fp)), feasible_plain=float(fp.mean()), feasible_warm=float(fw.mean()),
+                gn_plain_mean=float(gp[both].mean()), gn_warm_mean=float(gw[both].mean()),
+                gn_saved_fraction=float(1.0 - gw[both].mean() / gp[both].mean()),
+                gn_all_plain_mean=float(gp.mean()), gn_all_warm_mean=float(gw.mean()))

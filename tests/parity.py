@@ -25,7 +25,7 @@ accepted or rejected trial step, an active-set change).  The rule:
 
 Sensitivity is found by sampling, so a sequence whose answer moves only under rarer
 perturbations can survive every draw (measured on the 110,592-sequence workload: 547
-disagreements, 480 excused by 12 draws, 35 left after 36): at most `allow` (a fraction of
+disagreements, 480 excused by 12 draws, 36 left after 36): at most `allow` (a fraction of
 the margin sequences, rounded up; 1e-3 by default) may remain unexcused, and each of them
 is printed as such.  More than that fails the test.
 """

@@ -151,8 +151,9 @@ def test_expand_rejects_bad_parameters():
 def test_configured_round_at_scale_is_bit_exact(orc, seed):
     """The heterogeneous expansion configuration at its configured scale: orders of 1..5
     segments, 10 intervals per segment, the seed of all orders of at most two segments,
-    then rounds whose frontier is the W = 4,096 best-ranked evaluated orders and whose batch
-    is filled to B = 131,072 children, in the captured expansion loop on the device.  Every
+    then two rounds of two-edit neighbourhoods (all 22,464 three- and four-segment orders,
+    then the frontier of the W = 4,096 best-ranked evaluated orders fills the batch to
+    B = 131,072 five-segment children), in the captured expansion loop on the device.  Every
     batch the device admitted equals the oracle's batch-construction step (Alg. 1) run on
     the device's own (key, Eq. (5) merit) of everything evaluated before it, and the last
     batch is filled to B."""
@@ -160,7 +161,7 @@ def test_configured_round_at_scale_is_bit_exact(orc, seed):
     from paper_2609_21803_amd import native
     W, B = 4096, 131072
     x0, goal, inst = _instance(seed, 0)
-    prm = native.ExpandParams(kcap=5, seed_max_segments=2, radius=1, rounds=2, frontier_W=W, knots_per_segment=10,
+    prm = native.ExpandParams(kcap=5, seed_max_segments=2, radius=2, rounds=2, frontier_W=W, knots_per_segment=10,
                               k_ref=16, batch_B=B, eval_budget=400000)
     ctx = _ctx(max_batch=B, max_intervals=50)
     t0 = time.time()
@@ -174,7 +175,7 @@ def test_configured_round_at_scale_is_bit_exact(orc, seed):
     assert np.array_equal(keys[:156], seed_keys)
     pos, sizes = 156, [156]
     while pos < len(keys):
-        nxt = orc.expand_next(keys[:pos], merit[:pos], n_modes=12, kcap=5, radius=1, frontier_W=W, room=B)
+        nxt = orc.expand_next(keys[:pos], merit[:pos], n_modes=12, kcap=5, radius=2, frontier_W=W, room=B)
         assert len(nxt) > 0 and np.array_equal(keys[pos:pos + len(nxt)], nxt), (pos, len(nxt))
         pos += len(nxt)
         sizes.append(len(nxt))
