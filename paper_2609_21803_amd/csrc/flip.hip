@@ -7,9 +7,10 @@
 // (u_k, x_{k+1}) the per-stage algebra (32 x 25 row Jacobian, 25 x 25 Gauss-Newton block,
 // 17 x 17 factorisation with 9 right-hand sides) is too large for one lane's registers, so
 // it is spread over the lanes: lanes over rows for the linearisation (Jacobian rows staged
-// in LDS), lane a holding row a of the Gauss-Newton block for the assembly, lanes 8..24
-// eliminating the block with the pivot row broadcast by readlane, lanes over intervals for
-// the trial steps and the feasibility, multiplier and scoring passes.  All arithmetic is
+// in LDS), the Gauss-Newton block assembled on the FP64 matrix cores, lane i holding row i
+// of the bordered block in registers for the elimination and the back substitution (pivot
+// row broadcast by readlane), lanes over intervals for the trial steps and the
+// feasibility, multiplier and scoring passes.  All arithmetic is
 // FP64: the blocks carry 1/mu-scaled rank-deficient terms as in the pushing task.
 //
 // Task model (state, controls, rows, units): see include/comet.h, COMET_TASK_FLIP.
@@ -397,7 +398,6 @@ struct Shm {
   double A[NR][NV + 1];
   double cr[NR], wr[NR], yr[NR];
   double M[NV + 1][NV + 2];   // bordered Gauss-Newton block, lower triangle (see sweep)
-  double invd[NW];            // inverse pivots
   double Pm[NX][NX + 1], pv[NX];
   double h[NV];
   double v[NV];           // row arguments of the interval being linearised
@@ -481,55 +481,73 @@ __device__ __forceinline__ double stage_merit(const FlipArgs& A, const Shm& sh, 
   return phi;
 }
 
-// Per-lane slot table of the factorisation, fixed for the whole solve: tri[t] is entry
-// e = lane + 64 t of the lower triangle of an order-25 block enumerated row by row, packed
-// as (row << 8) | column (-1 past the end); the first n (n + 1) / 2 entries of that
-// enumeration are the lower triangle of order n, so one table serves every pivot.
-struct Slots {
-  int tri[6];
-};
-__device__ inline Slots make_slots(int lane) {
-  Slots S;
-  for (int t = 0; t < 6; ++t) {
-    const int e = lane + 64 * t;
-    int i = 0;
-    while ((i + 1) * (i + 2) / 2 <= e) ++i;
-    S.tri[t] = (e < NV * (NV + 1) / 2) ? ((i << 8) | (e - i * (i + 1) / 2)) : -1;
-  }
-  return S;
-}
-
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// One pivot step of the symmetric elimination over NS slots of the trailing triangle of
-// order T = n (n + 1) / 2 (entries p+1 .. NV): M[i][j] -= M[i][p] M[j][p] / d.  The slot
-// code is straight-line: a lane whose slot lies past T reads entry (NV, NV) and stores into
-// the padding column, so every load of the step is in flight at once.  Returns the updated
-// entry (p+1, p+1) in lane 0 (slot 0 of lane 0), the next pivot.
-template <int NS>
-__device__ __forceinline__ double elim_step(double* Mf, const int* tri, int lane, int p, int T, double id) {
-  constexpr int LD = NV + 2;
-  int at[NS];
-  double mi[NS], mj[NS], mij[NS];
+// Factorisation of one interval's bordered block, held in LDS as its lower triangle (see
+// sweep), with one block row per lane: lane i < 26 mirrors row i into registers (entry (i, j)
+// from (max, min)).  Symmetric elimination of the 17 w pivots: the pivot row p is broadcast
+// from lane p by readlane and every lane below it updates its whole row,
+// M[i][j] -= M[i][p] M[j][p] / d_p, so the mirrored rows stay exact transposes of each other
+// (the product is commutative).  After the elimination, column p of the rows below p holds
+// the unit lower factor times d_p, and columns 17..25 of rows 0..16 hold d_p (L^{-1} [Q_wx,
+// q_w])[p]; the back substitution X[p] = (z_p - sum_{i>p} M[i][p] X[i]) / d_p runs from the
+// last pivot, lane i solving its row for all nine right-hand sides and broadcasting them.
+// Lane p < 17 then writes gain row p (k = -X[:, q_w], K = -X[:, Q_wx]); lanes 17..24 write
+// the value function of x_k (trailing block and border).  Returns 1 if a pivot is not
+// positive and finite (S not positive definite); gains and value function are then left as
+// they were.
+__device__ __forceinline__ int factor_rows(const FlipArgs& A, Shm& sh, int lane, int64_t b, int k) {
+  constexpr int NB = NV + 1;
+  const int li = lane < NB ? lane : 0;
+  double m[NB];
 #pragma unroll
-  for (int t = 0; t < NS; ++t) {
-    const bool in = lane + 64 * t < T;
-    const int ij = tri[t];
-    const int i = in ? p + 1 + (ij >> 8) : NV;
-    const int j = in ? p + 1 + (ij & 255) : NV;
-    at[t] = in ? i * LD + j : NV * LD + NV + 1;
-    mi[t] = Mf[i * LD + p];
-    mj[t] = Mf[j * LD + p];
-    mij[t] = Mf[i * LD + j];
-  }
-  double nd = 0.0;
+  for (int j = 0; j < NB; ++j) m[j] = (j <= li) ? sh.M[li][j] : sh.M[j][li];
+  double idv = 0.0;   // inverse of this lane's pivot
 #pragma unroll
-  for (int t = 0; t < NS; ++t) {
-    const double val = mij[t] - mi[t] * mj[t] * id;
-    Mf[at[t]] = val;
-    if (t == 0) nd = val;
+  for (int p = 0; p < NW; ++p) {
+    const double d = bcast(m[p], p);
+    if (!(d > 0.0) || !isfinite(d)) return 1;
+    const double id = 1.0 / d;
+    if (lane == p) idv = id;
+    double mp[NB];
+#pragma unroll
+    for (int j = p + 1; j < NB; ++j) mp[j] = bcast(m[j], p);
+    if (lane > p && lane < NB) {
+      const double mi = m[p];
+#pragma unroll
+      for (int j = p + 1; j < NB; ++j) m[j] = m[j] - mi * mp[j] * id;
+    }
   }
-  return nd;
+  double x[NX + 1];
+#pragma unroll
+  for (int c = 0; c <= NX; ++c) x[c] = m[NW + c];
+#pragma unroll
+  for (int i = NW - 1; i >= 0; --i) {
+    if (lane == i) {
+#pragma unroll
+      for (int c = 0; c <= NX; ++c) x[c] = x[c] * idv;
+    }
+    double xi[NX + 1];
+#pragma unroll
+    for (int c = 0; c <= NX; ++c) xi[c] = bcast(x[c], i);
+    if (lane < i) {
+      const double mli = m[i];
+#pragma unroll
+      for (int c = 0; c <= NX; ++c) x[c] = x[c] - mli * xi[c];
+    }
+  }
+  if (lane < NW) {
+    double* kk = A.kk + (b * A.nmax + k) * NW;
+    double* KK = A.KK + ((b * A.nmax + k) * NW + lane) * NX;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) KK[c] = -x[c];
+    kk[lane] = -x[NX];
+  } else if (lane < NV) {
+#pragma unroll
+    for (int j = 0; j < NX; ++j) sh.Pm[lane - NW][j] = m[NW + j];
+    sh.pv[lane - NW] = m[NV];
+  }
+  return 0;
 }
 
 // Backward sweep over the intervals.  Always computes the merit phi and the gradient g of
@@ -541,13 +559,13 @@ __device__ __forceinline__ double elim_step(double* Mf, const int* tri, int lane
 // order-26 matrix  [[S, Q_wx, q_w], [Q_xw, Q_xx, q_x], [q_w', q_x', .]]  in the variable
 // order (u_k, x_{k+1}, x_k, 1).  Its row part sum_r w_r a_r a_r' (and the row gradient
 // sum_r y_r a_r in the border row) is one dense 26 x 32 x 26 product on the FP64 matrix
-// cores.  Symmetric elimination of the 17 w pivots (lanes over the entries of the trailing
-// triangle) leaves, by the Schur complement, the value function (P, p) of x_k in the
-// trailing block and L^{-1} [Q_wx, q_w] (scaled by the pivots) in the eliminated columns;
-// a back substitution with one lane per right-hand side then gives the gains.  The
-// pivots are the squares of the Cholesky diagonal of S, so a non-positive pivot is the
-// positive-definiteness failure.
-__device__ __forceinline__ int sweep(const FlipArgs& A, Shm& sh, const Slots& SL, int64_t b, bool factor, double mu,
+// cores.  Symmetric elimination of the 17 w pivots (factor_rows: one block row per lane)
+// leaves, by the Schur complement, the value function (P, p) of x_k in the trailing block
+// and L^{-1} [Q_wx, q_w] (scaled by the pivots) in the eliminated columns; a back
+// substitution over the pivot rows then gives the gains.  The pivots are the squares of
+// the Cholesky diagonal of S, so a non-positive pivot is the positive-definiteness
+// failure.
+__device__ __forceinline__ int sweep(const FlipArgs& A, Shm& sh, int64_t b, bool factor, double mu,
                                      double rho, const double* lamT, double& phi_out, double& gnorm_out) {
   const int lane = threadIdx.x, N = sh.N;
   const double imu = 1.0 / mu;
@@ -708,62 +726,7 @@ __device__ __forceinline__ int sweep(const FlipArgs& A, Shm& sh, const Slots& SL
         if (j < i) sh.M[NU + i][NU + j] += sh.Pm[i][j];
       }
       __syncthreads();
-      // symmetric elimination of the w pivots 0..16 over the trailing lower triangle; all
-      // loads of a pivot step are issued before its stores
-      // The next pivot is entry (p+1, p+1), the first of the trailing triangle: lane 0 updates
-      // it in slot 0 and passes it on by readlane, so each step costs one LDS round trip.
-      int fail = 0;
-      double d = uniform(sh.M[0][0]);
-#pragma unroll 1
-      for (int p = 0; p < NW; ++p) {
-        if (!(d > 0.0) || !isfinite(d)) {
-          fail = 1;
-          break;
-        }
-        const double id = 1.0 / d;
-        if (lane == 0) sh.invd[p] = id;
-        const int n = NV - p, T = n * (n + 1) / 2;
-        // six slots while the triangle has more than 192 entries (p < 6), then three
-        const double nd = (T > 192) ? elim_step<6>(&sh.M[0][0], SL.tri, lane, p, T, id)
-                                    : elim_step<3>(&sh.M[0][0], SL.tri, lane, p, T, id);
-        d = bcast(nd, 0);
-        __syncthreads();
-      }
-      if (fail) {
-        ok = 0;
-      } else {
-        // gains X = S^{-1} [Q_wx, q_w]: lane c < 9 solves for column c in registers.  Column
-        // p of the eliminated block holds z_p = d_p (L^{-1} [Q_wx, q_w])[p] with L unit lower,
-        // L[i][p] = M[i][p] / d_p, so X[p] = (z_p - sum_{i>p} M[i][p] X[i]) / d_p
-        if (lane <= NX) {
-          double zc[NW];
-#pragma unroll
-          for (int pp = 0; pp < NW; ++pp) zc[pp] = sh.M[NW + lane][pp];
-#pragma unroll
-          for (int i = NW - 1; i >= 0; --i) {
-            const double xi = zc[i] * sh.invd[i];
-            zc[i] = xi;
-#pragma unroll
-            for (int pp = 0; pp < i; ++pp) zc[pp] -= sh.M[i][pp] * xi;
-          }
-          // k = -X[:, q_w], K = -X[:, Q_wx]
-          double* kk = A.kk + (b * A.nmax + k) * NW;
-          double* KK = A.KK + (b * A.nmax + k) * NW * NX;
-#pragma unroll
-          for (int pp = 0; pp < NW; ++pp) {
-            if (lane < NX)
-              KK[pp * NX + lane] = -zc[pp];
-            else
-              kk[pp] = -zc[pp];
-          }
-        }
-        // value function of x_k: the trailing block after the elimination
-        {
-          const int i = lane / NX, j = lane % NX;
-          sh.Pm[i][j] = sh.M[NW + max(i, j)][NW + min(i, j)];
-        }
-        if (lane < NX) sh.pv[lane] = sh.M[NV][NW + lane];
-      }
+      if (factor_rows(A, sh, lane, b, k)) ok = 0;
     }
     __syncthreads();
   }
@@ -1068,7 +1031,6 @@ __global__ __launch_bounds__(64, 2) void k_flip_solve(FlipArgs A) {
   for (int e = lane; e < N * NI; e += 64) A.nu[b * A.nmax * NI + e] = 0.0;
   __syncthreads();
 
-  const Slots SL = make_slots(lane);
   double mu = A.warm ? prm.mu0_warm : prm.mu0;
   double eta = pow(mu, 0.1), omega = mu, rho = prm.rho0;
   double lamT[NT] = {0, 0, 0, 0, 0};
@@ -1079,7 +1041,7 @@ __global__ __launch_bounds__(64, 2) void k_flip_solve(FlipArgs A) {
     al_iters = al + 1;
     for (int it = 0; it < prm.gn_max; ++it) {
       double phi0, gnorm;
-      int ok = sweep(A, sh, SL, b, true, mu, rho, lamT, phi0, gnorm);
+      int ok = sweep(A, sh, b, true, mu, rho, lamT, phi0, gnorm);
       if (gnorm <= omega) break;
       int tries = 0;
       while (!ok && tries < prm.chol_retries) {
@@ -1087,7 +1049,7 @@ __global__ __launch_bounds__(64, 2) void k_flip_solve(FlipArgs A) {
         rho = fmax(10.0 * rho, 1e-8);
         ++tries;
         double p2, g2;
-        ok = sweep(A, sh, SL, b, true, mu, rho, lamT, p2, g2);
+        ok = sweep(A, sh, b, true, mu, rho, lamT, p2, g2);
       }
       if (!ok) ++cfails;
       ++gn_iters;
@@ -1124,7 +1086,7 @@ __global__ __launch_bounds__(64, 2) void k_flip_solve(FlipArgs A) {
     // outer update at the final inner iterate
     double vs, rc, phi_u, gnorm;
     viol_pass(A, sh, b, mu, false, lamT, vs, rc);
-    (void)sweep(A, sh, SL, b, false, mu, rho, lamT, phi_u, gnorm);
+    (void)sweep(A, sh, b, false, mu, rho, lamT, phi_u, gnorm);
     double zbad = 0.0;
     for (int e = lane; e < N * NW; e += 64) zbad = fmax(zbad, isfinite(z[e]) ? 0.0 : 1.0);
     zbad = wave_max(zbad);
