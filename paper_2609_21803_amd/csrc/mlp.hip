@@ -63,7 +63,8 @@ enum { EPI_HIDDEN = 0, EPI_OUT = 1, EPI_DX = 2, EPI_PARTIAL = 3 };
 
 struct Epi {
   const float* bias;   // [N] (EPI_HIDDEN, EPI_OUT)
-  float* z;            // FP32 pre-activation out (EPI_HIDDEN) / FP32 result (EPI_OUT, EPI_PARTIAL)
+  float* z;            // FP32 pre-activation out (EPI_HIDDEN; null when no backward pass follows) /
+                       // FP32 result (EPI_OUT, EPI_PARTIAL)
   bf16* h;             // BF16 activation (EPI_HIDDEN) / BF16 gradient (EPI_DX)
   const float* zprev;  // pre-activation of the layer below (EPI_DX)
   long ldc;            // row stride of the outputs
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
         const long o = (long)m * ep.ldc + n;
         if (EPI == EPI_HIDDEN) {
           const float z = v + ep.bias[n];
-          zo[o] = z;
+          if (zo) zo[o] = z;
           const bf16 hb = to_bf16(gelu(z));
           ep.h[o] = hb;
           tv[r] = (short)hb;
@@ -778,13 +779,16 @@ void refresh_weights(comet_mlp* m, hipStream_t s) {
 
 namespace comet {
 
-void mlp_forward_t(comet_mlp* m, hipStream_t s, int B, const long long* B_dev, bool keep_transposed);
+void mlp_forward_t(comet_mlp* m, hipStream_t s, int B, const long long* B_dev, bool keep_transposed, bool train);
 
 // forward for B rows of m->H[0] (at most *B_dev rows if given); Y filled.
-void mlp_forward(comet_mlp* m, hipStream_t s, int B, const long long* B_dev) { mlp_forward_t(m, s, B, B_dev, false); }
+void mlp_forward(comet_mlp* m, hipStream_t s, int B, const long long* B_dev) {
+  mlp_forward_t(m, s, B, B_dev, false, false);
+}
 
-// forward; with keep_transposed the hidden activations are also written transposed (HT)
-void mlp_forward_t(comet_mlp* m, hipStream_t s, int B, const long long* B_dev, bool keep_transposed) {
+// forward; with keep_transposed the hidden activations are also written transposed (HT);
+// the FP32 pre-activations Z, which only the backward pass reads, are written when training
+void mlp_forward_t(comet_mlp* m, hipStream_t s, int B, const long long* B_dev, bool keep_transposed, bool train) {
   for (int l = 0; l < m->nl; ++l) {
     const int K = m->K[l], N = m->N[l];
     Epi ep{};
@@ -792,7 +796,7 @@ void mlp_forward_t(comet_mlp* m, hipStream_t s, int B, const long long* B_dev, b
     ep.ldc = N;
     const bf16* Wl = m->Wb + m->wboff[l];
     if (l < m->nl - 1) {
-      ep.z = m->Z[l];
+      ep.z = train ? m->Z[l] : nullptr;
       ep.h = m->H[l + 1];
       if (keep_transposed) {
         ep.ht = m->HT[l + 1];
@@ -994,7 +998,7 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
   if (tr)
     hipLaunchKernelGGL(k_transpose_bf16, dim3(nblk(m->in_dim, 64), nblk(Bi, 64)), dim3(256), 0, s, m->H[0],
                        (long)m->in_dim, Bi, m->in_dim, m->HT[0], m->ldt);
-  mlp_forward_t(m, s, Bi, nullptr, tr);
+  mlp_forward_t(m, s, Bi, nullptr, tr, true);
   hipLaunchKernelGGL(k_loss_counts, dim3(LOSS_BLOCKS), dim3(256), 0, s, Bi, Wn, y_feas, traj_mask, m->red);
   hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, m->red, LOSS_BLOCKS, 2, m->cnt);
   hipLaunchKernelGGL(k_loss_grad, dim3(LOSS_BLOCKS), dim3(256), 0, s, Bi, O, Wn, m->Y, y_feas, y_cost, y_traj,
