@@ -41,10 +41,18 @@ typedef enum {
 } comet_status;
 
 /* Tasks: planar pushing (Sec. IV-A) with a fixed step, bimanual flipping of a box in a
- * vertical plane (Sec. IV-B), and planar pushing with optimised timing (Sec. III-C: the
+ * vertical plane (Sec. IV-B), planar pushing with optimised timing (Sec. III-C: the
  * interval durations become controls; Sec. IV-A runs pushing with an optimised time step
- * under a duration bound); their dimensions and layouts are given at comet_evaluate. */
-typedef enum { COMET_TASK_PUSH = 0, COMET_TASK_FLIP = 1, COMET_TASK_PUSH_TIMED = 2 } comet_task;
+ * under a duration bound), and planar pushing with free-motion segments (the admissible
+ * language of Sec. III-A: modes are contact events or free motion, and a contact changes
+ * faces only through free motion); their dimensions and layouts are given at
+ * comet_evaluate. */
+typedef enum {
+  COMET_TASK_PUSH = 0,
+  COMET_TASK_FLIP = 1,
+  COMET_TASK_PUSH_TIMED = 2,
+  COMET_TASK_PUSH_FREE = 3
+} comet_task;
 
 typedef struct comet_ctx comet_ctx; /* opaque */
 typedef struct comet_mlp comet_mlp; /* opaque: learned proposal / warm-start network */
@@ -154,7 +162,30 @@ comet_status comet_check(comet_ctx* ctx, void* stream);
  * 0.02 s <= h_k <= 0.2 s, and cost = sum h_k ((F_n^2 + F_t^2) / f_max^2 + (v_s / v_ref)^2
  * + 0.01) charges the elapsed time; the schedule-derived start has h_k = 0.1 s.
  *   traj  [B, Nmax+1, 8] rows (x_k, u_k); warm likewise.  With the learned network the
- *                  eighth warm-start channel carries the interval duration. */
+ *                  eighth warm-start channel carries the interval duration.
+ *
+ * Pushing with free motion (COMET_TASK_PUSH_FREE): the slider of the pushing task and a
+ * point pusher whose position is part of the state.
+ *   x0    [B, 5]  start (x, y, theta, p_x, p_y): slider pose, pusher position in the
+ *                 slider frame
+ *   goal  [B, 3]  slider pose (x, y, theta); the pusher may end anywhere
+ *   inst  [B]     pusher-slider friction coefficient
+ *   modes ids 0..11 contact on face id / 3 with slip id % 3 (stick, slide+, slide-), face
+ *                 j with outward normal at angle j pi/2; ids 12..15 free motion in front of
+ *                 face id - 12 (the half-plane where n . p >= a/2)
+ *   controls u = (F_n, F_t, v_x, v_y): contact force and the pusher's velocity in the
+ *                 slider frame, p_{k+1} = p_k + 0.1 s v; the slider's twist follows the
+ *                 limit surface of the pushing task with the moment M = p x F.  Contact
+ *                 rows: the pusher on the face at p_k (n . p_k = a/2) and moving along it
+ *                 (n . v = 0), stick (t . v = 0) or slide (F_t = +-mu F_n, +-t . v >= 0),
+ *                 F_n >= 0 and the cone when sticking, |t . p| <= a/2 at both knots.
+ *                 Free rows: F_n = F_t = 0 and no penetration, n . p >= a/2 at both knots.
+ *                 An order whose first segment is a contact needs the pusher on that face
+ *                 at the start; any order is evaluated (the language is the expansion's).
+ *   cost  sum 0.1 ((F_n^2 + F_t^2) / f_max^2 + |v|^2 / v_ref^2)
+ *   traj  [B, Nmax+1, 9] rows (x_k, u_k); warm likewise.  The schedule-derived start puts
+ *                 the pusher at the centre of the scheduled face during a contact segment
+ *                 and 2 cm in front of the face during a free segment. */
 comet_status comet_evaluate(comet_ctx* ctx, void* stream, int64_t B, const float* x0, const float* goal,
                             const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                             const float* warm, int32_t refine, float* cost, float* viol, uint8_t* feasible,

@@ -73,11 +73,11 @@ __host__ __device__ inline unsigned long long raw1_decode(unsigned long long p, 
 }
 
 // e-th raw neighbour within r edits: the one-edit list, then for every entry of that
-// list (in order) its own one-edit list, each padded to raw1max slots.  With `flip` set an
-// entry of the one-edit list that is outside the flipping language starts no second edit
-// (Sec. III-B: every intermediate order of an r-edit path stays admissible).
+// list (in order) its own one-edit list, each padded to raw1max slots.  For a task with a
+// language an entry of the one-edit list outside it starts no second edit (Sec. III-B:
+// every intermediate order of an r-edit path stays admissible).
 __host__ __device__ inline unsigned long long raw_decode(unsigned long long p, long long e, int M, int kcap, int radius,
-                                                          int raw1max, bool flip) {
+                                                          int raw1max, int task) {
   const int n1 = raw1_count(key_len(p), M, kcap);
   if (e < n1) return raw1_decode(p, (int)e, M, kcap);
   if (radius < 2) return EMPTY;
@@ -86,7 +86,7 @@ __host__ __device__ inline unsigned long long raw_decode(unsigned long long p, l
   const int e2 = (int)(t % raw1max);
   if (q >= n1) return EMPTY;
   const unsigned long long k1 = raw1_decode(p, (int)q, M, kcap);
-  if (flip && !flip_admissible_key(k1)) return EMPTY;
+  if (!admissible_key(task, k1)) return EMPTY;
   return (e2 < raw1_count(key_len(k1), M, kcap)) ? raw1_decode(k1, e2, M, kcap) : EMPTY;
 }
 
@@ -381,7 +381,7 @@ __global__ void k_seed_cand(ExpCfg g, int kmax, long long n_seed, ExpCounters* C
     c /= g.M;
   }
   unsigned long long k = key_make(K, q);
-  if (g.task == COMET_TASK_FLIP && !flip_admissible_key(k)) k = EMPTY;
+  if (!admissible_key(g.task, k)) k = EMPTY;
   ckey[t] = k;
   if (k != EMPTY) first_insert(hkeys, hmin, g.cmask, k, (unsigned)t);
 }
@@ -465,7 +465,7 @@ __global__ void k_sample(ExpCfg g, const ExpCounters* C, const unsigned long lon
   int m[6] = {0, 0, 0, 0, 0, 0};
   for (int j = 0; j < K; ++j) m[j] = (int)(splitmix64_out(g.sseed, 8ull * c + 1ull + j) % (unsigned long long)g.M);
   unsigned long long k = key_make(K, m);
-  if (g.task == COMET_TASK_FLIP && !flip_admissible_key(k)) k = EMPTY;
+  if (!admissible_key(g.task, k)) k = EMPTY;
   if (k != EMPTY && set_has(vset, g.vmask, k)) k = EMPTY;
   ckey[t] = k;
   if (k != EMPTY) first_insert(hkeys, hmin, g.cmask, k, (unsigned)t);
@@ -502,8 +502,8 @@ __global__ void k_gen(ExpCfg g, const ExpCounters* C, const unsigned* ranked, co
   if (t >= C->nCand) return;
   const long long p = t / g.rawmax, e = t % g.rawmax;
   const unsigned long long parent = vkey[ranked[p]];
-  unsigned long long k = raw_decode(parent, e, g.M, g.kcap, g.radius, g.raw1max, g.task == COMET_TASK_FLIP);
-  if (k != EMPTY && g.task == COMET_TASK_FLIP && !flip_admissible_key(k)) k = EMPTY;
+  unsigned long long k = raw_decode(parent, e, g.M, g.kcap, g.radius, g.raw1max, g.task);
+  if (k != EMPTY && !admissible_key(g.task, k)) k = EMPTY;
   if (k != EMPTY && set_has(vset, g.vmask, k)) k = EMPTY;
   ckey[t] = k;
   if (k != EMPTY) first_insert(hkeys, hmin, g.cmask, k, (unsigned)t);
@@ -730,9 +730,9 @@ comet_status check_expand_params(comet_ctx* c, const comet_expand_params* p) {
 }
 
 comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
-  const bool flip = (c->task == COMET_TASK_FLIP);
-  const int M = flip ? 845 : push::NMODES;
-  const int rowW = flip ? 17 : (c->task == COMET_TASK_PUSH_TIMED ? 8 : 7);
+  const bool flip = (c->task == COMET_TASK_FLIP), lang = task_has_language(c->task);
+  const int M = flip ? 845 : (c->task == COMET_TASK_PUSH_FREE ? push_free::NMODES : push::NMODES);
+  const int rowW = flip ? 17 : (c->task == COMET_TASK_PUSH_TIMED ? 8 : (c->task == COMET_TASK_PUSH_FREE ? 9 : 7));
   int raw1max = 0;
   for (int K = 1; K <= p->kcap; ++K) raw1max = std::max(raw1max, raw1_count(K, M, p->kcap));
   const long long rawmax = (p->radius >= 2) ? (long long)raw1max + (long long)raw1max * raw1max : raw1max;
@@ -743,7 +743,7 @@ comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
   }
   const bool sampling = p->policy == COMET_POLICY_UNIFORM;
   const long long ncand = (p->policy == COMET_POLICY_MCTS) ? 1
-                          : sampling ? p->sample_draws : std::max(rawmax * p->frontier_W, flip ? n_seed : 0ll);
+                          : sampling ? p->sample_draws : std::max(rawmax * p->frontier_W, lang ? n_seed : 0ll);
   if (ncand > (1ll << 27)) return fail_msg(c, COMET_EINVAL, "frontier_W x neighbourhood size exceeds 2^27 candidates");
   const long long Vcap = p->eval_budget + p->batch_B + 16;
   comet_expand_ws* w = c->xws;
@@ -994,8 +994,8 @@ comet_status enqueue_expand(comet_ctx* c, hipStream_t s) {
   if (g.policy == COMET_POLICY_UNIFORM) {
     hipLaunchKernelGGL(k_sample_start, dim3(1), dim3(1), 0, s, g, w->C);
     enqueue_sample_batch(c, s);
-  } else if (g.task == COMET_TASK_FLIP) {
-    // the flip language filters its seed: all orders of 1..kmax segments as candidates,
+  } else if (task_has_language(g.task)) {
+    // a task language filters the seed: all orders of 1..kmax segments as candidates,
     // kept in key order by the candidate pipeline
     hipLaunchKernelGGL(k_fill_u64, dim3(blocks(g.cmask + 1, 256 * 8)), dim3(256), 0, s, w->hkeys, EMPTY,
                        (long long)(g.cmask + 1));
@@ -1073,6 +1073,8 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
   const bool flip = (c->task == COMET_TASK_FLIP);
   if (learned && (mlp_max_batch(learned) < params->batch_B || mlp_in_dim(learned) < 400 || mlp_out_dim(learned) < 722))
     return fail_msg(c, COMET_EINVAL, "learned network: max_batch < batch_B, in_dim < 400 or out_dim < 722");
+  if (learned && c->task == COMET_TASK_PUSH_FREE)
+    return fail_msg(c, COMET_EINVAL, "the learned network serves the pushing, timed-pushing and flipping tasks");
   if (learned && params->policy == COMET_POLICY_MCTS)
     return fail_msg(c, COMET_EINVAL, "the learned network ranks expansion or sampling batches, not MCTS");
   st = ensure_ws(c, params);
@@ -1090,7 +1092,8 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
   hipEvent_t e_in, e_t0, e_t1;
   if (hipEventCreate(&e_in) != hipSuccess || hipEventCreate(&e_t0) != hipSuccess || hipEventCreate(&e_t1) != hipSuccess)
     return fail_msg(c, COMET_EHIP, "event creation failed");
-  (void)hipMemcpyAsync(w->ix0, x0, 4 * (flip ? 8 : push::NX), hipMemcpyDeviceToDevice, us);
+  (void)hipMemcpyAsync(w->ix0, x0, 4 * (flip ? 8 : (c->task == COMET_TASK_PUSH_FREE ? push_free::NX : push::NX)),
+                       hipMemcpyDeviceToDevice, us);
   (void)hipMemcpyAsync(w->igoal, goal, 4 * (flip ? 2 : 3), hipMemcpyDeviceToDevice, us);
   (void)hipMemcpyAsync(w->iinst, inst, 4 * 1, hipMemcpyDeviceToDevice, us);
   (void)hipEventRecord(e_in, us);

@@ -1,10 +1,12 @@
-// keys.h -- order keys and the flipping language, shared by the device expansion and the
-// host MCTS tree.
+// keys.h -- order keys and the languages of the flipping and free-motion pushing tasks,
+// shared by the device expansion and the host MCTS tree.
 //
 // Keys pack (K, m_0, ..., m_5): K << 60 | m_0 << 50 | m_1 << 40 | ... (10 bits per id), so
 // comparing keys compares the segment count first and then the ids lexicographically.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include "../../include/comet.h"
 
 namespace comet {
 
@@ -48,6 +50,42 @@ __host__ __device__ inline bool flip_admissible_key(unsigned long long k) {
     prev_id = id;
   }
   return true;
+}
+
+// Admissibility of a free-motion pushing order (the transition rules of Sec. III-A with
+// the readings of the free-motion model): ids 0..11 are contacts (face id / 3), 12..15 free
+// motion in front of face id - 12; no two consecutive segments are equal; a contact keeps
+// its face (it may change its slip) until a free segment; leaving contact on face j enters
+// the region in front of face j and a contact on face j starts from there; a free region
+// connects to the regions of the neighbouring faces.
+__host__ __device__ inline bool free_admissible_key(unsigned long long k) {
+  const int K = key_len(k);
+  int prev = -1;
+  for (int j = 0; j < K; ++j) {
+    const int id = key_mode(k, j);
+    if (id >= 16) return false;
+    if (prev >= 0) {
+      if (id == prev) return false;
+      const bool ca = prev < 12, cb = id < 12;
+      const int fa = ca ? prev / 3 : prev - 12, fb = cb ? id / 3 : id - 12;
+      if (ca || cb) {
+        if (fa != fb) return false;
+      } else if (((fb - fa + 4) & 3) != 1 && ((fa - fb + 4) & 3) != 1) {
+        return false;
+      }
+    }
+    prev = id;
+  }
+  return true;
+}
+
+// a task's language: flipping and free-motion pushing restrict the orders, the other
+// pushing tasks evaluate every order of their product space
+__host__ __device__ inline bool task_has_language(int task) {
+  return task == COMET_TASK_FLIP || task == COMET_TASK_PUSH_FREE;
+}
+__host__ __device__ inline bool admissible_key(int task, unsigned long long k) {
+  return task == COMET_TASK_FLIP ? flip_admissible_key(k) : (task == COMET_TASK_PUSH_FREE ? free_admissible_key(k) : true);
 }
 
 }  // namespace comet

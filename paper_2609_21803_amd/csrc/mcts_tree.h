@@ -53,8 +53,7 @@ struct MctsTree {
   std::vector<MctsNode> nodes;
 
   bool admissible(const int* m, int n) const {
-    if (task != COMET_TASK_FLIP) return true;
-    return flip_admissible_key(key_make(n, m));
+    return admissible_key(task, key_make(n, m));
   }
   void ids_after(const int* m, int n, std::vector<int>& out) const {
     out.clear();

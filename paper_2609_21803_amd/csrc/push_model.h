@@ -157,6 +157,9 @@ __host__ __device__ inline int row_type(int r, bool stick) {
   }
 }
 
+// row type of slot r for an interval's mode code (the solver's lookup of the row scale)
+__host__ __device__ inline int rtype(int r, int code) { return row_type(r, ((code >> 2) & 3) == 0); }
+
 // stage cost and its gradient / constant diagonal Hessian w.r.t. u
 __host__ __device__ inline double stage_cost(const double* u) {
   return DT * ((u[0] * u[0] + u[1] * u[1]) / (FMAX * FMAX) + WV * u[2] * u[2] / (VREF * VREF));
@@ -304,6 +307,7 @@ __host__ __device__ inline void rows(const double* xk, const double* uk, const d
 }
 
 __host__ __device__ inline int row_type(int r, bool stick) { return r >= 10 ? T_DUR : push::row_type(r, stick); }
+__host__ __device__ inline int rtype(int r, int code) { return row_type(r, ((code >> 2) & 3) == 0); }
 
 constexpr double CF = 1.0 / (FMAX * FMAX), CV = WV / (VREF * VREF);
 
@@ -328,4 +332,204 @@ __host__ __device__ inline void initial_u(double fn, double sg, double mu, doubl
 }
 
 }  // namespace push_timed
+
+// --------------------------------------------------------------------------------------
+// Free-motion pushing (the admissible language of Sec. III-A: modes are contact events or
+// free motion, and a contact changes faces only through a free-motion segment).  Readings
+// of the model: the state adds the point pusher's position p in the slider frame, x = (x,
+// y, theta, p_x, p_y); the control is u = (F_n, F_t, v_x, v_y), the contact force and the
+// pusher's velocity in the slider frame, and p_{k+1} = p_k + dt v.  The slider moves by the
+// quasi-static law of the fixed-step model with the moment M = p x F, which on face j
+// (p = (a/2) n + s t) is (a/2) F_t + s F_n.  Mode ids 0..11: contact on face id / 3 with
+// slip id % 3; ids 12..15: free motion in front of face id - 12 (the half-plane n . p >=
+// a/2).  Mode code: face | kind << 2, kind 0 stick, 1 slide+, 2 slide-, 3 free.
+// Row slots (equalities first):
+//   0..4  defects (pose and pusher position)
+//   contact: 5 n.p_k - a/2 = 0, 6 n.v = 0, 7 stick t.v = 0 | slide F_t - sg mu F_n = 0,
+//            8 -F_n <= 0, 9 stick F_t - mu F_n <= 0 | slide -sg t.v <= 0,
+//            10 stick -F_t - mu F_n <= 0, 11, 12 +-t.p_{k+1} - a/2 <= 0, 13, 14 +-t.p_k - a/2 <= 0
+//   free:    5 F_n = 0, 6 F_t = 0, 8 a/2 - n.p_k <= 0, 9 a/2 - n.p_{k+1} <= 0 (no penetration)
+// Terminal rows (x_N, y_N, theta_N) - goal = 0.  Objective sum_k dt [ (F_n^2 + F_t^2) /
+// f_max^2 + w_v |v|^2 / v_ref^2 ].
+// --------------------------------------------------------------------------------------
+namespace push_free {
+
+constexpr int NX = 5, NU = 4, NW = 9, NV = 14, NR = 15, NE = 8, NI = NR - NE, NT = 3;
+constexpr int NMODES = 16, NTYPES = 16, NGAIN = NW + NW * NX;
+constexpr bool PREFETCH_GAINS = false;
+using push::SIDE;
+using push::MASS;
+using push::GRAV;
+using push::MU_G;
+using push::VREF;
+using push::DT;
+using push::WV;
+using push::FMAX;
+using push::CLS;
+using push::K1;
+using push::KM;
+using push::HALF;
+using push::face_dirs;
+constexpr double DFREE = 0.02;   // initial guess: a free segment's knots this far in front of its face
+
+enum { VX = 0, VY, VTH, VPX, VPY, VFN, VFT, VVX, VVY, VX1, VY1, VTH1, VPX1, VPY1 };
+// row types of the internal scaling (n.p - a/2 and n.v share one)
+enum { T_DX, T_DY, T_DTH, T_DPX, T_DPY, T_ONF, T_STICK, T_SLIDE, T_FREEF, T_FN, T_CONE, T_SLIP, T_NPEN, T_FACE,
+       T_TXY, T_TTH };
+
+__host__ __device__ inline int make_code(int mode, int smask) {
+  (void)smask;
+  return mode < 12 ? (mode / 3) | ((mode % 3) << 2) : (mode - 12) | (3 << 2);
+}
+
+__host__ __device__ constexpr bool nz(int r, int i) {
+  return (r == 0) ? (i == VX || i == VTH || i == VFN || i == VFT || i == VX1)
+       : (r == 1) ? (i == VY || i == VTH || i == VFN || i == VFT || i == VY1)
+       : (r == 2) ? (i == VTH || i == VPX || i == VPY || i == VFN || i == VFT || i == VTH1)
+       : (r == 3) ? (i == VPX || i == VVX || i == VPX1)
+       : (r == 4) ? (i == VPY || i == VVY || i == VPY1)
+       : (r == 5 || r == 8) ? (i == VPX || i == VPY || i == VFN)
+       : (r == 6) ? (i == VVX || i == VVY || i == VFT)
+       : (r == 7) ? (i == VVX || i == VVY || i == VFN || i == VFT)
+       : (r == 9) ? (i == VPX1 || i == VPY1 || i == VVX || i == VVY || i == VFN || i == VFT)
+       : (r == 10) ? (i == VFN || i == VFT)
+       : (r == 11 || r == 12) ? (i == VPX1 || i == VPY1)
+       : (i == VPX || i == VPY);
+}
+
+// residuals in double, the Jacobian (every structural entry of the union, zeros where the
+// mode has none) in T
+template <typename T>
+__host__ __device__ inline void rows_sc(const double* xk, const double* uk, const double* x1, int code, double mu,
+                                        double st, double ct, double* c, T (*J)[NV], int* en) {
+  const int face = code & 3, kind = (code >> 2) & 3;
+  const bool fr = (kind == 3), stick = (kind == 0);
+  const double sg = (kind == 1) ? 1.0 : ((kind == 2) ? -1.0 : 0.0);
+  double nx, ny;
+  face_dirs<double>(face, nx, ny);
+  const double tx = -ny, ty = nx;
+  const double px = xk[3], py = xk[4], Fn = uk[0], Ft = uk[1], vx = uk[2], vy = uk[3];
+  const double px1 = x1[3], py1 = x1[4];
+  const double Fbx = -Fn * nx + Ft * tx, Fby = -Fn * ny + Ft * ty;
+  const double M = px * Fby - py * Fbx;
+  const double xi_x = K1 * Fbx, xi_y = K1 * Fby, xi_t = KM * M;
+  const double wx = ct * xi_x - st * xi_y, wy = st * xi_x + ct * xi_y;
+  const double pn = nx * px + ny * py, pt = tx * px + ty * py;
+  const double p1n = nx * px1 + ny * py1, p1t = tx * px1 + ty * py1;
+  const double vn = nx * vx + ny * vy, vt = tx * vx + ty * vy;
+  c[0] = (x1[0] - xk[0]) - DT * wx;
+  c[1] = (x1[1] - xk[1]) - DT * wy;
+  c[2] = (x1[2] - xk[2]) - DT * xi_t;
+  c[3] = (px1 - px) - DT * vx;
+  c[4] = (py1 - py) - DT * vy;
+  c[5] = fr ? Fn : pn - HALF;
+  c[6] = fr ? Ft : vn;
+  c[7] = fr ? 0.0 : (stick ? vt : Ft - sg * mu * Fn);
+  c[8] = fr ? HALF - pn : -Fn;
+  c[9] = fr ? HALF - p1n : (stick ? Ft - mu * Fn : -sg * vt);
+  c[10] = (!fr && stick) ? -Ft - mu * Fn : 0.0;
+  c[11] = fr ? 0.0 : p1t - HALF;
+  c[12] = fr ? 0.0 : -p1t - HALF;
+  c[13] = fr ? 0.0 : pt - HALF;
+  c[14] = fr ? 0.0 : -pt - HALF;
+  en[0] = en[1] = en[2] = en[3] = en[4] = en[5] = en[6] = 1;
+  en[7] = fr ? 0 : 1;
+  en[8] = en[9] = 1;
+  en[10] = (!fr && stick) ? 1 : 0;
+  en[11] = en[12] = en[13] = en[14] = fr ? 0 : 1;
+  if (J) {
+    const T k1 = T(K1), km = T(KM), dt = T(DT), one = T(1), zero = T(0);
+    const T stT = T(st), ctT = T(ct), nxT = T(nx), nyT = T(ny), txT = T(tx), tyT = T(ty);
+    const T muT = T(mu), sgT = T(sg), wxT = T(wx), wyT = T(wy), FbxT = T(Fbx), FbyT = T(Fby);
+    const T pxT = T(px), pyT = T(py);
+    const T dwx_dFn = k1 * (ctT * (-nxT) - stT * (-nyT)), dwy_dFn = k1 * (stT * (-nxT) + ctT * (-nyT));
+    const T dwx_dFt = k1 * (ctT * txT - stT * tyT), dwy_dFt = k1 * (stT * txT + ctT * tyT);
+    J[0][VX] = -one; J[0][VTH] = dt * wyT; J[0][VFN] = -dt * dwx_dFn; J[0][VFT] = -dt * dwx_dFt; J[0][VX1] = one;
+    J[1][VY] = -one; J[1][VTH] = -dt * wxT; J[1][VFN] = -dt * dwy_dFn; J[1][VFT] = -dt * dwy_dFt; J[1][VY1] = one;
+    J[2][VTH] = -one; J[2][VPX] = -dt * km * FbyT; J[2][VPY] = dt * km * FbxT;
+    J[2][VFN] = -dt * km * (-pxT * nyT + pyT * nxT); J[2][VFT] = -dt * km * (pxT * tyT - pyT * txT);
+    J[2][VTH1] = one;
+    J[3][VPX] = -one; J[3][VVX] = -dt; J[3][VPX1] = one;
+    J[4][VPY] = -one; J[4][VVY] = -dt; J[4][VPY1] = one;
+    J[5][VPX] = fr ? zero : nxT; J[5][VPY] = fr ? zero : nyT; J[5][VFN] = fr ? one : zero;
+    J[6][VVX] = fr ? zero : nxT; J[6][VVY] = fr ? zero : nyT; J[6][VFT] = fr ? one : zero;
+    J[7][VVX] = (!fr && stick) ? txT : zero; J[7][VVY] = (!fr && stick) ? tyT : zero;
+    J[7][VFN] = (!fr && !stick) ? -sgT * muT : zero; J[7][VFT] = (!fr && !stick) ? one : zero;
+    J[8][VPX] = fr ? -nxT : zero; J[8][VPY] = fr ? -nyT : zero; J[8][VFN] = fr ? zero : -one;
+    J[9][VPX1] = fr ? -nxT : zero; J[9][VPY1] = fr ? -nyT : zero;
+    J[9][VVX] = (!fr && !stick) ? -sgT * txT : zero; J[9][VVY] = (!fr && !stick) ? -sgT * tyT : zero;
+    J[9][VFN] = (!fr && stick) ? -muT : zero; J[9][VFT] = (!fr && stick) ? one : zero;
+    J[10][VFN] = (!fr && stick) ? -muT : zero; J[10][VFT] = (!fr && stick) ? -one : zero;
+    J[11][VPX1] = fr ? zero : txT; J[11][VPY1] = fr ? zero : tyT;
+    J[12][VPX1] = fr ? zero : -txT; J[12][VPY1] = fr ? zero : -tyT;
+    J[13][VPX] = fr ? zero : txT; J[13][VPY] = fr ? zero : tyT;
+    J[14][VPX] = fr ? zero : -txT; J[14][VPY] = fr ? zero : -tyT;
+  }
+}
+
+template <typename T>
+__host__ __device__ inline void rows(const double* xk, const double* uk, const double* x1, int code, double mu,
+                                     double* c, T (*J)[NV], int* en) {
+  double st, ct;
+  sincos_d(xk[2], &st, &ct);
+  rows_sc<T>(xk, uk, x1, code, mu, st, ct, c, J, en);
+}
+
+__host__ __device__ inline int rtype(int r, int code) {
+  const int kind = (code >> 2) & 3;
+  const bool fr = (kind == 3), stick = (kind == 0);
+  switch (r) {
+    case 0: return T_DX;
+    case 1: return T_DY;
+    case 2: return T_DTH;
+    case 3: return T_DPX;
+    case 4: return T_DPY;
+    case 5:
+    case 6: return fr ? T_FREEF : T_ONF;
+    case 7: return stick ? T_STICK : T_SLIDE;
+    case 8: return fr ? T_NPEN : T_FN;
+    case 9: return fr ? T_NPEN : (stick ? T_CONE : T_SLIP);
+    case 10: return T_CONE;
+    default: return T_FACE;
+  }
+}
+
+constexpr double HF = DT * 2.0 / (FMAX * FMAX), HV = DT * 2.0 * WV / (VREF * VREF);
+__host__ __device__ inline double stage_cost(const double* u) {
+  return DT * ((u[0] * u[0] + u[1] * u[1]) / (FMAX * FMAX) + WV * (u[2] * u[2] + u[3] * u[3]) / (VREF * VREF));
+}
+__host__ __device__ inline void add_cost_grad(const double* u, double* h) {
+  h[VFN] += HF * u[0];
+  h[VFT] += HF * u[1];
+  h[VVX] += HV * u[2];
+  h[VVY] += HV * u[3];
+}
+__host__ __device__ inline void add_cost_hess(const double* u, double (*G)[NV]) {
+  (void)u;
+  G[VFN][VFN] += HF;
+  G[VFT][VFT] += HF;
+  G[VVX][VVX] += HV;
+  G[VVY][VVY] += HV;
+}
+
+// Schedule-derived initial guess of one interval (the paper's construction: the pusher is
+// placed on each scheduled face during each contact segment): the interval's end knot p1
+// at the face centre for contact, DFREE in front of the face for free motion; the velocity
+// that moves the pusher from p0 there in one step; F_n = fn with F_t on the cone edge for
+// sliding contact, no force in free motion.
+__host__ __device__ inline void initial_knot(int code, double fn, double mu, const double* p0, double* u, double* p1) {
+  const int face = code & 3, kind = (code >> 2) & 3;
+  double nx, ny;
+  face_dirs<double>(face, nx, ny);
+  const double d = (kind == 3) ? HALF + DFREE : HALF;
+  const double sg = (kind == 1) ? 1.0 : ((kind == 2) ? -1.0 : 0.0);
+  p1[0] = d * nx;
+  p1[1] = d * ny;
+  u[0] = (kind == 3) ? 0.0 : fn;
+  u[1] = (kind == 3) ? 0.0 : sg * mu * fn;
+  u[2] = (p1[0] - p0[0]) / DT;
+  u[3] = (p1[1] - p0[1]) / DT;
+}
+
+}  // namespace push_free
 }  // namespace comet

@@ -149,6 +149,42 @@ def flip_batch(seed: int, B: int, n_pairs: int = 32, kmin: int = 1, kmax: int = 
     return dict(x0=x0[pair], goal=goal[pair], inst=inst[pair], nseg=nseg, modes=modes, knots=kn)
 
 
+# free-motion pushing: pusher start positions 3 cm in front of face j (slider frame)
+_FREE_START = 0.08 * np.array([[1.0, 0.0], [0.0, 1.0], [-1.0, 0.0], [0.0, -1.0]])
+
+
+def push_free_pairs(seed: int, n: int):
+    """n start/goal pairs of free-motion pushing: x0 [n, 5] (slider at rest at the origin,
+    pusher 3 cm in front of a face drawn uniformly), goal [n, 3] (x, y ~ U[-0.15, 0.15] m,
+    theta ~ U[-pi/2, pi/2]), inst [n, 1] (pusher friction ~ U[0.3, 0.5])."""
+    rng = np.random.default_rng(seed)
+    goal = np.empty((n, 3))
+    goal[:, 0] = rng.uniform(-0.15, 0.15, n)
+    goal[:, 1] = rng.uniform(-0.15, 0.15, n)
+    goal[:, 2] = rng.uniform(-np.pi / 2, np.pi / 2, n)
+    mu = rng.uniform(0.3, 0.5, n)
+    face = rng.integers(0, 4, n)
+    x0 = np.zeros((n, 5))
+    x0[:, 3:] = _FREE_START[face]
+    return x0, goal, mu.reshape(n, 1)
+
+
+def orders_batch(x0, goal, inst, pair, orders, knots) -> dict:
+    """Sequences given one by one: pair [B] indexes x0/goal/inst, orders / knots are lists
+    of B lists (segment ids, intervals per segment)."""
+    B = len(orders)
+    modes = np.zeros((B, MAXSEG), np.int32)
+    kn = np.zeros((B, MAXSEG), np.int32)
+    nseg = np.zeros(B, np.int32)
+    for i, (o, k) in enumerate(zip(orders, knots)):
+        nseg[i] = len(o)
+        modes[i, :len(o)] = o
+        kn[i, :len(k)] = k
+    pair = np.asarray(pair)
+    return dict(x0=x0[pair].copy(), goal=goal[pair].copy(), inst=inst[pair].copy(), nseg=nseg, modes=modes,
+                knots=kn, pair=pair)
+
+
 def flip_tiny(seed: int = 3000, B: int = 512) -> dict:
     """Small flipping batch for parity: K ~ U{1..3}, 5 intervals per segment."""
     return flip_batch(seed, B, n_pairs=8, kmin=1, kmax=3, knots=5)

@@ -1,0 +1,172 @@
+"""GPU parity of free-motion pushing (COMET_TASK_PUSH_FREE: the admissible language of Sec.
+III-A, with the pusher position in the state and non-penetration rows) against the FP64
+free-motion oracle, called through the C ABI.
+
+* Evaluation, sequence by sequence with the rule of tests/parity.py (margin sequences agree
+  on the feasible flag, and on cost within 1e-4 and violation within 1e-5 where both are
+  feasible; a disagreement is excused only where the oracle itself moves under float32-level
+  perturbations), on every admissible order of at most two segments and on a ragged batch
+  of admissible orders of up to four segments.
+* The closed form of a free approach followed by a straight push.
+* The device expansion over this language: bit-exact batch construction against the
+  oracle's batch step, and a whole expansion whose evaluated orders are all admissible and
+  whose returned plan the oracle confirms.
+Inputs are rounded to float32 before they reach the oracle.
+"""
+import numpy as np
+import pytest
+
+import parity
+from paper_2609_21803_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+# what the device keeps in float32, as the oracle's rounding switch for the excuse draws:
+# step (1), multipliers (2), scaled Jacobians (4), gains with the forward recursion (8)
+ROUND32 = 1 | 2 | 4 | 8
+
+
+def f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def run_gpu(batch, max_intervals):
+    import torch
+    from paper_2609_21803_amd import native
+    B = len(batch["nseg"])
+    ctx = native.Context(max_batch=max(B, 1), max_segments=6, max_intervals=max_intervals,
+                         task=native.TASK_PUSH_FREE)
+    out = ctx.evaluate(**native.to_device(batch))
+    torch.cuda.synchronize()
+    ctx.check()
+    return {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+
+
+def run_oracle(batch, nmax, params=None):
+    import oracle
+    from oracle import free as F
+    return F.evaluate(f32(batch["x0"]), f32(batch["goal"]), f32(batch["inst"]), batch["nseg"], batch["modes"],
+                      batch["knots"], params=params or oracle.Params(), nmax=nmax)
+
+
+def compare(g, o, batch, label, nmax):
+    import oracle
+
+    def solve(sub, rows, r32):
+        return run_oracle(sub, nmax, oracle.Params(round32=r32))
+    parity.check(g, o, batch, solve, label, round32=ROUND32)
+
+
+def _orders(kmax):
+    from oracle import free as F
+    return [F.key_modes(int(k)) for k in F.seed(kmax)]
+
+
+def test_all_short_orders_match_oracle():
+    """8 instances x all 72 admissible orders of one and two segments, 10 intervals each."""
+    x0, goal, inst = I.push_free_pairs(5000, 8)
+    orders = _orders(2)
+    pair = np.repeat(np.arange(8), len(orders))
+    b = I.orders_batch(x0, goal, inst, pair, orders * 8, [[10] * len(o) for o in orders] * 8)
+    g = run_gpu(b, 20)
+    o = run_oracle(b, 20)
+    print("feasible oracle / device:", int(o["feasible"].sum()), int(g["feasible"].sum()))
+    assert o["feasible"].sum() >= 8
+    compare(g, o, b, "free <= 2 segments", 20)
+
+
+def test_ragged_orders_match_oracle():
+    """1,024 admissible orders of 1..4 segments drawn uniformly, 4..10 intervals per segment,
+    on 16 instances."""
+    rng = np.random.default_rng(5100)
+    x0, goal, inst = I.push_free_pairs(5101, 16)
+    pool = _orders(4)
+    pick = rng.integers(0, len(pool), 1024)
+    orders = [pool[i] for i in pick]
+    knots = [list(rng.integers(4, 11, len(o))) for o in orders]
+    b = I.orders_batch(x0, goal, inst, rng.integers(0, 16, 1024), orders, knots)
+    g = run_gpu(b, 40)
+    o = run_oracle(b, 40)
+    print("feasible oracle / device:", int(o["feasible"].sum()), int(g["feasible"].sum()))
+    compare(g, o, b, "free ragged", 40)
+
+
+def test_free_approach_then_straight_push_on_gpu():
+    """Pusher 3 cm in front of face 2, goal (d, 0, 0), order [free in front of face 2, stick
+    on face 2]: J* = 0.03^2 / (N1 dt) + d^2 / (N2 dt) (see the oracle's pins), reached within
+    1e-3 at the exploration budget; the pusher arrives at the face centre."""
+    from oracle import free as F
+    cases = [(0.05, 6, 10), (0.12, 10, 12), (0.02, 4, 6)]
+    x0 = np.tile([0.0, 0.0, 0.0, -0.08, 0.0], (len(cases), 1))
+    goal = np.array([[d, 0.0, 0.0] for d, _, _ in cases])
+    b = I.orders_batch(x0, goal, np.full((len(cases), 1), 0.4), np.arange(len(cases)),
+                       [[F.free(2), F.contact(2, 0)]] * len(cases), [[n1, n2] for _, n1, n2 in cases])
+    g = run_gpu(b, 24)
+    for i, (d, n1, n2) in enumerate(cases):
+        Jstar = 0.03 ** 2 / (n1 * 0.1) + d ** 2 / (n2 * 0.1)
+        assert g["feasible"][i] == 1 and abs(g["cost"][i] - Jstar) <= 1e-3 * Jstar, (i, g["cost"][i], Jstar)
+        assert np.allclose(g["traj"][i, n1, 3:5], [-0.05, 0.0], atol=1e-4)
+
+
+def _ctx(max_batch=4096, max_intervals=40):
+    from paper_2609_21803_amd import native
+    return native.Context(max_batch=max_batch, max_segments=6, max_intervals=max_intervals, task=native.TASK_PUSH_FREE)
+
+
+@pytest.mark.parametrize("radius,kcap,n,W,room", [(1, 3, 40, 4096, 3000), (2, 3, 30, 8, 20000), (1, 6, 300, 64, 5000),
+                                                 (2, 4, 5, 3, 4000), (1, 2, 1, 1, 7)])
+def test_free_batch_construction_is_bit_exact(radius, kcap, n, W, room):
+    import torch
+    from oracle import free as F
+    from paper_2609_21803_amd import native
+    rng = np.random.default_rng(20 * radius + n)
+    pool = [int(k) for k in F.seed(min(kcap, 4))]
+    keys = np.array([pool[i] for i in rng.choice(len(pool), n, replace=False)], np.uint64)
+    merit = rng.choice([0.1, 0.5, 1.0, np.inf, np.nan], size=n) + np.where(rng.random(n) < 0.5, 0.0, rng.random(n))
+    ref = F.expand_next(keys, merit, kcap, radius, W, room)
+    ctx = _ctx(max_batch=max(room, 8))
+    prm = native.ExpandParams(kcap=kcap, radius=radius, frontier_W=W, batch_B=room, eval_budget=max(n, 1),
+                              knots_per_segment=5, rounds=1, k_ref=1, seed_max_segments=1)
+    got = native.expand_next(ctx, torch.as_tensor(keys.view(np.int64)).cuda(), torch.as_tensor(merit).cuda(), prm,
+                             room)
+    got = got.cpu().numpy().view(np.uint64)
+    assert len(got) == len(ref) and np.array_equal(got, ref), (len(got), len(ref))
+
+
+@pytest.mark.parametrize("seed", [5200, 5201])
+def test_free_expansion_stays_in_the_language_and_its_plan_is_confirmed(seed):
+    """Seed = every admissible order of at most two segments (72, in key order), two rounds of
+    one-edit neighbourhoods; every evaluated order is admissible, the first batch is the seed,
+    and the returned plan is feasible and re-solved by the oracle (refinement budget) to the
+    same cost within 1e-3."""
+    import torch
+    import oracle
+    from oracle import free as F
+    from paper_2609_21803_amd import native
+    x0, goal, inst = I.push_free_pairs(seed, 1)
+    prm = native.ExpandParams(kcap=4, seed_max_segments=2, radius=1, rounds=2, frontier_W=64, knots_per_segment=10,
+                              k_ref=16, batch_B=4096, eval_budget=20000)
+    ctx = _ctx(max_batch=4096, max_intervals=40)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+    o, st = native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm)
+    torch.cuda.synchronize()
+    o = {k: v.cpu().numpy() for k, v in o.items()}
+    keys, J, v = native.expand_trace(ctx)
+    keys = [int(k) for k in keys.cpu().numpy().view(np.uint64)]
+    seedk = [int(k) for k in F.seed(2)]
+    K = int(o["nseg"][0])
+    print("evaluated", len(keys), "feasible", int((v.cpu().numpy() <= 1e-5).sum()), "plan", list(o["modes"][:K]),
+          "cost", float(o["cost"][0]), flush=True)
+    assert keys[:len(seedk)] == seedk
+    assert all(F.admissible(F.key_modes(k)) for k in keys)
+    assert len(set(keys)) == len(keys)
+    assert K >= 1 and float(o["viol"][0]) <= 1e-5
+    modes = np.zeros((1, 6), np.int32)
+    knots = np.zeros((1, 6), np.int32)
+    modes[0, :K] = o["modes"][:K]
+    knots[0, :K] = o["knots"][:K]
+    assert F.admissible(list(modes[0, :K]))
+    r = F.evaluate(f32(x0), f32(goal), f32(inst), np.array([K]), modes, knots,
+                   params=oracle.Params(**oracle.REFINE))
+    assert r["feasible"][0] == 1 and abs(r["cost"][0] - float(o["cost"][0])) <= 1e-3 * abs(r["cost"][0]), \
+        (r["cost"][0], float(o["cost"][0]))
