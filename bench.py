@@ -60,6 +60,11 @@ FLIP_FLOP_PER_INTERVAL_GN = 10000.0
 # squared row fill grows from 109 to 151 entries), 8x8 Cholesky ~200, gains ~640, value
 # update ~230, forward pass ~70 and ~130 per trial step length (8 trials): ~3.0 kflop.
 TIMED_FLOP_PER_INTERVAL_GN = 3000.0
+# Pushing with free motion (9 stage unknowns, 15 row slots, 14 row arguments): linearisation
+# ~250, block assembly ~350 (squared row fill ~200 entries), 9x9 Cholesky ~240, the solves
+# for 5 + 1 right-hand sides ~490 each way, value update ~360, forward pass ~90 and ~130 per
+# trial step length (8 trials): ~3.3 kflop.
+FREE_FLOP_PER_INTERVAL_GN = 3300.0
 HBM_PEAK_GBS = 8000.0
 
 
@@ -262,6 +267,106 @@ def hetero_leg(native, I, torch, B=131072):
             "default_schedule": {"kernel_ms": float(np.mean(default_ms)), "solves_per_s": B / (np.mean(default_ms) * 1e-3)},
             "autotuned_schedule": {"schedule": sched, "kernel_ms": float(np.mean(best)),
                                    "solves_per_s": B / (np.mean(best) * 1e-3)}}
+
+
+def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cpu=True):
+    """Pushing with free motion (the Sec. III-A language, 16 mode ids, at most six segments:
+    14,760 admissible orders), in the paper's planner configurations on the device: full
+    enumeration (every admissible order, which with a cap of six segments is also the seed
+    of the paper's "seed only") and expansion with s_max = 2 (seed of the 72 orders of at most
+    two segments, two rounds of one-edit neighbourhoods, W = 256); 10 intervals per segment,
+    refinement of the 16 best.  Then the evaluator alone on every admissible order for each
+    of 8 instances (118,080 TOs), one launch timed after a warm-up, with its roofline, and
+    the oracle's rate on a strided sample."""
+    ctx = native.Context(max_batch=16384, max_segments=6, max_intervals=60, task=native.TASK_PUSH_FREE)
+    configs = {"full_enumeration": native.ExpandParams(kcap=6, seed_max_segments=6, radius=1, rounds=0, frontier_W=1,
+                                                         knots_per_segment=10, k_ref=16, batch_B=16384,
+                                                         eval_budget=16384),
+               "expansion_smax2": native.ExpandParams(kcap=6, seed_max_segments=2, radius=1, rounds=2, frontier_W=256,
+                                                        knots_per_segment=10, k_ref=16, batch_B=16384,
+                                                        eval_budget=16384)}
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+    rows, all_keys = {k: [] for k in configs}, None
+    for name, prm in configs.items():
+        for sd in seeds:
+            x0, goal, inst = I.push_free_pairs(sd, 1)
+            native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm)          # capture + warm-up
+            torch.cuda.synchronize()
+            o, st = native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm)
+            torch.cuda.synchronize()
+            K = int(o["nseg"].item())
+            if all_keys is None and name == "full_enumeration":
+                all_keys = native.expand_trace(ctx)[0].cpu().numpy().view(np.uint64)
+            rows[name].append({"seed": sd, "evaluated": st["evaluated"], "rounds": st["rounds_done"],
+                               "feasible": st["n_feasible"], "device_ms": st["t_total_ms"],
+                               "t_first_feasible_ms": st["t_first_feasible_ms"],
+                               "plan": o["modes"].cpu().numpy()[:K].tolist(),
+                               "plan_cost": float(o["cost"].item()) if K else None})
+    # the evaluator alone: every admissible order (the full enumeration's evaluated set) on
+    # each of n_eval_inst instances
+    n1 = len(all_keys)
+    nseg1 = (all_keys >> np.uint64(60)).astype(np.int32)
+    modes1 = np.zeros((n1, 6), np.int32)
+    for i in range(6):
+        modes1[:, i] = ((all_keys >> np.uint64(50 - 10 * i)) & np.uint64(1023)).astype(np.int32)
+    modes1[np.arange(6)[None, :] >= nseg1[:, None]] = 0
+    x0, goal, inst = I.push_free_pairs(5400, n_eval_inst)
+    pair = np.repeat(np.arange(n_eval_inst), n1)
+    nseg = np.tile(nseg1, n_eval_inst)
+    batch = dict(x0=x0[pair], goal=goal[pair], inst=inst[pair], nseg=nseg, modes=np.tile(modes1, (n_eval_inst, 1)),
+                 knots=np.where(np.arange(6)[None, :] < nseg[:, None], 10, 0).astype(np.int32))
+    n = len(nseg)
+    ectx = native.Context(max_batch=n, max_segments=6, max_intervals=60, task=native.TASK_PUSH_FREE)
+    d = native.to_device(batch)
+    ectx.evaluate(**d)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    out = ectx.evaluate(**d)
+    e1.record()
+    torch.cuda.synchronize()
+    ms, kms = e0.elapsed_time(e1), ectx.kernel_ms()
+    st = out["stats"].cpu().numpy()
+    N = I.n_intervals(batch).astype(np.float64)
+    flops = float((st[:, 1] * N).sum()) * FREE_FLOP_PER_INTERVAL_GN + float((st[:, 0] * N).sum()) * FLOP_PER_INTERVAL_AL
+    ach = flops / (kms * 1e-3) / 1e12
+    res = {"workload": "pushing with free motion (16 mode ids, the Sec. III-A language, <= 6 segments: "
+                       f"{n1} admissible orders), 10 intervals per segment; planner configurations on the goals of "
+                       f"seeds 5300..; evaluator on all {n1} orders x {n_eval_inst} instances (seed 5400)",
+           "planner": rows,
+           "evaluate": {"orders": n, "value": n / (ms * 1e-3), "unit": "solves/s", "ms": ms,
+                        "mean_intervals": float(N.mean()), "mean_gn_iterations": float(st[:, 1].mean()),
+                        "feasible_fraction": float(out["feasible"].float().mean().item()),
+                        "roofline": {"bound": "alu", "kernel": "k_push_solve (free motion)", "achieved": ach,
+                                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
+                                     "kernel_ms": kms, "flop_per_launch": flops, "traffic": None}}}
+    if cpu:
+        res["evaluate"]["cpu_baseline"] = free_cpu_baseline(batch)
+    return res
+
+
+def free_cpu_baseline(batch, seconds_target=10.0):
+    """Free-motion oracle (FP64, plain C, one order per thread over all host threads) on an
+    evenly strided sample of the batch; returns solves/s."""
+    from oracle import free as F
+    n_threads = os.cpu_count() or 1
+    B = len(batch["nseg"])
+    f32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+
+    def run(n):
+        idx = np.linspace(0, B - 1, n).astype(np.int64)
+        sub = {k: v[idx] for k, v in batch.items()}
+        t0 = time.perf_counter()
+        F.evaluate(f32(sub["x0"]), f32(sub["goal"]), f32(sub["inst"]), sub["nseg"], sub["modes"], sub["knots"],
+                   nthreads=n_threads)
+        return time.perf_counter() - t0
+
+    n = 4 * n_threads
+    dt = run(n)
+    n2 = int(min(B, max(n, n * seconds_target / max(dt, 1e-3))))
+    dt = run(n2)
+    return dict(value=n2 / dt, unit="solves/s", cores=n_threads, kind="oracle", value_per_core=n2 / dt / n_threads,
+                sample=f"{n2} of {B} orders, evenly strided over the batch, FP64, {n_threads} threads, {dt:.1f} s")
 
 
 def expand_scale_leg(native, I, torch, seeds=(2000, 2001)):
@@ -506,6 +611,7 @@ def main():
     ap.add_argument("--no-policies", action="store_true", help="skip the allocation-policy comparison")
     ap.add_argument("--no-timed", action="store_true", help="skip the optimised-timing pushing leg")
     ap.add_argument("--no-scale", action="store_true", help="skip the expansion legs at the configured scale")
+    ap.add_argument("--no-free", action="store_true", help="skip the free-motion pushing leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -605,6 +711,7 @@ def main():
             ("policies", not args.no_policies, lambda: policy_leg(native, I, torch)),
             ("expand_scale", not args.no_scale, lambda: expand_scale_leg(native, I, torch)),
             ("flip_expand_scale", not args.no_scale, lambda: flip_expand_scale_leg(native, I, torch)),
+            ("free", not args.no_free, lambda: free_leg(native, I, torch, cpu=not args.no_cpu)),
             ("learned", not args.no_learned, lambda: learned_leg(native, I, torch)),
             ("learned_flip", not args.no_learned, lambda: learned_flip_leg(native, I, torch)),
             ("cpu_baseline", not args.no_cpu, lambda: cpu_baseline(batch))]

@@ -334,7 +334,13 @@ typedef struct {
  * never share a face, change faces only through a free segment, a pivot keeps a finger in
  * contact, no two consecutive equal segments, consecutive pivots keep their direction, no
  * finger on the face on the table -- the support face, and in a pivot the landing face);
- * the seed and every generated neighbour are filtered by it.  The loop runs as one captured HIP graph on an internal
+ * pushing with free motion, the orders of its 16 ids where no two consecutive segments are
+ * equal, a contact keeps its face until a free segment, contact on face j is entered from
+ * and left to the free region in front of face j, and free regions connect to the regions
+ * of the neighbouring faces (Sec. III-A); the seed and every generated neighbour are
+ * filtered by it, and a two-edit neighbour only through an admissible one-edit order.
+ * The learned network serves the pushing, timed-pushing and flipping tasks (EINVAL with
+ * free motion).  The loop runs as one captured HIP graph on an internal
  * stream ordered after `stream`; the call synchronises and fills `stats` (host).  Outputs
  * (device): best_nseg [1] (0 = no feasible plan), best_modes / best_knots [max_segments],
  * best_cost / best_viol [1] (refined), best_traj [max_intervals+1, nx+nu] or NULL.

@@ -12,6 +12,10 @@ Workloads (planar pushing, square slider of side 0.1 m, one point pusher):
                           intervals per segment ~ U{5..15}, on 64 pairs.
 Start at rest at the origin with the pusher at the face centre; goal x, y ~ U[-0.3, 0.3] m,
 theta ~ U[-pi, pi]; pusher friction mu ~ U[0.3, 0.5].
+Free-motion pushing (``push_free_pairs``): the same slider at rest at the origin with the
+pusher 3 cm in front of a face drawn uniformly; goal x, y ~ U[-0.15, 0.15] m, theta ~
+U[-pi/2, pi/2]; ``orders_batch`` lays out orders given one by one.  Flipping: see the
+``flip_*`` generators below.
 """
 from __future__ import annotations
 
