@@ -6,7 +6,8 @@ free-motion oracle, called through the C ABI.
   on the feasible flag, and on cost within 1e-4 and violation within 1e-5 where both are
   feasible; a disagreement is excused only where the oracle itself moves under float32-level
   perturbations), on every admissible order of at most two segments and on a ragged batch
-  of admissible orders of up to four segments.
+  of admissible orders of up to four segments, and on a strided sample of the benchmark's
+  launch (every admissible order of at most six segments on 8 instances).
 * The closed form of a free approach followed by a straight push.
 * The device expansion over this language: bit-exact batch construction against the
   oracle's batch step, and a whole expansion whose evaluated orders are all admissible and
@@ -89,6 +90,25 @@ def test_ragged_orders_match_oracle():
     o = run_oracle(b, 40)
     print("feasible oracle / device:", int(o["feasible"].sum()), int(g["feasible"].sum()))
     compare(g, o, b, "free ragged", 40)
+
+
+def test_free_full_size_workload_sampled():
+    """Every admissible order of at most six segments (14,760) on 8 instances, 10 intervals per
+    segment (118,080 TOs, up to 60 intervals) in one launch, as the benchmark times it;
+    1,024 evenly strided sequences checked against the oracle one by one."""
+    from oracle import free as F
+    orders = [F.key_modes(int(k)) for k in F.seed(6)]
+    assert len(orders) == 14760
+    x0, goal, inst = I.push_free_pairs(5400, 8)
+    pair = np.repeat(np.arange(8), len(orders))
+    b = I.orders_batch(x0, goal, inst, pair, orders * 8, [[10] * len(o) for o in orders] * 8)
+    g = run_gpu(b, 60)
+    idx = np.linspace(0, len(b["nseg"]) - 1, 1024).astype(np.int64)
+    sub = I.subset(b, idx)
+    o = run_oracle(sub, 60)
+    print("feasible in the launch:", int(g["feasible"].sum()), "sampled oracle / device:", int(o["feasible"].sum()),
+          int(g["feasible"][idx].sum()))
+    compare({k: v[idx] for k, v in g.items()}, o, sub, "free full size (1,024 strided)", 60)
 
 
 def test_free_approach_then_straight_push_on_gpu():
