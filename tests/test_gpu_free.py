@@ -190,3 +190,66 @@ def test_free_expansion_stays_in_the_language_and_its_plan_is_confirmed(seed):
                    params=oracle.Params(**oracle.REFINE))
     assert r["feasible"][0] == 1 and abs(r["cost"][0] - float(o["cost"][0])) <= 1e-3 * abs(r["cost"][0]), \
         (r["cost"][0], float(o["cost"][0]))
+
+
+def test_free_invalid_sequences_empty_batch_and_network_hooks():
+    """Invalid orders (an id outside the 16 of this task, no segment, a non-finite pusher
+    position or goal, more intervals than the context holds) come back with NaN cost, +inf
+    violation and status 3 and raise the device error counter; the valid orders beside them
+    are solved.  An empty batch is a no-op; the learned network does not serve this task."""
+    import torch
+    from oracle import free as F
+    from paper_2609_21803_amd import native
+    x0, goal, inst = I.push_free_pairs(5500, 8)
+    orders = [[F.free(3), F.contact(3, 0)]] * 8
+    b = I.orders_batch(x0, goal, inst, np.arange(8), orders, [[5, 5]] * 8)
+    b["modes"][1, 1] = 16            # outside the 16 ids
+    b["nseg"][2] = 0                 # no segment
+    b["x0"][3, 4] = np.nan           # pusher position not finite
+    b["goal"][4, 2] = np.inf         # goal not finite
+    b["knots"][5, 1] = 40            # 45 intervals > 20
+    ctx = _ctx(max_batch=8, max_intervals=20)
+    out = ctx.evaluate(**native.to_device(b))
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+    for i in (1, 2, 3, 4, 5):
+        assert np.isnan(g["cost"][i]) and np.isinf(g["viol"][i]) and g["feasible"][i] == 0, i
+        assert g["stats"][i, 3] == 3, i
+    assert np.all(np.isfinite(g["cost"][[0, 6, 7]]))
+    with pytest.raises(native.CometError):
+        ctx.check()
+    ctx.check()                      # the counter was cleared
+    e = {k: v[:0] for k, v in native.to_device(b).items()}
+    assert ctx.evaluate(**e)["cost"].numel() == 0
+    with pytest.raises(native.CometError):
+        native.mlp_encode(native.to_device(b), task=native.TASK_PUSH_FREE)
+
+
+def test_free_maximum_length_orders_match_oracle():
+    """Orders at the longest work-space height (510 of 512 intervals): a free approach of
+    255 intervals then a straight push of 255, whose optimum is 0.03^2 / (N1 dt) + d^2 /
+    (N2 dt), and three admissible six-segment orders of 85 intervals per segment.  Where
+    both sides converge the flags agree and the costs agree within 1e-3 (the stopping
+    region is wide over 510 stages, as for the pushing tasks); the straight push converges
+    on both sides and reaches its closed form within 5e-3; trajectory rows past the last
+    knot stay zero."""
+    import oracle
+    from oracle import free as F
+    x0 = np.array([[0.0, 0.0, 0.0, -0.08, 0.0]] * 4)
+    goal = np.array([[0.1, 0.0, 0.0], [0.05, 0.05, 0.3], [-0.05, 0.08, -0.4], [0.08, -0.03, 0.5]])
+    six = [[14, 6, 14, 15, 9, 15], [14, 6, 7, 14, 13, 4], [14, 8, 14, 15, 12, 1]]
+    assert all(F.admissible(o) for o in six)
+    orders = [[F.free(2), F.contact(2, 0)]] + six
+    knots = [[255, 255]] + [[85] * 6] * 3
+    b = I.orders_batch(x0, goal, np.full((4, 1), 0.4), np.arange(4), orders, knots)
+    g = run_gpu(b, 512)
+    o = run_oracle(b, 512)
+    conv = (g["stats"][:, 3] == 1) & (o["stats"][:, 3] == 1)
+    rel = np.abs(g["cost"].astype(np.float64) - o["cost"]) / np.maximum(np.abs(o["cost"]), 1e-12)
+    print("statuses gpu / oracle:", g["stats"][:, 3], o["stats"][:, 3], "feasible:", g["feasible"], o["feasible"],
+          "rel cost:", rel, flush=True)
+    assert conv[0]
+    Jstar = 0.03 ** 2 / (255 * 0.1) + 0.1 ** 2 / (255 * 0.1)
+    assert abs(g["cost"][0] - Jstar) <= 5e-3 * Jstar and abs(o["cost"][0] - Jstar) <= 5e-3 * Jstar
+    assert np.all(g["feasible"][conv] == o["feasible"][conv]) and np.all(rel[conv] <= 1e-3)
+    assert np.all(g["traj"][:, 511:] == 0) and np.all(g["traj"][:, 510, 5:] == 0)

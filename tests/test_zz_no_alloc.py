@@ -59,6 +59,8 @@ def test_noalloc_rejects_what_does_not_fit_and_other_tasks():
         native.evaluate_noalloc(**big, max_intervals=75, task=native.TASK_PUSH)
     with pytest.raises(native.CometError):
         native.evaluate_noalloc(**d, max_intervals=75, task=native.TASK_FLIP)
+    with pytest.raises(native.CometError):
+        native.evaluate_noalloc(**d, max_intervals=75, task=native.TASK_PUSH_FREE)
     e = {k: v[:0] for k, v in d.items()}
     o = native.evaluate_noalloc(**e, max_intervals=75, task=native.TASK_PUSH)   # B = 0: no-op
     assert o["cost"].numel() == 0
