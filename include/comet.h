@@ -87,8 +87,9 @@ void comet_default_params(comet_solver_params* p);
 /* Create a context for one task on the current HIP device.  Allocates the device work
  * space for up to max_batch sequences of up to max_segments segments and max_intervals
  * control intervals each (synchronous).  Returns COMET_EINVAL for max_segments outside
- * [1, 6], max_intervals outside [1, 512] or max_batch < 1, COMET_ENOMEM if the work space
- * does not fit. */
+ * [1, 6] ([1, 8] for COMET_TASK_PUSH_FREE, whose orders the paper caps at eight segments,
+ * Sec. IV-A), max_intervals outside [1, 512] or max_batch < 1, COMET_ENOMEM if the work
+ * space does not fit. */
 comet_status comet_create(comet_task task, const comet_solver_params* params, int64_t max_batch,
                           int32_t max_segments, int32_t max_intervals, comet_ctx** out);
 void comet_destroy(comet_ctx* ctx);
@@ -250,9 +251,13 @@ comet_status comet_last_kernel_ms(comet_ctx* ctx, float* ms);
 /* ---------------------------------------------------------------------------------
  * Greedy contact-mode expansion (Alg. 1, Sec. III-B) on the device.
  *
- * Orders are keys: K << 60 | m_0 << 50 | m_1 << 40 | ... | m_5 << 0 (10 bits per mode id),
- * so comparing keys compares the segment count, then the ids lexicographically.  The
- * language is every order of 1..kcap segments over the task's mode ids.
+ * Orders are keys: K << 60 | m_0 << 50 | m_1 << 40 | ... | m_5 << 0 (10 bits per mode id;
+ * with free motion K << 60 | m_0 << 56 | m_1 << 52 | ... | m_7 << 28, 4 bits per id, up to
+ * eight segments), so comparing keys compares the segment count, then the ids
+ * lexicographically.  The language is every order of 1..kcap segments over the task's mode
+ * ids, restricted by the task's rules where it has them (below).  With free motion the seed
+ * pass enumerates the admissible orders themselves (the product space of eight segments
+ * has 16^8 orders), so a seed of eight segments is the whole language: 205,632 orders.
  *   kcap               segment cap (<= max_segments)
  *   seed_max_segments  seed batch F_0 = every order with at most this many segments, in key order
  *   radius             r of the r-edit neighbourhood (1 or 2): an edit inserts, deletes or

@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).  The numerical work lives 
 ``free_oracle.c``; this module marshals NumPy arrays.
 
 Layouts: x0 [B, 5] = (x, y, theta, p_x, p_y), the pusher in the slider frame; goal [B, 3]
-= (x, y, theta); inst [B] = pusher friction; modes / knots [B, 6]; trajectory rows
+= (x, y, theta); inst [B] = pusher friction; modes / knots [B, smax <= 8]; trajectory rows
 (x_k, u_k) of 9 values with u = (F_n, F_t, v_x, v_y), the pusher velocity in the slider
 frame.  Mode ids 0..11: contact on face id // 3 with slip id % 3 (stick, slide+, slide-);
 12..15: free motion in front of face id - 12.
@@ -25,7 +25,7 @@ _SRC = os.path.join(_HERE, "free_oracle.c")
 _LIB = os.path.join(_HERE, "libfree_oracle.so")
 
 NX, NU, NW, NV, NE, NI, NR, NT = 5, 4, 9, 14, 8, 7, 15, 3
-MAXSEG = 6
+MAXSEG = 8
 N_MODES = 16
 N_TYPES = 16
 # slider at rest at the origin, pusher 3 cm in front of face 3 (below the slider)
@@ -188,18 +188,19 @@ def admissible(modes) -> bool:
 
 
 def key_make(modes) -> int:
+    """K << 60 | m_0 << 56 | m_1 << 52 | ... (4 bits per id, up to 8 segments)"""
     k = len(modes) << 60
     for i, m in enumerate(modes):
-        k |= int(m) << (50 - 10 * i)
+        k |= int(m) << (56 - 4 * i)
     return k
 
 
 def key_modes(k: int):
-    return [(int(k) >> (50 - 10 * i)) & 1023 for i in range(int(k) >> 60)]
+    return [(int(k) >> (56 - 4 * i)) & 15 for i in range(int(k) >> 60)]
 
 
 def neighbours(key: int, kcap: int, radius: int) -> np.ndarray:
-    out = np.zeros(240 * 240 + 16, np.uint64)
+    out = np.zeros(260 * 260 + 16, np.uint64)
     n = lib().free_neighbours(int(key), kcap, radius, _p(out))
     return out[:n]
 

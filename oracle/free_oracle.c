@@ -40,7 +40,7 @@
 #define QNI 7
 #define QNT 3
 #define QMODES 16
-#define MAXSEG 6
+#define MAXSEG 8
 #define MAXN 512
 
 static const double Q_A = 0.1, Q_MASS = 1.0, Q_G = 9.81, Q_MUG = 0.5;
@@ -898,15 +898,17 @@ int free_admissible(int32_t K, const int32_t *modes) {
   return 1;
 }
 
+/* keys: K << 60 | m_0 << 56 | m_1 << 52 | ... (4 bits per id, up to 8 segments), so that */
+/* comparing keys compares the segment count, then the ids lexicographically             */
 typedef uint64_t QKey;
 static QKey qkey_make(int K, const int *m) {
   QKey k = (QKey)K << 60;
   int i;
-  for (i = 0; i < K; ++i) k |= (QKey)m[i] << (50 - 10 * i);
+  for (i = 0; i < K; ++i) k |= (QKey)m[i] << (56 - 4 * i);
   return k;
 }
 static int qkey_len(QKey k) { return (int)(k >> 60); }
-static int qkey_mode(QKey k, int i) { return (int)((k >> (50 - 10 * i)) & 1023u); }
+static int qkey_mode(QKey k, int i) { return (int)((k >> (56 - 4 * i)) & 15u); }
 static int qkey_admissible(QKey k) {
   int32_t m[MAXSEG];
   int K = qkey_len(k), i;
@@ -1017,24 +1019,28 @@ int64_t free_neighbours(uint64_t key, int32_t kcap, int32_t radius, uint64_t *ou
   return qneigh((QKey)key, kcap, radius, (QKey *)out);
 }
 
-/* seed: the admissible orders of 1..kmax segments in key order, at most cap */
+/* seed: the admissible orders of 1..kmax segments in key order, at most cap.  For each  */
+/* length, a depth-first walk that tries the ids of every position in ascending order   */
+/* and extends only admissible prefixes (the product space of eight segments, 16^8      */
+/* orders, is too large to filter)                                                      */
+static void q_seed_walk(int K, int d, int *q, int64_t cap, int64_t *n, uint64_t *out) {
+  int id;
+  if (d == K) {
+    if (*n < cap) out[(*n)++] = qkey_make(K, q);
+    return;
+  }
+  for (id = 0; id < QMODES && *n < cap; ++id) {
+    if (d > 0 && !q_step_ok(q[d - 1], id)) continue;
+    q[d] = id;
+    q_seed_walk(K, d + 1, q, cap, n, out);
+  }
+}
+
 int64_t free_seed(int32_t kmax, int64_t cap, uint64_t *out) {
   int64_t n = 0;
-  int K, i, q[MAXSEG];
-  for (K = 1; K <= kmax && n < cap; ++K) {
-    int64_t total = 1, c;
-    for (i = 0; i < K; ++i) total *= QMODES;
-    for (c = 0; c < total && n < cap; ++c) {
-      int64_t t = c;
-      QKey k;
-      for (i = K - 1; i >= 0; --i) {
-        q[i] = (int)(t % QMODES);
-        t /= QMODES;
-      }
-      k = qkey_make(K, q);
-      if (qkey_admissible(k)) out[n++] = k;
-    }
-  }
+  int K, q[MAXSEG];
+  if (kmax > MAXSEG) kmax = MAXSEG;
+  for (K = 1; K <= kmax && n < cap; ++K) q_seed_walk(K, 0, q, cap, &n, out);
   return n;
 }
 

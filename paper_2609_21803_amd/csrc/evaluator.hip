@@ -56,6 +56,7 @@ using namespace push_timed;
 }  // namespace timed_step
 
 namespace free_step {
+constexpr int MAXSEG = MAXSEG_FREE;   // orders of up to eight segments
 using namespace push_free;
 #define PUSH_MODEL_FREE 1
 #include "push_solver.inc"
@@ -297,7 +298,7 @@ comet_status comet_create(comet_task task, const comet_solver_params* params, in
   if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP && task != COMET_TASK_PUSH_TIMED &&
        task != COMET_TASK_PUSH_FREE) || max_batch < 1 ||
       max_segments < 1 ||
-      max_segments > comet::MAXSEG ||
+      max_segments > (task == COMET_TASK_PUSH_FREE ? comet::MAXSEG_FREE : comet::MAXSEG) ||
       max_intervals < 1 || max_intervals > comet::MAXN)
     return COMET_EINVAL;
   comet_ctx* c = new comet_ctx();

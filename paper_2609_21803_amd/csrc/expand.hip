@@ -41,24 +41,24 @@ __host__ __device__ inline int raw1_count(int K, int M, int kcap) {
 // The e-th raw one-edit neighbour in enumeration order (substitutions by position then
 // id, skipping the current id; deletions by position; insertions by position then id).
 // Returns 0 when e is out of range.
-__host__ __device__ inline unsigned long long raw1_decode(unsigned long long p, int e, int M, int kcap) {
-  int m[6], q[7];
+__host__ __device__ inline unsigned long long raw1_decode(unsigned long long p, int e, int M, int kcap, int w) {
+  int m[KEY_MAXSEG], q[KEY_MAXSEG + 1];
   const int K = key_len(p);
-  for (int i = 0; i < K; ++i) m[i] = key_mode(p, i);
+  for (int i = 0; i < K; ++i) m[i] = key_mode(p, i, w);
   const int nsub = K * (M - 1), ndel = (K > 1) ? K : 0, nins = (K < kcap) ? (K + 1) * M : 0;
   if (e < 0) return EMPTY;
   if (e < nsub) {
     const int i = e / (M - 1), j = e % (M - 1);
     for (int t = 0; t < K; ++t) q[t] = m[t];
     q[i] = (j < m[i]) ? j : j + 1;
-    return key_make(K, q);
+    return key_make(K, q, w);
   }
   e -= nsub;
   if (e < ndel) {
     int t = 0;
     for (int j = 0; j < K; ++j)
       if (j != e) q[t++] = m[j];
-    return key_make(K - 1, q);
+    return key_make(K - 1, q, w);
   }
   e -= ndel;
   if (e < nins) {
@@ -67,7 +67,7 @@ __host__ __device__ inline unsigned long long raw1_decode(unsigned long long p, 
     for (int j = 0; j < i; ++j) q[t++] = m[j];
     q[t++] = id;
     for (int j = i; j < K; ++j) q[t++] = m[j];
-    return key_make(K + 1, q);
+    return key_make(K + 1, q, w);
   }
   return EMPTY;
 }
@@ -78,16 +78,17 @@ __host__ __device__ inline unsigned long long raw1_decode(unsigned long long p, 
 // every intermediate order of an r-edit path stays admissible).
 __host__ __device__ inline unsigned long long raw_decode(unsigned long long p, long long e, int M, int kcap, int radius,
                                                           int raw1max, int task) {
+  const int w = key_bits(task);
   const int n1 = raw1_count(key_len(p), M, kcap);
-  if (e < n1) return raw1_decode(p, (int)e, M, kcap);
+  if (e < n1) return raw1_decode(p, (int)e, M, kcap, w);
   if (radius < 2) return EMPTY;
   const long long t = e - n1;
   const long long q = t / raw1max;
   const int e2 = (int)(t % raw1max);
   if (q >= n1) return EMPTY;
-  const unsigned long long k1 = raw1_decode(p, (int)q, M, kcap);
+  const unsigned long long k1 = raw1_decode(p, (int)q, M, kcap, w);
   if (!admissible_key(task, k1)) return EMPTY;
-  return (e2 < raw1_count(key_len(k1), M, kcap)) ? raw1_decode(k1, e2, M, kcap) : EMPTY;
+  return (e2 < raw1_count(key_len(k1), M, kcap)) ? raw1_decode(k1, e2, M, kcap, w) : EMPTY;
 }
 
 // Table slot of a key.  Keys carry their information in the high bits (segment count and
@@ -346,21 +347,23 @@ __global__ void k_seed(ExpCfg g, int kmax, long long n_seed, ExpCounters* C, uns
     ++K;
     cnt *= g.M;
   }
-  int q[6];
+  int q[KEY_MAXSEG];
   for (int i = K - 1; i >= 0; --i) {
     q[i] = (int)(c % g.M);
     c /= g.M;
   }
-  const unsigned long long k = key_make(K, q);
+  const unsigned long long k = key_make(K, q, key_bits(g.task));
   F[t] = k;
   set_insert(vset, g.vmask, k);
 }
 
 // seed as candidates (languages with a filter): slot t holds the t-th order of 1..kmax
 // segments in key order, or EMPTY if it is not admissible; the candidate pipeline then
-// keeps the admissible ones in order
+// keeps the admissible ones in order.  Pushing with free motion enumerates its language
+// directly (slot t = the t-th admissible order, read off the continuation counts fc): its
+// product space of eight segments (16^8 orders) is too large to filter.
 __global__ void k_seed_cand(ExpCfg g, int kmax, long long n_seed, ExpCounters* C, unsigned long long* ckey,
-                            unsigned long long* hkeys, unsigned* hmin) {
+                            unsigned long long* hkeys, unsigned* hmin, FreeCounts fc) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {
     C->nCand = n_seed;
@@ -368,20 +371,31 @@ __global__ void k_seed_cand(ExpCfg g, int kmax, long long n_seed, ExpCounters* C
     C->kept = 0;
   }
   if (t >= n_seed) return;
-  long long c = t, cnt = g.M;
-  int K = 1;
-  while (K < kmax && c >= cnt) {
-    c -= cnt;
-    ++K;
-    cnt *= g.M;
+  unsigned long long k;
+  if (g.task == COMET_TASK_PUSH_FREE) {
+    long long c = t;
+    int K = 1;
+    for (long long n = free_count_len(fc, 1); K < kmax && c >= n; n = free_count_len(fc, K)) {
+      c -= n;
+      ++K;
+    }
+    k = free_unrank(fc, K, c);
+  } else {
+    long long c = t, cnt = g.M;
+    int K = 1;
+    while (K < kmax && c >= cnt) {
+      c -= cnt;
+      ++K;
+      cnt *= g.M;
+    }
+    int q[KEY_MAXSEG];
+    for (int i = K - 1; i >= 0; --i) {
+      q[i] = (int)(c % g.M);
+      c /= g.M;
+    }
+    k = key_make(K, q, key_bits(g.task));
+    if (!admissible_key(g.task, k)) k = EMPTY;
   }
-  int q[6];
-  for (int i = K - 1; i >= 0; --i) {
-    q[i] = (int)(c % g.M);
-    c /= g.M;
-  }
-  unsigned long long k = key_make(K, q);
-  if (!admissible_key(g.task, k)) k = EMPTY;
   ckey[t] = k;
   if (k != EMPTY) first_insert(hkeys, hmin, g.cmask, k, (unsigned)t);
 }
@@ -396,7 +410,7 @@ __global__ void k_build(ExpCfg g, const long long* n_dev, const unsigned long lo
   nseg[i] = K;
   for (int j = 0; j < smax; ++j) {
     const bool live = j < K;
-    modes[i * smax + j] = live ? key_mode(k, j) : 0;
+    modes[i * smax + j] = live ? key_mode(k, j, key_bits(g.task)) : 0;
     int n = 0;
     if (live) n = (g.knots_per_segment > 0) ? g.knots_per_segment : g.n_total / K + ((j < g.n_total % K) ? 1 : 0);
     knots[i * smax + j] = n;
@@ -462,9 +476,9 @@ __global__ void k_sample(ExpCfg g, const ExpCounters* C, const unsigned long lon
   if (t >= C->nCand) return;
   const unsigned long long c = C->draw_base + (unsigned long long)t;
   const int K = 1 + (int)(splitmix64_out(g.sseed, 8ull * c) % (unsigned long long)g.kcap);
-  int m[6] = {0, 0, 0, 0, 0, 0};
+  int m[KEY_MAXSEG] = {};
   for (int j = 0; j < K; ++j) m[j] = (int)(splitmix64_out(g.sseed, 8ull * c + 1ull + j) % (unsigned long long)g.M);
-  unsigned long long k = key_make(K, m);
+  unsigned long long k = key_make(K, m, key_bits(g.task));
   if (!admissible_key(g.task, k)) k = EMPTY;
   if (k != EMPTY && set_has(vset, g.vmask, k)) k = EMPTY;
   ckey[t] = k;
@@ -627,7 +641,7 @@ __global__ void k_best_out(ExpCfg g, const ExpCounters* C, const float* rtraj, i
   }
   if (t < smax) {
     const bool live = (k != 0) && t < K;
-    best_modes[t] = live ? key_mode(k, t) : 0;
+    best_modes[t] = live ? key_mode(k, t, key_bits(g.task)) : 0;
     best_knots[t] = live ? ((g.knots_per_segment > 0) ? g.knots_per_segment
                                                       : g.n_total / K + ((t < g.n_total % K) ? 1 : 0))
                          : 0;
@@ -729,6 +743,22 @@ comet_status check_expand_params(comet_ctx* c, const comet_expand_params* p) {
   return COMET_OK;
 }
 
+// slots of the seed pass: every order of 1..kmax segments of the product space (filtered
+// on the device by the task's language), or, with free motion, its admissible orders only
+long long seed_slots(int task, int M, int kmax) {
+  long long n = 0, t = 1;
+  if (task == COMET_TASK_PUSH_FREE) {
+    const FreeCounts f = free_counts();
+    for (int K = 1; K <= kmax; ++K) n += free_count_len(f, K);
+    return n;
+  }
+  for (int K = 1; K <= kmax; ++K) {
+    t *= M;
+    n += t;
+  }
+  return n;
+}
+
 comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
   const bool flip = (c->task == COMET_TASK_FLIP), lang = task_has_language(c->task);
   const int M = flip ? 845 : (c->task == COMET_TASK_PUSH_FREE ? push_free::NMODES : push::NMODES);
@@ -736,11 +766,7 @@ comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
   int raw1max = 0;
   for (int K = 1; K <= p->kcap; ++K) raw1max = std::max(raw1max, raw1_count(K, M, p->kcap));
   const long long rawmax = (p->radius >= 2) ? (long long)raw1max + (long long)raw1max * raw1max : raw1max;
-  long long n_seed = 0;
-  for (long long K = 1, t = 1; K <= std::min(p->seed_max_segments, p->kcap); ++K) {
-    t *= M;
-    n_seed += t;
-  }
+  const long long n_seed = seed_slots(c->task, M, std::min(p->seed_max_segments, p->kcap));
   const bool sampling = p->policy == COMET_POLICY_UNIFORM;
   const long long ncand = (p->policy == COMET_POLICY_MCTS) ? 1
                           : sampling ? p->sample_draws : std::max(rawmax * p->frontier_W, lang ? n_seed : 0ll);
@@ -986,11 +1012,7 @@ comet_status enqueue_expand(comet_ctx* c, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u64, dim3(blocks(g.vmask + 1, 256 * 8)), dim3(256), 0, s, w->vset, EMPTY,
                      (long long)(g.vmask + 1));
   const int kmax = std::min(p.seed_max_segments, p.kcap);
-  long long n_seed = 0, t = 1;
-  for (int K = 1; K <= kmax; ++K) {
-    t *= g.M;
-    n_seed += t;
-  }
+  const long long n_seed = seed_slots(g.task, g.M, kmax);
   if (g.policy == COMET_POLICY_UNIFORM) {
     hipLaunchKernelGGL(k_sample_start, dim3(1), dim3(1), 0, s, g, w->C);
     enqueue_sample_batch(c, s);
@@ -1002,7 +1024,7 @@ comet_status enqueue_expand(comet_ctx* c, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks(g.cmask + 1, 256 * 8)), dim3(256), 0, s, w->hmin, 0xFFFFFFFFu,
                        (long long)(g.cmask + 1));
     hipLaunchKernelGGL(k_seed_cand, dim3(blocks(n_seed, 256)), dim3(256), 0, s, g, kmax, n_seed, w->C, w->ckey,
-                       w->hkeys, w->hmin);
+                       w->hkeys, w->hmin, free_counts());
     hipLaunchKernelGGL(k_first, dim3(blocks(n_seed, 256)), dim3(256), 0, s, g, w->C, w->ckey, w->hkeys, w->hmin,
                        w->cflag);
     w->scan.run(s, w->cflag, w->cpos, &w->C->nCand, n_seed, &w->C->kept);

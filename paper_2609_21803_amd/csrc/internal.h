@@ -9,7 +9,8 @@
 
 namespace comet {
 
-constexpr int MAXSEG = 6;
+constexpr int MAXSEG = 6;        // segments per order: pushing, timed pushing and flipping
+constexpr int MAXSEG_FREE = 8;   // pushing with free motion (its 16 ids pack into 4-bit key fields)
 constexpr int MAXN = 512;
 constexpr int MAX_TRIALS = 16;
 constexpr int WAVE = 64;

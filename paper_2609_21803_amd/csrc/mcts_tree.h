@@ -29,7 +29,7 @@ namespace comet {
 // ---------------------------------------------------------------------------------
 struct MctsNode {
   int len;
-  int pre[6];
+  int pre[KEY_MAXSEG];
   bool stop;
   std::vector<int> acts;   // untried actions (from `next`), -1 = stop
   size_t next = 0;
@@ -53,11 +53,11 @@ struct MctsTree {
   std::vector<MctsNode> nodes;
 
   bool admissible(const int* m, int n) const {
-    return admissible_key(task, key_make(n, m));
+    return admissible_key(task, key_make(n, m, key_bits(task)));
   }
   void ids_after(const int* m, int n, std::vector<int>& out) const {
     out.clear();
-    int q[6];
+    int q[KEY_MAXSEG];
     for (int i = 0; i < n; ++i) q[i] = m[i];
     for (int a = 0; a < M; ++a) {
       q[n] = a;
@@ -67,7 +67,7 @@ struct MctsTree {
   int make(const int* pre, int len, bool stop) {
     MctsNode nd;
     nd.len = len;
-    for (int i = 0; i < 6; ++i) nd.pre[i] = (i < len) ? pre[i] : 0;
+    for (int i = 0; i < KEY_MAXSEG; ++i) nd.pre[i] = (i < len) ? pre[i] : 0;
     nd.stop = stop;
     if (!stop) {
       if (len >= 1) nd.acts.push_back(-1);
@@ -98,7 +98,7 @@ struct MctsTree {
       if (nd.next < nd.acts.size()) {
         const int a = nd.acts[nd.next++];
         --untried;
-        int pre[6];
+        int pre[KEY_MAXSEG];
         for (int i = 0; i < nodes[v].len; ++i) pre[i] = nodes[v].pre[i];
         int len = nodes[v].len;
         bool stop = (a == -1);
@@ -181,9 +181,9 @@ struct MctsSearch {
     sel.clear();
     fresh.clear();
     for (long long q = 0; q < batch_B; ++q) {
-      int order[6], K = 0;
+      int order[KEY_MAXSEG], K = 0;
       T.select(path, order, K);
-      const unsigned long long k = key_make(K, order);
+      const unsigned long long k = key_make(K, order, key_bits(T.task));
       if (!cache.count(k) && std::find(fresh.begin(), fresh.end(), k) == fresh.end()) {
         if (nV + (long long)fresh.size() >= eval_budget) {
           for (int i : path) --T.nodes[i].N;   // not taken

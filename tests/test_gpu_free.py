@@ -128,23 +128,25 @@ def test_free_approach_then_straight_push_on_gpu():
         assert np.allclose(g["traj"][i, n1, 3:5], [-0.05, 0.0], atol=1e-4)
 
 
-def _ctx(max_batch=4096, max_intervals=40):
+def _ctx(max_batch=4096, max_intervals=40, max_segments=6):
     from paper_2609_21803_amd import native
-    return native.Context(max_batch=max_batch, max_segments=6, max_intervals=max_intervals, task=native.TASK_PUSH_FREE)
+    return native.Context(max_batch=max_batch, max_segments=max_segments, max_intervals=max_intervals,
+                          task=native.TASK_PUSH_FREE)
 
 
 @pytest.mark.parametrize("radius,kcap,n,W,room", [(1, 3, 40, 4096, 3000), (2, 3, 30, 8, 20000), (1, 6, 300, 64, 5000),
-                                                 (2, 4, 5, 3, 4000), (1, 2, 1, 1, 7)])
+                                                 (2, 4, 5, 3, 4000), (1, 2, 1, 1, 7), (2, 8, 60, 16, 30000),
+                                                 (1, 8, 500, 500, 60000)])
 def test_free_batch_construction_is_bit_exact(radius, kcap, n, W, room):
     import torch
     from oracle import free as F
     from paper_2609_21803_amd import native
     rng = np.random.default_rng(20 * radius + n)
-    pool = [int(k) for k in F.seed(min(kcap, 4))]
+    pool = [int(k) for k in F.seed(min(kcap, 4))] if kcap < 8 else [int(k) for k in F.seed(8)[::97]]
     keys = np.array([pool[i] for i in rng.choice(len(pool), n, replace=False)], np.uint64)
     merit = rng.choice([0.1, 0.5, 1.0, np.inf, np.nan], size=n) + np.where(rng.random(n) < 0.5, 0.0, rng.random(n))
     ref = F.expand_next(keys, merit, kcap, radius, W, room)
-    ctx = _ctx(max_batch=max(room, 8))
+    ctx = _ctx(max_batch=max(room, 8), max_segments=max(kcap, 6))
     prm = native.ExpandParams(kcap=kcap, radius=radius, frontier_W=W, batch_B=room, eval_budget=max(n, 1),
                               knots_per_segment=5, rounds=1, k_ref=1, seed_max_segments=1)
     got = native.expand_next(ctx, torch.as_tensor(keys.view(np.int64)).cuda(), torch.as_tensor(merit).cuda(), prm,
@@ -253,3 +255,63 @@ def test_free_maximum_length_orders_match_oracle():
     assert abs(g["cost"][0] - Jstar) <= 5e-3 * Jstar and abs(o["cost"][0] - Jstar) <= 5e-3 * Jstar
     assert np.all(g["feasible"][conv] == o["feasible"][conv]) and np.all(rel[conv] <= 1e-3)
     assert np.all(g["traj"][:, 511:] == 0) and np.all(g["traj"][:, 510, 5:] == 0)
+
+
+def test_free_seed_of_eight_segments_is_the_whole_language():
+    """Full enumeration at the segment cap of eight (Sec. IV-A): the seed pass of an
+    expansion with s = 8 and no further round evaluates exactly the oracle's admissible
+    orders of 1..8 segments (205,632), in key order; the order of every evaluated key's
+    batch row is the key's own (segment count, ids, two intervals per segment)."""
+    import torch
+    from oracle import free as F
+    from paper_2609_21803_amd import native
+    x0, goal, inst = I.push_free_pairs(5600, 1)
+    ref = F.seed(8)
+    assert len(ref) == 205632
+    prm = native.ExpandParams(kcap=8, seed_max_segments=8, radius=1, rounds=0, frontier_W=1, knots_per_segment=2,
+                              k_ref=1, batch_B=len(ref), eval_budget=len(ref))
+    ctx = _ctx(max_batch=len(ref), max_intervals=16, max_segments=8)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+    o, st = native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm)
+    torch.cuda.synchronize()
+    keys = native.expand_trace(ctx)[0].cpu().numpy().view(np.uint64)
+    print("evaluated", st["evaluated"], "feasible", st["n_feasible"], "plan", o["modes"].cpu().numpy()[:int(o["nseg"])],
+          flush=True)
+    assert st["evaluated"] == len(ref) and np.array_equal(keys, ref)
+    K = int(o["nseg"].item())
+    if K:
+        assert F.admissible(list(o["modes"].cpu().numpy()[:K])) and np.all(o["knots"].cpu().numpy()[:K] == 2)
+
+
+@pytest.mark.parametrize("policy", ["uniform", "mcts"])
+def test_free_sampling_and_mcts_stay_in_the_eight_segment_language(policy):
+    """The ablation policies over the free-motion evaluator at the segment cap of eight:
+    every evaluated order is admissible and distinct, at most the budget is spent, and the
+    returned plan is admissible, feasible and re-solved by the oracle to the same cost."""
+    import torch
+    import oracle
+    from oracle import free as F
+    from paper_2609_21803_amd import native
+    x0, goal, inst = I.push_free_pairs(5700, 1)
+    pol = native.POLICY_UNIFORM if policy == "uniform" else native.POLICY_MCTS
+    prm = native.ExpandParams(kcap=8, seed_max_segments=2, radius=1, rounds=3, frontier_W=64, knots_per_segment=6,
+                              k_ref=16, batch_B=1024, eval_budget=3072, policy=pol, sample_seed=17, sample_draws=8192)
+    ctx = _ctx(max_batch=1024, max_intervals=48, max_segments=8)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+    o, st = native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm)
+    torch.cuda.synchronize()
+    keys = [int(k) for k in native.expand_trace(ctx)[0].cpu().numpy().view(np.uint64)]
+    K = int(o["nseg"].item())
+    print(policy, "evaluated", len(keys), "feasible", st["n_feasible"], "lengths",
+          np.bincount([k >> 60 for k in keys], minlength=9)[1:], "plan", list(o["modes"].cpu().numpy()[:K]),
+          float(o["cost"].item()), flush=True)
+    assert 0 < len(keys) <= 3072 and len(set(keys)) == len(keys)
+    assert all(F.admissible(F.key_modes(k)) for k in keys)
+    assert K >= 1 and float(o["viol"][0]) <= 1e-5
+    modes = np.zeros((1, 8), np.int32)
+    knots = np.zeros((1, 8), np.int32)
+    modes[0, :K] = o["modes"].cpu().numpy()[:K]
+    knots[0, :K] = o["knots"].cpu().numpy()[:K]
+    assert F.admissible(list(modes[0, :K]))
+    r = F.evaluate(f32(x0), f32(goal), f32(inst), np.array([K]), modes, knots, params=oracle.Params(**oracle.REFINE))
+    assert r["feasible"][0] == 1 and abs(r["cost"][0] - float(o["cost"][0])) <= 1e-3 * abs(r["cost"][0])

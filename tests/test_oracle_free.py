@@ -268,17 +268,34 @@ def test_language_by_brute_force(orc):
     assert [list(o) for o in orders] == got          # same set, in key order
     for o in itertools.product(range(16), repeat=3):
         assert F.admissible(o) == _admissible(o)
-    counts = [len(F.seed(K)) for K in range(1, 7)]          # orders of 1..K segments
-    # the same counts by the transfer matrix of the rules, and on to eight segments
+    counts = [len(F.seed(K)) for K in range(1, 9)]          # orders of 1..K segments
+    # the same counts by the transfer matrix of the rules
     A = np.array([[1 if _step_ok(a, b) else 0 for b in range(16)] for a in range(16)], dtype=object)
     v, tot = np.ones(16, dtype=object), []
     for _ in range(8):
         tot.append(int(v.sum()))
         v = v.dot(A)
     cum = np.cumsum(tot)
-    assert list(cum[:6]) == counts
+    assert list(cum) == counts
+    # the seed of eight segments: strictly increasing keys, each admissible by the rules
+    # above, as many as the transfer matrix counts -- so it is the whole language, in key order
+    s8 = [int(k) for k in F.seed(8)]
+    assert all(a < b for a, b in zip(s8, s8[1:]))
+    assert all(_admissible(tuple(F.key_modes(k))) for k in s8[::7] + s8[-200:])
     print(f"free-motion language: {cum[5]} orders of <= 6 segments, {cum[7]} of <= 8 "
           f"(the paper's box benchmark: 601 / 6,297 -- parity unpinned: its transition rules are not stated)")
+
+
+def test_keys_order_by_length_then_ids():
+    """Keys of up to eight segments (4 bits per id) round-trip, and comparing keys compares
+    the segment count first, then the ids lexicographically."""
+    rng = np.random.default_rng(11)
+    orders = [tuple(int(x) for x in rng.integers(0, 16, rng.integers(1, 9))) for _ in range(3000)]
+    orders += [(15,) * 8, (0,), (15,), (0, 0), (15,) * 7]
+    for o in orders:
+        assert tuple(F.key_modes(F.key_make(o))) == o
+    by_key = sorted(orders, key=F.key_make)
+    assert by_key == sorted(orders, key=lambda o: (len(o), o))
 
 
 def _neigh1(order, kcap):
@@ -320,11 +337,12 @@ def _neigh(order, kcap, r):
     return out
 
 
-@pytest.mark.parametrize("order,r", [((15,), 1), ((15, 9), 2), ((12, 0, 1, 12), 2), ((15, 9, 15, 12), 1),
-                                     ((13, 12, 15, 9, 10), 2)])
-def test_neighbourhoods_by_brute_force(orc, order, r):
-    want = [F.key_make(o) for o in _neigh(order, 6, r)]
-    got = [int(k) for k in F.neighbours(F.key_make(order), 6, r)]
+@pytest.mark.parametrize("order,r,kcap", [((15,), 1, 6), ((15, 9), 2, 6), ((12, 0, 1, 12), 2, 6), ((15, 9, 15, 12), 1, 6),
+                                          ((13, 12, 15, 9, 10), 2, 6), ((14, 6, 14, 15, 9, 15, 12), 2, 8),
+                                          ((14, 6, 7, 14, 13, 4, 3, 13), 2, 8), ((12, 13), 2, 8)])
+def test_neighbourhoods_by_brute_force(orc, order, r, kcap):
+    want = [F.key_make(o) for o in _neigh(order, kcap, r)]
+    got = [int(k) for k in F.neighbours(F.key_make(order), kcap, r)]
     assert got == want
 
 
@@ -338,11 +356,11 @@ def test_expand_next_matches_a_set_based_twin(orc, W, room, r):
     merit = rng.uniform(0, 1, 40)
     merit[rng.choice(40, 5, replace=False)] = np.nan
     merit[3] = merit[4]                                   # a tie, decided by the key
-    got = [int(k) for k in F.expand_next(np.array(keys, np.uint64), merit, 6, r, W, room)]
+    got = [int(k) for k in F.expand_next(np.array(keys, np.uint64), merit, 8, r, W, room)]
     rank = sorted(range(40), key=lambda i: (np.inf if np.isnan(merit[i]) else merit[i], keys[i]))
     seen, want = set(keys), []
     for i in rank[:W]:
-        for o in _neigh(tuple(F.key_modes(keys[i])), 6, r):
+        for o in _neigh(tuple(F.key_modes(keys[i])), 8, r):
             k = F.key_make(o)
             if len(want) < room and k not in seen:
                 seen.add(k)
