@@ -270,23 +270,30 @@ def hetero_leg(native, I, torch, B=131072):
 
 
 def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cpu=True):
-    """Pushing with free motion (the Sec. III-A language, 16 mode ids, at most six segments:
-    14,760 admissible orders), in the paper's planner configurations on the device: full
-    enumeration (every admissible order, which with a cap of six segments is also the seed
-    of the paper's "seed only") and expansion with s_max = 2 (seed of the 72 orders of at most
-    two segments, two rounds of one-edit neighbourhoods, W = 256); 10 intervals per segment,
-    refinement of the 16 best.  Then the evaluator alone on every admissible order for each
-    of 8 instances (118,080 TOs), one launch timed after a warm-up, with its roofline, and
-    the oracle's rate on a strided sample."""
-    ctx = native.Context(max_batch=16384, max_segments=6, max_intervals=60, task=native.TASK_PUSH_FREE)
-    configs = {"full_enumeration": native.ExpandParams(kcap=6, seed_max_segments=6, radius=1, rounds=0, frontier_W=1,
-                                                         knots_per_segment=10, k_ref=16, batch_B=16384,
-                                                         eval_budget=16384),
-               "expansion_smax2": native.ExpandParams(kcap=6, seed_max_segments=2, radius=1, rounds=2, frontier_W=256,
-                                                        knots_per_segment=10, k_ref=16, batch_B=16384,
-                                                        eval_budget=16384)}
+    """Pushing with free motion: the Sec. III-A language at the paper's segment cap of eight
+    (205,632 admissible orders, 14,760 of them of at most six segments), 10 intervals per
+    segment, in the planner configurations of Sec. IV-A on the device: full enumeration
+    (every admissible order in one batch), seed only (every order of at most six segments),
+    and expansion with s_max = 1 and 3 rounds after that seed (r = 2, batches of up to
+    16,384, at most 1,024 best-ranked orders expanded per round); refinement of the 256 best
+    feasible orders.  Per goal: orders evaluated, device time of the whole search, time to
+    the first feasible order, the plan, and whether it recovers the full enumeration's plan
+    cost (within 1e-4).  Then the evaluator alone on every order of at most six segments for
+    each of 8 instances (118,080 TOs), one launch timed after a warm-up, with its roofline,
+    and the oracle's rate on a strided sample."""
+    full = 205632
+    ctx = native.Context(max_batch=full, max_segments=8, max_intervals=80, task=native.TASK_PUSH_FREE)
+    common = dict(kcap=8, radius=2, knots_per_segment=10, k_ref=256)
+    configs = {"full_enumeration": native.ExpandParams(**common, seed_max_segments=8, rounds=0, frontier_W=1,
+                                                         batch_B=full, eval_budget=full),
+               "seed_only": native.ExpandParams(**common, seed_max_segments=6, rounds=0, frontier_W=1, batch_B=16384,
+                                                eval_budget=16384),
+               "expansion_smax1": native.ExpandParams(**common, seed_max_segments=6, rounds=1, frontier_W=1024,
+                                                      batch_B=16384, eval_budget=full),
+               "expansion_smax3": native.ExpandParams(**common, seed_max_segments=6, rounds=3, frontier_W=1024,
+                                                      batch_B=16384, eval_budget=full)}
     t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
-    rows, all_keys = {k: [] for k in configs}, None
+    rows, seed6 = {k: [] for k in configs}, None
     for name, prm in configs.items():
         for sd in seeds:
             x0, goal, inst = I.push_free_pairs(sd, 1)
@@ -295,20 +302,30 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
             o, st = native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm)
             torch.cuda.synchronize()
             K = int(o["nseg"].item())
-            if all_keys is None and name == "full_enumeration":
-                all_keys = native.expand_trace(ctx)[0].cpu().numpy().view(np.uint64)
+            if seed6 is None and name == "seed_only":
+                seed6 = native.expand_trace(ctx)[0].cpu().numpy().view(np.uint64)
             rows[name].append({"seed": sd, "evaluated": st["evaluated"], "rounds": st["rounds_done"],
                                "feasible": st["n_feasible"], "device_ms": st["t_total_ms"],
                                "t_first_feasible_ms": st["t_first_feasible_ms"],
                                "plan": o["modes"].cpu().numpy()[:K].tolist(),
                                "plan_cost": float(o["cost"].item()) if K else None})
-    # the evaluator alone: every admissible order (the full enumeration's evaluated set) on
-    # each of n_eval_inst instances
+    ref = {r["seed"]: r["plan_cost"] for r in rows["full_enumeration"]}
+    summary = {}
+    for name, rs in rows.items():
+        for r in rs:
+            J, Jf = r["plan_cost"], ref[r["seed"]]
+            r["recovers_full_enumeration"] = bool(J is not None and Jf is not None and abs(J - Jf) <= 1e-4 * abs(Jf))
+        summary[name] = {"recovered": f"{sum(r['recovers_full_enumeration'] for r in rs)}/{len(rs)}",
+                         "median_evaluated": float(np.median([r["evaluated"] for r in rs])),
+                         "median_device_ms": float(np.median([r["device_ms"] for r in rs]))}
+    all_keys = seed6
+    # the evaluator alone: every admissible order of at most six segments (the seed-only
+    # configuration's evaluated set) on each of n_eval_inst instances
     n1 = len(all_keys)
     nseg1 = (all_keys >> np.uint64(60)).astype(np.int32)
     modes1 = np.zeros((n1, 6), np.int32)
-    for i in range(6):
-        modes1[:, i] = ((all_keys >> np.uint64(50 - 10 * i)) & np.uint64(1023)).astype(np.int32)
+    for i in range(6):   # free-motion keys: 4 bits per id below the segment count
+        modes1[:, i] = ((all_keys >> np.uint64(56 - 4 * i)) & np.uint64(15)).astype(np.int32)
     modes1[np.arange(6)[None, :] >= nseg1[:, None]] = 0
     x0, goal, inst = I.push_free_pairs(5400, n_eval_inst)
     pair = np.repeat(np.arange(n_eval_inst), n1)
@@ -330,10 +347,11 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
     N = I.n_intervals(batch).astype(np.float64)
     flops = float((st[:, 1] * N).sum()) * FREE_FLOP_PER_INTERVAL_GN + float((st[:, 0] * N).sum()) * FLOP_PER_INTERVAL_AL
     ach = flops / (kms * 1e-3) / 1e12
-    res = {"workload": "pushing with free motion (16 mode ids, the Sec. III-A language, <= 6 segments: "
-                       f"{n1} admissible orders), 10 intervals per segment; planner configurations on the goals of "
-                       f"seeds 5300..; evaluator on all {n1} orders x {n_eval_inst} instances (seed 5400)",
-           "planner": rows,
+    res = {"workload": "pushing with free motion (16 mode ids, the Sec. III-A language capped at 8 segments: "
+                       f"{full} admissible orders, {n1} of <= 6), 10 intervals per segment; planner configurations "
+                       f"on the goals of seeds {seeds[0]}..{seeds[-1]}; evaluator on all {n1} orders of <= 6 segments x "
+                       f"{n_eval_inst} instances (seed 5400)",
+           "planner_summary": summary, "planner": rows,
            "evaluate": {"orders": n, "value": n / (ms * 1e-3), "unit": "solves/s", "ms": ms,
                         "mean_intervals": float(N.mean()), "mean_gn_iterations": float(st[:, 1].mean()),
                         "feasible_fraction": float(out["feasible"].float().mean().item()),
