@@ -72,6 +72,7 @@ KERNEL_SOURCES = ["paper_2609_21803_amd/csrc/evaluator.hip", "paper_2609_21803_a
                   "paper_2609_21803_amd/csrc/push_model.h", "paper_2609_21803_amd/csrc/dmath.h"]
 PROFILE = os.path.join(ROOT, "profiles", "k_push_solve_push_plain_110592.txt")
 PROFILE_TIMED = os.path.join(ROOT, "profiles", "k_push_solve_timed_push_plain_110592.txt")
+PROFILE_FREE = os.path.join(ROOT, "profiles", "k_push_solve_free_118080.txt")
 FLIP_SOURCES = ["paper_2609_21803_amd/csrc/flip.hip", "paper_2609_21803_amd/csrc/dmath.h"]
 PROFILE_FLIP = os.path.join(ROOT, "profiles", "k_flip_solve_flip_32768.txt")
 
@@ -269,7 +270,7 @@ def hetero_leg(native, I, torch, B=131072):
                                    "solves_per_s": B / (np.mean(best) * 1e-3)}}
 
 
-def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cpu=True):
+def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cpu=True, planner=True):
     """Pushing with free motion: the Sec. III-A language at the paper's segment cap of eight
     (205,632 admissible orders, 14,760 of them of at most six segments), 10 intervals per
     segment, in the planner configurations of Sec. IV-A on the device: full enumeration
@@ -280,7 +281,9 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
     the first feasible order, the plan, and whether it recovers the full enumeration's plan
     cost (within 1e-4).  Then the evaluator alone on every order of at most six segments for
     each of 8 instances (118,080 TOs), one launch timed after a warm-up, with its roofline,
-    and the oracle's rate on a strided sample."""
+    and the oracle's rate on a strided sample.  planner=False runs only the seed pass that
+    lists the orders of at most six segments (two intervals per segment) before the
+    evaluator launch."""
     full = 205632
     ctx = native.Context(max_batch=full, max_segments=8, max_intervals=80, task=native.TASK_PUSH_FREE)
     common = dict(kcap=8, radius=2, knots_per_segment=10, k_ref=256)
@@ -294,6 +297,14 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
                                                       batch_B=16384, eval_budget=full)}
     t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
     rows, seed6 = {k: [] for k in configs}, None
+    if not planner:
+        x0, goal, inst = I.push_free_pairs(seeds[0], 1)
+        native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]),
+                      native.ExpandParams(kcap=8, radius=1, knots_per_segment=2, k_ref=1, seed_max_segments=6, rounds=0,
+                                          frontier_W=1, batch_B=16384, eval_budget=16384))
+        torch.cuda.synchronize()
+        seed6 = native.expand_trace(ctx)[0].cpu().numpy().view(np.uint64)
+        configs, rows = {}, {}
     for name, prm in configs.items():
         for sd in seeds:
             x0, goal, inst = I.push_free_pairs(sd, 1)
@@ -309,7 +320,7 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
                                "t_first_feasible_ms": st["t_first_feasible_ms"],
                                "plan": o["modes"].cpu().numpy()[:K].tolist(),
                                "plan_cost": float(o["cost"].item()) if K else None})
-    ref = {r["seed"]: r["plan_cost"] for r in rows["full_enumeration"]}
+    ref = {r["seed"]: r["plan_cost"] for r in rows.get("full_enumeration", [])}
     summary = {}
     for name, rs in rows.items():
         for r in rs:
@@ -357,7 +368,8 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
                         "feasible_fraction": float(out["feasible"].float().mean().item()),
                         "roofline": {"bound": "alu", "kernel": "k_push_solve (free motion)", "achieved": ach,
                                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
-                                     "kernel_ms": kms, "flop_per_launch": flops, "traffic": None}}}
+                                     "kernel_ms": kms, "flop_per_launch": flops,
+                                     "traffic": profiled_traffic(PROFILE_FREE)}}}
     if cpu:
         res["evaluate"]["cpu_baseline"] = free_cpu_baseline(batch)
     return res
@@ -630,6 +642,8 @@ def main():
     ap.add_argument("--no-timed", action="store_true", help="skip the optimised-timing pushing leg")
     ap.add_argument("--no-scale", action="store_true", help="skip the expansion legs at the configured scale")
     ap.add_argument("--no-free", action="store_true", help="skip the free-motion pushing leg")
+    ap.add_argument("--no-free-planner", action="store_true",
+                    help="free-motion leg: the evaluator launch only, not the four planner configurations")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -729,7 +743,8 @@ def main():
             ("policies", not args.no_policies, lambda: policy_leg(native, I, torch)),
             ("expand_scale", not args.no_scale, lambda: expand_scale_leg(native, I, torch)),
             ("flip_expand_scale", not args.no_scale, lambda: flip_expand_scale_leg(native, I, torch)),
-            ("free", not args.no_free, lambda: free_leg(native, I, torch, cpu=not args.no_cpu)),
+            ("free", not args.no_free, lambda: free_leg(native, I, torch, cpu=not args.no_cpu,
+                                                        planner=not args.no_free_planner)),
             ("learned", not args.no_learned, lambda: learned_leg(native, I, torch)),
             ("learned_flip", not args.no_learned, lambda: learned_flip_leg(native, I, torch)),
             ("cpu_baseline", not args.no_cpu, lambda: cpu_baseline(batch))]
