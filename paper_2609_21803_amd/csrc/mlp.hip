@@ -723,17 +723,27 @@ struct comet_mlp {
   std::vector<bf16*> H;                // activations (H[0] = X0) [B][dim]
   float *Y = nullptr, *dY = nullptr;   // output and its gradient [B][out]
   bf16 *dYb = nullptr;
-  float *dzcol = nullptr;              // per-wave column sums of a hidden gradient [2 ceil(B/128)][hidden]
-  bf16 *dZb[2] = {nullptr, nullptr};   // BF16 gradient ping-pong [B][max(hidden, out)]
+  // backward buffers, one per layer so that the two streams of the backward pass never
+  // wait for a buffer to be free: dzc[l] per-wave column sums of the hidden gradient that
+  // layer l's input product leaves [2 ceil(B/128)][hidden]; dZl[l] BF16 gradient of hidden
+  // layer l [B][hidden]
+  std::vector<float*> dzc;
+  std::vector<bf16*> dZl;
   float *cnt = nullptr, *lossd = nullptr;
   float* part = nullptr;               // partial sums: split weight gradients / bias column sums
   float* red = nullptr;                // per-block partials of the loss reductions [LOSS_BLOCKS][4]
   // batch-contiguous BF16 copies for the weight-gradient products (training, B % 8 == 0):
   // HT[l] = H[l]^T [K_l][ldt], GT = the current layer's output gradient transposed [N][ldt]
   std::vector<bf16*> HT;
-  bf16* GT = nullptr;
+  std::vector<bf16*> GTl;              // GTl[l] = layer l's output gradient transposed [N_l][ldt]
   long ldt = 0;
   long long step = 0;
+  // the backward pass runs the chain of input-gradient products on the caller's stream and
+  // each layer's weight gradient and bias sums beside it on this stream: evB[l] = layer l's
+  // input gradient done, done = all weight gradients done
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, done = nullptr;
+  std::vector<hipEvent_t> evB;
 };
 
 namespace {
@@ -886,13 +896,21 @@ comet_status comet_mlp_create(int32_t in_dim, int32_t hidden, int32_t layers, in
   A((void**)&m->Y, 4 * B * out_dim);
   A((void**)&m->dY, 4 * B * out_dim);
   A((void**)&m->dYb, 2 * B * out_dim);
-  A((void**)&m->dzcol, 4 * 2 * ((B + GBM - 1) / GBM) * hidden);
-  A((void**)&m->dZb[0], 2 * B * std::max(hidden, out_dim));
-  A((void**)&m->dZb[1], 2 * B * std::max(hidden, out_dim));
+  m->dzc.assign(m->nl, nullptr);
+  m->dZl.assign(m->nl, nullptr);
+  for (int l = 1; l < m->nl; ++l) A((void**)&m->dzc[l], 4 * 2 * ((B + GBM - 1) / GBM) * hidden);
+  for (int l = 0; l < m->nl - 1; ++l) A((void**)&m->dZl[l], 2 * B * hidden);
   m->ldt = (long)((B + 7) / 8 * 8);
   m->HT.assign(m->nl, nullptr);
   for (int l = 0; l < m->nl; ++l) A((void**)&m->HT[l], 2 * (size_t)m->K[l] * m->ldt);
-  A((void**)&m->GT, 2 * (size_t)std::max(hidden, out_dim) * m->ldt);
+  m->GTl.assign(m->nl, nullptr);
+  for (int l = 0; l < m->nl; ++l) A((void**)&m->GTl[l], 2 * (size_t)m->N[l] * m->ldt);
+  ok = ok && hipStreamCreateWithFlags(&m->aux, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&m->fork, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&m->done, hipEventDisableTiming) == hipSuccess;
+  m->evB.assign(m->nl, nullptr);
+  for (int l = 0; l < m->nl; ++l)
+    ok = ok && hipEventCreateWithFlags(&m->evB[l], hipEventDisableTiming) == hipSuccess;
   A((void**)&m->cnt, 4 * 4);
   A((void**)&m->lossd, 4 * 4);
   {
@@ -929,14 +947,21 @@ comet_status comet_mlp_create(int32_t in_dim, int32_t hidden, int32_t layers, in
 
 void comet_mlp_destroy(comet_mlp* m) {
   if (!m) return;
-  std::vector<void*> ps = {m->P, m->G, m->Mm, m->Vv, m->Wb, m->WT, m->Y, m->dY, m->dYb, m->dzcol, m->dZb[0], m->dZb[1],
-                           m->cnt, m->lossd, m->part, m->red};
+  std::vector<void*> ps = {m->P, m->G, m->Mm, m->Vv, m->Wb, m->WT, m->Y, m->dY, m->dYb, m->cnt, m->lossd, m->part,
+                           m->red};
   for (auto* h : m->H) ps.push_back(h);
   for (auto* z : m->Z) ps.push_back(z);
   for (auto* h : m->HT) ps.push_back(h);
-  ps.push_back(m->GT);
+  for (auto* h : m->GTl) ps.push_back(h);
+  for (auto* h : m->dZl) ps.push_back(h);
+  for (auto* h : m->dzc) ps.push_back(h);
   for (void* p : ps)
     if (p) (void)hipFree(p);
+  for (auto* e : m->evB)
+    if (e) (void)hipEventDestroy(e);
+  if (m->fork) (void)hipEventDestroy(m->fork);
+  if (m->done) (void)hipEventDestroy(m->done);
+  if (m->aux) (void)hipStreamDestroy(m->aux);
   delete m;
 }
 
@@ -1004,15 +1029,36 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
   hipLaunchKernelGGL(k_loss_grad, dim3(LOSS_BLOCKS), dim3(256), 0, s, Bi, O, Wn, m->Y, y_feas, y_cost, y_traj,
                      traj_mask, m->cnt, m->dY, m->dYb, m->red);
   hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, m->red, LOSS_BLOCKS, 3, m->lossd);
+  const int L = m->nl;
   if (tr)
     hipLaunchKernelGGL(k_transpose_bf16, dim3(nblk(O, 64), nblk(Bi, 64)), dim3(256), 0, s, m->dYb, (long)O, Bi, O,
-                       m->GT, m->ldt);
-  // backward through the linear layers
-  const bf16* g = m->dYb;
-  const float* g32 = m->dY;
-  int cur = 0;
-  for (int l = m->nl - 1; l >= 0; --l) {
+                       m->GTl[L - 1], m->ldt);
+  // backward through the linear layers: the chain of input-gradient products runs on the
+  // caller's stream; each layer's weight gradient and bias sums run beside it on m->aux,
+  // after the input product that produced the gradient they read (event evB[l+1]).
+  // Every gradient buffer belongs to one layer, so neither stream waits for a buffer.
+  if (hipEventRecord(m->fork, s) != hipSuccess || hipStreamWaitEvent(m->aux, m->fork, 0) != hipSuccess)
+    return COMET_EHIP;
+  for (int l = L - 1; l >= 1; --l) {
+    // dZ_{l-1} [B][K] = (G [B][N] . W_l [N][K]) * gelu'(Z_{l-1}), W_l read through its
+    // transpose so both operands are contraction-contiguous
     const int K = m->K[l], N = m->N[l];
+    const bf16* g = (l == L - 1) ? m->dYb : m->dZl[l];
+    Epi ex{};
+    ex.colpart = m->dzc[l];
+    ex.h = m->dZl[l - 1];
+    ex.zprev = m->Z[l - 1];
+    ex.ldc = K;
+    if (tr) {   // layer l-1's weight gradient reads it transposed
+      ex.ht = m->GTl[l - 1];
+      ex.ldt = m->ldt;
+    }
+    gemm<true, true, EPI_DX>(s, Bi, K, N, g, N, m->WT + m->wboff[l], N, ex);
+    if (hipEventRecord(m->evB[l], s) != hipSuccess) return COMET_EHIP;
+  }
+  for (int l = L - 1; l >= 0; --l) {
+    const int K = m->K[l], N = m->N[l];
+    if (l < L - 1 && hipStreamWaitEvent(m->aux, m->evB[l + 1], 0) != hipSuccess) return COMET_EHIP;
     // dW_l [N][K] = G^T [N][B] . H_l [B][K]: contraction over the batch, split into
     // partial-sum slabs that k_sum_slabs adds
     const int split = wgrad_splits(N, K, Bi);
@@ -1020,36 +1066,24 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
     ew.z = m->part;
     ew.ldc = K;
     ew.slab = (long)N * K;
-    const int nzs = tr ? gemm<true, true, EPI_PARTIAL>(s, N, K, Bi, m->GT, m->ldt, m->HT[l], m->ldt, ew, nullptr, split)
-                       : gemm<false, false, EPI_PARTIAL>(s, N, K, Bi, g, N, m->H[l], K, ew, nullptr, split);
-    hipLaunchKernelGGL(k_sum_slabs, dim3(nblk((long long)N * K, 256)), dim3(256), 0, s, m->part, nzs, (long)N * K,
-                       m->G + m->woff[l]);
-    if (g32) {   // output layer: column sums of the FP32 loss gradient
+    const bf16* g = (l == L - 1) ? m->dYb : m->dZl[l];
+    const int nzs = tr ? gemm<true, true, EPI_PARTIAL>(m->aux, N, K, Bi, m->GTl[l], m->ldt, m->HT[l], m->ldt, ew,
+                                                       nullptr, split)
+                       : gemm<false, false, EPI_PARTIAL>(m->aux, N, K, Bi, g, N, m->H[l], K, ew, nullptr, split);
+    hipLaunchKernelGGL(k_sum_slabs, dim3(nblk((long long)N * K, 256)), dim3(256), 0, m->aux, m->part, nzs,
+                       (long)N * K, m->G + m->woff[l]);
+    if (l == L - 1) {   // output layer: column sums of the FP32 loss gradient
       const int ry = std::max(1, std::min(COLSUM_ROWS, (Bi + 31) / 32));
-      hipLaunchKernelGGL(k_colsum_part, dim3(nblk(N, 256), ry), dim3(256), 0, s, g32, Bi, N, m->part);
-      hipLaunchKernelGGL(k_sum_rows, dim3(nblk(N, 64)), dim3(256), 0, s, m->part, ry, (long)N, m->G + m->boff[l]);
-    } else {     // hidden layers: the per-wave column sums left by the input-gradient epilogue
-      hipLaunchKernelGGL(k_sum_rows, dim3(nblk(N, 64)), dim3(256), 0, s, m->dzcol, 2 * (int)nblk(Bi, GBM), (long)N,
+      hipLaunchKernelGGL(k_colsum_part, dim3(nblk(N, 256), ry), dim3(256), 0, m->aux, m->dY, Bi, N, m->part);
+      hipLaunchKernelGGL(k_sum_rows, dim3(nblk(N, 64)), dim3(256), 0, m->aux, m->part, ry, (long)N,
                          m->G + m->boff[l]);
-    }
-    if (l > 0) {
-      // dZ_{l-1} [B][K] = (G [B][N] . W_l [N][K]) * gelu'(Z_{l-1}), W_l read through its
-      // transpose so both operands are contraction-contiguous
-      Epi ex{};
-      ex.colpart = m->dzcol;
-      ex.h = m->dZb[cur];
-      ex.zprev = m->Z[l - 1];
-      ex.ldc = K;
-      if (tr) {   // the next layer's weight gradient reads it transposed (its own product above is done)
-        ex.ht = m->GT;
-        ex.ldt = m->ldt;
-      }
-      gemm<true, true, EPI_DX>(s, Bi, K, N, g, N, m->WT + m->wboff[l], N, ex);
-      g = m->dZb[cur];
-      g32 = nullptr;
-      cur ^= 1;
+    } else {            // hidden layers: the per-wave column sums left by layer l+1's input product
+      hipLaunchKernelGGL(k_sum_rows, dim3(nblk(N, 64)), dim3(256), 0, m->aux, m->dzc[l + 1], 2 * (int)nblk(Bi, GBM),
+                         (long)N, m->G + m->boff[l]);
     }
   }
+  if (hipEventRecord(m->done, m->aux) != hipSuccess || hipStreamWaitEvent(s, m->done, 0) != hipSuccess)
+    return COMET_EHIP;
   // AdamW on the FP32 masters, then refresh the BF16 copies
   m->step += 1;
   const float b1 = 0.9f, b2 = 0.999f;
