@@ -286,8 +286,11 @@ comet_status comet_last_kernel_ms(comet_ctx* ctx, float* ms);
  *                      task's language, already evaluated, or equal to an earlier draw of the
  *                      round is dropped; the batch is the first min(room, kept) remaining draws
  *                      in draw order.  So each segment count is equally likely and, given the
- *                      count, every admissible order is.  Refinement and the returned plan are
- *                      as for the expansion.
+ *                      count, every admissible order is.  With free motion (whose admissible
+ *                      eight-segment orders are 1 in 28,500 of the product space) draw c takes
+ *                      t = out(8c+1) mod (number of admissible orders of K segments) and the
+ *                      t-th of them in key order instead, without rejection.  Refinement and
+ *                      the returned plan are as for the expansion.
  *   sample_draws       draws per round (policy 1; 1 .. 2^27)
  *   policy COMET_POLICY_MCTS (2): the UCT allocation of the baselines (Sec. IV-A, IV-B) on the
  *                      same evaluator and refinement, batch_B selections per update (the

@@ -9,8 +9,12 @@ generator of Java's SplittableRandom), draw c taking outputs 8c .. 8c+6: the seg
 K = 1 + out(8c) mod kcap, then id j = out(8c+1+j) mod M.  Draws outside the task's
 language, already evaluated, or repeating an earlier draw of the round are dropped, and
 the round's batch is the first `room` remaining draws in draw order.  Each segment count is
-equally likely and, given the count, every admissible order (rejection sampling).  The
-search then evaluates batch after batch up to the budget and refines like the expansion.
+equally likely and, given the count, every admissible order (rejection sampling).  For
+pushing with free motion, whose admissible orders of eight segments are 1 in 28,500 of the
+product space, draw c instead takes t = out(8c+1) mod (number of admissible orders of K
+segments) and the t-th of them in key order: uniform over that count without rejection.
+The search then evaluates batch after batch up to the budget and refines like the
+expansion.
 """
 from __future__ import annotations
 
@@ -57,9 +61,59 @@ def draws(seed: int, first: int, n: int, kcap: int, n_modes: int):
     return [list(ids[i, :K[i]]) for i in range(n)]
 
 
+def free_counts():
+    """c[r][a] = number of id sequences of length r allowed after id a (c[0][a] = 1), from
+    the free-motion oracle's admissibility of two-segment orders."""
+    from . import free as F
+    step = [[F.admissible([a, b]) for b in range(16)] for a in range(16)]
+    c = [[1] * 16]
+    for r in range(1, 8):
+        c.append([sum(c[r - 1][b] for b in range(16) if step[a][b]) for a in range(16)])
+    return c, step
+
+
+def free_unrank(K: int, t: int, counts=None):
+    """The t-th (from 0) admissible free-motion order of K segments in key order."""
+    c, step = counts or free_counts()
+    out, prev = [], None
+    for d in range(K):
+        rest = K - 1 - d
+        for b in range(16):
+            if prev is not None and not step[prev][b]:
+                continue
+            if t < c[rest][b]:
+                out.append(b)
+                break
+            t -= c[rest][b]
+        prev = out[-1]
+    return out
+
+
+def free_draws(seed: int, first: int, n: int, kcap: int):
+    """The orders of draws first .. first+n-1 of the free-motion task (unranked)."""
+    counts = free_counts()
+    c = np.arange(first, first + n, dtype=np.uint64)
+    K = 1 + (splitmix64_array(seed, c * np.uint64(8)) % np.uint64(kcap)).astype(np.int64)
+    u = splitmix64_array(seed, c * np.uint64(8) + np.uint64(1))
+    tot = [0] + [sum(counts[0][k - 1][a] for a in range(16)) for k in range(1, 9)]   # orders of exactly K segments
+    return [free_unrank(int(K[i]), int(u[i] % np.uint64(tot[int(K[i])])), counts) for i in range(n)]
+
+
 def sample_round(task: int, seed: int, first: int, n_draws: int, kcap: int, seen: set, room: int):
     """One round's batch: the first `room` draws that are in the language, unseen and not
     repeated earlier in the round, in draw order (keys)."""
+    if task == 3:
+        from . import free as F
+        out, round_seen = [], set()
+        for m in free_draws(seed, first, n_draws, kcap):
+            if len(out) >= room:
+                break
+            k = F.key_make(m)
+            if k in seen or k in round_seen:
+                continue
+            round_seen.add(k)
+            out.append(k)
+        return out
     if task == 1:
         from . import flip as F
         admissible, n_modes = F.admissible, 845
@@ -80,10 +134,13 @@ def sample_round(task: int, seed: int, first: int, n_draws: int, kcap: int, seen
 def _evaluate(task, keys, x0, goal, inst, knots_per_segment, params):
     B = len(keys)
     nseg = np.array([k >> 60 for k in keys], np.int32)
-    modes = np.zeros((B, 6), np.int32)
-    knots = np.zeros((B, 6), np.int32)
+    S = 8 if task == 3 else 6
+    modes = np.zeros((B, S), np.int32)
+    knots = np.zeros((B, S), np.int32)
+    if task == 3:
+        from . import free as F
     for b, k in enumerate(keys):
-        m = key_modes(k)
+        m = F.key_modes(k) if task == 3 else key_modes(k)
         modes[b, :len(m)] = m
         knots[b, :len(m)] = knots_per_segment
     X0 = np.tile(np.asarray(x0, np.float64), (B, 1))
@@ -92,6 +149,8 @@ def _evaluate(task, keys, x0, goal, inst, knots_per_segment, params):
     nmax = int(max(1, knots.sum(1).max(initial=1)))
     if task == 1:
         from . import flip as F
+        r = F.evaluate(X0, G, Iv, nseg, modes, knots, params=params, nmax=nmax)
+    elif task == 3:
         r = F.evaluate(X0, G, Iv, nseg, modes, knots, params=params, nmax=nmax)
     else:
         import oracle

@@ -469,17 +469,25 @@ __device__ inline unsigned long long splitmix64_out(unsigned long long seed, uns
 }
 
 // uniform sampling: draw C->draw_base + t for slot t < nCand; outside the language or
-// already evaluated -> EMPTY; first occurrences are marked as for generated candidates
+// already evaluated -> EMPTY; first occurrences are marked as for generated candidates.
+// Free motion draws the index of an admissible order of K segments and unranks it (fc):
+// its eight-segment orders are too rare in the product space to find by rejection.
 __global__ void k_sample(ExpCfg g, const ExpCounters* C, const unsigned long long* vset, unsigned long long* ckey,
-                         unsigned long long* hkeys, unsigned* hmin) {
+                         unsigned long long* hkeys, unsigned* hmin, FreeCounts fc) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= C->nCand) return;
   const unsigned long long c = C->draw_base + (unsigned long long)t;
   const int K = 1 + (int)(splitmix64_out(g.sseed, 8ull * c) % (unsigned long long)g.kcap);
-  int m[KEY_MAXSEG] = {};
-  for (int j = 0; j < K; ++j) m[j] = (int)(splitmix64_out(g.sseed, 8ull * c + 1ull + j) % (unsigned long long)g.M);
-  unsigned long long k = key_make(K, m, key_bits(g.task));
-  if (!admissible_key(g.task, k)) k = EMPTY;
+  unsigned long long k;
+  if (g.task == COMET_TASK_PUSH_FREE) {
+    const unsigned long long n = (unsigned long long)free_count_len(fc, K);
+    k = free_unrank(fc, K, (long long)(splitmix64_out(g.sseed, 8ull * c + 1ull) % n));
+  } else {
+    int m[KEY_MAXSEG] = {};
+    for (int j = 0; j < K; ++j) m[j] = (int)(splitmix64_out(g.sseed, 8ull * c + 1ull + j) % (unsigned long long)g.M);
+    k = key_make(K, m, key_bits(g.task));
+    if (!admissible_key(g.task, k)) k = EMPTY;
+  }
   if (k != EMPTY && set_has(vset, g.vmask, k)) k = EMPTY;
   ckey[t] = k;
   if (k != EMPTY) first_insert(hkeys, hmin, g.cmask, k, (unsigned)t);
@@ -914,7 +922,7 @@ void enqueue_sample_batch(comet_ctx* c, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3(blocks(g.cmask + 1, 256 * 8)), dim3(256), 0, s, w->hmin, 0xFFFFFFFFu,
                      (long long)(g.cmask + 1));
   hipLaunchKernelGGL(k_sample, dim3(blocks(ncand, 256)), dim3(256), 0, s, g, w->C, w->vset, w->ckey, w->hkeys,
-                     w->hmin);
+                     w->hmin, free_counts());
   hipLaunchKernelGGL(k_first, dim3(blocks(ncand, 256)), dim3(256), 0, s, g, w->C, w->ckey, w->hkeys, w->hmin,
                      w->cflag);
   w->scan.run(s, w->cflag, w->cpos, &w->C->nCand, ncand, &w->C->kept);

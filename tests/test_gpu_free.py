@@ -315,3 +315,42 @@ def test_free_sampling_and_mcts_stay_in_the_eight_segment_language(policy):
     assert F.admissible(list(modes[0, :K]))
     r = F.evaluate(f32(x0), f32(goal), f32(inst), np.array([K]), modes, knots, params=oracle.Params(**oracle.REFINE))
     assert r["feasible"][0] == 1 and abs(r["cost"][0] - float(o["cost"][0])) <= 1e-3 * abs(r["cost"][0])
+
+
+def test_free_uniform_sampling_batches_are_the_oracles():
+    """Uniform sampling over the free-motion language at the segment cap of eight: each draw
+    picks a segment count, then the index of an admissible order of that count (unranked),
+    so long orders are drawn as often as short ones; the evaluated orders equal the oracle's
+    draws bit for bit, and the returned plan is confirmed by the oracle's refinement."""
+    import torch
+    import oracle
+    from oracle import free as F
+    from oracle import sample as S
+    from paper_2609_21803_amd import native
+    x0, goal, inst = I.push_free_pairs(5800, 1)
+    ep = dict(kcap=8, rounds=2, knots_per_segment=5, k_ref=16, batch_B=512, eval_budget=1280)
+    prm = native.ExpandParams(**ep, policy=native.POLICY_UNIFORM, sample_seed=23, sample_draws=1024)
+    ctx = _ctx(max_batch=512, max_intervals=40, max_segments=8)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+    o, st = native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm)
+    torch.cuda.synchronize()
+    keys = native.expand_trace(ctx)[0].cpu().numpy().view(np.uint64)
+    bk, bJ, bv, okeys, J, v = S.uniform_search(3, f32(x0[0]), f32(goal[0]), f32(inst[0]), ep["kcap"], ep["rounds"],
+                                               ep["batch_B"], ep["eval_budget"], 1024, 23, ep["knots_per_segment"],
+                                               ep["k_ref"])
+    K = int(o["nseg"].item())
+    m = list(o["modes"].cpu().numpy()[:K])
+    lens = np.bincount([int(k) >> 60 for k in keys], minlength=9)[1:]
+    print("free uniform: evaluated", len(keys), "lengths", lens, "device plan", m, float(o["cost"].item()),
+          "oracle plan", F.key_modes(bk), bJ, flush=True)
+    assert np.array_equal(keys, np.array(okeys, np.uint64)) and st["evaluated"] == len(okeys) == 1280
+    assert lens[0] == 16 and lens[2:].min() >= 100    # long orders as often as short ones
+    assert K >= 1 and float(o["viol"][0]) <= 1e-5
+    modes = np.zeros((1, 8), np.int32)
+    knots = np.zeros((1, 8), np.int32)
+    modes[0, :K] = m
+    knots[0, :K] = 5
+    r = F.evaluate(f32(x0), f32(goal), f32(inst), np.array([K]), modes, knots, params=oracle.Params(**oracle.REFINE))
+    assert r["feasible"][0] == 1 and abs(r["cost"][0] - float(o["cost"][0])) <= 1e-3 * abs(r["cost"][0])
+    if F.key_modes(bk) != m:
+        assert abs(bJ - float(o["cost"].item())) <= 1e-3 * abs(bJ)

@@ -366,3 +366,22 @@ def test_expand_next_matches_a_set_based_twin(orc, W, room, r):
                 seen.add(k)
                 want.append(k)
     assert got == want
+
+
+def test_free_unranking_lists_the_language_in_key_order(orc):
+    """The sampler's unranking (the t-th admissible order of K segments) enumerates exactly
+    the seed's orders of K segments, in key order: all of them for K <= 5, a strided sample
+    and both ends for K = 6..8; free-motion draws have uniform segment counts."""
+    from oracle import sample as S
+    counts = S.free_counts()
+    s8 = [int(k) for k in F.seed(8)]
+    by_len = {K: [k for k in s8 if k >> 60 == K] for K in range(1, 9)}
+    for K in range(1, 9):
+        ref = by_len[K]
+        ts = range(len(ref)) if K <= 5 else sorted(set(list(range(0, len(ref), 997)) + [0, len(ref) - 1]))
+        for t in ts:
+            assert F.key_make(S.free_unrank(K, t, counts)) == ref[t], (K, t)
+    d = S.free_draws(7, 0, 4000, 8)
+    assert all(F.admissible(m) for m in d)
+    hist = np.bincount([len(m) for m in d], minlength=9)[1:]
+    assert hist.min() > 400 and hist.max() < 600
