@@ -276,8 +276,9 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
     segment, in the planner configurations of Sec. IV-A on the device: full enumeration
     (every admissible order in one batch), seed only (every order of at most six segments),
     and expansion with s_max = 1 and 3 rounds after that seed (r = 2, batches of up to
-    16,384, at most 1,024 best-ranked orders expanded per round); refinement of the 256 best
-    feasible orders.  Per goal: orders evaluated, device time of the whole search, time to
+    16,384, at most 1,024 best-ranked orders expanded per round); and the ablations'
+    uniform sampling and MCTS (pool 1,024) with a budget of 40,960 orders, about what three
+    expansion rounds evaluate; refinement of the 256 best feasible orders.  Per goal: orders evaluated, device time of the whole search, time to
     the first feasible order, the plan, and whether it recovers the full enumeration's plan
     cost (within 1e-4).  Then the evaluator alone on every order of at most six segments for
     each of 8 instances (118,080 TOs), one launch timed after a warm-up, with its roofline,
@@ -294,7 +295,14 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
                "expansion_smax1": native.ExpandParams(**common, seed_max_segments=6, rounds=1, frontier_W=1024,
                                                       batch_B=16384, eval_budget=full),
                "expansion_smax3": native.ExpandParams(**common, seed_max_segments=6, rounds=3, frontier_W=1024,
-                                                      batch_B=16384, eval_budget=full)}
+                                                      batch_B=16384, eval_budget=full),
+               # the ablations' allocation policies at the budget of three expansion rounds
+               "uniform_sampling": native.ExpandParams(**common, seed_max_segments=6, rounds=16, frontier_W=1,
+                                                       batch_B=16384, eval_budget=40960,
+                                                       policy=native.POLICY_UNIFORM, sample_seed=11,
+                                                       sample_draws=32768),
+               "mcts_p1024": native.ExpandParams(**common, seed_max_segments=6, rounds=0, frontier_W=1, batch_B=1024,
+                                                 eval_budget=40960, policy=native.POLICY_MCTS, sample_seed=11)}
     t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
     rows, seed6 = {k: [] for k in configs}, None
     if not planner:
