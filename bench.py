@@ -272,8 +272,9 @@ def hetero_leg(native, I, torch, B=131072):
 
 def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cpu=True, planner=True):
     """Pushing with free motion: the Sec. III-A language at the paper's segment cap of eight
-    (205,632 admissible orders, 14,760 of them of at most six segments), 10 intervals per
-    segment, in the planner configurations of Sec. IV-A on the device: full enumeration
+    (205,632 admissible orders, 14,760 of them of at most six segments), in the planner
+    configurations of Sec. IV-A on the device, 50 intervals per order as the paper's
+    transcription (split evenly over the segments, the remainder to the first ones): full enumeration
     (every admissible order in one batch), seed only (every order of at most six segments),
     and expansion with s_max = 1 and 3 rounds after that seed (r = 2, batches of up to
     16,384, at most 1,024 best-ranked orders expanded per round); and the ablations'
@@ -287,7 +288,7 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
     evaluator launch."""
     full = 205632
     ctx = native.Context(max_batch=full, max_segments=8, max_intervals=80, task=native.TASK_PUSH_FREE)
-    common = dict(kcap=8, radius=2, knots_per_segment=10, k_ref=256)
+    common = dict(kcap=8, radius=2, knots_per_segment=0, n_total=50, k_ref=256)   # the paper's 50 knots per order
     configs = {"full_enumeration": native.ExpandParams(**common, seed_max_segments=8, rounds=0, frontier_W=1,
                                                          batch_B=full, eval_budget=full),
                "seed_only": native.ExpandParams(**common, seed_max_segments=6, rounds=0, frontier_W=1, batch_B=16384,
@@ -367,9 +368,9 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
     flops = float((st[:, 1] * N).sum()) * FREE_FLOP_PER_INTERVAL_GN + float((st[:, 0] * N).sum()) * FLOP_PER_INTERVAL_AL
     ach = flops / (kms * 1e-3) / 1e12
     res = {"workload": "pushing with free motion (16 mode ids, the Sec. III-A language capped at 8 segments: "
-                       f"{full} admissible orders, {n1} of <= 6), 10 intervals per segment; planner configurations "
+                       f"{full} admissible orders, {n1} of <= 6); planner configurations with 50 intervals per order "
                        f"on the goals of seeds {seeds[0]}..{seeds[-1]}; evaluator on all {n1} orders of <= 6 segments x "
-                       f"{n_eval_inst} instances (seed 5400)",
+                       f"{n_eval_inst} instances (seed 5400), 10 intervals per segment",
            "planner_summary": summary, "planner": rows,
            "evaluate": {"orders": n, "value": n / (ms * 1e-3), "unit": "solves/s", "ms": ms,
                         "mean_intervals": float(N.mean()), "mean_gn_iterations": float(st[:, 1].mean()),
