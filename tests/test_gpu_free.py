@@ -354,3 +354,47 @@ def test_free_uniform_sampling_batches_are_the_oracles():
     assert r["feasible"][0] == 1 and abs(r["cost"][0] - float(o["cost"][0])) <= 1e-3 * abs(r["cost"][0])
     if F.key_modes(bk) != m:
         assert abs(bJ - float(o["cost"].item())) <= 1e-3 * abs(bJ)
+
+
+def test_free_expansion_at_the_paper_configuration_replays_on_the_oracle():
+    """The free-motion expansion as the paper configures it (Sec. IV-A): segment cap eight,
+    seed of every admissible order of at most six segments, three rounds of two-edit
+    neighbourhoods, 50 intervals per order, refinement of the 256 best.  The seed batch is
+    the oracle's, every later batch equals the oracle's batch step on the device's own
+    (key, Eq. (5) merit) of everything evaluated before it, and the returned plan is
+    re-solved by the oracle at the refinement budget to the same cost."""
+    import torch
+    import oracle
+    from oracle import free as F
+    from paper_2609_21803_amd import native
+    x0, goal, inst = I.push_free_pairs(5300, 1)
+    B, W, budget = 16384, 1024, 205632
+    prm = native.ExpandParams(kcap=8, seed_max_segments=6, radius=2, rounds=3, frontier_W=W, knots_per_segment=0,
+                              n_total=50, k_ref=256, batch_B=B, eval_budget=budget)
+    ctx = _ctx(max_batch=B, max_intervals=50, max_segments=8)
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+    o, st = native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm)
+    torch.cuda.synchronize()
+    keys, J, v = [a.cpu().numpy() for a in native.expand_trace(ctx)]
+    keys = keys.view(np.uint64)
+    merit = np.array([oracle.merit(a, b) for a, b in zip(J, v)])
+    seed = F.seed(6)
+    assert np.array_equal(keys[:len(seed)], seed)
+    pos, sizes = len(seed), [len(seed)]
+    while pos < len(keys):
+        nxt = F.expand_next(keys[:pos], merit[:pos], 8, 2, W, min(B, budget - pos))
+        assert len(nxt) > 0 and np.array_equal(keys[pos:pos + len(nxt)], nxt), (pos, len(nxt))
+        pos += len(nxt)
+        sizes.append(len(nxt))
+    K = int(o["nseg"].item())
+    print(f"free expansion: batches {sizes}, evaluated {st['evaluated']}, feasible {st['n_feasible']}, plan "
+          f"{o['modes'].cpu().numpy()[:K]} knots {o['knots'].cpu().numpy()[:K]} cost {float(o['cost'].item()):.6f}",
+          flush=True)
+    assert st["evaluated"] == len(keys) and len(sizes) == st["rounds_done"]
+    assert K >= 1 and float(o["viol"][0]) <= 1e-5 and int(o["knots"].cpu().numpy()[:K].sum()) == 50
+    modes = np.zeros((1, 8), np.int32)
+    knots = np.zeros((1, 8), np.int32)
+    modes[0, :K] = o["modes"].cpu().numpy()[:K]
+    knots[0, :K] = o["knots"].cpu().numpy()[:K]
+    r = F.evaluate(f32(x0), f32(goal), f32(inst), np.array([K]), modes, knots, params=oracle.Params(**oracle.REFINE))
+    assert r["feasible"][0] == 1 and abs(r["cost"][0] - float(o["cost"][0])) <= 1e-3 * abs(r["cost"][0])
