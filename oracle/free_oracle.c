@@ -20,6 +20,11 @@
  *     free:     5 F_n = 0 ; 6 F_t = 0 ; 8 a/2 - n.p_k <= 0 ; 9 a/2 - n.p_{k+1} <= 0
  *   terminal rows (x_N, y_N, theta_N) = goal; the pusher ends anywhere.
  *   Objective sum_k dt [ (F_n^2 + F_t^2) / f_max^2 + w_v |v|^2 / v_ref^2 ].
+ * Optimised timing (-DFREE_TIMED): u = (F_n, F_t, v_x, v_y, h) with the duration h of the
+ *   interval, every defect steps by h, rows 15, 16: h_min - h <= 0, h - h_max <= 0 (their
+ *   unit Jacobian rows share the scale type of the face-bound rows), objective
+ *   sum_k h [ ... + w_T ], Gauss-Newton cost Hessian 2 max(h, h_min / 2) on the force and
+ *   velocity entries, none on h (as the timed pushing oracle).
  * Solver: the augmented-Lagrangian Gauss-Newton scheme of Sec. III-C with the same
  * readings as the pushing oracle (comet_oracle.c): PHR merit, Riccati recursion with
  * Cholesky and damping retries, backtracking over a fixed number of trial steps, the
@@ -32,12 +37,24 @@
 #include <string.h>
 
 #define QNX 5
+#ifdef FREE_TIMED
+/* optimised timing (built as its own library with -DFREE_TIMED): the duration h_k of every  */
+/* interval is a fifth control, bounded per interval, and the objective charges time        */
+#define QNU 5
+#define QNW 10
+#define QNV 15
+#define QNR 17
+#define QNE 8
+#define QNI 9
+#else
 #define QNU 4
 #define QNW 9
 #define QNV 14
 #define QNR 15
 #define QNE 8
 #define QNI 7
+#endif
+#define IX1 (QNX + QNU) /* column of x_{k+1} in v = (x_k, u_k, x_{k+1}) */
 #define QNT 3
 #define QMODES 16
 #define MAXSEG 8
@@ -46,6 +63,9 @@
 static const double Q_A = 0.1, Q_MASS = 1.0, Q_G = 9.81, Q_MUG = 0.5;
 static const double Q_VREF = 1.0, Q_DT = 0.1, Q_WV = 1.0;
 static const double Q_DFREE = 0.02; /* initial guess: free-motion waypoint this far in front of its face */
+#ifdef FREE_TIMED
+static const double Q_HMIN = 0.02, Q_HMAX = 0.2, Q_WT = 0.01; /* duration bounds and time charge */
+#endif
 static double q_fmax(void) { return Q_MUG * Q_MASS * Q_G; }
 static double q_cls(void) { return Q_A * (sqrt(2.0) + log(1.0 + sqrt(2.0))) / 6.0; }
 static const double QFACE_N[4][2] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
@@ -80,10 +100,15 @@ typedef struct {
 /* ------------------------------------------------------------------------------ */
 static void q_rows(int face, int kind, double mu, const double *v, double *c, double J[QNR][QNV], int *en,
                    int *type) {
-  const double fmax = q_fmax(), cls2 = q_cls() * q_cls(), k1 = Q_VREF / fmax, dt = Q_DT, h = 0.5 * Q_A;
+#ifdef FREE_TIMED
+  const double dt = v[9];
+#else
+  const double dt = Q_DT;
+#endif
+  const double fmax = q_fmax(), cls2 = q_cls() * q_cls(), k1 = Q_VREF / fmax, h = 0.5 * Q_A;
   const double nx = QFACE_N[face][0], ny = QFACE_N[face][1], tx = -ny, ty = nx;
   const double th = v[2], px = v[3], py = v[4], Fn = v[5], Ft = v[6], vx = v[7], vy = v[8];
-  const double px1 = v[12], py1 = v[13];
+  const double px1 = v[IX1 + 3], py1 = v[IX1 + 4];
   const double Fbx = -Fn * nx + Ft * tx, Fby = -Fn * ny + Ft * ty;
   const double M = px * Fby - py * Fbx;
   const double xi_x = k1 * Fbx, xi_y = k1 * Fby, xi_t = k1 * M / cls2;
@@ -99,24 +124,29 @@ static void q_rows(int face, int kind, double mu, const double *v, double *c, do
     type[r] = T_FACE;
     for (j = 0; j < QNV; ++j) J[r][j] = 0.0;
   }
-  c[0] = v[9] - v[0] - dt * wx;
-  J[0][0] = -1; J[0][2] = dt * wy; J[0][5] = -dt * dwx_dFn; J[0][6] = -dt * dwx_dFt; J[0][9] = 1;
-  c[1] = v[10] - v[1] - dt * wy;
-  J[1][1] = -1; J[1][2] = -dt * wx; J[1][5] = -dt * dwy_dFn; J[1][6] = -dt * dwy_dFt; J[1][10] = 1;
-  c[2] = v[11] - th - dt * xi_t;
+  c[0] = v[IX1] - v[0] - dt * wx;
+  J[0][0] = -1; J[0][2] = dt * wy; J[0][5] = -dt * dwx_dFn; J[0][6] = -dt * dwx_dFt; J[0][IX1] = 1;
+  c[1] = v[IX1 + 1] - v[1] - dt * wy;
+  J[1][1] = -1; J[1][2] = -dt * wx; J[1][5] = -dt * dwy_dFn; J[1][6] = -dt * dwy_dFt; J[1][IX1 + 1] = 1;
+  c[2] = v[IX1 + 2] - th - dt * xi_t;
   J[2][2] = -1; J[2][3] = -km * Fby; J[2][4] = km * Fbx; J[2][5] = -km * (-px * ny + py * nx);
-  J[2][6] = -km * (px * ty - py * tx); J[2][11] = 1;
+  J[2][6] = -km * (px * ty - py * tx); J[2][IX1 + 2] = 1;
   c[3] = px1 - px - dt * vx;
-  J[3][3] = -1; J[3][7] = -dt; J[3][12] = 1;
+  J[3][3] = -1; J[3][7] = -dt; J[3][IX1 + 3] = 1;
   c[4] = py1 - py - dt * vy;
-  J[4][4] = -1; J[4][8] = -dt; J[4][13] = 1;
+  J[4][4] = -1; J[4][8] = -dt; J[4][IX1 + 4] = 1;
   en[0] = en[1] = en[2] = en[3] = en[4] = 1;
   type[0] = T_DX; type[1] = T_DY; type[2] = T_DTH; type[3] = T_DPX; type[4] = T_DPY;
+#ifdef FREE_TIMED
+  J[0][9] = -wx; J[1][9] = -wy; J[2][9] = -xi_t; J[3][9] = -vx; J[4][9] = -vy;
+  c[15] = Q_HMIN - dt; J[15][9] = -1; en[15] = 1; type[15] = T_FACE;
+  c[16] = dt - Q_HMAX; J[16][9] = 1; en[16] = 1; type[16] = T_FACE;
+#endif
   if (kind == 3) {
     c[5] = Fn; J[5][5] = 1; en[5] = 1; type[5] = T_FREEF;
     c[6] = Ft; J[6][6] = 1; en[6] = 1; type[6] = T_FREEF;
     c[8] = h - (nx * px + ny * py); J[8][3] = -nx; J[8][4] = -ny; en[8] = 1; type[8] = T_NPEN;
-    c[9] = h - (nx * px1 + ny * py1); J[9][12] = -nx; J[9][13] = -ny; en[9] = 1; type[9] = T_NPEN;
+    c[9] = h - (nx * px1 + ny * py1); J[9][IX1 + 3] = -nx; J[9][IX1 + 4] = -ny; en[9] = 1; type[9] = T_NPEN;
     return;
   }
   c[5] = nx * px + ny * py - h; J[5][3] = nx; J[5][4] = ny; en[5] = 1; type[5] = T_ONF;
@@ -137,8 +167,8 @@ static void q_rows(int face, int kind, double mu, const double *v, double *c, do
     c[9] = -sg * (tx * vx + ty * vy); J[9][7] = -sg * tx; J[9][8] = -sg * ty; type[9] = T_SLIP;
   }
   en[9] = 1;
-  c[11] = tx * px1 + ty * py1 - h; J[11][12] = tx; J[11][13] = ty;
-  c[12] = -(tx * px1 + ty * py1) - h; J[12][12] = -tx; J[12][13] = -ty;
+  c[11] = tx * px1 + ty * py1 - h; J[11][IX1 + 3] = tx; J[11][IX1 + 4] = ty;
+  c[12] = -(tx * px1 + ty * py1) - h; J[12][IX1 + 3] = -tx; J[12][IX1 + 4] = -ty;
   c[13] = tx * px + ty * py - h; J[13][3] = tx; J[13][4] = ty;
   c[14] = -(tx * px + ty * py) - h; J[14][3] = -tx; J[14][4] = -ty;
   en[11] = en[12] = en[13] = en[14] = 1;
@@ -155,6 +185,25 @@ static void q_term(const double *goal, const double *xN, double *c, double J[QNT
 
 /* stage cost dt q(u), its gradient and (constant, diagonal) Hessian; hu [QNU][QNU] */
 static double q_cost(const double *u, double *gu, double hu[QNU][QNU]) {
+#ifdef FREE_TIMED
+  const double fm2 = q_fmax() * q_fmax(), vr2 = Q_VREF * Q_VREF, dt = u[4], hm = fmax(u[4], 0.5 * Q_HMIN);
+  const double q = (u[0] * u[0] + u[1] * u[1]) / fm2 + Q_WV * (u[2] * u[2] + u[3] * u[3]) / vr2 + Q_WT;
+  int i, j;
+  if (gu) {
+    gu[0] = dt * 2.0 * u[0] / fm2;
+    gu[1] = dt * 2.0 * u[1] / fm2;
+    gu[2] = dt * 2.0 * Q_WV * u[2] / vr2;
+    gu[3] = dt * 2.0 * Q_WV * u[3] / vr2;
+    gu[4] = q;
+  }
+  if (hu) {
+    for (i = 0; i < QNU; ++i)
+      for (j = 0; j < QNU; ++j) hu[i][j] = 0.0;
+    hu[0][0] = hu[1][1] = hm * 2.0 / fm2;
+    hu[2][2] = hu[3][3] = hm * 2.0 * Q_WV / vr2;
+  }
+  return dt * q;
+#else
   const double fm2 = q_fmax() * q_fmax(), vr2 = Q_VREF * Q_VREF, dt = Q_DT;
   int i, j;
   if (gu) {
@@ -170,6 +219,7 @@ static double q_cost(const double *u, double *gu, double hu[QNU][QNU]) {
     hu[2][2] = hu[3][3] = dt * 2.0 * Q_WV / vr2;
   }
   return dt * ((u[0] * u[0] + u[1] * u[1]) / fm2 + Q_WV * (u[2] * u[2] + u[3] * u[3]) / vr2);
+#endif
 }
 
 /* primal layout z[k*QNW + 0..3] = u_k, z[k*QNW + 4..8] = x_{k+1} */
@@ -480,6 +530,9 @@ static void q_initial(const QProb *P, double *z) {
     z[k * QNW + 1] = (kind == 3) ? 0.0 : sg * P->mu * fn;
     z[k * QNW + 2] = (p1x - p[0]) / Q_DT;
     z[k * QNW + 3] = (p1y - p[1]) / Q_DT;
+#ifdef FREE_TIMED
+    z[k * QNW + 4] = Q_DT;
+#endif
     for (i = 0; i < 3; ++i) z[k * QNW + QNU + i] = P->x0[i] + (P->goal[i] - P->x0[i]) * t;
     z[k * QNW + QNU + 3] = p1x;
     z[k * QNW + QNU + 4] = p1y;
@@ -694,7 +747,7 @@ static void q_solve(const QProb *P, const QParams *prm, int warm, double *z, QSt
 
 /* ------------------------------------------------------------------------------ */
 /* Batched evaluation, one sequence per thread.  x0 [B][5] (pose, pusher in the     */
-/* slider frame), goal [B][3], inst [B] (pusher friction).  traj [B][nmax+1][9]      */
+/* slider frame), goal [B][3], inst [B] (pusher friction).  traj [B][nmax+1][QNX+QNU] */
 /* rows (x_k, u_k), u_N = 0, rows beyond N zero; stats [B][4].                       */
 /* ------------------------------------------------------------------------------ */
 typedef struct {
