@@ -51,7 +51,8 @@ typedef enum {
   COMET_TASK_PUSH = 0,
   COMET_TASK_FLIP = 1,
   COMET_TASK_PUSH_TIMED = 2,
-  COMET_TASK_PUSH_FREE = 3
+  COMET_TASK_PUSH_FREE = 3,
+  COMET_TASK_PUSH_FREE_TIMED = 4
 } comet_task;
 
 typedef struct comet_ctx comet_ctx; /* opaque */

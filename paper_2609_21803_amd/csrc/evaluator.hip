@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "keys.h"
 
 namespace comet {
 
@@ -62,6 +63,14 @@ using namespace push_free;
 #include "push_solver.inc"
 #undef PUSH_MODEL_FREE
 }  // namespace free_step
+
+namespace free_timed_step {
+constexpr int MAXSEG = MAXSEG_FREE;   // orders of up to eight segments
+using namespace push_free_timed;
+#define PUSH_MODEL_FREE 1
+#include "push_solver.inc"
+#undef PUSH_MODEL_FREE
+}  // namespace free_timed_step
 
 // --------------------------------------------------------------------------------
 // Queue set-up kernels: reset the head, and (optionally) order the sequences by
@@ -203,6 +212,8 @@ comet_status launch_evaluate(comet_ctx* c, hipStream_t s, const EvalLaunch& L) {
     hipLaunchKernelGGL(timed_step::k_push_solve, dim3(grid), dim3(WAVE), 0, s, A);
   else if (c->task == COMET_TASK_PUSH_FREE)
     hipLaunchKernelGGL(free_step::k_push_solve, dim3(grid), dim3(WAVE), 0, s, A);
+  else if (c->task == COMET_TASK_PUSH_FREE_TIMED)
+    hipLaunchKernelGGL(free_timed_step::k_push_solve, dim3(grid), dim3(WAVE), 0, s, A);
   else
     hipLaunchKernelGGL(fixed_step::k_push_solve, dim3(grid), dim3(WAVE), 0, s, A);
   if (timed && c->ev1) (void)hipEventRecord(c->ev1, s);
@@ -296,9 +307,9 @@ comet_status comet_create(comet_task task, const comet_solver_params* params, in
   if (!out) return COMET_EINVAL;
   *out = nullptr;
   if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP && task != COMET_TASK_PUSH_TIMED &&
-       task != COMET_TASK_PUSH_FREE) || max_batch < 1 ||
+       task != COMET_TASK_PUSH_FREE && task != COMET_TASK_PUSH_FREE_TIMED) || max_batch < 1 ||
       max_segments < 1 ||
-      max_segments > (task == COMET_TASK_PUSH_FREE ? comet::MAXSEG_FREE : comet::MAXSEG) ||
+      max_segments > (comet::is_free_task(task) ? comet::MAXSEG_FREE : comet::MAXSEG) ||
       max_intervals < 1 || max_intervals > comet::MAXN)
     return COMET_EINVAL;
   comet_ctx* c = new comet_ctx();
@@ -315,10 +326,12 @@ comet_status comet_create(comet_task task, const comet_solver_params* params, in
   c->max_segments = max_segments;
   c->max_intervals = max_intervals;
   (void)hipGetDevice(&c->device);
-  const bool timed = (task == COMET_TASK_PUSH_TIMED), freem = (task == COMET_TASK_PUSH_FREE);
+  const bool timed = (task == COMET_TASK_PUSH_TIMED), freem = (task == COMET_TASK_PUSH_FREE),
+             freet = (task == COMET_TASK_PUSH_FREE_TIMED);
   for (int t = 0; t < comet::MAX_TYPES; ++t) c->scale[t] = 1.0;
   if (timed) comet::timed_step::compute_scales(c->scale);
   else if (freem) comet::free_step::compute_scales(c->scale);
+  else if (freet) comet::free_timed_step::compute_scales(c->scale);
   else comet::fixed_step::compute_scales(c->scale);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) {
@@ -343,15 +356,20 @@ comet_status comet_create(comet_task task, const comet_solver_params* params, in
   const hipError_t oe =
       timed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, comet::timed_step::k_push_solve, comet::WAVE, 0)
       : freem ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, comet::free_step::k_push_solve, comet::WAVE, 0)
+      : freet ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, comet::free_timed_step::k_push_solve, comet::WAVE, 0)
               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, comet::fixed_step::k_push_solve, comet::WAVE, 0);
   if (oe != hipSuccess || nb < 1) nb = 1;
   c->occ_blocks_per_cu = nb;
   const int64_t R = max_intervals, S = c->S;
   // per-interval work-space widths of the task's model
-  const int64_t NW = timed ? comet::push_timed::NW : (freem ? comet::push_free::NW : comet::push::NW);
-  const int64_t NE = timed ? comet::push_timed::NE : (freem ? comet::push_free::NE : comet::push::NE);
-  const int64_t NI = timed ? comet::push_timed::NI : (freem ? comet::push_free::NI : comet::push::NI);
-  const int64_t NGAIN = timed ? comet::push_timed::NGAIN : (freem ? comet::push_free::NGAIN : comet::push::NGAIN);
+  const int64_t NW = timed ? comet::push_timed::NW
+                     : freem ? comet::push_free::NW : freet ? comet::push_free_timed::NW : comet::push::NW;
+  const int64_t NE = timed ? comet::push_timed::NE
+                     : freem ? comet::push_free::NE : freet ? comet::push_free_timed::NE : comet::push::NE;
+  const int64_t NI = timed ? comet::push_timed::NI
+                     : freem ? comet::push_free::NI : freet ? comet::push_free_timed::NI : comet::push::NI;
+  const int64_t NGAIN = timed ? comet::push_timed::NGAIN
+                        : freem ? comet::push_free::NGAIN : freet ? comet::push_free_timed::NGAIN : comet::push::NGAIN;
   bool okm = hipMalloc(&c->zd, sizeof(double) * R * NW * S) == hipSuccess &&
              hipMalloc(&c->lam, sizeof(float) * R * NE * S) == hipSuccess &&
              hipMalloc(&c->nu, sizeof(float) * R * NI * S) == hipSuccess &&
@@ -401,9 +419,13 @@ const char* comet_last_error(const comet_ctx* c) { return c ? c->msg.c_str() : c
 comet_status comet_dims(const comet_ctx* c, int32_t* nx, int32_t* nu, int32_t* np, int32_t* nm, int32_t* ms,
                         int32_t* mi, int64_t* mb) {
   if (!c) return COMET_EINVAL;
-  const bool fl = (c->task == COMET_TASK_FLIP), fr = (c->task == COMET_TASK_PUSH_FREE);
+  const bool fl = (c->task == COMET_TASK_FLIP), fr = comet::is_free_task(c->task);
   if (nx) *nx = fl ? 8 : (fr ? comet::push_free::NX : comet::push::NX);
-  if (nu) *nu = fl ? 9 : (c->task == COMET_TASK_PUSH_TIMED ? comet::push_timed::NU : (fr ? comet::push_free::NU : comet::push::NU));
+  if (nu)
+    *nu = fl ? 9
+          : c->task == COMET_TASK_PUSH_TIMED ? comet::push_timed::NU
+          : c->task == COMET_TASK_PUSH_FREE_TIMED ? comet::push_free_timed::NU
+          : fr ? comet::push_free::NU : comet::push::NU;
   if (np) *np = 1;
   if (nm) *nm = fl ? 845 : (fr ? comet::push_free::NMODES : comet::push::NMODES);
   if (ms) *ms = c->max_segments;
@@ -415,7 +437,7 @@ comet_status comet_dims(const comet_ctx* c, int32_t* nx, int32_t* nu, int32_t* n
 comet_status comet_row_scales(const comet_ctx* c, double* out, int32_t n) {
   if (!c || !out || c->task == COMET_TASK_FLIP) return COMET_EINVAL;
   const int nt = (c->task == COMET_TASK_PUSH_TIMED) ? comet::push_timed::NTYPES
-                 : (c->task == COMET_TASK_PUSH_FREE) ? comet::push_free::NTYPES : comet::push::NTYPES;
+                 : comet::is_free_task(c->task) ? comet::push_free::NTYPES : comet::push::NTYPES;
   if (n < nt) return COMET_EINVAL;
   for (int t = 0; t < nt; ++t) out[t] = c->scale[t];
   return COMET_OK;

@@ -372,7 +372,7 @@ __global__ void k_seed_cand(ExpCfg g, int kmax, long long n_seed, ExpCounters* C
   }
   if (t >= n_seed) return;
   unsigned long long k;
-  if (g.task == COMET_TASK_PUSH_FREE) {
+  if (is_free_task(g.task)) {
     long long c = t;
     int K = 1;
     for (long long n = free_count_len(fc, 1); K < kmax && c >= n; n = free_count_len(fc, K)) {
@@ -479,7 +479,7 @@ __global__ void k_sample(ExpCfg g, const ExpCounters* C, const unsigned long lon
   const unsigned long long c = C->draw_base + (unsigned long long)t;
   const int K = 1 + (int)(splitmix64_out(g.sseed, 8ull * c) % (unsigned long long)g.kcap);
   unsigned long long k;
-  if (g.task == COMET_TASK_PUSH_FREE) {
+  if (is_free_task(g.task)) {
     const unsigned long long n = (unsigned long long)free_count_len(fc, K);
     k = free_unrank(fc, K, (long long)(splitmix64_out(g.sseed, 8ull * c + 1ull) % n));
   } else {
@@ -755,7 +755,7 @@ comet_status check_expand_params(comet_ctx* c, const comet_expand_params* p) {
 // on the device by the task's language), or, with free motion, its admissible orders only
 long long seed_slots(int task, int M, int kmax) {
   long long n = 0, t = 1;
-  if (task == COMET_TASK_PUSH_FREE) {
+  if (is_free_task(task)) {
     const FreeCounts f = free_counts();
     for (int K = 1; K <= kmax; ++K) n += free_count_len(f, K);
     return n;
@@ -769,8 +769,11 @@ long long seed_slots(int task, int M, int kmax) {
 
 comet_status ensure_ws(comet_ctx* c, const comet_expand_params* p) {
   const bool flip = (c->task == COMET_TASK_FLIP), lang = task_has_language(c->task);
-  const int M = flip ? 845 : (c->task == COMET_TASK_PUSH_FREE ? push_free::NMODES : push::NMODES);
-  const int rowW = flip ? 17 : (c->task == COMET_TASK_PUSH_TIMED ? 8 : (c->task == COMET_TASK_PUSH_FREE ? 9 : 7));
+  const int M = flip ? 845 : (is_free_task(c->task) ? push_free::NMODES : push::NMODES);
+  const int rowW = flip ? 17
+                   : c->task == COMET_TASK_PUSH_TIMED ? 8
+                   : c->task == COMET_TASK_PUSH_FREE ? 9
+                   : c->task == COMET_TASK_PUSH_FREE_TIMED ? 10 : 7;
   int raw1max = 0;
   for (int K = 1; K <= p->kcap; ++K) raw1max = std::max(raw1max, raw1_count(K, M, p->kcap));
   const long long rawmax = (p->radius >= 2) ? (long long)raw1max + (long long)raw1max * raw1max : raw1max;
@@ -1103,7 +1106,7 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
   const bool flip = (c->task == COMET_TASK_FLIP);
   if (learned && (mlp_max_batch(learned) < params->batch_B || mlp_in_dim(learned) < 400 || mlp_out_dim(learned) < 722))
     return fail_msg(c, COMET_EINVAL, "learned network: max_batch < batch_B, in_dim < 400 or out_dim < 722");
-  if (learned && c->task == COMET_TASK_PUSH_FREE)
+  if (learned && is_free_task(c->task))
     return fail_msg(c, COMET_EINVAL, "the learned network serves the pushing, timed-pushing and flipping tasks");
   if (learned && params->policy == COMET_POLICY_MCTS)
     return fail_msg(c, COMET_EINVAL, "the learned network ranks expansion or sampling batches, not MCTS");
@@ -1122,7 +1125,7 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
   hipEvent_t e_in, e_t0, e_t1;
   if (hipEventCreate(&e_in) != hipSuccess || hipEventCreate(&e_t0) != hipSuccess || hipEventCreate(&e_t1) != hipSuccess)
     return fail_msg(c, COMET_EHIP, "event creation failed");
-  (void)hipMemcpyAsync(w->ix0, x0, 4 * (flip ? 8 : (c->task == COMET_TASK_PUSH_FREE ? push_free::NX : push::NX)),
+  (void)hipMemcpyAsync(w->ix0, x0, 4 * (flip ? 8 : (is_free_task(c->task) ? push_free::NX : push::NX)),
                        hipMemcpyDeviceToDevice, us);
   (void)hipMemcpyAsync(w->igoal, goal, 4 * (flip ? 2 : 3), hipMemcpyDeviceToDevice, us);
   (void)hipMemcpyAsync(w->iinst, inst, 4 * 1, hipMemcpyDeviceToDevice, us);

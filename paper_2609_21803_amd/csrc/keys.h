@@ -13,7 +13,11 @@
 namespace comet {
 
 constexpr int KEY_MAXSEG = 8;   // the longest order a key holds (free motion; the others stop at 6)
-__host__ __device__ constexpr int key_bits(int task) { return task == COMET_TASK_PUSH_FREE ? 4 : 10; }
+// pushing with free motion, with the fixed step or with optimised timing: one language
+__host__ __device__ constexpr bool is_free_task(int task) {
+  return task == COMET_TASK_PUSH_FREE || task == COMET_TASK_PUSH_FREE_TIMED;
+}
+__host__ __device__ constexpr int key_bits(int task) { return is_free_task(task) ? 4 : 10; }
 __host__ __device__ inline int key_len(unsigned long long k) { return (int)(k >> 60); }
 __host__ __device__ inline int key_mode(unsigned long long k, int i, int w) {
   return (int)((k >> (60 - w * (i + 1))) & ((1ull << w) - 1ull));
@@ -128,10 +132,10 @@ __host__ __device__ inline unsigned long long free_unrank(const FreeCounts& f, i
 // a task's language: flipping and free-motion pushing restrict the orders, the other
 // pushing tasks evaluate every order of their product space
 __host__ __device__ inline bool task_has_language(int task) {
-  return task == COMET_TASK_FLIP || task == COMET_TASK_PUSH_FREE;
+  return task == COMET_TASK_FLIP || is_free_task(task);
 }
 __host__ __device__ inline bool admissible_key(int task, unsigned long long k) {
-  return task == COMET_TASK_FLIP ? flip_admissible_key(k) : (task == COMET_TASK_PUSH_FREE ? free_admissible_key(k) : true);
+  return task == COMET_TASK_FLIP ? flip_admissible_key(k) : (is_free_task(task) ? free_admissible_key(k) : true);
 }
 
 }  // namespace comet

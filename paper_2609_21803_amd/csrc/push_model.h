@@ -532,4 +532,206 @@ __host__ __device__ inline void initial_knot(int code, double fn, double mu, con
 }
 
 }  // namespace push_free
+
+// --------------------------------------------------------------------------------------
+// Free-motion pushing with optimised timing (the paper's pushing transcription: the
+// language of Sec. III-A with interval durations as controls, Sec. III-C / IV-A).  The
+// free-motion model above with u = (F_n, F_t, v_x, v_y, h): every defect steps by the
+// interval's duration h, rows 15, 16 bound it (h_min - h <= 0, h - h_max <= 0; unit rows,
+// scaled as the face-bound rows), the objective charges sum_k h [ q(u_k) + w_T ], and the
+// Gauss-Newton cost Hessian keeps the force and velocity block only.
+// --------------------------------------------------------------------------------------
+namespace push_free_timed {
+
+constexpr int NX = 5, NU = 5, NW = 10, NV = 15, NR = 17, NE = 8, NI = NR - NE, NT = 3;
+constexpr int NMODES = 16, NTYPES = 16, NGAIN = NW + NW * NX;
+constexpr bool PREFETCH_GAINS = false;
+using push::SIDE;
+using push::MASS;
+using push::GRAV;
+using push::MU_G;
+using push::VREF;
+using push::DT;
+using push::WV;
+using push::FMAX;
+using push::CLS;
+using push::K1;
+using push::KM;
+using push::HALF;
+using push::face_dirs;
+constexpr double DFREE = 0.02;   // initial guess: a free segment's knots this far in front of its face
+constexpr double H_MIN = 0.02, H_MAX = 0.2, W_T = 0.01;   // duration bounds, time charge
+
+enum { VX = 0, VY, VTH, VPX, VPY, VFN, VFT, VVX, VVY, VH, VX1, VY1, VTH1, VPX1, VPY1 };
+// row types of the internal scaling (n.p - a/2 and n.v share one)
+enum { T_DX, T_DY, T_DTH, T_DPX, T_DPY, T_ONF, T_STICK, T_SLIDE, T_FREEF, T_FN, T_CONE, T_SLIP, T_NPEN, T_FACE,
+       T_TXY, T_TTH };
+
+__host__ __device__ inline int make_code(int mode, int smask) {
+  (void)smask;
+  return mode < 12 ? (mode / 3) | ((mode % 3) << 2) : (mode - 12) | (3 << 2);
+}
+
+__host__ __device__ constexpr bool nz(int r, int i) {
+  return (r == 0) ? (i == VX || i == VTH || i == VFN || i == VFT || i == VH || i == VX1)
+       : (r == 1) ? (i == VY || i == VTH || i == VFN || i == VFT || i == VH || i == VY1)
+       : (r == 2) ? (i == VTH || i == VPX || i == VPY || i == VFN || i == VFT || i == VH || i == VTH1)
+       : (r == 3) ? (i == VPX || i == VVX || i == VH || i == VPX1)
+       : (r == 4) ? (i == VPY || i == VVY || i == VH || i == VPY1)
+       : (r == 5 || r == 8) ? (i == VPX || i == VPY || i == VFN)
+       : (r == 6) ? (i == VVX || i == VVY || i == VFT)
+       : (r == 7) ? (i == VVX || i == VVY || i == VFN || i == VFT)
+       : (r == 9) ? (i == VPX1 || i == VPY1 || i == VVX || i == VVY || i == VFN || i == VFT)
+       : (r == 10) ? (i == VFN || i == VFT)
+       : (r == 11 || r == 12) ? (i == VPX1 || i == VPY1)
+       : (r == 13 || r == 14) ? (i == VPX || i == VPY)
+       : (i == VH);
+}
+
+// residuals in double, the Jacobian (every structural entry of the union, zeros where the
+// mode has none) in T
+template <typename T>
+__host__ __device__ inline void rows_sc(const double* xk, const double* uk, const double* x1, int code, double mu,
+                                        double st, double ct, double* c, T (*J)[NV], int* en) {
+  const int face = code & 3, kind = (code >> 2) & 3;
+  const bool fr = (kind == 3), stick = (kind == 0);
+  const double sg = (kind == 1) ? 1.0 : ((kind == 2) ? -1.0 : 0.0);
+  double nx, ny;
+  face_dirs<double>(face, nx, ny);
+  const double tx = -ny, ty = nx;
+  const double px = xk[3], py = xk[4], Fn = uk[0], Ft = uk[1], vx = uk[2], vy = uk[3], h = uk[4];
+  const double px1 = x1[3], py1 = x1[4];
+  const double Fbx = -Fn * nx + Ft * tx, Fby = -Fn * ny + Ft * ty;
+  const double M = px * Fby - py * Fbx;
+  const double xi_x = K1 * Fbx, xi_y = K1 * Fby, xi_t = KM * M;
+  const double wx = ct * xi_x - st * xi_y, wy = st * xi_x + ct * xi_y;
+  const double pn = nx * px + ny * py, pt = tx * px + ty * py;
+  const double p1n = nx * px1 + ny * py1, p1t = tx * px1 + ty * py1;
+  const double vn = nx * vx + ny * vy, vt = tx * vx + ty * vy;
+  c[0] = (x1[0] - xk[0]) - h * wx;
+  c[1] = (x1[1] - xk[1]) - h * wy;
+  c[2] = (x1[2] - xk[2]) - h * xi_t;
+  c[3] = (px1 - px) - h * vx;
+  c[4] = (py1 - py) - h * vy;
+  c[5] = fr ? Fn : pn - HALF;
+  c[6] = fr ? Ft : vn;
+  c[7] = fr ? 0.0 : (stick ? vt : Ft - sg * mu * Fn);
+  c[8] = fr ? HALF - pn : -Fn;
+  c[9] = fr ? HALF - p1n : (stick ? Ft - mu * Fn : -sg * vt);
+  c[10] = (!fr && stick) ? -Ft - mu * Fn : 0.0;
+  c[11] = fr ? 0.0 : p1t - HALF;
+  c[12] = fr ? 0.0 : -p1t - HALF;
+  c[13] = fr ? 0.0 : pt - HALF;
+  c[14] = fr ? 0.0 : -pt - HALF;
+  en[0] = en[1] = en[2] = en[3] = en[4] = en[5] = en[6] = 1;
+  en[7] = fr ? 0 : 1;
+  en[8] = en[9] = 1;
+  en[10] = (!fr && stick) ? 1 : 0;
+  en[11] = en[12] = en[13] = en[14] = fr ? 0 : 1;
+  c[15] = H_MIN - h;
+  c[16] = h - H_MAX;
+  en[15] = en[16] = 1;
+  if (J) {
+    const T k1 = T(K1), km = T(KM), dt = T(h), one = T(1), zero = T(0);
+    const T stT = T(st), ctT = T(ct), nxT = T(nx), nyT = T(ny), txT = T(tx), tyT = T(ty);
+    const T muT = T(mu), sgT = T(sg), wxT = T(wx), wyT = T(wy), FbxT = T(Fbx), FbyT = T(Fby);
+    const T pxT = T(px), pyT = T(py);
+    const T dwx_dFn = k1 * (ctT * (-nxT) - stT * (-nyT)), dwy_dFn = k1 * (stT * (-nxT) + ctT * (-nyT));
+    const T dwx_dFt = k1 * (ctT * txT - stT * tyT), dwy_dFt = k1 * (stT * txT + ctT * tyT);
+    J[0][VX] = -one; J[0][VTH] = dt * wyT; J[0][VFN] = -dt * dwx_dFn; J[0][VFT] = -dt * dwx_dFt; J[0][VX1] = one;
+    J[1][VY] = -one; J[1][VTH] = -dt * wxT; J[1][VFN] = -dt * dwy_dFn; J[1][VFT] = -dt * dwy_dFt; J[1][VY1] = one;
+    J[2][VTH] = -one; J[2][VPX] = -dt * km * FbyT; J[2][VPY] = dt * km * FbxT;
+    J[2][VFN] = -dt * km * (-pxT * nyT + pyT * nxT); J[2][VFT] = -dt * km * (pxT * tyT - pyT * txT);
+    J[2][VTH1] = one;
+    J[3][VPX] = -one; J[3][VVX] = -dt; J[3][VPX1] = one;
+    J[4][VPY] = -one; J[4][VVY] = -dt; J[4][VPY1] = one;
+    J[5][VPX] = fr ? zero : nxT; J[5][VPY] = fr ? zero : nyT; J[5][VFN] = fr ? one : zero;
+    J[6][VVX] = fr ? zero : nxT; J[6][VVY] = fr ? zero : nyT; J[6][VFT] = fr ? one : zero;
+    J[7][VVX] = (!fr && stick) ? txT : zero; J[7][VVY] = (!fr && stick) ? tyT : zero;
+    J[7][VFN] = (!fr && !stick) ? -sgT * muT : zero; J[7][VFT] = (!fr && !stick) ? one : zero;
+    J[8][VPX] = fr ? -nxT : zero; J[8][VPY] = fr ? -nyT : zero; J[8][VFN] = fr ? zero : -one;
+    J[9][VPX1] = fr ? -nxT : zero; J[9][VPY1] = fr ? -nyT : zero;
+    J[9][VVX] = (!fr && !stick) ? -sgT * txT : zero; J[9][VVY] = (!fr && !stick) ? -sgT * tyT : zero;
+    J[9][VFN] = (!fr && stick) ? -muT : zero; J[9][VFT] = (!fr && stick) ? one : zero;
+    J[10][VFN] = (!fr && stick) ? -muT : zero; J[10][VFT] = (!fr && stick) ? -one : zero;
+    J[11][VPX1] = fr ? zero : txT; J[11][VPY1] = fr ? zero : tyT;
+    J[12][VPX1] = fr ? zero : -txT; J[12][VPY1] = fr ? zero : -tyT;
+    J[13][VPX] = fr ? zero : txT; J[13][VPY] = fr ? zero : tyT;
+    J[14][VPX] = fr ? zero : -txT; J[14][VPY] = fr ? zero : -tyT;
+    // the duration column: each defect steps by h
+    J[0][VH] = -wxT; J[1][VH] = -wyT; J[2][VH] = -T(xi_t); J[3][VH] = -T(vx); J[4][VH] = -T(vy);
+    J[15][VH] = -one;
+    J[16][VH] = one;
+  }
+}
+
+template <typename T>
+__host__ __device__ inline void rows(const double* xk, const double* uk, const double* x1, int code, double mu,
+                                     double* c, T (*J)[NV], int* en) {
+  double st, ct;
+  sincos_d(xk[2], &st, &ct);
+  rows_sc<T>(xk, uk, x1, code, mu, st, ct, c, J, en);
+}
+
+__host__ __device__ inline int rtype(int r, int code) {
+  const int kind = (code >> 2) & 3;
+  const bool fr = (kind == 3), stick = (kind == 0);
+  switch (r) {
+    case 0: return T_DX;
+    case 1: return T_DY;
+    case 2: return T_DTH;
+    case 3: return T_DPX;
+    case 4: return T_DPY;
+    case 5:
+    case 6: return fr ? T_FREEF : T_ONF;
+    case 7: return stick ? T_STICK : T_SLIDE;
+    case 8: return fr ? T_NPEN : T_FN;
+    case 9: return fr ? T_NPEN : (stick ? T_CONE : T_SLIP);
+    case 10: return T_CONE;
+    default: return T_FACE;
+  }
+}
+
+constexpr double CF = 1.0 / (FMAX * FMAX), CV = WV / (VREF * VREF);
+__host__ __device__ inline double stage_cost(const double* u) {
+  return u[4] * ((u[0] * u[0] + u[1] * u[1]) * CF + CV * (u[2] * u[2] + u[3] * u[3]) + W_T);
+}
+__host__ __device__ inline void add_cost_grad(const double* u, double* h) {
+  h[VFN] += 2.0 * CF * u[4] * u[0];
+  h[VFT] += 2.0 * CF * u[4] * u[1];
+  h[VVX] += 2.0 * CV * u[4] * u[2];
+  h[VVY] += 2.0 * CV * u[4] * u[3];
+  h[VH] += (u[0] * u[0] + u[1] * u[1]) * CF + CV * (u[2] * u[2] + u[3] * u[3]) + W_T;
+}
+// Gauss-Newton model of the cost Hessian: the exact force and velocity block 2h diag at
+// max(h, h_min / 2), without the (u, h) and (h, h) entries (as the timed pushing model)
+__host__ __device__ inline void add_cost_hess(const double* u, double (*G)[NV]) {
+  const double he = fmax(u[4], 0.5 * H_MIN);
+  G[VFN][VFN] += 2.0 * CF * he;
+  G[VFT][VFT] += 2.0 * CF * he;
+  G[VVX][VVX] += 2.0 * CV * he;
+  G[VVY][VVY] += 2.0 * CV * he;
+}
+
+// Schedule-derived initial guess of one interval (the paper's construction: the pusher is
+// placed on each scheduled face during each contact segment): the interval's end knot p1
+// at the face centre for contact, DFREE in front of the face for free motion; the velocity
+// that moves the pusher from p0 there in one step; F_n = fn with F_t on the cone edge for
+// sliding contact, no force in free motion.
+__host__ __device__ inline void initial_knot(int code, double fn, double mu, const double* p0, double* u, double* p1) {
+  const int face = code & 3, kind = (code >> 2) & 3;
+  double nx, ny;
+  face_dirs<double>(face, nx, ny);
+  const double d = (kind == 3) ? HALF + DFREE : HALF;
+  const double sg = (kind == 1) ? 1.0 : ((kind == 2) ? -1.0 : 0.0);
+  p1[0] = d * nx;
+  p1[1] = d * ny;
+  u[0] = (kind == 3) ? 0.0 : fn;
+  u[1] = (kind == 3) ? 0.0 : sg * mu * fn;
+  u[2] = (p1[0] - p0[0]) / DT;
+  u[3] = (p1[1] - p0[1]) / DT;
+  u[4] = DT;
+}
+
+}  // namespace push_free_timed
 }  // namespace comet

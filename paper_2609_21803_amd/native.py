@@ -15,9 +15,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcomet.so")
 
 COMET_OK, COMET_EINVAL, COMET_EHIP, COMET_ENOMEM, COMET_ESTATE = 0, -1, -2, -3, -4
-TASK_PUSH, TASK_FLIP, TASK_PUSH_TIMED, TASK_PUSH_FREE = 0, 1, 2, 3
+TASK_PUSH, TASK_FLIP, TASK_PUSH_TIMED, TASK_PUSH_FREE, TASK_PUSH_FREE_TIMED = 0, 1, 2, 3, 4
 POLICY_EXPAND, POLICY_UNIFORM, POLICY_MCTS = 0, 1, 2
-ROW_WIDTH = {TASK_PUSH: 7, TASK_FLIP: 17, TASK_PUSH_TIMED: 8, TASK_PUSH_FREE: 9}   # trajectory row (x_k, u_k)
+ROW_WIDTH = {TASK_PUSH: 7, TASK_FLIP: 17, TASK_PUSH_TIMED: 8, TASK_PUSH_FREE: 9, TASK_PUSH_FREE_TIMED: 10}   # trajectory row (x_k, u_k)
 
 
 class SolverParamsC(C.Structure):
@@ -245,7 +245,7 @@ class Context:
         import numpy as np
         out = np.zeros(16)
         check(lib().comet_row_scales(self._h, out.ctypes.data_as(C.c_void_p), 16), self._h)
-        return out[:{TASK_PUSH_TIMED: 13, TASK_PUSH_FREE: 16}.get(self.task, 12)]
+        return out[:{TASK_PUSH_TIMED: 13, TASK_PUSH_FREE: 16, TASK_PUSH_FREE_TIMED: 16}.get(self.task, 12)]
 
     def check(self, stream=None):
         check(lib().comet_check(self._h, _stream(stream)), self._h)
