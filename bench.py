@@ -65,6 +65,10 @@ TIMED_FLOP_PER_INTERVAL_GN = 3000.0
 # for 5 + 1 right-hand sides ~490 each way, value update ~360, forward pass ~90 and ~130 per
 # trial step length (8 trials): ~3.3 kflop.
 FREE_FLOP_PER_INTERVAL_GN = 3300.0
+# Free motion with optimised timing (10 stage unknowns, 17 row slots): the free-motion count
+# with the duration column in the five defects and the two bound rows, a 10x10 Cholesky
+# (~330) and solves for 5 + 1 right-hand sides on 10 unknowns: ~3.8 kflop.
+FREE_TIMED_FLOP_PER_INTERVAL_GN = 3800.0
 HBM_PEAK_GBS = 8000.0
 
 
@@ -270,7 +274,7 @@ def hetero_leg(native, I, torch, B=131072):
                                    "solves_per_s": B / (np.mean(best) * 1e-3)}}
 
 
-def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cpu=True, planner=True):
+def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cpu=True, planner=True, timed=False):
     """Pushing with free motion: the Sec. III-A language at the paper's segment cap of eight
     (205,632 admissible orders, 14,760 of them of at most six segments), in the planner
     configurations of Sec. IV-A on the device, 50 intervals per order as the paper's
@@ -285,9 +289,12 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
     each of 8 instances (118,080 TOs), one launch timed after a warm-up, with its roofline,
     and the oracle's rate on a strided sample.  planner=False runs only the seed pass that
     lists the orders of at most six segments (two intervals per segment) before the
-    evaluator launch."""
+    evaluator launch.  timed=True: the same with optimised timing (the interval durations
+    as controls with bounds, the paper's pushing transcription), the evaluator launch with
+    50 intervals per order."""
     full = 205632
-    ctx = native.Context(max_batch=full, max_segments=8, max_intervals=80, task=native.TASK_PUSH_FREE)
+    task = native.TASK_PUSH_FREE_TIMED if timed else native.TASK_PUSH_FREE
+    ctx = native.Context(max_batch=full, max_segments=8, max_intervals=80, task=task)
     common = dict(kcap=8, radius=2, knots_per_segment=0, n_total=50, k_ref=256)   # the paper's 50 knots per order
     configs = {"full_enumeration": native.ExpandParams(**common, seed_max_segments=8, rounds=0, frontier_W=1,
                                                          batch_B=full, eval_budget=full),
@@ -317,8 +324,8 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
     for name, prm in configs.items():
         for sd in seeds:
             x0, goal, inst = I.push_free_pairs(sd, 1)
-            native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm)          # capture + warm-up
-            torch.cuda.synchronize()
+            # one search per goal: its time (HIP events around the launch of the captured loop)
+            # does not include graph capture and instantiation
             o, st = native.expand(ctx, t(x0[0]), t(goal[0]), t(inst[0]), prm)
             torch.cuda.synchronize()
             K = int(o["nseg"].item())
@@ -350,10 +357,15 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
     x0, goal, inst = I.push_free_pairs(5400, n_eval_inst)
     pair = np.repeat(np.arange(n_eval_inst), n1)
     nseg = np.tile(nseg1, n_eval_inst)
+    if timed:   # 50 intervals per order, split evenly, the remainder to the first segments
+        j = np.arange(6)[None, :]
+        kn = np.where(j < nseg[:, None], 50 // nseg[:, None] + (j < (50 % nseg)[:, None]), 0).astype(np.int32)
+    else:
+        kn = np.where(np.arange(6)[None, :] < nseg[:, None], 10, 0).astype(np.int32)
     batch = dict(x0=x0[pair], goal=goal[pair], inst=inst[pair], nseg=nseg, modes=np.tile(modes1, (n_eval_inst, 1)),
-                 knots=np.where(np.arange(6)[None, :] < nseg[:, None], 10, 0).astype(np.int32))
+                 knots=kn)
     n = len(nseg)
-    ectx = native.Context(max_batch=n, max_segments=6, max_intervals=60, task=native.TASK_PUSH_FREE)
+    ectx = native.Context(max_batch=n, max_segments=6, max_intervals=60, task=task)
     d = native.to_device(batch)
     ectx.evaluate(**d)
     torch.cuda.synchronize()
@@ -365,26 +377,30 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
     ms, kms = e0.elapsed_time(e1), ectx.kernel_ms()
     st = out["stats"].cpu().numpy()
     N = I.n_intervals(batch).astype(np.float64)
-    flops = float((st[:, 1] * N).sum()) * FREE_FLOP_PER_INTERVAL_GN + float((st[:, 0] * N).sum()) * FLOP_PER_INTERVAL_AL
+    fgn = FREE_TIMED_FLOP_PER_INTERVAL_GN if timed else FREE_FLOP_PER_INTERVAL_GN
+    flops = float((st[:, 1] * N).sum()) * fgn + float((st[:, 0] * N).sum()) * FLOP_PER_INTERVAL_AL
     ach = flops / (kms * 1e-3) / 1e12
-    res = {"workload": "pushing with free motion (16 mode ids, the Sec. III-A language capped at 8 segments: "
+    res = {"workload": ("pushing with free motion and optimised timing" if timed else "pushing with free motion") +
+                       " (16 mode ids, the Sec. III-A language capped at 8 segments: "
                        f"{full} admissible orders, {n1} of <= 6); planner configurations with 50 intervals per order "
                        f"on the goals of seeds {seeds[0]}..{seeds[-1]}; evaluator on all {n1} orders of <= 6 segments x "
-                       f"{n_eval_inst} instances (seed 5400), 10 intervals per segment",
+                       f"{n_eval_inst} instances (seed 5400), " + ("50 intervals per order" if timed else
+                                                                    "10 intervals per segment"),
            "planner_summary": summary, "planner": rows,
            "evaluate": {"orders": n, "value": n / (ms * 1e-3), "unit": "solves/s", "ms": ms,
                         "mean_intervals": float(N.mean()), "mean_gn_iterations": float(st[:, 1].mean()),
                         "feasible_fraction": float(out["feasible"].float().mean().item()),
-                        "roofline": {"bound": "alu", "kernel": "k_push_solve (free motion)", "achieved": ach,
+                        "roofline": {"bound": "alu", "kernel": "k_push_solve (free motion" +
+                                     (", optimised timing)" if timed else ")"), "achieved": ach,
                                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
                                      "kernel_ms": kms, "flop_per_launch": flops,
-                                     "traffic": profiled_traffic(PROFILE_FREE)}}}
+                                     "traffic": None if timed else profiled_traffic(PROFILE_FREE)}}}
     if cpu:
-        res["evaluate"]["cpu_baseline"] = free_cpu_baseline(batch)
+        res["evaluate"]["cpu_baseline"] = free_cpu_baseline(batch, timed=timed)
     return res
 
 
-def free_cpu_baseline(batch, seconds_target=10.0):
+def free_cpu_baseline(batch, seconds_target=10.0, timed=False):
     """Free-motion oracle (FP64, plain C, one order per thread over all host threads) on an
     evenly strided sample of the batch; returns solves/s."""
     from oracle import free as F
@@ -397,7 +413,7 @@ def free_cpu_baseline(batch, seconds_target=10.0):
         sub = {k: v[idx] for k, v in batch.items()}
         t0 = time.perf_counter()
         F.evaluate(f32(sub["x0"]), f32(sub["goal"]), f32(sub["inst"]), sub["nseg"], sub["modes"], sub["knots"],
-                   nthreads=n_threads)
+                   nthreads=n_threads, timed=timed)
         return time.perf_counter() - t0
 
     n = 4 * n_threads
@@ -651,6 +667,7 @@ def main():
     ap.add_argument("--no-timed", action="store_true", help="skip the optimised-timing pushing leg")
     ap.add_argument("--no-scale", action="store_true", help="skip the expansion legs at the configured scale")
     ap.add_argument("--no-free", action="store_true", help="skip the free-motion pushing leg")
+    ap.add_argument("--no-free-timed", action="store_true", help="skip the free-motion leg with optimised timing")
     ap.add_argument("--no-free-planner", action="store_true",
                     help="free-motion leg: the evaluator launch only, not the four planner configurations")
     ap.add_argument("--copy-probe", action="store_true",
@@ -754,6 +771,8 @@ def main():
             ("flip_expand_scale", not args.no_scale, lambda: flip_expand_scale_leg(native, I, torch)),
             ("free", not args.no_free, lambda: free_leg(native, I, torch, cpu=not args.no_cpu,
                                                         planner=not args.no_free_planner)),
+            ("free_timed", not args.no_free_timed, lambda: free_leg(native, I, torch, cpu=not args.no_cpu,
+                                                                    planner=not args.no_free_planner, timed=True)),
             ("learned", not args.no_learned, lambda: learned_leg(native, I, torch)),
             ("learned_flip", not args.no_learned, lambda: learned_flip_leg(native, I, torch)),
             ("cpu_baseline", not args.no_cpu, lambda: cpu_baseline(batch))]

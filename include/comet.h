@@ -88,7 +88,7 @@ void comet_default_params(comet_solver_params* p);
 /* Create a context for one task on the current HIP device.  Allocates the device work
  * space for up to max_batch sequences of up to max_segments segments and max_intervals
  * control intervals each (synchronous).  Returns COMET_EINVAL for max_segments outside
- * [1, 6] ([1, 8] for COMET_TASK_PUSH_FREE, whose orders the paper caps at eight segments,
+ * [1, 6] ([1, 8] for the free-motion tasks, whose orders the paper caps at eight segments,
  * Sec. IV-A), max_intervals outside [1, 512] or max_batch < 1, COMET_ENOMEM if the work
  * space does not fit. */
 comet_status comet_create(comet_task task, const comet_solver_params* params, int64_t max_batch,
@@ -187,7 +187,15 @@ comet_status comet_check(comet_ctx* ctx, void* stream);
  *   cost  sum 0.1 ((F_n^2 + F_t^2) / f_max^2 + |v|^2 / v_ref^2)
  *   traj  [B, Nmax+1, 9] rows (x_k, u_k); warm likewise.  The schedule-derived start puts
  *                 the pusher at the centre of the scheduled face during a contact segment
- *                 and 2 cm in front of the face during a free segment. */
+ *                 and 2 cm in front of the face during a free segment.
+ *
+ * Pushing with free motion and optimised timing (COMET_TASK_PUSH_FREE_TIMED; the paper's
+ * pushing transcription optimises the time step, Sec. IV-A): the free-motion task with the
+ * duration h_k of every interval as a fifth control, u = (F_n, F_t, v_x, v_y, h); every
+ * defect steps by h_k, each interval carries 0.02 s <= h_k <= 0.2 s, cost = sum h_k
+ * ((F_n^2 + F_t^2) / f_max^2 + |v|^2 / v_ref^2 + 0.01); the start has h_k = 0.1 s and the
+ * same language, segment cap and keys as COMET_TASK_PUSH_FREE.
+ *   traj  [B, Nmax+1, 10] rows (x_k, u_k); warm likewise. */
 comet_status comet_evaluate(comet_ctx* ctx, void* stream, int64_t B, const float* x0, const float* goal,
                             const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                             const float* warm, int32_t refine, float* cost, float* viol, uint8_t* feasible,
