@@ -77,6 +77,7 @@ KERNEL_SOURCES = ["paper_2609_21803_amd/csrc/evaluator.hip", "paper_2609_21803_a
 PROFILE = os.path.join(ROOT, "profiles", "k_push_solve_push_plain_110592.txt")
 PROFILE_TIMED = os.path.join(ROOT, "profiles", "k_push_solve_timed_push_plain_110592.txt")
 PROFILE_FREE = os.path.join(ROOT, "profiles", "k_push_solve_free_118080.txt")
+PROFILE_FREE_TIMED = os.path.join(ROOT, "profiles", "k_push_solve_free_timed_118080.txt")
 FLIP_SOURCES = ["paper_2609_21803_amd/csrc/flip.hip", "paper_2609_21803_amd/csrc/dmath.h"]
 PROFILE_FLIP = os.path.join(ROOT, "profiles", "k_flip_solve_flip_32768.txt")
 
@@ -394,7 +395,7 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
                                      (", optimised timing)" if timed else ")"), "achieved": ach,
                                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
                                      "kernel_ms": kms, "flop_per_launch": flops,
-                                     "traffic": None if timed else profiled_traffic(PROFILE_FREE)}}}
+                                     "traffic": profiled_traffic(PROFILE_FREE_TIMED if timed else PROFILE_FREE)}}}
     if cpu:
         res["evaluate"]["cpu_baseline"] = free_cpu_baseline(batch, timed=timed)
     return res
