@@ -291,11 +291,14 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
     and the oracle's rate on a strided sample.  planner=False runs only the seed pass that
     lists the orders of at most six segments (two intervals per segment) before the
     evaluator launch.  timed=True: the same with optimised timing (the interval durations
-    as controls with bounds, the paper's pushing transcription), the evaluator launch with
-    50 intervals per order."""
+    as controls with bounds, the paper's pushing transcription), the planner with the
+    paper's budgets of that transcription (t_exp = 300 and t_ref = 1,500 iterations per
+    candidate: at most 30 x 10 and 60 x 25 Gauss-Newton iterations), the evaluator launch
+    with 50 intervals per order at the exploration budget of the other tasks."""
     full = 205632
     task = native.TASK_PUSH_FREE_TIMED if timed else native.TASK_PUSH_FREE
-    ctx = native.Context(max_batch=full, max_segments=8, max_intervals=80, task=task)
+    budgets = native.SolverParams(al_max=30, gn_max=10, ref_al_max=60, ref_gn_max=25) if timed else None
+    ctx = native.Context(max_batch=full, max_segments=8, max_intervals=80, task=task, params=budgets)
     common = dict(kcap=8, radius=2, knots_per_segment=0, n_total=50, k_ref=256)   # the paper's 50 knots per order
     configs = {"full_enumeration": native.ExpandParams(**common, seed_max_segments=8, rounds=0, frontier_W=1,
                                                          batch_B=full, eval_budget=full),
@@ -386,7 +389,9 @@ def free_leg(native, I, torch, seeds=(5300, 5301, 5302, 5303), n_eval_inst=8, cp
                        f"{full} admissible orders, {n1} of <= 6); planner configurations with 50 intervals per order "
                        f"on the goals of seeds {seeds[0]}..{seeds[-1]}; evaluator on all {n1} orders of <= 6 segments x "
                        f"{n_eval_inst} instances (seed 5400), " + ("50 intervals per order" if timed else
-                                                                    "10 intervals per segment"),
+                                                                    "10 intervals per segment") +
+                       ("; planner budgets t_exp = 300 (30 x 10), t_ref = 1,500 (60 x 25) Gauss-Newton iterations"
+                        if timed else ""),
            "planner_summary": summary, "planner": rows,
            "evaluate": {"orders": n, "value": n / (ms * 1e-3), "unit": "solves/s", "ms": ms,
                         "mean_intervals": float(N.mean()), "mean_gn_iterations": float(st[:, 1].mean()),
