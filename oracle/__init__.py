@@ -5,8 +5,11 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 the HIP library in ``paper_2609_21803_amd`` and never imports it.
 
 The numerical work lives in ``comet_oracle.c`` (plain C, FP64, ``-ffp-contract=off``);
-this module only marshals NumPy arrays through ctypes.  ``mlp.py`` holds the NumPy
-oracle of the learned proposal network.
+this module only marshals NumPy arrays through ctypes.  Beside it: ``flip.py`` /
+``flip_oracle.c`` (bimanual flipping), ``free.py`` / ``free_oracle.c`` (pushing with free
+motion, built with and without optimised timing), ``sample.py`` and ``mcts.py`` (the
+ablations' allocation policies) and ``mlp.py`` (the NumPy oracle of the learned proposal
+network).
 """
 from __future__ import annotations
 
