@@ -356,8 +356,8 @@ typedef struct {
  * and left to the free region in front of face j, and free regions connect to the regions
  * of the neighbouring faces (Sec. III-A); the seed and every generated neighbour are
  * filtered by it, and a two-edit neighbour only through an admissible one-edit order.
- * The learned network serves the pushing, timed-pushing and flipping tasks (EINVAL with
- * free motion).  The loop runs as one captured HIP graph on an internal
+ * The learned network serves every task (its encoding and warm-start block must be wide
+ * enough for the task: see comet_mlp_encode).  The loop runs as one captured HIP graph on an internal
  * stream ordered after `stream`; the call synchronises and fills `stats` (host).  Outputs
  * (device): best_nseg [1] (0 = no feasible plan), best_modes / best_knots [max_segments],
  * best_cost / best_viol [1] (refined), best_traj [max_intervals+1, nx+nu] or NULL.
@@ -390,10 +390,14 @@ comet_status comet_expand_trace(comet_ctx* ctx, void* stream, int64_t cap, uint6
 /* ---------------------------------------------------------------------------------
  * Learned proposal / warm-start network (BF16 matrix-core kernels, FP32 accumulation).
  * in_dim -> `layers` hidden layers of width `hidden` (exact-erf GELU) -> out_dim.  Output
- * row: [0] feasibility logit, [1] predicted log(1 + J), [2 .. 2 + 720) warm start: for
- * each of 6 segment slots, 15 samples at normalised times i/14 of 8 channels (pushing: the
- * 7 trajectory channels (x, y, theta, s, F_n, F_t, v_s) and a zero channel; timed pushing:
- * the same with the interval duration as channel 7; flipping: the 8 states).  Flat parameter
+ * row: [0] feasibility logit, [1] predicted log(1 + J), [2 .. 2 + 120 S) warm start: for
+ * each of S = min(8, (out_dim - 2) / 120) segment slots, 15 samples at normalised times
+ * i/14 of 8 channels (pushing: the 7 trajectory channels (x, y, theta, s, F_n, F_t, v_s)
+ * and a zero channel; timed pushing: the same with the interval duration as channel 7;
+ * flipping: the 8 states; free motion: (x, y, theta, p_x, p_y, F_n, F_t) and, with
+ * optimised timing, the duration as channel 7).  A network for the pushing, timed-pushing
+ * and flipping tasks has S = 6 (out_dim 736: 722 padded to a multiple of 8), for free
+ * motion S = 8 (out_dim >= 962, e.g. 968).  Flat parameter
  * layout: for each linear layer in order, W [out][in] row-major then b [out] (FP32).
  * Initialisation: W ~ U(-1/sqrt(in), 1/sqrt(in)) from a counter-based hash of (seed, index),
  * b = 0.  Training: AdamW (beta 0.9 / 0.999, eps 1e-8) on FP32 masters; GEMM operands
@@ -414,34 +418,42 @@ comet_status comet_mlp_grads(comet_mlp* mlp, void* stream, float* flat);
 /* out [B, out_dim] = network(x [B, in_dim] BF16 bits), B <= max_batch */
 comet_status comet_mlp_forward(comet_mlp* mlp, void* stream, int64_t B, const uint16_t* x_bf16, float* out);
 /* One AdamW step on a batch: y_feas [B] in {0,1}, y_cost [B] (log(1+J), used where feasible),
- * y_traj / traj_mask [B, 720] (outputs beyond 2 + 720 get no gradient; y_traj 8-byte and
- * traj_mask 16-byte aligned, B * out_dim < 2^31, else COMET_EINVAL).  out_dim >= 722.
+ * y_traj / traj_mask [B, 120 S] with S the network's warm-start segments (outputs beyond
+ * 2 + 120 S get no gradient; y_traj 8-byte and traj_mask 16-byte aligned, B * out_dim <
+ * 2^31, else COMET_EINVAL).
  * loss (device, 3 floats, may be NULL): mean BCE,
  * cost MSE over feasible samples, warm-start MSE over the mask, before the step. */
 comet_status comet_mlp_train_step(comet_mlp* mlp, void* stream, int64_t B, const uint16_t* x_bf16,
                                   const float* y_feas, const float* y_cost, const float* y_traj,
                                   const float* traj_mask, float lr, float weight_decay, float* loss);
 /* Input encoding of orders (same arguments as comet_evaluate, Smax = smax) into in_dim
- * (>= 400) BF16 values per order, a pose block of 16 then 6 segment slots of 64 (absent
- * segments all zero, values beyond 400 zero).
+ * BF16 values per order, a pose block of 16 then S segment slots of 64 (absent segments
+ * all zero, values beyond 16 + 64 S zero): S = 6 and in_dim >= 400, smax <= 6 (pushing,
+ * timed pushing, flipping), S = 8 and in_dim >= 528, smax <= 8 (free motion).
  *   COMET_TASK_PUSH: pose = start and goal (x, y, cos, sin), goal - start (x, y, theta),
  *     pusher friction; slot = one-hot mode id (12), intervals / 15, present flag.
  *   COMET_TASK_FLIP: pose = start (px, py, cos, sin), goal (px, 0, cos, sin), goal - start
  *     (px, 0, theta), table friction; slot = one-hot finger-1 code (13), one-hot finger-2
  *     code (13), one-hot table mode (5), intervals / 15, present flag.
  *   COMET_TASK_PUSH_TIMED: as COMET_TASK_PUSH.
+ *   COMET_TASK_PUSH_FREE, COMET_TASK_PUSH_FREE_TIMED: the pushing pose block and the
+ *     pusher's start position (p_x, p_y) at 12 and 13; slot = one-hot mode id (16),
+ *     intervals / 15, present flag.
  * The network proposes orders and warm starts; it is an addition to the paper's method
  * (the paper has no learned component), so no passage defines it.  Other tasks: COMET_EINVAL. */
 comet_status comet_mlp_encode(comet_task task, void* stream, int64_t B, const float* x0, const float* goal,
                               const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                               int32_t smax, int32_t in_dim, uint16_t* x_bf16);
 /* Training targets from evaluator results (traj [B, nmax+1, row] in comet_evaluate's
- * layout, row = 7 pushing / 8 timed pushing / 17 flipping; feasible; cost): y_feas, y_cost = log(1 + J)
- * (0 if infeasible), y_traj [B, 720] per-segment samples (6 slots x 15 times i/14 x 8
- * channels) by linear interpolation of the rows, traj_mask [B, 720] = 1 on the learned
- * channels of present segments of feasible orders.  Learned channels: pushing, the 7 row
- * entries (channel 7 zero); timed pushing, the 8 row entries (channel 7 the duration);
- * flipping, the 8 state entries.  A sequence whose segment count is outside [1, smax], or
+ * layout, row = 7 pushing / 8 timed pushing / 17 flipping / 9 free motion / 10 free motion
+ * with optimised timing; feasible; cost): y_feas, y_cost = log(1 + J) (0 if infeasible),
+ * y_traj [B, 120 S] per-segment samples (S slots x 15 times i/14 x 8 channels; S = 6, or 8
+ * for free motion, with smax <= S) by linear interpolation of the rows, traj_mask [B, 120 S]
+ * = 1 on the learned channels of present segments of feasible orders.  Learned channels:
+ * pushing, the 7 row entries (channel 7 zero); timed pushing, the 8 row entries (channel 7
+ * the duration); flipping, the 8 state entries; free motion, row entries 0..6 (states and
+ * forces; channel 7 zero), with optimised timing also the duration (row entry 9) as
+ * channel 7.  A sequence whose segment count is outside [1, smax], or
  * whose live knot counts are not each >= 1 with a sum <= nmax, is treated as empty: its
  * y_traj and traj_mask rows are zero. */
 comet_status comet_mlp_targets(comet_task task, void* stream, int64_t B, const float* traj, int32_t nmax,
@@ -458,8 +470,13 @@ comet_status comet_mlp_targets(comet_task task, void* stream, int64_t B, const f
  *     differences over dt = 0.1 s, a contact finger pushes with mg/2 normal force (a
  *     sliding one on its cone edge in the slip direction), a free finger zero; the last
  *     row's controls are zero.
- * A sequence with invalid segment or knot counts (as for comet_mlp_targets) gets zero rows
- * with x0 in row 0. */
+ *   COMET_TASK_PUSH_FREE (row 9), COMET_TASK_PUSH_FREE_TIMED (row 10): states and forces
+ *     interpolated (with optimised timing also the duration, entry 9, clamped to
+ *     [0.02, 0.2] s), row 0 takes x0; the pusher velocity of interval k is
+ *     (p_{k+1} - p_k) / h_k of the decoded positions (h_k = 0.1 s with the fixed step);
+ *     the last row's controls are zero.  `modes` may be NULL.  out_dim >= 962.
+ * For the other tasks out_dim >= 722.  A sequence with invalid segment or knot counts (as
+ * for comet_mlp_targets) gets zero rows with x0 in row 0. */
 comet_status comet_mlp_decode_warm(comet_task task, void* stream, int64_t B, const float* out, int32_t out_dim,
                                    const float* x0, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                                    int32_t smax, int32_t nmax, float* warm);

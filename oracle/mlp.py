@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  Written from the network's
 definition: in_dim -> `layers` hidden layers (exact-erf GELU) -> out_dim; heads
-[0] feasibility logit, [1] log(1 + J), [2:] warm start (6 segments x 15 samples x 8
-channels); loss = mean BCE + MSE of the cost head over feasible samples + MSE of the warm
+[0] feasibility logit, [1] log(1 + J), [2:] warm start (6 segments, or 8 for free motion,
+x 15 samples x 8 channels); loss = mean BCE + MSE of the cost head over feasible samples + MSE of the warm
 start over its mask; AdamW.
 
 With quantize=True the tensors that the matrix-core kernels take as BF16 operands are
@@ -194,13 +194,46 @@ def encode_flip(x0, goal, inst, nseg, modes, knots, in_dim=416):
     return X
 
 
-def targets(traj, nseg, knots, feas, cost, nch=7):
-    """Warm-start targets: per segment, 15 samples at normalised times i/14 by linear
-    interpolation between trajectory rows of the first `nch` channels (pushing: the 7
-    row entries; flipping: the 8 states); mask on those channels of present segments of
-    feasible orders."""
+FREE_SEGS, FREE_MODES = 8, 16
+
+
+def encode_free(x0, goal, inst, nseg, modes, knots, in_dim=528):
+    """Input encoding of free-motion pushing orders (float32, then BF16): the pushing pose
+    block (x0 holds the slider pose and then the pusher position), the pusher's start
+    position at 12 and 13; per segment (up to eight) a one-hot of the 16 ids, the interval
+    count / 15 at 16 and a presence flag at 17."""
     B = len(nseg)
-    y_traj = np.zeros((B, N_SEG * WS_SLOTS * WS_CH))
+    X = np.zeros((B, in_dim), np.float32)
+    x0 = np.asarray(x0, np.float32)
+    goal = np.asarray(goal, np.float32)
+    inst = np.asarray(inst, np.float32).reshape(B, -1)
+    X[:, 0], X[:, 1] = x0[:, 0], x0[:, 1]
+    X[:, 2], X[:, 3] = np.cos(x0[:, 2]), np.sin(x0[:, 2])
+    X[:, 4], X[:, 5] = goal[:, 0], goal[:, 1]
+    X[:, 6], X[:, 7] = np.cos(goal[:, 2]), np.sin(goal[:, 2])
+    X[:, 8] = goal[:, 0] - x0[:, 0]
+    X[:, 9] = goal[:, 1] - x0[:, 1]
+    X[:, 10] = goal[:, 2] - x0[:, 2]
+    X[:, 11] = inst[:, 0]
+    X[:, 12], X[:, 13] = x0[:, 3], x0[:, 4]
+    for b in range(B):
+        for j in range(int(nseg[b])):
+            base = POSE_DIMS + SEG_SLOT * j
+            X[b, base + int(modes[b, j])] = 1.0
+            X[b, base + FREE_MODES] = np.float32(knots[b, j]) / np.float32(15.0)
+            X[b, base + FREE_MODES + 1] = 1.0
+    return X
+
+
+def targets(traj, nseg, knots, feas, cost, nch=7, n_seg=N_SEG, cols=None):
+    """Warm-start targets: per segment (n_seg slots), 15 samples at normalised times i/14
+    by linear interpolation between trajectory rows of `nch` channels, channel c taken from
+    row column cols[c] (default c; pushing: the 7 row entries; flipping: the 8 states;
+    free motion: the 5 states and 2 forces, with optimised timing the duration, column 9,
+    as channel 7); mask on those channels of present segments of feasible orders."""
+    cols = list(range(nch)) if cols is None else list(cols)
+    B = len(nseg)
+    y_traj = np.zeros((B, n_seg * WS_SLOTS * WS_CH))
     mask = np.zeros_like(y_traj)
     for b in range(B):
         k0 = 0
@@ -211,8 +244,8 @@ def targets(traj, nseg, knots, feas, cost, nch=7):
                 k = min(int(math.floor(p)), max(nj - 1, 0))
                 fr = p - k
                 for c in range(nch):
-                    a0 = traj[b, k0 + k, c]
-                    a1 = traj[b, k0 + min(k + 1, nj), c]
+                    a0 = traj[b, k0 + k, cols[c]]
+                    a1 = traj[b, k0 + min(k + 1, nj), cols[c]]
                     e = (j * WS_SLOTS + i) * WS_CH + c
                     y_traj[b, e] = a0 + fr * (a1 - a0)
                     mask[b, e] = 1.0 if feas[b] else 0.0
@@ -268,4 +301,43 @@ def decode_warm_flip(Y, x0, nseg, modes, knots, nmax):
                     u[3 + 3 * f], u[4 + 3 * f] = fn, ft
                     u[5 + 3 * f] = (xb[6 + f] - xa[6 + f]) / FLIP_DT
                 kk += 1
+    return W
+
+
+FREE_DT, FREE_H_MIN, FREE_H_MAX = 0.1, 0.02, 0.2
+
+
+def decode_warm_free(Y, x0, nseg, knots, nmax, timed=False):
+    """Free-motion warm start from network outputs Y [B, >= 962]: the states (x, y, theta,
+    p_x, p_y) and forces (F_n, F_t) of every knot interpolated linearly from the segment's
+    15 samples (knot k of n at sample position 14 k / n), with optimised timing also the
+    duration (channel 7) clamped to [h_min, h_max]; knot 0 takes the start state; the pusher
+    velocity of interval k is the difference of the decoded pusher positions over the
+    interval's duration (dt with the fixed step), which is what the pusher's defect rows
+    ask; the last knot's controls are zero.  Rows (x_k, u_k) of width 9, or 10 with h."""
+    width = 10 if timed else 9
+    B = len(nseg)
+    W = np.zeros((B, nmax + 1, width))
+    for b in range(B):
+        y = np.asarray(Y[b, 2:2 + FREE_SEGS * WS_SLOTS * WS_CH], np.float64).reshape(FREE_SEGS, WS_SLOTS, WS_CH)
+        k0 = 0
+        for j in range(int(nseg[b])):
+            nj = int(knots[b, j])
+            for k in range(nj + 1):
+                if k0 + k > nmax:
+                    break
+                p = k / nj * (WS_SLOTS - 1) if nj > 0 else 0.0
+                i = min(int(math.floor(p)), WS_SLOTS - 2)
+                fr = p - i
+                v = y[j, i] + fr * (y[j, i + 1] - y[j, i])
+                W[b, k0 + k, :7] = v[:7]
+                if timed:
+                    W[b, k0 + k, 9] = min(max(v[7], FREE_H_MIN), FREE_H_MAX)
+            k0 += nj
+        N = min(k0, nmax)
+        W[b, 0, :5] = x0[b][:5]
+        for k in range(N):
+            h = W[b, k, 9] if timed else FREE_DT
+            W[b, k, 7:9] = (W[b, k + 1, 3:5] - W[b, k, 3:5]) / h
+        W[b, N, 5:] = 0.0
     return W

@@ -1104,10 +1104,12 @@ comet_status comet_expand(comet_ctx* c, void* stream, const float* x0, const flo
   comet_status st = check_expand_params(c, params);
   if (st != COMET_OK) return st;
   const bool flip = (c->task == COMET_TASK_FLIP);
-  if (learned && (mlp_max_batch(learned) < params->batch_B || mlp_in_dim(learned) < 400 || mlp_out_dim(learned) < 722))
-    return fail_msg(c, COMET_EINVAL, "learned network: max_batch < batch_B, in_dim < 400 or out_dim < 722");
-  if (learned && is_free_task(c->task))
-    return fail_msg(c, COMET_EINVAL, "the learned network serves the pushing, timed-pushing and flipping tasks");
+  if (learned && (mlp_max_batch(learned) < params->batch_B || mlp_in_dim(learned) < mlp_task_in_dim(c->task) ||
+                  mlp_warm_segments(learned) < mlp_task_segments(c->task)))
+    return fail_msg(c, COMET_EINVAL,
+                    "learned network: max_batch < batch_B, or in_dim / out_dim too small for the task's encoding "
+                    "(in_dim >= " + std::to_string(mlp_task_in_dim(c->task)) + ", out_dim >= " +
+                        std::to_string(mlp_task_out_dim(c->task)) + ")");
   if (learned && params->policy == COMET_POLICY_MCTS)
     return fail_msg(c, COMET_EINVAL, "the learned network ranks expansion or sampling batches, not MCTS");
   st = ensure_ws(c, params);

@@ -117,6 +117,10 @@ comet_status launch_flip(comet_ctx* c, hipStream_t s, const EvalLaunch& L);
 // learned network hooks (mlp.hip)
 int mlp_in_dim(const comet_mlp* m);
 int mlp_out_dim(const comet_mlp* m);
+int mlp_warm_segments(const comet_mlp* m);   // segments the warm-start block holds
+int mlp_task_segments(int task);             // segments the task's encodings hold (6, free motion 8)
+int mlp_task_in_dim(int task);               // smallest in_dim of the task's encoding
+int mlp_task_out_dim(int task);              // smallest out_dim of the task's warm-start block
 long long mlp_max_batch(const comet_mlp* m);
 const float* mlp_output(const comet_mlp* m);
 void mlp_forward(comet_mlp* m, hipStream_t s, int B, const long long* B_dev);

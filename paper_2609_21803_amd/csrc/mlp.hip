@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "keys.h"
 
 namespace comet {
 
@@ -561,6 +562,54 @@ __global__ void k_encode_flip(long B, const float* x0, const float* goal, const 
   X[i] = to_bf16(v);
 }
 
+// Free-motion pushing orders (up to 8 segments): the pushing pose block (start state with
+// the slider pose, goal, goal - start, pusher friction) plus the pusher's start position
+// (body frame) at 12 and 13, then 8 segment slots of 64: one-hot of the 16 ids, intervals
+// / 15 at 16, presence flag at 17.
+constexpr int FREE_SEGS = 8, FREE_KN = 16, FREE_PRESENT = 17;
+__global__ void k_encode_free(long B, const float* x0, const float* goal, const float* inst, int inst_stride,
+                              const int32_t* nseg, const int32_t* modes, const int32_t* knots, int smax, int in_dim,
+                              bf16* X, const long long* B_dev) {
+  const long Bn = B_dev ? *B_dev : B;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Bn * in_dim) return;
+  const long b = i / in_dim;
+  const int d = (int)(i % in_dim);
+  const long bi = b * inst_stride;
+  float v = 0.f;
+  if (d < POSE_DIMS) {
+    const float sx = x0[bi * 5 + 0], sy = x0[bi * 5 + 1], st = x0[bi * 5 + 2];
+    const float gx = goal[bi * 3 + 0], gy = goal[bi * 3 + 1], gt = goal[bi * 3 + 2];
+    switch (d) {
+      case 0: v = sx; break;
+      case 1: v = sy; break;
+      case 2: v = cosf(st); break;
+      case 3: v = sinf(st); break;
+      case 4: v = gx; break;
+      case 5: v = gy; break;
+      case 6: v = cosf(gt); break;
+      case 7: v = sinf(gt); break;
+      case 8: v = gx - sx; break;
+      case 9: v = gy - sy; break;
+      case 10: v = gt - st; break;
+      case 11: v = inst[bi]; break;
+      case 12: v = x0[bi * 5 + 3]; break;
+      case 13: v = x0[bi * 5 + 4]; break;
+      default: v = 0.f;
+    }
+  } else if (d < POSE_DIMS + FREE_SEGS * SEG_SLOT) {
+    const int j = (d - POSE_DIMS) / SEG_SLOT, q = (d - POSE_DIMS) % SEG_SLOT;
+    const int K = nseg[b];
+    if (j < K && j < smax) {
+      const int m = modes[b * smax + j];
+      if (q < push_free::NMODES) v = (q == m) ? 1.f : 0.f;
+      else if (q == FREE_KN) v = (float)knots[b * smax + j] / 15.f;
+      else if (q == FREE_PRESENT) v = 1.f;
+    }
+  }
+  X[i] = to_bf16(v);
+}
+
 // Segment count of a sequence whose live knot counts are each >= 1 and sum to at most
 // nmax, else 0 (the sequence is then treated as empty).  Counts are compared with the room
 // left, so no sum of large counts can wrap.
@@ -576,12 +625,15 @@ __device__ inline int checked_segments(const int32_t* nseg, const int32_t* knots
   return K;
 }
 
-// Warm-start targets: per segment, 15 samples at normalised times i/14 by linear
-// interpolation of the trajectory rows; channels 0..nch-1 of each row (pushing: the 7
-// state and control entries, flipping: the 8 states), row width `row`.
-__global__ void k_targets(long B, const float* traj, int nmax, int row, int nch, const int32_t* nseg,
-                          const int32_t* knots, int smax, const uint8_t* feas, const float* cost, float* y_feas,
-                          float* y_cost, float* y_traj, float* mask) {
+// Warm-start targets: per segment (nsegs slots: 6, or 8 for free motion), 15 samples at
+// normalised times i/14 by linear interpolation of the trajectory rows; channels
+// 0..nch-1, channel c read from row column c except channel 7 from column col7 (pushing:
+// the 7 state and control entries; timed pushing: the same and the duration; flipping:
+// the 8 states; free motion: the 5 states and the two forces, with optimised timing the
+// duration from column 9), row width `row`.
+__global__ void k_targets(long B, const float* traj, int nmax, int row, int nch, int col7, int nsegs,
+                          const int32_t* nseg, const int32_t* knots, int smax, const uint8_t* feas, const float* cost,
+                          float* y_feas, float* y_cost, float* y_traj, float* mask) {
   const long b = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   const int K = checked_segments(nseg, knots, b, smax, nmax);
@@ -590,7 +642,7 @@ __global__ void k_targets(long B, const float* traj, int nmax, int row, int nch,
   y_cost[b] = feas[b] ? log1pf(fmaxf(cost[b], 0.f)) : 0.f;
   const float* T = traj + b * (long)(nmax + 1) * row;
   int k0 = 0;
-  for (int j = 0; j < 6; ++j) {
+  for (int j = 0; j < nsegs; ++j) {
     const bool live = j < K;
     const int nj = live ? knots[b * smax + j] : 0;
     for (int i = 0; i < WS_SLOTS; ++i) {
@@ -598,10 +650,11 @@ __global__ void k_targets(long B, const float* traj, int nmax, int row, int nch,
       const int k = min((int)floorf(p), max(nj - 1, 0));
       const float fr = p - (float)k;
       for (int c = 0; c < WS_CH; ++c) {
-        const long e = b * (6L * WS_SLOTS * WS_CH) + ((long)j * WS_SLOTS + i) * WS_CH + c;
+        const long e = b * ((long)nsegs * WS_SLOTS * WS_CH) + ((long)j * WS_SLOTS + i) * WS_CH + c;
+        const int col = (c == 7) ? col7 : c;
         float val = 0.f;
         if (live && c < nch) {
-          const float a0 = T[(k0 + k) * row + c], a1 = T[(k0 + min(k + 1, nj)) * row + c];
+          const float a0 = T[(k0 + k) * row + col], a1 = T[(k0 + min(k + 1, nj)) * row + col];
           val = a0 + fr * (a1 - a0);
         }
         y_traj[e] = val;
@@ -701,6 +754,53 @@ __global__ void k_decode_warm_flip(long B, const long long* B_dev, const float* 
   }
 }
 
+// Free-motion warm start: states (x, y, theta, p_x, p_y) and forces (F_n, F_t) interpolated
+// from the network samples at every knot, with optimised timing also the duration
+// (channel 7, clamped to its bounds); the start state at knot 0; the pusher velocity of
+// interval k as the forward difference (p_{k+1} - p_k) / h_k of the decoded positions
+// (h_k = dt with the fixed step), so the pusher defect rows hold; row N has u = 0.
+// Row width 9 (u = F_n, F_t, v_x, v_y) or 10 (and h).
+__global__ void k_decode_warm_free(long B, const long long* B_dev, const float* Y, int O, const float* x0,
+                                   int inst_stride, const int32_t* nseg, const int32_t* knots, int smax, int nmax,
+                                   int timed, float* warm) {
+  const int width = timed ? 10 : 9;
+  const long Bn = B_dev ? *B_dev : B;
+  const long b = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= Bn) return;
+  const int K = checked_segments(nseg, knots, b, smax, nmax);
+  const float* y = Y + b * (long)O + 2;
+  float* Wr = warm + b * (long)(nmax + 1) * width;
+  for (int r = 0; r < (nmax + 1) * width; ++r) Wr[r] = 0.f;
+  int k0 = 0;
+  for (int j = 0; j < K && j < smax; ++j) {
+    const int nj = knots[b * smax + j];
+    for (int k = 0; k <= nj && k0 + k <= nmax; ++k) {
+      const float p = (nj > 0) ? (float)k / (float)nj * (WS_SLOTS - 1) : 0.f;
+      const int i = min((int)floorf(p), WS_SLOTS - 2);
+      const float fr = p - (float)i;
+      for (int c = 0; c < (timed ? 8 : 7); ++c) {
+        const float a0 = y[((long)j * WS_SLOTS + i) * WS_CH + c], a1 = y[((long)j * WS_SLOTS + i + 1) * WS_CH + c];
+        const float val = a0 + fr * (a1 - a0);
+        if (c < 7)
+          Wr[(k0 + k) * width + c] = val;
+        else
+          Wr[(k0 + k) * width + 9] =
+              fminf(fmaxf(val, (float)push_free_timed::H_MIN), (float)push_free_timed::H_MAX);
+      }
+    }
+    k0 += nj;
+  }
+  const int N = min(k0, nmax);
+  for (int c = 0; c < 5; ++c) Wr[c] = x0[b * inst_stride * 5 + c];
+  for (int k = 0; k < N; ++k) {
+    float* r = Wr + k * width;
+    const float h = timed ? r[9] : (float)push_free::DT;
+    r[7] = (r[width + 3] - r[3]) / h;
+    r[8] = (r[width + 4] - r[4]) / h;
+  }
+  for (int c = 5; c < width; ++c) Wr[N * width + c] = 0.f;
+}
+
 }  // namespace comet
 
 // ==================================================================================
@@ -710,6 +810,7 @@ using namespace comet;
 
 struct comet_mlp {
   int in_dim, hidden, layers, out_dim;
+  int wsegs;                           // segments of the warm-start block: min(8, (out_dim - 2) / 120)
   long long max_batch;
   int nl;                              // linear layers = layers + 1
   std::vector<int> K, N;               // per linear layer: in, out
@@ -829,12 +930,9 @@ const float* mlp_output(const comet_mlp* m) { return m->Y; }
 void mlp_encode_dev(comet_mlp* m, int task, hipStream_t s, long long Bmax, const long long* B_dev, const float* x0,
                     const float* goal, const float* inst, int inst_stride, const int32_t* nseg, const int32_t* modes,
                     const int32_t* knots, int smax) {
-  if (task == COMET_TASK_FLIP)
-    hipLaunchKernelGGL(k_encode_flip, dim3(nblk(Bmax * m->in_dim, 256)), dim3(256), 0, s, (long)Bmax, x0, goal, inst,
-                       inst_stride, nseg, modes, knots, smax, m->in_dim, m->H[0], B_dev);
-  else
-    hipLaunchKernelGGL(k_encode_push, dim3(nblk(Bmax * m->in_dim, 256)), dim3(256), 0, s, (long)Bmax, x0, goal, inst,
-                       inst_stride, nseg, modes, knots, smax, m->in_dim, m->H[0], B_dev);
+  auto kern = task == COMET_TASK_FLIP ? k_encode_flip : (is_free_task(task) ? k_encode_free : k_encode_push);
+  hipLaunchKernelGGL(kern, dim3(nblk(Bmax * m->in_dim, 256)), dim3(256), 0, s, (long)Bmax, x0, goal, inst,
+                     inst_stride, nseg, modes, knots, smax, m->in_dim, m->H[0], B_dev);
 }
 
 void mlp_decode_warm_dev(comet_mlp* m, int task, hipStream_t s, long long Bmax, const long long* B_dev,
@@ -843,10 +941,20 @@ void mlp_decode_warm_dev(comet_mlp* m, int task, hipStream_t s, long long Bmax, 
   if (task == COMET_TASK_FLIP)
     hipLaunchKernelGGL(k_decode_warm_flip, dim3(nblk(Bmax, 128)), dim3(128), 0, s, (long)Bmax, B_dev, m->Y,
                        m->out_dim, x0, inst_stride, nseg, modes, knots, smax, nmax, warm);
+  else if (is_free_task(task))
+    hipLaunchKernelGGL(k_decode_warm_free, dim3(nblk(Bmax, 128)), dim3(128), 0, s, (long)Bmax, B_dev, m->Y,
+                       m->out_dim, x0, inst_stride, nseg, knots, smax, nmax,
+                       task == COMET_TASK_PUSH_FREE_TIMED ? 1 : 0, warm);
   else
     hipLaunchKernelGGL(k_decode_warm, dim3(nblk(Bmax, 128)), dim3(128), 0, s, (long)Bmax, B_dev, m->Y, m->out_dim,
                        x0, inst_stride, nseg, knots, smax, nmax, task == COMET_TASK_PUSH_TIMED ? 8 : 7, warm);
 }
+
+// segments of an order and of the warm-start block, and the encoded width, per task
+int mlp_task_segments(int task) { return is_free_task(task) ? FREE_SEGS : 6; }
+int mlp_task_in_dim(int task) { return POSE_DIMS + mlp_task_segments(task) * SEG_SLOT; }
+int mlp_task_out_dim(int task) { return 2 + mlp_task_segments(task) * WS_SLOTS * WS_CH; }
+int mlp_warm_segments(const comet_mlp* m) { return m->wsegs; }
 
 }  // namespace comet
 
@@ -863,6 +971,7 @@ comet_status comet_mlp_create(int32_t in_dim, int32_t hidden, int32_t layers, in
   m->hidden = hidden;
   m->layers = layers;
   m->out_dim = out_dim;
+  m->wsegs = std::min(FREE_SEGS, (out_dim - 2) / (WS_SLOTS * WS_CH));
   m->max_batch = max_batch;
   m->nl = layers + 1;
   long long off = 0, woff = 0;
@@ -1012,7 +1121,7 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
   // the loss kernel reads the warm-start targets in pairs and the mask in fours
   if ((uintptr_t)y_traj % 8 || (uintptr_t)traj_mask % 16) return COMET_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  const int Bi = (int)B, O = m->out_dim, Wn = 6 * WS_SLOTS * WS_CH;
+  const int Bi = (int)B, O = m->out_dim, Wn = m->wsegs * WS_SLOTS * WS_CH;
   if (hipMemcpyAsync(m->H[0], x_bf16, 2 * B * m->in_dim, hipMemcpyDeviceToDevice, s) != hipSuccess) return COMET_EHIP;
   // With B a multiple of 8 the weight gradients contract over batch-contiguous copies of
   // their operands (16-byte loads straight into the matrix-core tiles): the hidden
@@ -1095,50 +1204,63 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
   return hipGetLastError() == hipSuccess ? COMET_OK : COMET_EHIP;
 }
 
+static bool mlp_task_ok(int task) {
+  return task == COMET_TASK_PUSH || task == COMET_TASK_FLIP || task == COMET_TASK_PUSH_TIMED || is_free_task(task);
+}
+
 comet_status comet_mlp_encode(comet_task task, void* stream, int64_t B, const float* x0, const float* goal,
                               const float* inst, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                               int32_t smax, int32_t in_dim, uint16_t* x_bf16) {
-  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP && task != COMET_TASK_PUSH_TIMED) || B < 0 || smax < 1 || smax > 6 ||
-      in_dim < POSE_DIMS + 6 * SEG_SLOT)
+  if (!mlp_task_ok(task) || B < 0 || smax < 1 || smax > mlp_task_segments(task) || in_dim < mlp_task_in_dim(task))
     return COMET_EINVAL;
   if (B == 0) return COMET_OK;   // empty batch: no array is touched, pointers may be NULL
   if (!x0 || !goal || !inst || !nseg || !modes || !knots || !x_bf16) return COMET_EINVAL;
-  if (task == COMET_TASK_FLIP)
-    hipLaunchKernelGGL(k_encode_flip, dim3(nblk(B * in_dim, 256)), dim3(256), 0, (hipStream_t)stream, (long)B, x0,
-                       goal, inst, 1, nseg, modes, knots, smax, in_dim, (bf16*)x_bf16, (const long long*)nullptr);
-  else
-    hipLaunchKernelGGL(k_encode_push, dim3(nblk(B * in_dim, 256)), dim3(256), 0, (hipStream_t)stream, (long)B, x0,
-                       goal, inst, 1, nseg, modes, knots, smax, in_dim, (bf16*)x_bf16, (const long long*)nullptr);
+  auto kern = task == COMET_TASK_FLIP ? k_encode_flip : (is_free_task(task) ? k_encode_free : k_encode_push);
+  hipLaunchKernelGGL(kern, dim3(nblk(B * in_dim, 256)), dim3(256), 0, (hipStream_t)stream, (long)B, x0, goal, inst, 1,
+                     nseg, modes, knots, smax, in_dim, (bf16*)x_bf16, (const long long*)nullptr);
   return hipGetLastError() == hipSuccess ? COMET_OK : COMET_EHIP;
 }
 
 comet_status comet_mlp_targets(comet_task task, void* stream, int64_t B, const float* traj, int32_t nmax,
                                const int32_t* nseg, const int32_t* knots, int32_t smax, const uint8_t* feasible,
                                const float* cost, float* y_feas, float* y_cost, float* y_traj, float* traj_mask) {
-  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP && task != COMET_TASK_PUSH_TIMED) || B < 0 || smax < 1 || smax > 6 || nmax < 1) return COMET_EINVAL;
+  if (!mlp_task_ok(task) || B < 0 || smax < 1 || smax > mlp_task_segments(task) || nmax < 1) return COMET_EINVAL;
   if (B == 0) return COMET_OK;   // empty batch: no array is touched, pointers may be NULL
   if (!traj || !nseg || !knots || !feasible || !cost || !y_feas || !y_cost || !y_traj || !traj_mask)
     return COMET_EINVAL;
-  // trajectory row width and the channels sampled: pushing (x, u) 7, timed pushing 8 (with
-  // the duration), flipping the 8 states of a 17-wide row
-  const int row = task == COMET_TASK_FLIP ? 17 : (task == COMET_TASK_PUSH_TIMED ? 8 : 7);
-  const int nch = task == COMET_TASK_PUSH ? 7 : 8;
+  // trajectory row width, the channels sampled and the column of channel 7: pushing (x, u)
+  // 7 channels; timed pushing 8 (with the duration); flipping the 8 states of a 17-wide
+  // row; free motion the 5 states and 2 forces of a 9-wide row, with optimised timing also
+  // the duration from column 9 of a 10-wide row
+  int row = 7, nch = 7, col7 = 7;
+  switch (task) {
+    case COMET_TASK_FLIP: row = 17; nch = 8; break;
+    case COMET_TASK_PUSH_TIMED: row = 8; nch = 8; break;
+    case COMET_TASK_PUSH_FREE: row = 9; break;
+    case COMET_TASK_PUSH_FREE_TIMED: row = 10; nch = 8; col7 = 9; break;
+    default: break;
+  }
   hipLaunchKernelGGL(k_targets, dim3(nblk(B, 128)), dim3(128), 0, (hipStream_t)stream, (long)B, traj, nmax, row, nch,
-                     nseg, knots, smax, feasible, cost, y_feas, y_cost, y_traj, traj_mask);
+                     col7, mlp_task_segments(task), nseg, knots, smax, feasible, cost, y_feas, y_cost, y_traj,
+                     traj_mask);
   return hipGetLastError() == hipSuccess ? COMET_OK : COMET_EHIP;
 }
 
 comet_status comet_mlp_decode_warm(comet_task task, void* stream, int64_t B, const float* out, int32_t out_dim,
                                    const float* x0, const int32_t* nseg, const int32_t* modes, const int32_t* knots,
                                    int32_t smax, int32_t nmax, float* warm) {
-  if ((task != COMET_TASK_PUSH && task != COMET_TASK_FLIP && task != COMET_TASK_PUSH_TIMED) || B < 0 || smax < 1 || smax > 6 || nmax < 1 ||
-      out_dim < 2 + 6 * WS_SLOTS * WS_CH)
+  if (!mlp_task_ok(task) || B < 0 || smax < 1 || smax > mlp_task_segments(task) || nmax < 1 ||
+      out_dim < mlp_task_out_dim(task))
     return COMET_EINVAL;
   if (B == 0) return COMET_OK;   // empty batch: no array is touched, pointers may be NULL
   if (!out || !x0 || !nseg || !knots || !warm || (task == COMET_TASK_FLIP && !modes)) return COMET_EINVAL;
   if (task == COMET_TASK_FLIP)
     hipLaunchKernelGGL(k_decode_warm_flip, dim3(nblk(B, 128)), dim3(128), 0, (hipStream_t)stream, (long)B,
                        (const long long*)nullptr, out, out_dim, x0, 1, nseg, modes, knots, smax, nmax, warm);
+  else if (is_free_task(task))
+    hipLaunchKernelGGL(k_decode_warm_free, dim3(nblk(B, 128)), dim3(128), 0, (hipStream_t)stream, (long)B,
+                       (const long long*)nullptr, out, out_dim, x0, 1, nseg, knots, smax, nmax,
+                       task == COMET_TASK_PUSH_FREE_TIMED ? 1 : 0, warm);
   else
     hipLaunchKernelGGL(k_decode_warm, dim3(nblk(B, 128)), dim3(128), 0, (hipStream_t)stream, (long)B,
                        (const long long*)nullptr, out, out_dim, x0, 1, nseg, knots, smax, nmax,

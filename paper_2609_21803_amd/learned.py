@@ -53,14 +53,69 @@ def flip_seed_keys(ctx: native.Context, kcap: int = 2, knots: int = 10):
     return keys.clone()
 
 
-def decode_keys(keys, smax: int = 6):
-    """Order keys (3 bits K at 60, ten bits per mode from bit 50 down) -> nseg, modes."""
+def decode_keys(keys, smax: int = 6, bits: int = 10):
+    """Order keys (the segment count at bit 60, then `bits` bits per mode id from bit
+    60 - bits down: 10 for pushing, timed pushing and flipping, 4 for free motion) ->
+    nseg, modes."""
     import torch
     nseg = (keys >> 60).to(torch.int32)
-    shifts = torch.tensor([50 - 10 * j for j in range(smax)], device=keys.device, dtype=torch.int64)
-    modes = ((keys[:, None] >> shifts[None, :]) & 1023).to(torch.int32)
+    shifts = torch.tensor([60 - bits * (j + 1) for j in range(smax)], device=keys.device, dtype=torch.int64)
+    modes = ((keys[:, None] >> shifts[None, :]) & ((1 << bits) - 1)).to(torch.int32)
     modes = torch.where(torch.arange(smax, device=keys.device)[None, :] < nseg[:, None], modes, 0)
     return nseg, modes
+
+
+def split_knots(nseg, smax: int, n_total: int):
+    """n_total intervals per order split evenly over its segments, one more for each of the
+    first n_total mod K (the expansion's allocation when knots_per_segment is 0)."""
+    import torch
+    j = torch.arange(smax, device=nseg.device)[None, :]
+    K = nseg.clamp(min=1)[:, None]
+    return torch.where(j < nseg[:, None], n_total // K + (j < n_total % K).to(K.dtype), 0).to(torch.int32)
+
+
+def generate_free(n_instances: int, per_instance: int, seed: int = 6000, ctx: native.Context | None = None,
+                  kcap: int = 8, n_total: int = 50, chunk: int = 16384):
+    """Free-motion training data: on each seeded start/goal pair (``push_free_pairs``),
+    `per_instance` distinct admissible orders of up to kcap segments drawn by the device's
+    uniform sampler (each segment count equally likely, then every admissible order of
+    that count), n_total intervals per order split evenly; every order is solved by the
+    evaluator and turned into (X, targets) on the GPU.  `ctx` fixes the task (free motion
+    with the fixed step or with optimised timing)."""
+    import torch
+    ctx = ctx or native.Context(max_batch=chunk, max_segments=8, max_intervals=n_total, task=native.TASK_PUSH_FREE)
+    task = ctx.task
+    B = min(chunk, ctx.max_batch, per_instance)
+    prm = native.ExpandParams(kcap=kcap, seed_max_segments=1, radius=1, rounds=(per_instance + B - 1) // B + 8,
+                              frontier_W=1, knots_per_segment=0, n_total=n_total, k_ref=0, batch_B=B,
+                              eval_budget=per_instance, policy=native.POLICY_UNIFORM, sample_draws=4 * B)
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
+    x0, goal, inst = I.push_free_pairs(seed, n_instances)
+    in_dim, _ = native.mlp_dims(task)
+    W = 120 * native.mlp_segments(task)
+    parts = []
+    for i in range(n_instances):
+        prm.sample_seed = seed * 1000 + i
+        native.expand(ctx, f32(x0[i]), f32(goal[i]), f32(inst[i]), prm)
+        keys = native.expand_trace(ctx)[0].clone()
+        nseg, modes = decode_keys(keys, smax=ctx.max_segments, bits=4)
+        kn = split_knots(nseg, ctx.max_segments, n_total)
+        n = int(keys.shape[0])
+        X = torch.empty((n, in_dim), dtype=torch.int16, device="cuda")
+        yf, yc = torch.empty(n, device="cuda"), torch.empty(n, device="cuda")
+        yt, mk = torch.empty((n, W), device="cuda"), torch.empty((n, W), device="cuda")
+        for s in range(0, n, ctx.max_batch):
+            e = min(n, s + ctx.max_batch)
+            d = dict(x0=f32(x0[i])[None].expand(e - s, -1).contiguous(),
+                     goal=f32(goal[i])[None].expand(e - s, -1).contiguous(),
+                     inst=f32(inst[i]).reshape(1, 1).expand(e - s, 1).contiguous(), nseg=nseg[s:e].contiguous(),
+                     modes=modes[s:e].contiguous(), knots=kn[s:e].contiguous())
+            out = ctx.evaluate(**d)
+            X[s:e] = native.mlp_encode(d, task=task)
+            yf[s:e], yc[s:e], yt[s:e], mk[s:e] = native.mlp_targets(d, out, ctx.max_intervals, task=task)
+        parts.append((X, yf, yc, yt, mk))
+    cat = lambda k: torch.cat([p[k] for p in parts])
+    return dict(X=cat(0), y_feas=cat(1), y_cost=cat(2), y_traj=cat(3), mask=cat(4))
 
 
 def generate_flip(n_instances: int, seed: int = 5000, ctx: native.Context | None = None, kcap: int = 2,
@@ -167,13 +222,19 @@ def auc(score, label) -> float:
     return float((ranks[label].sum() - npos * (npos + 1) / 2) / (npos * nneg))
 
 
-def feasibility_auc(mlp: native.MLP, keys, feasible, x0, goal, inst, knots_per_segment: int, task=native.TASK_PUSH):
+def feasibility_auc(mlp: native.MLP, keys, feasible, x0, goal, inst, knots_per_segment: int, task=native.TASK_PUSH,
+                    n_total: int = 0):
     """AUC of the network's feasibility logit over evaluated orders (keys on the device) of one
-    instance, against the evaluator's flags."""
+    instance, against the evaluator's flags (knots_per_segment <= 0: n_total intervals split
+    evenly, as the expansion allocates them)."""
     import torch
     n = int(keys.shape[0])
-    nseg, modes = decode_keys(keys)
-    kn = torch.where(modes.new_ones(modes.shape).cumsum(1) <= nseg[:, None], knots_per_segment, 0).to(torch.int32)
+    S = native.mlp_segments(task)
+    nseg, modes = decode_keys(keys, smax=S, bits=4 if S == 8 else 10)
+    if knots_per_segment > 0:
+        kn = torch.where(modes.new_ones(modes.shape).cumsum(1) <= nseg[:, None], knots_per_segment, 0).to(torch.int32)
+    else:
+        kn = split_knots(nseg, S, n_total)
     f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32)).cuda()
     logits = []
     for s in range(0, n, mlp.max_batch):

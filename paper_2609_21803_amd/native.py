@@ -414,9 +414,23 @@ class MLP:
         return loss
 
 
-def mlp_encode(d: dict, in_dim=416, task=TASK_PUSH):
+def mlp_segments(task) -> int:
+    """Segments an encoding and a warm-start block hold: 8 for free motion, else 6."""
+    return 8 if task in (TASK_PUSH_FREE, TASK_PUSH_FREE_TIMED) else 6
+
+
+def mlp_dims(task) -> tuple[int, int]:
+    """(in_dim, out_dim) of a network for the task: 16 + 64 S inputs, 2 + 120 S outputs
+    (S segments), rounded up to multiples of 8."""
+    S = mlp_segments(task)
+    r8 = lambda n: (n + 7) // 8 * 8
+    return (416, 736) if S == 6 else (r8(16 + 64 * S), r8(2 + 120 * S))
+
+
+def mlp_encode(d: dict, in_dim=None, task=TASK_PUSH):
     """Encode device batches (as from to_device) for the network: [B, in_dim] BF16 bits."""
     import torch
+    in_dim = in_dim or mlp_dims(task)[0]
     B = int(d["nseg"].shape[0])
     smax = int(d["modes"].shape[1])
     x = torch.empty((B, in_dim), dtype=torch.int16, device="cuda")
@@ -430,7 +444,8 @@ def mlp_targets(d: dict, out: dict, nmax: int, task=TASK_PUSH):
     B = int(d["nseg"].shape[0])
     smax = int(d["modes"].shape[1])
     f = lambda *s: torch.empty(s, dtype=torch.float32, device="cuda")
-    yf, yc, yt, m = f(B), f(B), f(B, 720), f(B, 720)
+    W = 120 * mlp_segments(task)
+    yf, yc, yt, m = f(B), f(B), f(B, W), f(B, W)
     check(lib().comet_mlp_targets(task, _stream(), B, _ptr(out["traj"]), nmax, _ptr(d["nseg"]), _ptr(d["knots"]), smax,
                                   _ptr(out["feasible"]), _ptr(out["cost"]), _ptr(yf), _ptr(yc), _ptr(yt), _ptr(m)))
     return yf, yc, yt, m

@@ -94,5 +94,11 @@ def test_network_hooks_check_scalars_and_accept_an_empty_batch_on_the_host():
         assert enc(task, 0, smax=7) == EINVAL and enc(task, 0, in_dim=399) == EINVAL
         assert tgt(task, 0, nmax=0) == EINVAL and dec(task, 0, out_dim=721) == EINVAL
         assert enc(task, 4) == EINVAL and tgt(task, 4) == EINVAL and dec(task, 4) == EINVAL   # NULL arrays
-    assert enc(3, 0) == EINVAL and tgt(3, 0) == EINVAL and dec(3, 0) == EINVAL              # unknown task
+    for task in (native.TASK_PUSH_FREE, native.TASK_PUSH_FREE_TIMED):   # eight segments, wider blocks
+        assert enc(task, 0, smax=8, in_dim=528) == OK and tgt(task, 0, smax=8) == OK
+        assert dec(task, 0, out_dim=962) == OK
+        assert enc(task, 0, smax=9, in_dim=528) == EINVAL and enc(task, 0, smax=8, in_dim=527) == EINVAL
+        assert tgt(task, 0, smax=9) == EINVAL and dec(task, 0, out_dim=961) == EINVAL
+        assert enc(task, 4, smax=8, in_dim=528) == EINVAL and dec(task, 4, out_dim=962) == EINVAL
+    assert enc(5, 0) == EINVAL and tgt(5, 0) == EINVAL and dec(5, 0) == EINVAL              # unknown task
     assert L.comet_mlp_forward(None, None, 0, None, None) == EINVAL                          # no network

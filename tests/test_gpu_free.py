@@ -223,8 +223,6 @@ def test_free_invalid_sequences_empty_batch_and_network_hooks():
     ctx.check()                      # the counter was cleared
     e = {k: v[:0] for k, v in native.to_device(b).items()}
     assert ctx.evaluate(**e)["cost"].numel() == 0
-    with pytest.raises(native.CometError):
-        native.mlp_encode(native.to_device(b), task=native.TASK_PUSH_FREE)
 
 
 def test_free_maximum_length_orders_match_oracle():
