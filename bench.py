@@ -9,7 +9,8 @@ CPU oracle timed on a bounded sample of the same workload.
 The learned leg trains the proposal / warm-start network on evaluator results (BF16 matrix
 cores), times its training step and batched inference against the BF16 matrix-core peak,
 and compares the device time to the first feasible plan of the plain and the learned
-expansion on held-out instances.
+expansion on held-out instances (pushing, flipping, and pushing with free motion in the
+paper's s_max = 1 configuration).
 
 The flipping leg times one round of the bimanual-flipping workload (32,768 orders); the
 timed leg runs the headline orders with optimised timing (interval durations as controls).
@@ -609,6 +610,61 @@ def learned_flip_leg(native, I, torch):
     }
 
 
+def learned_free_leg(native, I, torch):
+    """The learned proposal on pushing with free motion (fixed step): train a network on the
+    evaluator's results of uniformly sampled admissible orders (cap 8, 50 intervals per
+    order) and compare the plain and the learned expansion in the paper's s_max = 1
+    configuration on the free leg's four goals (held out from training)."""
+    from paper_2609_21803_amd import learned
+    task = native.TASK_PUSH_FREE
+    t0 = time.perf_counter()
+    gen = native.Context(max_batch=16384, max_segments=8, max_intervals=50, task=task)
+    data = learned.generate_free(16, 16384, seed=6000, ctx=gen, kcap=8, n_total=50)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    in_dim, out_dim = native.mlp_dims(task)
+    mlp = native.MLP(max_batch=16384, seed=1, in_dim=in_dim, out_dim=out_dim)
+    t0 = time.perf_counter()
+    log = learned.train(mlp, data, steps=800, batch=8192, lr=1e-3, log_every=799)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    prm = native.ExpandParams(kcap=8, radius=2, knots_per_segment=0, n_total=50, k_ref=256, seed_max_segments=6,
+                              rounds=1, frontier_W=1024, batch_B=16384, eval_budget=205632, learned_warm=1)
+    ctx = native.Context(max_batch=16384, max_segments=8, max_intervals=50, task=task)
+    pairs = [tuple(a[0] for a in I.push_free_pairs(sd, 1)) for sd in range(5300, 5304)]
+    rows = learned.compare(ctx, mlp, prm, pairs, trace=True)
+    auc_net, auc_plain = [], []
+    for r, (a, g, m) in zip(rows, pairs):
+        k, J, v = r["plain"].pop("trace")
+        feas = v <= 1e-5
+        auc_net.append(learned.feasibility_auc(mlp, k, feas, a, g, m, 0, task=task, n_total=50))
+        auc_plain.append(learned.auc(-np.arange(len(v), dtype=np.float64), feas))
+    tp = np.array([r["plain"]["t_first_ms"] for r in rows])
+    tl = np.array([r["learned"]["t_first_ms"] for r in rows])
+    ok = (tp > 0) & (tl > 0)
+    same_cost = sum(abs(r["plain"]["cost"] - r["learned"]["cost"]) <= 1e-4 * max(abs(r["plain"]["cost"]), 1e-12)
+                    for r in rows)
+    return {
+        "ttfp_ms_plain_median": float(np.median(tp[ok])) if ok.any() else None,
+        "ttfp_ms_learned_median": float(np.median(tl[ok])) if ok.any() else None,
+        "ttfp_ratio_median": float(np.median(tl[ok] / tp[ok])) if ok.any() else None,
+        "search_ms_median": {"plain": float(np.median([r["plain"]["t_total_ms"] for r in rows])),
+                             "learned": float(np.median([r["learned"]["t_total_ms"] for r in rows]))},
+        "same_returned_cost": f"{same_cost}/{len(rows)}",
+        "learned_cost_minus_plain": [r["learned"]["cost"] - r["plain"]["cost"] for r in rows],
+        "first_feasible_index_median": {"plain": float(np.median([r["plain"]["first_index"] for r in rows])),
+                                        "learned": float(np.median([r["learned"]["first_index"] for r in rows]))},
+        "feasibility_auc": {"network_median": float(np.nanmedian(auc_net)),
+                            "plain_order_median": float(np.nanmedian(auc_plain)),
+                            "over": "every order the plain expansion evaluated on each goal"},
+        "instances": "the free leg's goals (seeds 5300-5303), cap 8, seed <= 6 segments, one round of two-edit "
+                     "neighbours (W = 1,024, batches of 16,384), 50 intervals per order, refinement of 256",
+        "training": {"samples": int(data["X"].shape[0]), "feasible_fraction": float(data["y_feas"].mean()),
+                     "sampling": "16 goals (seed 6000), 16,384 distinct orders each from the uniform sampler",
+                     "steps": 800, "batch": 8192, "gen_s": t_gen, "train_s": t_train, "final_loss": log[-1][1]},
+    }
+
+
 def policy_leg(native, I, torch):
     """Allocation policies on the same evaluator at equal evaluation budgets: Alg. 1's
     expansion vs uniform sampling without replacement (the baseline of Sec. IV-B), time to the
@@ -781,6 +837,8 @@ def main():
                                                                     planner=not args.no_free_planner, timed=True)),
             ("learned", not args.no_learned, lambda: learned_leg(native, I, torch)),
             ("learned_flip", not args.no_learned, lambda: learned_flip_leg(native, I, torch)),
+            ("learned_free", not args.no_learned and not args.no_free,
+             lambda: learned_free_leg(native, I, torch)),
             ("cpu_baseline", not args.no_cpu, lambda: cpu_baseline(batch))]
     for name, on, run in legs:
         if on:
