@@ -9,7 +9,8 @@ fixed step and with optimised timing.
   device expansion: ranking alone leaves the evaluated set and the returned plan exactly
   the plain planner's (the queue order never changes a result) and moves the first
   feasible order forward in the queue; with warm starts the returned plan, re-solved from
-  the plain start, is never worse than the plain planner's.
+  the plain start, is never worse than the plain planner's with the fixed step, and within
+  a few per cent of it with optimised timing.
 """
 import numpy as np
 import pytest
@@ -88,27 +89,34 @@ def test_free_encode_targets_and_decode_match_oracle(timed):
     assert np.all(np.abs(w[:, :, 7:9] - rw[:, :, 7:9]) <= (2e-5 + 2e-6 * pos) / np.maximum(h, 0.02) + 1e-5)
 
 
-def _free_rows(mlp, warm):
+def _free_rows(mlp, warm, task):
     from paper_2609_21803_amd import learned, native
-    ctx = native.Context(max_batch=16384, max_segments=8, max_intervals=24, task=native.TASK_PUSH_FREE)
+    ctx = native.Context(max_batch=16384, max_segments=8, max_intervals=24, task=task)
     prm = native.ExpandParams(kcap=6, seed_max_segments=2, radius=2, rounds=2, frontier_W=1024, knots_per_segment=0,
                               n_total=24, k_ref=64, batch_B=16384, eval_budget=40000, learned_warm=warm)
     x0, goal, inst = I.push_free_pairs(9300, 8)     # held out: the training seeds are 6000+
     return learned.compare(ctx, mlp, prm, list(zip(x0, goal, inst)))
 
 
-def test_free_learned_ranking_keeps_the_plain_plan_and_warm_starts_never_lose():
+@pytest.mark.parametrize("timed", [False, True])
+def test_free_learned_ranking_keeps_the_plain_plan_and_warm_starts_do_not_lose(timed):
+    """Ranking alone: the plain planner's evaluated set, feasible count, order and cost on
+    every goal, and an earlier first feasible order.  With warm starts: with the fixed step
+    a plan no worse than the plain one (1e-4 relative) on every goal; with optimised timing,
+    where a warm start can settle a solve in another local optimum of the durations (as for
+    timed pushing), within 3 % of the plain plan's cost on every goal."""
     from paper_2609_21803_amd import learned, native
-    gen = native.Context(max_batch=16384, max_segments=8, max_intervals=24, task=native.TASK_PUSH_FREE)
+    task = native.TASK_PUSH_FREE_TIMED if timed else native.TASK_PUSH_FREE
+    gen = native.Context(max_batch=16384, max_segments=8, max_intervals=24, task=task)
     data = learned.generate_free(16, 16384, seed=6000, ctx=gen, kcap=6, n_total=24)
     feas = float(data["y_feas"].mean())
-    in_dim, out_dim = native.mlp_dims(native.TASK_PUSH_FREE)
+    in_dim, out_dim = native.mlp_dims(task)
     mlp = native.MLP(max_batch=16384, seed=1, in_dim=in_dim, out_dim=out_dim)
     log = learned.train(mlp, data, steps=800, batch=8192, lr=1e-3, log_every=200)
     print("free training: samples", int(data["X"].shape[0]), "feasible fraction", feas, "loss", log)
     assert log[-1][1][0] < log[0][1][0]
 
-    rows = _free_rows(mlp, warm=0)
+    rows = _free_rows(mlp, 0, task)
     first = []
     for r in rows:
         p, l = r["plain"], r["learned"]
@@ -122,9 +130,19 @@ def test_free_learned_ranking_keeps_the_plain_plan_and_warm_starts_never_lose():
     first = np.array(first)
     assert len(first) >= 4 and np.median(first[:, 1]) < np.median(first[:, 0])
 
-    rows = _free_rows(mlp, warm=1)
+    rows = _free_rows(mlp, 1, task)
+    rel, ratios = [], []
     for r in rows:
         p, l = r["plain"], r["learned"]
         print("warm", p, l)
         if p["modes"]:
-            assert l["modes"] and l["cost"] <= p["cost"] + 1e-4 * abs(p["cost"])
+            assert l["modes"]
+            rel.append((l["cost"] - p["cost"]) / p["cost"])
+        if p["t_first_ms"] > 0 and l["t_first_ms"] > 0:
+            ratios.append(l["t_first_ms"] / p["t_first_ms"])
+    print("warm starts: returned cost learned/plain - 1", rel, "TTFP ratios learned/plain", ratios)
+    assert len(rel) >= 4
+    if timed:
+        assert max(abs(x) for x in rel) <= 0.03
+    else:
+        assert max(rel) <= 1e-4
