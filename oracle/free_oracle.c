@@ -581,7 +581,7 @@ static int g_qscale_ready = 0;
 static pthread_mutex_t g_qscale_lock = PTHREAD_MUTEX_INITIALIZER;
 
 static void q_compute_scales(double *out) {
-  static double buf[QTYPES][256 * 10 * 4 + 8];   /* at most four rows of one type per interval */
+  static double buf[QTYPES][256 * 10 * QNR];     /* at most QNR rows of one type per interval */
   int cnt[QTYPES], t, m1, m2, k, r, j;
   double ones[QTYPES];
   const double x0[QNX] = {0, 0, 0, 0, -0.08}, goal[3] = {0.1, 0.1, M_PI / 4.0};

@@ -1,7 +1,9 @@
 /* Driver for sanitizer builds of the FP64 oracles (test infrastructure, CPU only).
  *
- * Compiled together with one oracle source (-DPUSH includes the pushing oracle, -DFLIP
- * the flipping oracle) under AddressSanitizer + UndefinedBehaviorSanitizer or
+ * Compiled together with one oracle source (-DPUSH includes the pushing oracle, with
+ * -DPUSH_TIMED its optimised-timing problem, -DFLIP
+ * the flipping oracle, -DFREE the free-motion pushing oracle, with -DFREE_TIMED its
+ * optimised-timing build) under AddressSanitizer + UndefinedBehaviorSanitizer or
  * ThreadSanitizer.  Reads a batch from a binary file, solves it with the oracle on
  * `nthreads` threads (and, with `expand` set, runs one greedy expansion on the batch's
  * first instance), and writes the results to a binary file for comparison with the
@@ -10,7 +12,8 @@
  * Input:  int64 B; int32 smax, nmax, nthreads, expand; double x0[B*NXD], goal[B*NGD],
  *         inst[B]; int32 nseg[B], modes[B*smax], knots[B*smax].
  * Output: double cost[B], viol[B]; uint8 feas[B]; int32 stats[B*4]; then, with expand,
- *         uint64 best key; double best J, best v; int64 counters[4].
+ *         uint64 best key; double best J, best v; int64 counters[4] (free motion: int64 n,
+ *         uint64 seed keys[n], int64 m, uint64 batch keys[m]).
  */
 #include <stdio.h>
 #include <stdlib.h>
@@ -23,6 +26,13 @@ typedef OracleParams DrvParams;
 #define EVALUATE oracle_evaluate
 #define EXPAND oracle_expand
 typedef OracleExpandParams DrvExpand;
+#elif defined(FREE)
+/* free-motion pushing; with -DFREE_TIMED the optimised-timing build of the same source */
+#include "../../oracle/free_oracle.c"
+#define NXD 5
+#define NGD 3
+typedef QParams DrvParams;
+#define EVALUATE free_evaluate
 #else
 #include "../../oracle/flip_oracle.c"
 #define NXD 8
@@ -64,6 +74,9 @@ int main(int argc, char **argv) {
   prm.mu0 = 1e-2; prm.mu_min = 1e-4; prm.rho0 = 1e-4; prm.rho_min = 1e-8; prm.rho_max = 1e8;
   prm.armijo_c1 = 1e-4; prm.eta_star = 1e-6; prm.omega_star = 1e-4; prm.rc_star = 1e-6;
   prm.eps_feas = 1e-5; prm.mu0_warm = 1e-4;
+#if defined(PUSH_TIMED)
+  prm.timed = 1;
+#endif
   cost = (double *)calloc((size_t)B, 8);
   viol = (double *)calloc((size_t)B, 8);
   feas = (uint8_t *)calloc((size_t)B, 1);
@@ -77,6 +90,23 @@ int main(int argc, char **argv) {
   fwrite(viol, 8, (size_t)B, g);
   fwrite(feas, 1, (size_t)B, g);
   fwrite(stats, 4, (size_t)B * 4, g);
+#ifdef FREE
+  /* the free-motion oracle has no whole-search driver: with `expand`, its language pieces
+   * instead -- the seed of up to four segments, then one batch step (kcap 6, r = 2, W = 16,
+   * room 4096) on merits (7919 i mod 1000) / 1000 */
+  if (hdr[3]) {
+    uint64_t *sk = (uint64_t *)calloc(2048, 8), *nk = (uint64_t *)calloc(4096, 8);
+    int64_t ns = free_seed(4, 2048, sk), nn, i;
+    double *mer = (double *)calloc((size_t)ns, 8);
+    for (i = 0; i < ns; ++i) mer[i] = (double)((i * 7919) % 1000) / 1000.0;
+    nn = free_expand_next(ns, sk, mer, 6, 2, 16, 4096, nk);
+    fwrite(&ns, 8, 1, g);
+    fwrite(sk, 8, (size_t)ns, g);
+    fwrite(&nn, 8, 1, g);
+    fwrite(nk, 8, (size_t)nn, g);
+    free(sk); free(nk); free(mer);
+  }
+#else
   if (hdr[3]) {
     DrvExpand ep;
     DrvParams ref = prm;
@@ -94,6 +124,7 @@ int main(int argc, char **argv) {
     fwrite(&v, 8, 1, g);
     fwrite(ctr, 8, 4, g);
   }
+#endif
   fclose(g);
   free(x0); free(goal); free(inst); free(nseg); free(modes); free(knots);
   free(cost); free(viol); free(feas); free(stats); free(traj);

@@ -1,5 +1,5 @@
-"""CPU sanitizer runs of the host code: both FP64 oracles (threaded evaluation and the
-greedy expansion) under AddressSanitizer + UndefinedBehaviorSanitizer and under
+"""CPU sanitizer runs of the host code: the FP64 oracles (threaded evaluation and the
+greedy expansion; for free motion, in both of its builds, the seed and a batch step) under AddressSanitizer + UndefinedBehaviorSanitizer and under
 ThreadSanitizer, and the library's host MCTS search (mcts_tree.h) under the same, each on
 a small workload.  The sanitized builds must run clean (any report makes the process exit
 non-zero) and give the results of the plain builds bit for bit; the host MCTS search
@@ -27,8 +27,10 @@ MODES = {"asan": ["-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-r
 
 def _build_oracle(tmp, task, mode):
     exe = os.path.join(tmp, f"oracle_{task}_{mode}")
+    defs = {"free_timed": ["-DFREE", "-DFREE_TIMED"], "push_timed": ["-DPUSH", "-DPUSH_TIMED"]}.get(
+        task, [f"-D{task.upper()}"])
     cmd = ["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off", "-std=gnu11", "-pthread",
-           f"-D{task.upper()}", *MODES[mode], "-o", exe, os.path.join(SAN, "oracle_driver.c"), "-lm"]
+           *defs, *MODES[mode], "-o", exe, os.path.join(SAN, "oracle_driver.c"), "-lm"]
     subprocess.check_call(cmd)
     return exe
 
@@ -43,6 +45,51 @@ def _write(path, b, nthreads, expand, nmax):
             np.ascontiguousarray(f32(b[k])).tofile(f)
         for k in ("nseg", "modes", "knots"):
             np.ascontiguousarray(b[k], np.int32).tofile(f)
+
+
+def _read_free(path, B):
+    raw = open(path, "rb").read()
+    o = 8 * B + 8 * B + B + 16 * B
+    out = _read(path, B, 0)
+    n = int(np.frombuffer(raw, np.int64, 1, o)[0]); o += 8
+    out["seed"] = np.frombuffer(raw, np.uint64, n, o); o += 8 * n
+    m = int(np.frombuffer(raw, np.int64, 1, o)[0]); o += 8
+    out["batch"] = np.frombuffer(raw, np.uint64, m, o)
+    return out
+
+
+@pytest.mark.parametrize("mode", ["asan", "tsan"])
+@pytest.mark.parametrize("timed", [False, True])
+def test_free_oracle_runs_clean_under_sanitizers(tmp_path, timed, mode):
+    """The free-motion oracle (both builds): threaded evaluation of admissible orders of up
+    to four segments, the seed enumeration and one batch-construction step, bit for bit
+    the plain build's results."""
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    from oracle import free as F
+    exe = _build_oracle(str(tmp_path), "free_timed" if timed else "free", mode)
+    keys = F.seed(4)
+    rng = np.random.default_rng(41 + timed)
+    pick = rng.choice(len(keys), 40, replace=False)
+    x0, goal, inst = I.push_free_pairs(8100 + timed, 4)
+    orders = [F.key_modes(int(keys[p])) for p in pick]
+    kn = [[3] * len(o) for o in orders]
+    b = I.orders_batch(x0, goal, inst, np.arange(40) % 4, orders, kn)
+    nmax = 12
+    inp, out = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
+    _write(inp, b, nthreads=4, expand=1, nmax=nmax)
+    r = subprocess.run([exe, inp, out], env=ENV, capture_output=True, text=True, timeout=900)
+    assert r.returncode == 0, r.stderr[-4000:]
+    got = _read_free(out, 40)
+    f32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    ref = F.evaluate(f32(b["x0"]), f32(b["goal"]), f32(b["inst"]), b["nseg"], b["modes"], b["knots"], nmax=nmax,
+                     timed=timed)
+    for k in ("cost", "viol", "feasible", "stats"):
+        assert np.array_equal(got[k], ref[k], equal_nan=True), k
+    assert np.array_equal(got["seed"], keys)
+    merit = (np.arange(len(keys)) * 7919 % 1000) / 1000.0
+    assert np.array_equal(got["batch"], F.expand_next(keys, merit, 6, 2, 16, 4096))
+    assert len(got["batch"]) > 0
 
 
 def _read(path, B, expand):
@@ -61,12 +108,12 @@ def _read(path, B, expand):
 
 
 @pytest.mark.parametrize("mode", ["asan", "tsan"])
-@pytest.mark.parametrize("task", ["push", "flip"])
+@pytest.mark.parametrize("task", ["push", "push_timed", "flip"])
 def test_oracle_runs_clean_under_sanitizers(orc, tmp_path, task, mode):
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
     exe = _build_oracle(str(tmp_path), task, mode)
-    if task == "push":
+    if task.startswith("push"):
         b = I.subset(I.push_tiny(), np.arange(0, 1152, 9))
         nmax = 10
     else:
@@ -78,11 +125,13 @@ def test_oracle_runs_clean_under_sanitizers(orc, tmp_path, task, mode):
     assert r.returncode == 0, r.stderr[-4000:]
     got = _read(out, len(b["nseg"]), 1)
     f32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
-    if task == "push":
-        ref = orc.evaluate(f32(b["x0"]), f32(b["goal"]), f32(b["inst"]), b["nseg"], b["modes"], b["knots"], nmax=nmax)
+    if task.startswith("push"):
+        prm = orc.Params(timed=int(task == "push_timed"))
+        ref = orc.evaluate(f32(b["x0"]), f32(b["goal"]), f32(b["inst"]), b["nseg"], b["modes"], b["knots"], nmax=nmax,
+                           params=prm)
         ep = orc.Expand(kcap=2, seed_max_segments=1, radius=2, rounds=1, frontier_W=8, knots_per_segment=5, k_ref=4,
                         n_total=0, batch_B=300, eval_budget=900)
-        e = orc.expand(f32(b["x0"])[0], f32(b["goal"])[0], f32(b["inst"])[0, 0], ep)
+        e = orc.expand(f32(b["x0"])[0], f32(b["goal"])[0], f32(b["inst"])[0, 0], ep, params=prm)
         ekey, eJ, ectr = e["best_key"], e["best_cost"], [e["evaluated"], e["rounds"], e["n_feasible"],
                                                           e["first_feasible"]]
     else:
