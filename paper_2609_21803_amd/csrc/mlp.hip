@@ -72,7 +72,7 @@ struct Epi {
   long slab;           // EPI_PARTIAL: elements between the partial-sum slabs
   bf16* ht;            // optional (EPI_HIDDEN, EPI_DX): the BF16 output again, transposed: ht[n * ldt + m]
   long ldt;            // row stride of ht (a multiple of 4)
-  float* colpart;      // EPI_DX: column sums of dZ over each wave's 64 rows, row 2 * blockIdx.y + wm,
+  float* colpart;      // EPI_DX: column sums of dZ over each wave's 64 rows, row 2 * (M-tile) + wm,
                        // stride ldc (the layer's bias gradient is their sum; dZ itself is not stored)
 };
 
@@ -131,9 +131,24 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
   __shared__ __attribute__((aligned(16))) bf16 As[2][GBM][GLD];
   __shared__ __attribute__((aligned(16))) bf16 Bs[2][GBN][GLD];
   if (M_dev) M = (int)min((long long)M, *M_dev);
+  // XCD-aware tile order.  The dispatcher places workgroup L (x fastest) on XCD L mod 8, so
+  // with the identity mapping the N-tiles of one M-tile (consecutive L) land on eight
+  // different L2 caches and each re-reads the same A rows from memory.  When the tiles of
+  // a z-plane are a multiple of 8, XCD x takes the contiguous range [x T/8, (x+1) T/8) of
+  // the row-major (M-tile, N-tile) order instead, so the N-tiles of an M-tile share an L2.
+  int bx = blockIdx.x, by = blockIdx.y;
+  {
+    const int nbx = gridDim.x, T = nbx * gridDim.y;
+    if ((T & 7) == 0) {
+      const int L = blockIdx.y * nbx + blockIdx.x;
+      const int q = (L & 7) * (T >> 3) + (L >> 3);
+      bx = q % nbx;
+      by = q / nbx;
+    }
+  }
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int m0 = by * GBM, n0 = bx * GBN;
   if (m0 >= M) return;
   const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
   f32x4 acc[4][2];
@@ -225,7 +240,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
       v += __shfl_xor(v, 16);
       v += __shfl_xor(v, 32);
       const int n = n0 + wn * 32 + j * 16 + lane;
-      if (lane < 16 && n < N) ep.colpart[(long)(2 * blockIdx.y + wm) * ep.ldc + n] = v;
+      if (lane < 16 && n < N) ep.colpart[(long)(2 * by + wm) * ep.ldc + n] = v;
     }
   }
   if (TR && ep.ht) {
