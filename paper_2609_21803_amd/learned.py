@@ -58,7 +58,7 @@ def decode_keys(keys, smax: int = 6, bits: int = 10):
     60 - bits down: 10 for pushing, timed pushing and flipping, 4 for free motion) ->
     nseg, modes."""
     import torch
-    nseg = (keys >> 60).to(torch.int32)
+    nseg = ((keys >> 60) & 15).to(torch.int32)    # keys arrive as int64: K = 8 sets the sign bit
     shifts = torch.tensor([60 - bits * (j + 1) for j in range(smax)], device=keys.device, dtype=torch.int64)
     modes = ((keys[:, None] >> shifts[None, :]) & ((1 << bits) - 1)).to(torch.int32)
     modes = torch.where(torch.arange(smax, device=keys.device)[None, :] < nseg[:, None], modes, 0)
@@ -113,6 +113,7 @@ def generate_free(n_instances: int, per_instance: int, seed: int = 6000, ctx: na
             out = ctx.evaluate(**d)
             X[s:e] = native.mlp_encode(d, task=task)
             yf[s:e], yc[s:e], yt[s:e], mk[s:e] = native.mlp_targets(d, out, ctx.max_intervals, task=task)
+        ctx.check()                      # every sampled order must have been a valid one
         parts.append((X, yf, yc, yt, mk))
     cat = lambda k: torch.cat([p[k] for p in parts])
     return dict(X=cat(0), y_feas=cat(1), y_cost=cat(2), y_traj=cat(3), mask=cat(4))
