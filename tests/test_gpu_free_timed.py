@@ -6,6 +6,7 @@ pushing transcription) against the FP64 oracle built with -DFREE_TIMED, through 
   margin sequences, as for timed pushing), on every admissible order of at most two
   segments, a ragged batch of up to four segments, and a strided sample of every
   admissible order of at most six segments with 50 intervals per order on 8 instances.
+* The same at the planner's budgets of this transcription (exploration and refinement).
 * Row scales equal to the oracle's; closed forms of a free approach and a straight push
   with the durations inside and at both bounds.
 * The expansion in the paper's configuration (cap eight, seed of at most six segments,
@@ -115,6 +116,44 @@ def test_paper_transcription_sampled():
     print("feasible in the launch:", int(g["feasible"].sum()), "sampled oracle / device:", int(o["feasible"].sum()),
           int(g["feasible"][idx].sum()))
     compare({k: v[idx] for k, v in g.items()}, o, sub, "free timed, 50 intervals (1,024 strided)", 50)
+
+
+def test_paper_budgets_sampled():
+    """The planner's budgets of this transcription (t_exp = 300 read as at most 30 x 10
+    Gauss-Newton iterations, t_ref = 1,500 as 60 x 25): the 118,080-order launch at the
+    exploration budget with 1,024 evenly strided sequences checked one by one, and 256
+    strided orders at the refinement budget (comet_evaluate's refine flag)."""
+    import torch
+    import oracle
+    from paper_2609_21803_amd import native
+    orders = _orders(6)
+    x0, goal, inst = I.push_free_pairs(6300, 8)
+    pair = np.repeat(np.arange(8), len(orders))
+    b = I.orders_batch(x0, goal, inst, pair, orders * 8, [_split(len(o)) for o in orders] * 8)
+    n = len(b["nseg"])
+    ctx = native.Context(max_batch=n, max_segments=6, max_intervals=50, task=native.TASK_PUSH_FREE_TIMED,
+                         params=native.SolverParams(al_max=30, gn_max=10, ref_al_max=60, ref_gn_max=25))
+    d = native.to_device(b)
+    for refine, m, prm in ((0, 1024, dict(al_max=30, gn_max=10)), (1, 256, dict(al_max=60, gn_max=25))):
+        idx = np.linspace(0, n - 1, m).astype(np.int64)
+        if refine:
+            sub = I.subset(b, idx)
+            out = ctx.evaluate(**native.to_device(sub), refine=1)
+            sel = slice(None)
+        else:
+            sub = I.subset(b, idx)
+            out = ctx.evaluate(**d)
+            sel = idx
+        torch.cuda.synchronize()
+        ctx.check()
+        g = {k: v.cpu().numpy()[sel] for k, v in out.items() if v is not None}
+        o = run_oracle(sub, 50, oracle.Params(**prm))
+        print(f"budget {prm}: feasible oracle / device {int(o['feasible'].sum())} / {int(g['feasible'].sum())}, "
+              f"mean GN iterations {g['stats'][:, 1].mean():.1f} / {o['stats'][:, 1].mean():.1f}")
+
+        def solve(s2, rows, r32, prm=prm):
+            return run_oracle(s2, 50, oracle.Params(**prm, round32=r32))
+        parity.check(g, o, sub, solve, f"free timed, paper budget {prm}", round32=ROUND32, allow=2e-3)
 
 
 def test_row_scales_agree_with_oracle():
