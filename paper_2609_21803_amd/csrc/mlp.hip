@@ -444,8 +444,17 @@ __global__ __launch_bounds__(256) void k_loss_grad(int B, int O, int Wn, const f
   }
 }
 
-__global__ void k_adamw(float* w, float* m, float* v, const float* g, long n, float lr, float b1, float b2, float eps,
-                        float wd, float bc1, float bc2) {
+// AdamW fused with the BF16 refresh of the weights it updates: one pass over the flat
+// parameter vector; an element of a layer's weight block also writes its BF16 copy and the
+// transposed copy (the values an AdamW pass followed by k_refresh would write).
+constexpr int MAX_LINEAR = 17;   // layers <= 16 hidden, plus the output layer
+struct LayerTable {
+  int nl;
+  long long woff[MAX_LINEAR], boff[MAX_LINEAR], wboff[MAX_LINEAR];
+  int N[MAX_LINEAR], K[MAX_LINEAR];
+};
+__global__ void k_adamw_refresh(float* w, float* m, float* v, const float* g, long n, float lr, float b1, float b2,
+                                float eps, float wd, float bc1, float bc2, LayerTable T, bf16* Wb, bf16* WT) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
@@ -454,7 +463,18 @@ __global__ void k_adamw(float* w, float* m, float* v, const float* g, long n, fl
   m[i] = mi;
   v[i] = vi;
   const float mh = mi / bc1, vh = vi / bc2;
-  w[i] -= lr * (mh / (sqrtf(vh) + eps) + wd * w[i]);
+  const float wn = w[i] - lr * (mh / (sqrtf(vh) + eps) + wd * w[i]);
+  w[i] = wn;
+  int l = 0;
+  while (l + 1 < T.nl && i >= T.woff[l + 1]) ++l;
+  if (i < T.boff[l]) {   // weight block of layer l: W [N][K] row-major
+    const long j = i - T.woff[l];
+    const int K = T.K[l], N = T.N[l];
+    const int r = (int)(j / K), c = (int)(j % K);
+    const bf16 h = to_bf16(wn);
+    Wb[T.wboff[l] + j] = h;
+    WT[T.wboff[l] + (long)c * N + r] = h;
+  }
 }
 
 __global__ void k_zero(float* p, long n) {
@@ -1212,9 +1232,17 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
   m->step += 1;
   const float b1 = 0.9f, b2 = 0.999f;
   const float bc1 = 1.f - std::pow(b1, (float)m->step), bc2 = 1.f - std::pow(b2, (float)m->step);
-  hipLaunchKernelGGL(k_adamw, dim3(nblk(m->n_params, 256)), dim3(256), 0, s, m->P, m->Mm, m->Vv, m->G,
-                     (long)m->n_params, lr, b1, b2, 1e-8f, weight_decay, bc1, bc2);
-  refresh_weights(m, s);
+  LayerTable T{};
+  T.nl = m->nl;
+  for (int l = 0; l < m->nl; ++l) {
+    T.woff[l] = m->woff[l];
+    T.boff[l] = m->boff[l];
+    T.wboff[l] = m->wboff[l];
+    T.N[l] = m->N[l];
+    T.K[l] = m->K[l];
+  }
+  hipLaunchKernelGGL(k_adamw_refresh, dim3(nblk(m->n_params, 256)), dim3(256), 0, s, m->P, m->Mm, m->Vv, m->G,
+                     (long)m->n_params, lr, b1, b2, 1e-8f, weight_decay, bc1, bc2, T, m->Wb, m->WT);
   if (loss && hipMemcpyAsync(loss, m->lossd, 4 * 3, hipMemcpyDeviceToDevice, s) != hipSuccess) return COMET_EHIP;
   return hipGetLastError() == hipSuccess ? COMET_OK : COMET_EHIP;
 }
