@@ -313,6 +313,32 @@ __global__ __launch_bounds__(256) void k_sum_rows(const float* __restrict__ part
   if (ph == 0 && i < n) out[i] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
 }
 
+// A hidden layer's gradients in one launch: blocks [0, nbw) add the weight gradient's
+// split-K slabs as k_sum_slabs does, the remaining blocks add the bias gradient's partial
+// rows as k_sum_rows does (the same summation orders, so the same values).
+__global__ __launch_bounds__(256) void k_sum_grads(const float* __restrict__ slabs, int S, long nw,
+                                                   float* __restrict__ outw, int nbw, const float* __restrict__ rows,
+                                                   int R, long nb, float* __restrict__ outb) {
+  __shared__ float red[4][64];
+  if ((int)blockIdx.x < nbw) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nw) return;
+    float s = 0.f;
+    for (int z = 0; z < S; ++z) s += slabs[(long)z * nw + i];
+    outw[i] = s;
+    return;
+  }
+  const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const long i = (long)(blockIdx.x - nbw) * 64 + c;
+  float s = 0.f;
+  if (i < nb)
+#pragma unroll 8
+    for (int z = ph; z < R; z += 4) s += rows[(long)z * nb + i];
+  red[ph][c] = s;
+  __syncthreads();
+  if (ph == 0 && i < nb) outb[i] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+}
+
 // column sums of an FP32 [M][N] matrix (bias gradients), in two deterministic stages:
 // block (x, y) covers 256 columns (64 threads x 4 consecutive columns, 16-byte loads) and
 // rows y*4 + phase + k * gridDim.y * 4 (4 row phases), writing part[y][n]; k_sum_rows then
@@ -1214,16 +1240,19 @@ comet_status comet_mlp_train_step(comet_mlp* m, void* stream, int64_t B, const u
     const int nzs = tr ? gemm<true, true, EPI_PARTIAL>(m->aux, N, K, Bi, m->GTl[l], m->ldt, m->HT[l], m->ldt, ew,
                                                        nullptr, split)
                        : gemm<false, false, EPI_PARTIAL>(m->aux, N, K, Bi, g, N, m->H[l], K, ew, nullptr, split);
-    hipLaunchKernelGGL(k_sum_slabs, dim3(nblk((long long)N * K, 256)), dim3(256), 0, m->aux, m->part, nzs,
-                       (long)N * K, m->G + m->woff[l]);
-    if (l == L - 1) {   // output layer: column sums of the FP32 loss gradient
+    if (l == L - 1) {   // output layer: column sums of the FP32 loss gradient (they reuse m->part)
+      hipLaunchKernelGGL(k_sum_slabs, dim3(nblk((long long)N * K, 256)), dim3(256), 0, m->aux, m->part, nzs,
+                         (long)N * K, m->G + m->woff[l]);
       const int ry = std::max(1, std::min(COLSUM_ROWS, (Bi + 31) / 32));
       hipLaunchKernelGGL(k_colsum_part, dim3(nblk(N, 256), ry), dim3(256), 0, m->aux, m->dY, Bi, N, m->part);
       hipLaunchKernelGGL(k_sum_rows, dim3(nblk(N, 64)), dim3(256), 0, m->aux, m->part, ry, (long)N,
                          m->G + m->boff[l]);
-    } else {            // hidden layers: the per-wave column sums left by layer l+1's input product
-      hipLaunchKernelGGL(k_sum_rows, dim3(nblk(N, 64)), dim3(256), 0, m->aux, m->dzc[l + 1], 2 * (int)nblk(Bi, GBM),
-                         (long)N, m->G + m->boff[l]);
+    } else {            // hidden layers: the slabs and the per-wave column sums left by layer
+                        // l+1's input product, in one launch
+      const int nbw = (int)nblk((long long)N * K, 256);
+      hipLaunchKernelGGL(k_sum_grads, dim3(nbw + (int)nblk(N, 64)), dim3(256), 0, m->aux, m->part, nzs,
+                         (long)N * K, m->G + m->woff[l], nbw, m->dzc[l + 1], 2 * (int)nblk(Bi, GBM), (long)N,
+                         m->G + m->boff[l]);
     }
   }
   if (hipEventRecord(m->done, m->aux) != hipSuccess || hipStreamWaitEvent(s, m->done, 0) != hipSuccess)
