@@ -9,8 +9,8 @@ CPU oracle timed on a bounded sample of the same workload.
 The learned leg trains the proposal / warm-start network on evaluator results (BF16 matrix
 cores), times its training step and batched inference against the BF16 matrix-core peak,
 and compares the device time to the first feasible plan of the plain and the learned
-expansion on held-out instances (pushing, flipping, and pushing with free motion in the
-paper's s_max = 1 configuration).
+expansion on held-out instances (pushing, flipping, and pushing with free motion, with the
+fixed step and as the paper transcribes it, in the paper's s_max = 1 configuration).
 
 The flipping leg times one round of the bimanual-flipping workload (32,768 orders); the
 timed leg runs the headline orders with optimised timing (interval durations as controls).
@@ -610,15 +610,18 @@ def learned_flip_leg(native, I, torch):
     }
 
 
-def learned_free_leg(native, I, torch):
-    """The learned proposal on pushing with free motion (fixed step): train a network on the
-    evaluator's results of uniformly sampled admissible orders (cap 8, 50 intervals per
-    order) and compare the plain and the learned expansion in the paper's s_max = 1
-    configuration on the free leg's four goals (held out from training)."""
+def learned_free_leg(native, I, torch, timed=False):
+    """The learned proposal on pushing with free motion: train a network on the evaluator's
+    results of uniformly sampled admissible orders (cap 8, 50 intervals per order) and
+    compare the plain and the learned expansion in the paper's s_max = 1 configuration on
+    the free leg's four goals (held out from training).  timed=True: the paper's
+    transcription (optimised timing) with its budgets (30 x 10 and 60 x 25 Gauss-Newton
+    iterations), for the training data as for the searches."""
     from paper_2609_21803_amd import learned
-    task = native.TASK_PUSH_FREE
+    task = native.TASK_PUSH_FREE_TIMED if timed else native.TASK_PUSH_FREE
+    budgets = native.SolverParams(al_max=30, gn_max=10, ref_al_max=60, ref_gn_max=25) if timed else None
     t0 = time.perf_counter()
-    gen = native.Context(max_batch=16384, max_segments=8, max_intervals=50, task=task)
+    gen = native.Context(max_batch=16384, max_segments=8, max_intervals=50, task=task, params=budgets)
     data = learned.generate_free(16, 16384, seed=6000, ctx=gen, kcap=8, n_total=50)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
@@ -630,7 +633,7 @@ def learned_free_leg(native, I, torch):
     t_train = time.perf_counter() - t0
     prm = native.ExpandParams(kcap=8, radius=2, knots_per_segment=0, n_total=50, k_ref=256, seed_max_segments=6,
                               rounds=1, frontier_W=1024, batch_B=16384, eval_budget=205632, learned_warm=1)
-    ctx = native.Context(max_batch=16384, max_segments=8, max_intervals=50, task=task)
+    ctx = native.Context(max_batch=16384, max_segments=8, max_intervals=50, task=task, params=budgets)
     pairs = [tuple(a[0] for a in I.push_free_pairs(sd, 1)) for sd in range(5300, 5304)]
     rows = learned.compare(ctx, mlp, prm, pairs, trace=True)
     auc_net, auc_plain = [], []
@@ -658,7 +661,8 @@ def learned_free_leg(native, I, torch):
                             "plain_order_median": float(np.nanmedian(auc_plain)),
                             "over": "every order the plain expansion evaluated on each goal"},
         "instances": "the free leg's goals (seeds 5300-5303), cap 8, seed <= 6 segments, one round of two-edit "
-                     "neighbours (W = 1,024, batches of 16,384), 50 intervals per order, refinement of 256",
+                     "neighbours (W = 1,024, batches of 16,384), 50 intervals per order, refinement of 256" +
+                     ("; optimised timing, budgets 30 x 10 and 60 x 25 Gauss-Newton iterations" if timed else ""),
         "training": {"samples": int(data["X"].shape[0]), "feasible_fraction": float(data["y_feas"].mean()),
                      "sampling": "16 goals (seed 6000), 16,384 distinct orders each from the uniform sampler",
                      "steps": 800, "batch": 8192, "gen_s": t_gen, "train_s": t_train, "final_loss": log[-1][1]},
@@ -839,6 +843,8 @@ def main():
             ("learned_flip", not args.no_learned, lambda: learned_flip_leg(native, I, torch)),
             ("learned_free", not args.no_learned and not args.no_free,
              lambda: learned_free_leg(native, I, torch)),
+            ("learned_free_timed", not args.no_learned and not args.no_free_timed,
+             lambda: learned_free_leg(native, I, torch, timed=True)),
             ("cpu_baseline", not args.no_cpu, lambda: cpu_baseline(batch))]
     for name, on, run in legs:
         if on:
